@@ -1,0 +1,291 @@
+/*
+ * Stabilizer-tableau oracle -- TEST INFRASTRUCTURE ONLY.
+ *
+ * Plain, slow, byte-per-bit CPU implementation of the phase-space (stabilizer
+ * tableau) simulation the paper's Clifford backend is built on (Sec. 2, which
+ * cites Aaronson & Gottesman, Phys. Rev. A 70, 052328 (2004), "AG" below).
+ * Only the tests, the smoke check and the CPU-baseline leg of the benchmark may
+ * use it; the product path never links it.  It shares no code with the GPU
+ * library: the two meet only through the seeded circuit arrays.
+ *
+ * State (AG, "tableau" representation): rows 0..n-1 are destabilizers, rows
+ * n..2n-1 stabilizers, row 2n is scratch.  Row i stands for the Pauli product
+ * (-1)^r[i] * prod_j P(x[i][j], z[i][j]) with P(0,0)=I, P(1,0)=X, P(0,1)=Z,
+ * P(1,1)=Y.  Every entry is one byte holding 0 or 1.
+ *
+ * Readings where the paper (and its citation) leave a choice open:
+ *   - the pivot of a random measurement is the smallest stabilizer row with x=1;
+ *   - the random outcome is bit 0 of word 0 of Philox4x64-10 with
+ *     key = (seed, 0) and counter = (m, shot, circuit, 0), m = measurement index;
+ *   - S is diag(1, i).
+ */
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+
+typedef struct {
+    int n;
+    uint8_t *x;      /* (2n+1) rows x n columns, row-major */
+    uint8_t *z;
+    uint8_t *r;      /* 2n+1 */
+    long anomalies;  /* rowsums whose phase came out odd on a row other than p-n */
+} otab;
+
+#define X(t, i, j) ((t)->x[(size_t)(i) * (size_t)(t)->n + (size_t)(j)])
+#define Z(t, i, j) ((t)->z[(size_t)(i) * (size_t)(t)->n + (size_t)(j)])
+
+/* ---------------------------------------------------------------- Philox ---
+ * Philox4x64-10 (Salmon, Moraes, Dror, Shaw, "Parallel random numbers: as easy
+ * as 1, 2, 3", SC'11).  One round maps counter (c0,c1,c2,c3) with key (k0,k1)
+ * to (hi(B*c2) ^ c1 ^ k0, lo(B*c2), hi(A*c0) ^ c3 ^ k1, lo(A*c0)); the key is
+ * bumped by the Weyl constants between rounds.
+ */
+static void mul128(uint64_t a, uint64_t b, uint64_t *hi, uint64_t *lo) {
+    unsigned __int128 p = (unsigned __int128)a * (unsigned __int128)b;
+    *hi = (uint64_t)(p >> 64);
+    *lo = (uint64_t)p;
+}
+
+void orc_philox4x64_10(const uint64_t ctr[4], const uint64_t key[2], uint64_t out[4]) {
+    const uint64_t A = 0xD2E7470EE14C6C93ULL, B = 0xCA5A826395121157ULL;
+    const uint64_t W0 = 0x9E3779B97F4A7C15ULL, W1 = 0xBB67AE8584CAA73BULL;
+    uint64_t c0 = ctr[0], c1 = ctr[1], c2 = ctr[2], c3 = ctr[3];
+    uint64_t k0 = key[0], k1 = key[1];
+    for (int round = 0; round < 10; ++round) {
+        if (round > 0) { k0 += W0; k1 += W1; }
+        uint64_t hA, lA, hB, lB;
+        mul128(A, c0, &hA, &lA);
+        mul128(B, c2, &hB, &lB);
+        uint64_t n0 = hB ^ c1 ^ k0, n1 = lB, n2 = hA ^ c3 ^ k1, n3 = lA;
+        c0 = n0; c1 = n1; c2 = n2; c3 = n3;
+    }
+    out[0] = c0; out[1] = c1; out[2] = c2; out[3] = c3;
+}
+
+int orc_random_bit(uint64_t seed, uint64_t circuit, uint64_t shot, uint64_t m) {
+    uint64_t ctr[4] = {m, shot, circuit, 0}, key[2] = {seed, 0}, out[4];
+    orc_philox4x64_10(ctr, key, out);
+    return (int)(out[0] & 1u);
+}
+
+/* -------------------------------------------------------------- tableau --- */
+otab *orc_new(int n) {
+    otab *t = (otab *)calloc(1, sizeof(otab));
+    if (!t) return NULL;
+    size_t rows = 2 * (size_t)n + 1;
+    t->n = n;
+    t->x = (uint8_t *)calloc(rows * (size_t)n, 1);
+    t->z = (uint8_t *)calloc(rows * (size_t)n, 1);
+    t->r = (uint8_t *)calloc(rows, 1);
+    if (!t->x || !t->z || !t->r) { free(t->x); free(t->z); free(t->r); free(t); return NULL; }
+    /* |0...0>: destabilizer i = X_i, stabilizer n+i = Z_i, all signs + */
+    for (int i = 0; i < n; ++i) {
+        X(t, i, i) = 1;
+        Z(t, n + i, i) = 1;
+    }
+    return t;
+}
+
+void orc_free(otab *t) {
+    if (!t) return;
+    free(t->x); free(t->z); free(t->r); free(t);
+}
+
+otab *orc_clone(const otab *s) {
+    otab *t = orc_new(s->n);
+    if (!t) return NULL;
+    size_t rows = 2 * (size_t)s->n + 1;
+    memcpy(t->x, s->x, rows * (size_t)s->n);
+    memcpy(t->z, s->z, rows * (size_t)s->n);
+    memcpy(t->r, s->r, rows);
+    t->anomalies = s->anomalies;
+    return t;
+}
+
+int orc_n(const otab *t) { return t->n; }
+long orc_anomalies(const otab *t) { return t->anomalies; }
+
+/* Copy out / in the 2n real rows (scratch row excluded). */
+void orc_get(const otab *t, uint8_t *x, uint8_t *z, uint8_t *r) {
+    size_t cells = 2 * (size_t)t->n * (size_t)t->n;
+    memcpy(x, t->x, cells);
+    memcpy(z, t->z, cells);
+    memcpy(r, t->r, 2 * (size_t)t->n);
+}
+
+void orc_set(otab *t, const uint8_t *x, const uint8_t *z, const uint8_t *r) {
+    size_t cells = 2 * (size_t)t->n * (size_t)t->n;
+    memcpy(t->x, x, cells);
+    memcpy(t->z, z, cells);
+    memcpy(t->r, r, 2 * (size_t)t->n);
+}
+
+/* ---------------------------------------------------------------- gates ---
+ * Conjugation rules for every row i (AG): the sign picks up x*z for H and S,
+ * and x_a z_b (x_b xor z_a xor 1) for CNOT(a -> b).
+ */
+void orc_h(otab *t, int a) {
+    for (int i = 0; i < 2 * t->n; ++i) {
+        uint8_t xa = X(t, i, a), za = Z(t, i, a);
+        t->r[i] ^= (uint8_t)(xa & za);
+        X(t, i, a) = za;
+        Z(t, i, a) = xa;
+    }
+}
+
+void orc_s(otab *t, int a) {
+    for (int i = 0; i < 2 * t->n; ++i) {
+        uint8_t xa = X(t, i, a), za = Z(t, i, a);
+        t->r[i] ^= (uint8_t)(xa & za);
+        Z(t, i, a) = (uint8_t)(za ^ xa);
+    }
+}
+
+void orc_cnot(otab *t, int a, int b) {
+    for (int i = 0; i < 2 * t->n; ++i) {
+        uint8_t xa = X(t, i, a), za = Z(t, i, a), xb = X(t, i, b), zb = Z(t, i, b);
+        t->r[i] ^= (uint8_t)(xa & zb & (xb ^ za ^ 1));
+        X(t, i, b) = (uint8_t)(xb ^ xa);
+        Z(t, i, a) = (uint8_t)(za ^ zb);
+    }
+}
+
+/* Layered circuit: per qubit H (if h) then S (if s), then every CNOT pair. */
+void orc_apply_layers(otab *t, int depth, const uint8_t *h, const uint8_t *s,
+                      const uint32_t *ctrl, const uint32_t *tgt, int npairs) {
+    int n = t->n;
+    for (int l = 0; l < depth; ++l) {
+        for (int q = 0; q < n; ++q) {
+            if (h[(size_t)l * n + q]) orc_h(t, q);
+            if (s[(size_t)l * n + q]) orc_s(t, q);
+        }
+        for (int k = 0; k < npairs; ++k)
+            orc_cnot(t, (int)ctrl[(size_t)l * npairs + k], (int)tgt[(size_t)l * npairs + k]);
+    }
+}
+
+/* Gate list: op 0 = H(a), 1 = S(a), 2 = CNOT(a -> b). */
+void orc_apply_gates(otab *t, long count, const uint8_t *op, const uint32_t *a, const uint32_t *b) {
+    for (long k = 0; k < count; ++k) {
+        if (op[k] == 0) orc_h(t, (int)a[k]);
+        else if (op[k] == 1) orc_s(t, (int)a[k]);
+        else orc_cnot(t, (int)a[k], (int)b[k]);
+    }
+}
+
+/* ---------------------------------------------------------- g / rowsum ---
+ * g(x1,z1,x2,z2): exponent to which i is raised when the single-qubit Paulis
+ * P(x1,z1) and P(x2,z2) are multiplied (AG).
+ */
+int orc_g(int x1, int z1, int x2, int z2) {
+    if (x1 == 0 && z1 == 0) return 0;
+    if (x1 == 1 && z1 == 1) return z2 - x2;
+    if (x1 == 1 && z1 == 0) return z2 * (2 * x2 - 1);
+    return x2 * (1 - 2 * z2); /* x1 == 0, z1 == 1 */
+}
+
+/* rowsum(h, i): row h <- row i * row h with the sign tracked mod 4 (AG). */
+static void rowsum_raw(otab *t, int h, int i, int *e_out) {
+    int n = t->n;
+    long e = 2L * t->r[h] + 2L * t->r[i];
+    for (int j = 0; j < n; ++j)
+        e += orc_g(X(t, i, j), Z(t, i, j), X(t, h, j), Z(t, h, j));
+    e %= 4;
+    if (e < 0) e += 4;
+    *e_out = (int)e;
+    t->r[h] = (uint8_t)(e == 2 ? 1 : 0);
+    for (int j = 0; j < n; ++j) {
+        X(t, h, j) ^= X(t, i, j);
+        Z(t, h, j) ^= Z(t, i, j);
+    }
+}
+
+/* Exported single rowsum; returns e mod 4 (0 or 2 when the rows commute). */
+int orc_rowsum(otab *t, int h, int i) {
+    int e;
+    rowsum_raw(t, h, i, &e);
+    return e;
+}
+
+/* ----------------------------------------------------------- measurement ---
+ * Z-measurement of qubit a (AG).  Returns the outcome bit; *kind is set to 1
+ * when the outcome was random, 0 when it was determined by the state.
+ */
+int orc_measure(otab *t, int a, uint64_t seed, uint64_t circuit, uint64_t shot,
+                uint64_t m, int *kind) {
+    int n = t->n;
+    int p = -1;
+    for (int i = n; i < 2 * n; ++i)
+        if (X(t, i, a)) { p = i; break; }
+
+    if (p >= 0) {
+        /* random: multiply the pivot into every other row that anticommutes
+           with Z_a, move the pivot into its destabilizer slot, and replace it
+           by +-Z_a with a fresh random sign */
+        for (int i = 0; i < 2 * n; ++i) {
+            if (i == p || !X(t, i, a)) continue;
+            int e;
+            rowsum_raw(t, i, p, &e);
+            if ((e & 1) && i != p - n) t->anomalies++;
+        }
+        memcpy(&X(t, p - n, 0), &X(t, p, 0), (size_t)n);
+        memcpy(&Z(t, p - n, 0), &Z(t, p, 0), (size_t)n);
+        t->r[p - n] = t->r[p];
+        memset(&X(t, p, 0), 0, (size_t)n);
+        memset(&Z(t, p, 0), 0, (size_t)n);
+        Z(t, p, a) = 1;
+        t->r[p] = (uint8_t)orc_random_bit(seed, circuit, shot, m);
+        if (kind) *kind = 1;
+        return t->r[p];
+    }
+
+    /* deterministic: accumulate the product of the stabilizers whose
+       destabilizer partner anticommutes with Z_a in the scratch row */
+    int sc = 2 * n;
+    memset(&X(t, sc, 0), 0, (size_t)n);
+    memset(&Z(t, sc, 0), 0, (size_t)n);
+    t->r[sc] = 0;
+    for (int i = 0; i < n; ++i) {
+        if (!X(t, i, a)) continue;
+        int e;
+        rowsum_raw(t, sc, i + n, &e);
+        if (e & 1) t->anomalies++;
+    }
+    if (kind) *kind = 0;
+    return t->r[sc];
+}
+
+/*
+ * Whole circuit for one shot: gates on a fresh |0...0>, then measure
+ * qubits[0..k) in order with measurement index m = position.  Outcomes and
+ * kinds are written to out[k] / kind[k]; if x, z, r are non-NULL the final
+ * tableau (2n rows) is copied out.  Returns 0, or -1 on allocation failure.
+ */
+int orc_run_shot(int n, int depth, const uint8_t *h, const uint8_t *s,
+                 const uint32_t *ctrl, const uint32_t *tgt, int npairs,
+                 int k, const uint32_t *qubits, uint64_t seed, uint64_t circuit,
+                 uint64_t shot, uint8_t *out, uint8_t *kind,
+                 uint8_t *x, uint8_t *z, uint8_t *r) {
+    otab *t = orc_new(n);
+    if (!t) return -1;
+    orc_apply_layers(t, depth, h, s, ctrl, tgt, npairs);
+    for (int m = 0; m < k; ++m) {
+        int kd;
+        out[m] = (uint8_t)orc_measure(t, (int)qubits[m], seed, circuit, shot, (uint64_t)m, &kd);
+        if (kind) kind[m] = (uint8_t)kd;
+    }
+    if (x && z && r) orc_get(t, x, z, r);
+    orc_free(t);
+    return 0;
+}
+
+/* Measure qubits[0..k) on the given tableau (in place), indices m0.. */
+void orc_measure_list(otab *t, int k, const uint32_t *qubits, uint64_t seed,
+                      uint64_t circuit, uint64_t shot, uint64_t m0,
+                      uint8_t *out, uint8_t *kind) {
+    for (int m = 0; m < k; ++m) {
+        int kd;
+        out[m] = (uint8_t)orc_measure(t, (int)qubits[m], seed, circuit, shot, m0 + (uint64_t)m, &kd);
+        if (kind) kind[m] = (uint8_t)kd;
+    }
+}

@@ -1,0 +1,354 @@
+"""Pins for the CPU oracle against mathematics that does not use the tableau method.
+
+Each check targets a part of the oracle where a plausible slip (a dropped sign
+term, a swapped operand of g, a wrong pivot row, an off-by-n index) would show:
+  * Philox4x64-10 vs numpy's independent implementation and Random123 KATs;
+  * g vs explicit 2x2 Pauli products (all 16 cases);
+  * H / S / CNOT row updates vs explicit conjugation U P U^dagger;
+  * rowsum vs explicit Pauli-string products with the complex phase tracked;
+  * closed-form identities (H^2, S^4, S^2 = Z, CNOT^2, (HS)^3) bit-exactly;
+  * random circuits with interleaved measurements vs a dense statevector;
+  * Bell / GHZ correlations; symplectic invariants; log2 |supp psi|.
+"""
+import itertools
+
+import numpy as np
+import pytest
+
+import oracle
+from inputs import layered_circuit, random_gate_list
+from pins import (HM, PX, PY, PZ, SM, StateVector, kron_list, pauli1,
+                  pauli_string, symplectic_ok)
+
+pytestmark = pytest.mark.filterwarnings("ignore::DeprecationWarning")
+
+
+# ------------------------------------------------------------------ Philox ---
+
+def _numpy_philox_block(counter, key):
+    # numpy's Philox pre-increments its 256-bit counter before each block, so
+    # starting one below the wanted counter yields the block for that counter.
+    c = [int(v) for v in counter]
+    borrow = 1
+    for i in range(4):
+        v = c[i] - borrow
+        borrow = 1 if v < 0 else 0
+        c[i] = v % (1 << 64)
+    g = np.random.Philox(key=np.array(key, np.uint64), counter=np.array(c, np.uint64))
+    return g.random_raw(4)
+
+
+def test_philox_known_answers():
+    # Random123 known-answer vectors for philox4x64 with 10 rounds
+    zero = oracle.philox4x64_10([0, 0, 0, 0], [0, 0])
+    assert [int(v) for v in zero] == [0x16554D9ECA36314C, 0xDB20FE9D672D0FDC,
+                                      0xD7E772CEE186176B, 0x7E68B68AEC7BA23B]
+    pi = oracle.philox4x64_10([0x243F6A8885A308D3, 0x13198A2E03707344,
+                               0xA4093822299F31D0, 0x082EFA98EC4E6C89],
+                              [0x452821E638D01377, 0xBE5466CF34E90C6C])
+    assert [int(v) for v in pi] == [0xA528F45403E61D95, 0x38C72DBD566E9788,
+                                    0xA5A1610E72FD18B5, 0x57BD43B5E52B7FE6]
+
+
+def test_philox_matches_numpy():
+    rng = np.random.default_rng(123)
+    for _ in range(200):
+        ctr = rng.integers(0, 2 ** 63, size=4, dtype=np.uint64) * np.uint64(2) + rng.integers(0, 2, 4, dtype=np.uint64)
+        key = rng.integers(0, 2 ** 63, size=2, dtype=np.uint64) * np.uint64(2)
+        ours = oracle.philox4x64_10(ctr, key)
+        ref = _numpy_philox_block(ctr, key)
+        assert np.array_equal(ours, ref)
+
+
+def test_random_bit_keying():
+    seed, circ, shot, m = 0x240800384, 7, 3, 11
+    block = _numpy_philox_block([m, shot, circ, 0], [seed, 0])
+    assert oracle.random_bit(seed, circ, shot, m) == int(block[0]) & 1
+    bits = [oracle.random_bit(seed, 0, 0, m) for m in range(4000)]
+    assert 1800 < sum(bits) < 2200  # a fair coin, loosely
+
+
+# ----------------------------------------------------------------------- g ---
+
+def test_g_all_sixteen_cases():
+    for x1, z1, x2, z2 in itertools.product((0, 1), repeat=4):
+        prod = pauli1(x1, z1) @ pauli1(x2, z2)
+        res = pauli1(x1 ^ x2, z1 ^ z2)
+        k = oracle.g(x1, z1, x2, z2)
+        assert np.allclose(prod, (1j ** k) * res), (x1, z1, x2, z2, k)
+        assert -1 <= k <= 1
+
+
+# ------------------------------------------------------------- gate rules ---
+
+def _single_row_tableau(n, x, z, r):
+    """Tableau whose row 0 is the given Pauli; other rows are unused filler."""
+    t = oracle.Tableau(n)
+    X, Z, R = t.get()
+    X[0], Z[0], R[0] = x, z, r
+    t.set(X, Z, R)
+    return t
+
+
+def _conj_check(n, gate_fn, U):
+    for bits in itertools.product((0, 1), repeat=2 * n + 1):
+        x = np.array(bits[:n], np.uint8)
+        z = np.array(bits[n:2 * n], np.uint8)
+        r = bits[2 * n]
+        t = _single_row_tableau(n, x, z, r)
+        gate_fn(t)
+        X, Z, R = t.get()
+        want = U @ pauli_string(x, z, r) @ U.conj().T
+        got = pauli_string(X[0], Z[0], R[0])
+        assert np.allclose(want, got), (x, z, r)
+
+
+def test_h_rule():
+    _conj_check(1, lambda t: t.h(0), HM)
+
+
+def test_s_rule():
+    _conj_check(1, lambda t: t.s(0), SM)
+
+
+def test_cnot_rule_both_orientations():
+    # basis index bit j = qubit j; CNOT(control c, target t)
+    def cnot_matrix(c, tq):
+        U = np.zeros((4, 4), complex)
+        for i in range(4):
+            j = i ^ (1 << tq) if (i >> c) & 1 else i
+            U[j, i] = 1
+        return U
+    _conj_check(2, lambda t: t.cnot(0, 1), cnot_matrix(0, 1))
+    _conj_check(2, lambda t: t.cnot(1, 0), cnot_matrix(1, 0))
+
+
+# ------------------------------------------------------------------ rowsum ---
+
+@pytest.mark.parametrize("n", [1, 2, 5, 17, 64])
+def test_rowsum_vs_pauli_products(n):
+    rng = np.random.default_rng(n)
+    for _ in range(60):
+        # two random commuting Pauli strings: draw, then fix commutation by
+        # flipping one z bit where the first string has an x
+        x1, z1 = rng.integers(0, 2, n), rng.integers(0, 2, n)
+        x2, z2 = rng.integers(0, 2, n), rng.integers(0, 2, n)
+        r1, r2 = int(rng.integers(0, 2)), int(rng.integers(0, 2))
+        sym = int((x1 @ z2 + z1 @ x2) % 2)
+        if sym:
+            j = int(np.flatnonzero(x1 | z1)[0]) if np.any(x1 | z1) else None
+            if j is None:
+                continue
+            if x1[j]:
+                z2[j] ^= 1
+            else:
+                x2[j] ^= 1
+        assert int((x1 @ z2 + z1 @ x2) % 2) == 0
+        # explicit product phase: (-1)^r1 P1 * (-1)^r2 P2 per qubit with 2x2 matrices
+        phase = (-1) ** (r1 + r2) + 0j
+        for j in range(n):
+            prod = pauli1(x1[j], z1[j]) @ pauli1(x2[j], z2[j])
+            res = pauli1(x1[j] ^ x2[j], z1[j] ^ z2[j])
+            k = [c for c in range(4) if np.allclose(prod, (1j ** c) * res)]
+            assert len(k) == 1
+            phase *= 1j ** k[0]
+        assert np.isclose(phase.imag, 0) and np.isclose(abs(phase.real), 1)
+        want_r = 0 if phase.real > 0 else 1
+
+        t = oracle.Tableau(n)
+        X, Z, R = t.get()
+        X[0], Z[0], R[0] = x2, z2, r2   # h = 0 (target)
+        X[1], Z[1], R[1] = x1, z1, r1   # i = 1 (source): row0 <- row1 * row0
+        t.set(X, Z, R)
+        e = t.rowsum(0, 1)
+        X2, Z2, R2 = t.get()
+        assert e in (0, 2)
+        assert R2[0] == want_r
+        assert np.array_equal(X2[0], x1 ^ x2) and np.array_equal(Z2[0], z1 ^ z2)
+        assert np.array_equal(X2[1], x1) and R2[1] == r1
+
+
+# -------------------------------------------------------------- identities ---
+
+def _random_state(n, seed):
+    c = layered_circuit(n, 6, 1, gen_seed=seed)
+    t = oracle.Tableau(n)
+    t.apply_circuit_gates(c)
+    return t
+
+
+@pytest.mark.parametrize("seed", [0, 1, 2])
+def test_identities_bit_exact(seed):
+    n = 9
+    t = _random_state(n, seed)
+    base = t.get()
+    for a in range(n):
+        for seq in (["h", "h"], ["s"] * 4, ["h", "s"] * 3):
+            u = t.clone()
+            for gname in seq:
+                getattr(u, gname)(a)
+            for A, B in zip(u.get(), base):
+                assert np.array_equal(A, B), (a, seq)
+        u = t.clone().s(a).s(a)
+        X, Z, R = u.get()
+        assert np.array_equal(X, base[0]) and np.array_equal(Z, base[1])
+        assert np.array_equal(R, base[2] ^ base[0][:, a])  # S^2 = Z flips rows with x_a
+    for a in range(n):
+        for b in range(n):
+            if a != b:
+                u = t.clone().cnot(a, b).cnot(a, b)
+                for A, B in zip(u.get(), base):
+                    assert np.array_equal(A, B)
+
+
+# ------------------------------------------------------- vs a statevector ---
+
+def _check_stabilizers(t, sv):
+    X, Z, R = t.get()
+    n = t.n
+    for i in range(n, 2 * n):
+        v = sv.expect(pauli_string(X[i], Z[i], R[i]))
+        assert np.isclose(v, 1.0, atol=1e-9), (i, v)
+    assert symplectic_ok(X, Z)
+
+
+@pytest.mark.parametrize("seed", range(12))
+def test_random_circuits_with_measurements_vs_statevector(seed):
+    rng = np.random.default_rng(1000 + seed)
+    n = int(rng.integers(1, 8))
+    t = oracle.Tableau(n)
+    sv = StateVector(n)
+    m = 0
+    for block in range(6):
+        ops, a, b = random_gate_list(rng, n, int(rng.integers(1, 15)))
+        t.apply_gates(ops, a, b)
+        sv.apply_gates(ops, a, b)
+        _check_stabilizers(t, sv)
+        for _ in range(int(rng.integers(0, 3))):
+            q = int(rng.integers(0, n))
+            p1 = sv.prob_one(q)
+            bit, rnd = t.measure(q, seed=99, circuit=seed, shot=0, m=m)
+            if rnd:
+                assert np.isclose(p1, 0.5, atol=1e-9)
+                assert bit == oracle.random_bit(99, seed, 0, m)
+            else:
+                assert np.isclose(p1, float(bit), atol=1e-9)
+            sv.collapse(q, bit)
+            m += 1
+            _check_stabilizers(t, sv)
+    assert t.anomalies == 0
+
+
+@pytest.mark.parametrize("n", [3, 6, 10])
+def test_measure_all_random_count_is_log_support(n):
+    for seed in range(4):
+        c = layered_circuit(n, 5, 1, gen_seed=[n, seed])
+        t = oracle.Tableau(n).apply_circuit_gates(c)
+        sv = StateVector(n)
+        sv.apply_layers(c.h, c.s, c.ctrl, c.tgt)
+        _check_stabilizers(t, sv)
+        supp = sv.support_size()
+        out, kinds = t.measure_list(np.arange(n), seed=5, circuit=seed)
+        assert 2 ** int(kinds.sum()) == supp
+        # the outcome string lies in the support of the state
+        idx = int(sum(int(b) << j for j, b in enumerate(out)))
+        assert abs(sv.psi[idx]) > 1e-9
+        assert t.anomalies == 0
+
+
+def test_bell_and_ghz():
+    for shot in range(20):
+        t = oracle.Tableau(2).h(0).cnot(0, 1)
+        b0, r0 = t.measure(0, seed=1, shot=shot, m=0)
+        b1, r1 = t.measure(1, seed=1, shot=shot, m=1)
+        assert r0 and not r1 and b0 == b1
+    outs = set()
+    for shot in range(32):
+        n = 12
+        t = oracle.Tableau(n).h(0)
+        for q in range(1, n):
+            t.cnot(q - 1, q)
+        out, kinds = t.measure_list(np.arange(n), seed=3, shot=shot)
+        assert kinds[0] == 1 and kinds[1:].sum() == 0
+        assert len(set(out.tolist())) == 1
+        outs.add(int(out[0]))
+    assert outs == {0, 1}
+
+
+def test_plus_state_measured_twice_and_zero_state():
+    t = oracle.Tableau(1).h(0)
+    b0, r0 = t.measure(0, seed=4, m=0)
+    b1, r1 = t.measure(0, seed=4, m=1)
+    assert r0 and not r1 and b0 == b1
+    t = oracle.Tableau(7)
+    out, kinds = t.measure_list(np.arange(7))
+    assert out.sum() == 0 and kinds.sum() == 0
+    # |1> via H S S H = X: deterministic 1
+    t = oracle.Tableau(1).h(0).s(0).s(0).h(0)
+    assert t.measure(0) == (1, False)
+
+
+def test_symplectic_invariants_after_measurements():
+    n = 40
+    c = layered_circuit(n, 8, 1, gen_seed=77)
+    t = oracle.Tableau(n).apply_circuit_gates(c)
+    X, Z, _ = t.get()
+    assert symplectic_ok(X, Z)
+    for k in range(0, n, 3):
+        t.measure(k, m=k)
+        X, Z, _ = t.get()
+        assert symplectic_ok(X, Z)
+    assert t.anomalies == 0
+
+
+def test_run_shot_matches_stepwise():
+    c = layered_circuit(20, 10, 3, gen_seed=5, circuit_id=4)
+    for shot in range(3):
+        out, kind, (x, z, r) = oracle.run_shot(c, shot, want_tableau=True)
+        t = oracle.Tableau(20).apply_circuit_gates(c)
+        o2, k2 = t.measure_list(c.qubits, seed=c.seed, circuit=4, shot=shot)
+        assert np.array_equal(out, o2) and np.array_equal(kind, k2)
+        for A, B in zip((x, z, r), t.get()):
+            assert np.array_equal(A, B)
+
+
+def test_hand_worked_pivot_example():
+    """Worked by hand from the gate rules and the smallest-pivot reading.
+
+    n = 2, circuit H(0) H(1) CNOT(0 -> 1) gives rows
+      0: Z0   1: Z0 Z1   2: X0 X1   3: X1          (all signs +)
+    Measuring qubit 1: stabilizer rows 2 and 3 both have x_1 = 1, so p = 2.
+    Row 3 <- row 2 * row 3 = X0 (sign +), row 0 <- old row 2 = X0 X1, and
+    row 2 <- (-1)^b Z1 with b the Philox bit.  A largest-pivot choice would
+    instead leave rows 0..3 = Z0, X1, X0, Z1.
+    """
+    t = oracle.Tableau(2).h(0).h(1).cnot(0, 1)
+    X, Z, R = t.get()
+    assert X.tolist() == [[0, 0], [0, 0], [1, 1], [0, 1]]
+    assert Z.tolist() == [[1, 0], [1, 1], [0, 0], [0, 0]]
+    assert R.tolist() == [0, 0, 0, 0]
+    bit, rnd = t.measure(1, seed=11, circuit=2, shot=5, m=3)
+    assert rnd and bit == oracle.random_bit(11, 2, 5, 3)
+    X, Z, R = t.get()
+    assert X.tolist() == [[1, 1], [0, 0], [0, 0], [1, 0]]
+    assert Z.tolist() == [[0, 0], [1, 1], [0, 1], [0, 0]]
+    assert R.tolist() == [0, 0, bit, 0]
+
+
+def test_hand_worked_deterministic_sign():
+    """Worked by hand: on |0> the stabilizer is +Z.  H maps it to +X and S
+    maps X to +Y; a further H maps Y to -Y, and S maps -Y to +X.  H S S H
+    (X up to phase) maps +Z to -Z, so |1> measures 1 deterministically."""
+    t = oracle.Tableau(1).h(0).s(0)
+    X, Z, R = t.get()
+    assert (X[1, 0], Z[1, 0], R[1]) == (1, 1, 0)        # +Y
+    t.h(0)
+    X, Z, R = t.get()
+    assert (X[1, 0], Z[1, 0], R[1]) == (1, 1, 1)        # -Y
+    t.s(0)
+    X, Z, R = t.get()
+    assert (X[1, 0], Z[1, 0], R[1]) == (1, 0, 0)        # +X
+    u = oracle.Tableau(1).h(0).s(0).s(0).h(0)
+    X, Z, R = u.get()
+    assert (X[1, 0], Z[1, 0], R[1]) == (0, 1, 1)        # -Z
+    assert u.measure(0) == (1, False)
