@@ -1,0 +1,147 @@
+/*
+ * cliff.h -- C ABI of the MI355X (gfx950) stabilizer-tableau library.
+ *
+ * The library simulates Clifford circuits in the phase-space (stabilizer
+ * tableau) formalism that the paper's Clifford backend is built on (Sec. 2,
+ * "Simulation of Clifford circuits", which cites Aaronson & Gottesman,
+ * Phys. Rev. A 70, 052328 (2004) for the method).  A tableau on n qubits has
+ * 2n rows: rows 0..n-1 are destabilizers, rows n..2n-1 stabilizers; row i is
+ * the signed Pauli product (-1)^r_i * prod_j P(x_ij, z_ij).
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ *  - Return value: 0 (CLIFF_OK) or a negative CLIFF_E* code.  No call aborts
+ *    or throws across this boundary; cliff_last_error() gives a message for the
+ *    most recent failure on the calling thread.
+ *  - Device memory belongs to the caller.  A tableau is a view bound onto one
+ *    caller-owned device buffer of cliff_tab_bytes(n, shots) bytes; the library
+ *    never frees it.  The context owns only its own staging buffers.
+ *  - Host pointers are read (inputs) or written (outputs) before the call
+ *    returns.  Calls that return host data synchronize the context stream;
+ *    the others only enqueue work on it.
+ *  - Qubit indices are 0-based.  Row bits are packed LSB-first into 64-bit
+ *    words per qubit column (word w of column j holds rows 64w..64w+63).
+ *  - Shots: a tableau carries `shots` independent sign columns.  X/Z bits
+ *    never depend on signs or outcomes, so all shots share one X/Z sweep and
+ *    only the signs (and outcomes) differ per shot.
+ *  - Random outcomes: bit 0 of word 0 of Philox4x64-10 with key (seed, 0) and
+ *    counter (m, shot, circuit, 0), m = measurement index.
+ */
+#ifndef CLIFF_H
+#define CLIFF_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define CLIFF_OK 0
+#define CLIFF_EINVAL (-1)   /* bad argument: qubit >= n, CNOT a == b, bad op, NULL, size */
+#define CLIFF_ENOMEM (-2)   /* buffer too small / host allocation failed / budget exceeded */
+#define CLIFF_EDEVICE (-3)  /* HIP runtime error (message in cliff_last_error) */
+#define CLIFF_EBUSY (-4)    /* resource in use (e.g. admission slots full) */
+#define CLIFF_EINTERNAL (-5) /* a device-side consistency check failed */
+
+/* Gate op codes of cliff_apply_gates. */
+#define CLIFF_OP_H 0
+#define CLIFF_OP_S 1
+#define CLIFF_OP_CNOT 2
+
+typedef struct cliff_ctx cliff_ctx;
+typedef struct cliff_tab cliff_tab;
+
+/* Message for the last failing call on this thread (static storage). */
+const char *cliff_last_error(void);
+/* Name of a CLIFF_E* code. */
+const char *cliff_strerror(int code);
+
+/* Context: one device and one HIP stream (borrowed; may be NULL for the
+ * default stream).  All work of tableaux bound to it is enqueued on that
+ * stream.  Owns small staging buffers only. */
+int cliff_ctx_create(int device, void *hip_stream, cliff_ctx **out);
+int cliff_ctx_destroy(cliff_ctx *ctx);
+/* Block until all work enqueued by the context has finished. */
+int cliff_sync(cliff_ctx *ctx);
+/* Number of compute units of the context's device. */
+int cliff_ctx_num_cus(const cliff_ctx *ctx);
+
+/* Bytes of device memory a tableau of n qubits with `shots` sign columns needs,
+ * scratch included (X, Z, signs, measurement scratch, outcome staging). */
+size_t cliff_tab_bytes(uint32_t n, uint32_t shots);
+
+/* Bind a tableau view onto caller-owned device memory `dev` of `bytes` bytes
+ * (>= cliff_tab_bytes(n, shots), 256-byte aligned).  Does not allocate device
+ * memory and does not initialise it (call cliff_tab_init_zero or _import). */
+int cliff_tab_bind(cliff_ctx *ctx, uint32_t n, uint32_t shots, void *dev, size_t bytes,
+                   cliff_tab **out);
+int cliff_tab_unbind(cliff_tab *tab);
+int cliff_tab_info(const cliff_tab *tab, uint32_t *n, uint32_t *shots);
+
+/* |0...0>: destabilizer i = X_i, stabilizer n+i = Z_i, all signs + (the
+ * initial tableau of the phase-space method, Sec. 2 / AG). */
+int cliff_tab_init_zero(cliff_tab *tab);
+
+/* Apply gates in order.  op[k] in {CLIFF_OP_H, CLIFF_OP_S, CLIFF_OP_CNOT};
+ * a[k] is the qubit (CNOT control), b[k] the CNOT target (ignored otherwise).
+ * Update rules per row (AG, via Sec. 2):
+ *   H(a): r ^= x_a z_a, swap x_a and z_a;   S(a): r ^= x_a z_a, z_a ^= x_a;
+ *   CNOT(a->b): r ^= x_a z_b (x_b ^ z_a ^ 1), x_b ^= x_a, z_a ^= z_b.
+ * Validated on the host before any launch (EINVAL on bad op / qubit / a == b). */
+int cliff_apply_gates(cliff_tab *tab, const uint8_t *op, const uint32_t *a, const uint32_t *b,
+                      size_t count);
+
+/* Apply `depth` layers.  Layer l: for every qubit q, H if h[l*n+q], then S if
+ * s[l*n+q]; then CNOT(ctrl[l*npairs+k] -> tgt[l*npairs+k]) for k < npairs.
+ * The qubits of one layer's pairs must be distinct (EINVAL otherwise). */
+int cliff_apply_layers(cliff_tab *tab, const uint8_t *h, const uint8_t *s, const uint32_t *ctrl,
+                       const uint32_t *tgt, uint32_t npairs, uint32_t depth);
+
+/* Pre-encoded gate stream for repeated or device-resident use.
+ * cliff_encode_layers writes the library's op words for the layers above into
+ * ops (capacity in 64-bit words) and layer boundaries into offs[depth+1];
+ * *nops receives the word count.  With ops == NULL it only reports *nops.
+ * cliff_apply_encoded runs such a stream from DEVICE memory dev_ops, with the
+ * host array offs[depth+1] of layer boundaries. */
+int cliff_encode_layers(uint32_t n, const uint8_t *h, const uint8_t *s, const uint32_t *ctrl,
+                        const uint32_t *tgt, uint32_t npairs, uint32_t depth, uint64_t *ops,
+                        size_t cap, uint32_t *offs, size_t *nops);
+int cliff_apply_encoded(cliff_tab *tab, const uint64_t *dev_ops, const uint32_t *offs,
+                        uint32_t depth);
+
+/* Z-measure qubits[0..k) in order (AG measurement, via Sec. 2).  Measurement
+ * i has index m = m0 + i for the random-bit counter.  Random branch: the pivot
+ * is the smallest stabilizer row with x_a = 1; every other row with x_a = 1
+ * is multiplied by it (rowsum, phase function g, mod 4); the pivot moves to
+ * its destabilizer slot and becomes +-Z_a with the Philox bit as sign and
+ * outcome.  Deterministic branch: the outcome is the sign of the product of
+ * the stabilizers whose destabilizer has x_a = 1; the tableau is unchanged.
+ * All `shots` sign columns are measured at once: shot s uses counter shot
+ * index shot0 + s.  host_out (nullable) receives outcomes as uint8 [shots][k];
+ * host_random (nullable) receives 1 where measurement i was random. */
+int cliff_measure(cliff_tab *tab, const uint32_t *qubits, size_t k, uint64_t seed,
+                  uint64_t circuit, uint64_t shot0, uint64_t m0, uint8_t *host_out,
+                  uint8_t *host_random);
+
+/* Sampling without disturbing the state: copy `tab` into `work` (bound with
+ * the same n and at least `shots` sign columns; every sign column of work
+ * starts as sign column 0 of tab) and measure qubits[0..k) on `work`.  `tab`
+ * is left unchanged.  Output as for cliff_measure. */
+int cliff_sample(cliff_tab *tab, cliff_tab *work, const uint32_t *qubits, size_t k,
+                 uint64_t seed, uint64_t circuit, uint64_t shot0, uint8_t *host_out,
+                 uint8_t *host_random);
+
+/* Canonical byte-per-bit copy of the tableau: x, z as uint8 [2n][n] (row i,
+ * column j), r as uint8 [shots][2n].  Export synchronizes. */
+int cliff_tab_export(cliff_tab *tab, uint8_t *x, uint8_t *z, uint8_t *r);
+int cliff_tab_import(cliff_tab *tab, const uint8_t *x, const uint8_t *z, const uint8_t *r);
+
+/* Device-side consistency counters since bind: number of rowsums whose phase
+ * came out odd on a row that should commute with the pivot (must stay 0). */
+int cliff_tab_anomalies(cliff_tab *tab, uint64_t *count);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* CLIFF_H */

@@ -121,46 +121,48 @@ void orc_set(otab *t, const uint8_t *x, const uint8_t *z, const uint8_t *r) {
 }
 
 /* ---------------------------------------------------------------- gates ---
- * Conjugation rules for every row i (AG): the sign picks up x*z for H and S,
- * and x_a z_b (x_b xor z_a xor 1) for CNOT(a -> b).
+ * Conjugation rules, one row at a time (AG): the sign picks up x*z for H and
+ * S, and x_a z_b (x_b xor z_a xor 1) for CNOT(a -> b).  Each rule reads and
+ * writes only its own row, so a whole circuit may be applied row by row.
  */
-void orc_h(otab *t, int a) {
-    for (int i = 0; i < 2 * t->n; ++i) {
-        uint8_t xa = X(t, i, a), za = Z(t, i, a);
-        t->r[i] ^= (uint8_t)(xa & za);
-        X(t, i, a) = za;
-        Z(t, i, a) = xa;
-    }
+static void h_row(otab *t, int i, int a) {
+    uint8_t xa = X(t, i, a), za = Z(t, i, a);
+    t->r[i] ^= (uint8_t)(xa & za);
+    X(t, i, a) = za;
+    Z(t, i, a) = xa;
 }
 
-void orc_s(otab *t, int a) {
-    for (int i = 0; i < 2 * t->n; ++i) {
-        uint8_t xa = X(t, i, a), za = Z(t, i, a);
-        t->r[i] ^= (uint8_t)(xa & za);
-        Z(t, i, a) = (uint8_t)(za ^ xa);
-    }
+static void s_row(otab *t, int i, int a) {
+    uint8_t xa = X(t, i, a), za = Z(t, i, a);
+    t->r[i] ^= (uint8_t)(xa & za);
+    Z(t, i, a) = (uint8_t)(za ^ xa);
 }
 
-void orc_cnot(otab *t, int a, int b) {
-    for (int i = 0; i < 2 * t->n; ++i) {
-        uint8_t xa = X(t, i, a), za = Z(t, i, a), xb = X(t, i, b), zb = Z(t, i, b);
-        t->r[i] ^= (uint8_t)(xa & zb & (xb ^ za ^ 1));
-        X(t, i, b) = (uint8_t)(xb ^ xa);
-        Z(t, i, a) = (uint8_t)(za ^ zb);
-    }
+static void cnot_row(otab *t, int i, int a, int b) {
+    uint8_t xa = X(t, i, a), za = Z(t, i, a), xb = X(t, i, b), zb = Z(t, i, b);
+    t->r[i] ^= (uint8_t)(xa & zb & (xb ^ za ^ 1));
+    X(t, i, b) = (uint8_t)(xb ^ xa);
+    Z(t, i, a) = (uint8_t)(za ^ zb);
 }
 
-/* Layered circuit: per qubit H (if h) then S (if s), then every CNOT pair. */
+void orc_h(otab *t, int a) { for (int i = 0; i < 2 * t->n; ++i) h_row(t, i, a); }
+void orc_s(otab *t, int a) { for (int i = 0; i < 2 * t->n; ++i) s_row(t, i, a); }
+void orc_cnot(otab *t, int a, int b) { for (int i = 0; i < 2 * t->n; ++i) cnot_row(t, i, a, b); }
+
+/* Layered circuit: per qubit H (if h) then S (if s), then every CNOT pair;
+ * applied row by row (each row runs through all layers in order). */
 void orc_apply_layers(otab *t, int depth, const uint8_t *h, const uint8_t *s,
                       const uint32_t *ctrl, const uint32_t *tgt, int npairs) {
     int n = t->n;
-    for (int l = 0; l < depth; ++l) {
-        for (int q = 0; q < n; ++q) {
-            if (h[(size_t)l * n + q]) orc_h(t, q);
-            if (s[(size_t)l * n + q]) orc_s(t, q);
+    for (int i = 0; i < 2 * n; ++i) {
+        for (int l = 0; l < depth; ++l) {
+            for (int q = 0; q < n; ++q) {
+                if (h[(size_t)l * n + q]) h_row(t, i, q);
+                if (s[(size_t)l * n + q]) s_row(t, i, q);
+            }
+            for (int k = 0; k < npairs; ++k)
+                cnot_row(t, i, (int)ctrl[(size_t)l * npairs + k], (int)tgt[(size_t)l * npairs + k]);
         }
-        for (int k = 0; k < npairs; ++k)
-            orc_cnot(t, (int)ctrl[(size_t)l * npairs + k], (int)tgt[(size_t)l * npairs + k]);
     }
 }
 

@@ -1,0 +1,239 @@
+"""ctypes binding of libcliff.so: the C entry points under the same names.
+
+Argument marshalling only; every step of the simulation runs in the library's
+HIP kernels.  Device memory comes from torch tensors (plumbing), streams from
+torch.cuda.  Importing this module fails loudly when the library is missing.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "_lib", "libcliff.so")
+
+CLIFF_OK = 0
+CLIFF_EINVAL = -1
+CLIFF_ENOMEM = -2
+CLIFF_EDEVICE = -3
+CLIFF_EBUSY = -4
+CLIFF_EINTERNAL = -5
+OP_H, OP_S, OP_CNOT = 0, 1, 2
+
+
+class CliffError(RuntimeError):
+    def __init__(self, code: int, where: str, msg: str):
+        super().__init__("%s failed (%d): %s" % (where, code, msg))
+        self.code = code
+
+
+# One HIP runtime per process: PyTorch ships its own copy of the HIP/HSA
+# runtime, and a second copy cannot open the device.  Importing torch first
+# makes libcliff's libamdhip64.so.7 dependency resolve to the copy already
+# loaded, so device memory and streams are shared with torch.
+try:
+    import torch  # noqa: F401
+except ImportError:  # standalone use without PyTorch: /opt/rocm's runtime
+    torch = None
+
+if not os.path.exists(LIB_PATH):
+    raise ImportError("libcliff.so not built (expected %s); run "
+                      "`python -m paper_2408_00384_amd.build`" % LIB_PATH)
+
+_lib = ctypes.CDLL(LIB_PATH)
+_vp = ctypes.c_void_p
+_u8p = ctypes.POINTER(ctypes.c_uint8)
+_u32p = ctypes.POINTER(ctypes.c_uint32)
+_u64p = ctypes.POINTER(ctypes.c_uint64)
+_sz = ctypes.c_size_t
+_u32 = ctypes.c_uint32
+_u64 = ctypes.c_uint64
+
+_SIGS = {
+    "cliff_last_error": (ctypes.c_char_p, []),
+    "cliff_strerror": (ctypes.c_char_p, [ctypes.c_int]),
+    "cliff_ctx_create": (ctypes.c_int, [ctypes.c_int, _vp, ctypes.POINTER(_vp)]),
+    "cliff_ctx_destroy": (ctypes.c_int, [_vp]),
+    "cliff_sync": (ctypes.c_int, [_vp]),
+    "cliff_ctx_num_cus": (ctypes.c_int, [_vp]),
+    "cliff_tab_bytes": (_sz, [_u32, _u32]),
+    "cliff_tab_bind": (ctypes.c_int, [_vp, _u32, _u32, _vp, _sz, ctypes.POINTER(_vp)]),
+    "cliff_tab_unbind": (ctypes.c_int, [_vp]),
+    "cliff_tab_info": (ctypes.c_int, [_vp, _u32p, _u32p]),
+    "cliff_tab_init_zero": (ctypes.c_int, [_vp]),
+    "cliff_apply_gates": (ctypes.c_int, [_vp, _u8p, _u32p, _u32p, _sz]),
+    "cliff_apply_layers": (ctypes.c_int, [_vp, _u8p, _u8p, _u32p, _u32p, _u32, _u32]),
+    "cliff_encode_layers": (ctypes.c_int, [_u32, _u8p, _u8p, _u32p, _u32p, _u32, _u32, _u64p, _sz,
+                                           _u32p, ctypes.POINTER(_sz)]),
+    "cliff_apply_encoded": (ctypes.c_int, [_vp, _vp, _u32p, _u32]),
+    "cliff_measure": (ctypes.c_int, [_vp, _u32p, _sz, _u64, _u64, _u64, _u64, _u8p, _u8p]),
+    "cliff_sample": (ctypes.c_int, [_vp, _vp, _u32p, _sz, _u64, _u64, _u64, _u8p, _u8p]),
+    "cliff_tab_export": (ctypes.c_int, [_vp, _u8p, _u8p, _u8p]),
+    "cliff_tab_import": (ctypes.c_int, [_vp, _u8p, _u8p, _u8p]),
+    "cliff_tab_anomalies": (ctypes.c_int, [_vp, _u64p]),
+}
+
+for _name, (_res, _args) in _SIGS.items():
+    _f = getattr(_lib, _name)
+    _f.restype = _res
+    _f.argtypes = _args
+
+
+def exported_symbols():
+    """Names of the C entry points this binding declares."""
+    return list(_SIGS)
+
+
+def _check(rc: int, where: str):
+    if rc != CLIFF_OK:
+        raise CliffError(rc, where, _lib.cliff_last_error().decode(errors="replace"))
+
+
+def _ptr(a: np.ndarray, t):
+    return a.ctypes.data_as(t) if a is not None else None
+
+
+def _arr(a, dtype):
+    return np.ascontiguousarray(a, dtype=dtype)
+
+
+# --- the entry points, same names as the C ABI --------------------------------
+
+def cliff_last_error() -> str:
+    return _lib.cliff_last_error().decode(errors="replace")
+
+
+def cliff_strerror(code: int) -> str:
+    return _lib.cliff_strerror(code).decode()
+
+
+def cliff_ctx_create(device: int = 0, stream: int | None = None):
+    out = _vp()
+    _check(_lib.cliff_ctx_create(device, stream, ctypes.byref(out)), "cliff_ctx_create")
+    return out
+
+
+def cliff_ctx_destroy(ctx):
+    _check(_lib.cliff_ctx_destroy(ctx), "cliff_ctx_destroy")
+
+
+def cliff_sync(ctx):
+    _check(_lib.cliff_sync(ctx), "cliff_sync")
+
+
+def cliff_ctx_num_cus(ctx) -> int:
+    return int(_lib.cliff_ctx_num_cus(ctx))
+
+
+def cliff_tab_bytes(n: int, shots: int) -> int:
+    return int(_lib.cliff_tab_bytes(n, shots))
+
+
+def cliff_tab_bind(ctx, n: int, shots: int, dev_ptr: int, nbytes: int):
+    out = _vp()
+    _check(_lib.cliff_tab_bind(ctx, n, shots, dev_ptr, nbytes, ctypes.byref(out)), "cliff_tab_bind")
+    return out
+
+
+def cliff_tab_unbind(tab):
+    _check(_lib.cliff_tab_unbind(tab), "cliff_tab_unbind")
+
+
+def cliff_tab_info(tab):
+    n, s = _u32(), _u32()
+    _check(_lib.cliff_tab_info(tab, ctypes.byref(n), ctypes.byref(s)), "cliff_tab_info")
+    return int(n.value), int(s.value)
+
+
+def cliff_tab_init_zero(tab):
+    _check(_lib.cliff_tab_init_zero(tab), "cliff_tab_init_zero")
+
+
+def cliff_apply_gates(tab, ops, a, b):
+    ops, a, b = _arr(ops, np.uint8), _arr(a, np.uint32), _arr(b, np.uint32)
+    _check(_lib.cliff_apply_gates(tab, _ptr(ops, _u8p), _ptr(a, _u32p), _ptr(b, _u32p), len(ops)),
+           "cliff_apply_gates")
+
+
+def cliff_apply_layers(tab, h, s, ctrl, tgt):
+    h, s = _arr(h, np.uint8), _arr(s, np.uint8)
+    ctrl, tgt = _arr(ctrl, np.uint32), _arr(tgt, np.uint32)
+    depth = h.shape[0]
+    npairs = ctrl.shape[1] if ctrl.ndim == 2 else 0
+    _check(_lib.cliff_apply_layers(tab, _ptr(h, _u8p), _ptr(s, _u8p), _ptr(ctrl, _u32p),
+                                   _ptr(tgt, _u32p), npairs, depth), "cliff_apply_layers")
+
+
+def cliff_encode_layers(n, h, s, ctrl, tgt):
+    """Returns (ops uint64[nops], offs uint32[depth+1])."""
+    h, s = _arr(h, np.uint8), _arr(s, np.uint8)
+    ctrl, tgt = _arr(ctrl, np.uint32), _arr(tgt, np.uint32)
+    depth = h.shape[0]
+    npairs = ctrl.shape[1] if ctrl.ndim == 2 else 0
+    offs = np.zeros(depth + 1, np.uint32)
+    nops = _sz()
+    args = (n, _ptr(h, _u8p), _ptr(s, _u8p), _ptr(ctrl, _u32p), _ptr(tgt, _u32p), npairs, depth)
+    _check(_lib.cliff_encode_layers(*args, None, 0, _ptr(offs, _u32p), ctypes.byref(nops)),
+           "cliff_encode_layers")
+    ops = np.zeros(max(1, nops.value), np.uint64)
+    _check(_lib.cliff_encode_layers(*args, _ptr(ops, _u64p), ops.size, _ptr(offs, _u32p),
+                                    ctypes.byref(nops)), "cliff_encode_layers")
+    return ops[: nops.value], offs
+
+
+def cliff_apply_encoded(tab, dev_ops_ptr: int, offs):
+    offs = _arr(offs, np.uint32)
+    _check(_lib.cliff_apply_encoded(tab, dev_ops_ptr, _ptr(offs, _u32p), len(offs) - 1),
+           "cliff_apply_encoded")
+
+
+def cliff_measure(tab, qubits, seed=0, circuit=0, shot0=0, m0=0, want_out=True):
+    """Returns (outcomes uint8[shots, k] or None, random-flags uint8[k])."""
+    _, shots = cliff_tab_info(tab)
+    q = _arr(qubits, np.uint32)
+    out = np.zeros((shots, len(q)), np.uint8) if want_out else None
+    rnd = np.zeros(len(q), np.uint8)
+    _check(_lib.cliff_measure(tab, _ptr(q, _u32p), len(q), seed, circuit, shot0, m0,
+                              _ptr(out, _u8p), _ptr(rnd, _u8p)), "cliff_measure")
+    return out, rnd
+
+
+def cliff_sample(tab, work, qubits, seed=0, circuit=0, shot0=0):
+    _, shots = cliff_tab_info(work)
+    q = _arr(qubits, np.uint32)
+    out = np.zeros((shots, len(q)), np.uint8)
+    rnd = np.zeros(len(q), np.uint8)
+    _check(_lib.cliff_sample(tab, work, _ptr(q, _u32p), len(q), seed, circuit, shot0,
+                             _ptr(out, _u8p), _ptr(rnd, _u8p)), "cliff_sample")
+    return out, rnd
+
+
+def cliff_tab_export(tab):
+    """Returns (x uint8[2n, n], z uint8[2n, n], r uint8[shots, 2n])."""
+    n, shots = cliff_tab_info(tab)
+    x = np.zeros((2 * n, n), np.uint8)
+    z = np.zeros((2 * n, n), np.uint8)
+    r = np.zeros((shots, 2 * n), np.uint8)
+    _check(_lib.cliff_tab_export(tab, _ptr(x, _u8p), _ptr(z, _u8p), _ptr(r, _u8p)), "cliff_tab_export")
+    return x, z, r
+
+
+def cliff_tab_import(tab, x, z, r):
+    n, shots = cliff_tab_info(tab)
+    x = _arr(x, np.uint8).reshape(2 * n, n)
+    z = _arr(z, np.uint8).reshape(2 * n, n)
+    r = _arr(r, np.uint8).reshape(shots, 2 * n)
+    _check(_lib.cliff_tab_import(tab, _ptr(x, _u8p), _ptr(z, _u8p), _ptr(r, _u8p)), "cliff_tab_import")
+
+
+def cliff_tab_anomalies(tab) -> int:
+    v = _u64()
+    _check(_lib.cliff_tab_anomalies(tab, ctypes.byref(v)), "cliff_tab_anomalies")
+    return int(v.value)
+
+
+__all__ = [n for n in list(globals()) if n.startswith("cliff_")] + [
+    "CLIFF_OK", "CLIFF_EINVAL", "CLIFF_ENOMEM", "CLIFF_EDEVICE", "CLIFF_EBUSY",
+    "CLIFF_EINTERNAL", "OP_H", "OP_S", "OP_CNOT", "CliffError", "LIB_PATH", "exported_symbols"]

@@ -1,0 +1,504 @@
+// C ABI of the tableau library: argument checks, gate encoding, launches and
+// host <-> device marshalling.  Every step of the simulation itself runs in
+// the kernels of gates.hip / measure.hip / batch.hip.
+#include <stdarg.h>
+#include <stdio.h>
+#include <string.h>
+
+#include <algorithm>
+#include <string>
+#include <vector>
+
+#include "../../include/cliff.h"
+#include "internal.h"
+
+using namespace cliff;
+
+static thread_local std::string g_err;
+
+static int fail(int code, const char *fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof buf, fmt, ap);
+  va_end(ap);
+  g_err = buf;
+  return code;
+}
+
+#define HIP_TRY(expr)                                                                  \
+  do {                                                                                 \
+    hipError_t _e = (expr);                                                            \
+    if (_e != hipSuccess)                                                              \
+      return fail(CLIFF_EDEVICE, "%s: %s (%s:%d)", #expr, hipGetErrorString(_e), __FILE__, \
+                  __LINE__);                                                           \
+  } while (0)
+
+struct DeviceGuard {
+  int prev = -1;
+  bool ok = true;
+  explicit DeviceGuard(int dev) {
+    if (hipGetDevice(&prev) != hipSuccess) prev = -1;
+    if (prev != dev) ok = hipSetDevice(dev) == hipSuccess;
+  }
+  ~DeviceGuard() {
+    if (prev >= 0) (void)hipSetDevice(prev);
+  }
+};
+
+struct cliff_ctx {
+  int device = 0;
+  hipStream_t stream = nullptr;
+  int num_cus = 0;
+  uint64_t *dev_ops = nullptr;   // uploaded gate stream
+  size_t dev_ops_cap = 0;        // words
+  uint64_t *pinned = nullptr;    // pinned staging for uploads
+  size_t pinned_cap = 0;         // words
+  hipEvent_t upload_done = nullptr;
+  bool upload_pending = false;
+};
+
+struct cliff_tab {
+  cliff_ctx *ctx = nullptr;
+  Dims d{};
+  Offsets o{};
+  uint8_t *base = nullptr;
+  TabDev dev{};
+};
+
+extern "C" {
+
+const char *cliff_last_error(void) { return g_err.c_str(); }
+
+const char *cliff_strerror(int code) {
+  switch (code) {
+    case CLIFF_OK: return "ok";
+    case CLIFF_EINVAL: return "invalid argument";
+    case CLIFF_ENOMEM: return "out of memory / buffer too small";
+    case CLIFF_EDEVICE: return "device (HIP) error";
+    case CLIFF_EBUSY: return "busy";
+    case CLIFF_EINTERNAL: return "internal consistency check failed";
+    default: return "unknown error";
+  }
+}
+
+int cliff_ctx_create(int device, void *hip_stream, cliff_ctx **out) {
+  if (!out) return fail(CLIFF_EINVAL, "cliff_ctx_create: out is NULL");
+  *out = nullptr;
+  int ndev = 0;
+  HIP_TRY(hipGetDeviceCount(&ndev));
+  if (device < 0 || device >= ndev)
+    return fail(CLIFF_EINVAL, "cliff_ctx_create: device %d out of range [0,%d)", device, ndev);
+  DeviceGuard g(device);
+  if (!g.ok) return fail(CLIFF_EDEVICE, "cliff_ctx_create: hipSetDevice(%d) failed", device);
+  cliff_ctx *c = new (std::nothrow) cliff_ctx();
+  if (!c) return fail(CLIFF_ENOMEM, "cliff_ctx_create: host allocation failed");
+  c->device = device;
+  c->stream = reinterpret_cast<hipStream_t>(hip_stream);
+  hipDeviceProp_t prop;
+  hipError_t e = hipGetDeviceProperties(&prop, device);
+  if (e != hipSuccess) {
+    delete c;
+    return fail(CLIFF_EDEVICE, "hipGetDeviceProperties: %s", hipGetErrorString(e));
+  }
+  c->num_cus = prop.multiProcessorCount;
+  e = hipEventCreateWithFlags(&c->upload_done, hipEventDisableTiming);
+  if (e != hipSuccess) {
+    delete c;
+    return fail(CLIFF_EDEVICE, "hipEventCreate: %s", hipGetErrorString(e));
+  }
+  *out = c;
+  return CLIFF_OK;
+}
+
+int cliff_ctx_destroy(cliff_ctx *c) {
+  if (!c) return CLIFF_OK;
+  DeviceGuard g(c->device);
+  (void)hipStreamSynchronize(c->stream);
+  if (c->dev_ops) (void)hipFree(c->dev_ops);
+  if (c->pinned) (void)hipHostFree(c->pinned);
+  if (c->upload_done) (void)hipEventDestroy(c->upload_done);
+  delete c;
+  return CLIFF_OK;
+}
+
+int cliff_sync(cliff_ctx *c) {
+  if (!c) return fail(CLIFF_EINVAL, "cliff_sync: NULL context");
+  DeviceGuard g(c->device);
+  HIP_TRY(hipStreamSynchronize(c->stream));
+  return CLIFF_OK;
+}
+
+int cliff_ctx_num_cus(const cliff_ctx *c) { return c ? c->num_cus : 0; }
+
+size_t cliff_tab_bytes(uint32_t n, uint32_t shots) {
+  if (n == 0 || shots == 0 || n > (1u << 26)) return 0;
+  return make_offsets(make_dims(n, shots)).total;
+}
+
+int cliff_tab_bind(cliff_ctx *ctx, uint32_t n, uint32_t shots, void *dev, size_t bytes,
+                   cliff_tab **out) {
+  if (!ctx || !dev || !out) return fail(CLIFF_EINVAL, "cliff_tab_bind: NULL argument");
+  *out = nullptr;
+  if (n == 0 || shots == 0) return fail(CLIFF_EINVAL, "cliff_tab_bind: n and shots must be > 0");
+  if (n > (1u << 26)) return fail(CLIFF_EINVAL, "cliff_tab_bind: n = %u too large", n);
+  if (reinterpret_cast<uintptr_t>(dev) & 255)
+    return fail(CLIFF_EINVAL, "cliff_tab_bind: device buffer not 256-byte aligned");
+  const size_t need = cliff_tab_bytes(n, shots);
+  if (bytes < need)
+    return fail(CLIFF_ENOMEM, "cliff_tab_bind: buffer of %zu bytes < %zu needed", bytes, need);
+  cliff_tab *t = new (std::nothrow) cliff_tab();
+  if (!t) return fail(CLIFF_ENOMEM, "cliff_tab_bind: host allocation failed");
+  t->ctx = ctx;
+  t->d = make_dims(n, shots);
+  t->o = make_offsets(t->d);
+  t->base = reinterpret_cast<uint8_t *>(dev);
+  TabDev &v = t->dev;
+  auto at = [&](size_t off) { return t->base + off; };
+  v.X = reinterpret_cast<uint64_t *>(at(t->o.X));
+  v.Z = reinterpret_cast<uint64_t *>(at(t->o.Z));
+  v.R = reinterpret_cast<uint64_t *>(at(t->o.R));
+  v.P = reinterpret_cast<uint64_t *>(at(t->o.P));
+  v.M = reinterpret_cast<uint64_t *>(at(t->o.M));
+  v.xp = reinterpret_cast<uint64_t *>(at(t->o.xp));
+  v.zp = reinterpret_cast<uint64_t *>(at(t->o.zp));
+  v.rp = reinterpret_cast<uint64_t *>(at(t->o.rp));
+  v.part = reinterpret_cast<uint64_t *>(at(t->o.part));
+  v.state = reinterpret_cast<uint32_t *>(at(t->o.state));
+  v.out = at(t->o.out);
+  v.kind = at(t->o.kind);
+  v.n = n;
+  v.S = shots;
+  v.W = t->d.W;
+  v.Wp = t->d.Wp;
+  v.NW = t->d.NW;
+  v.SW = t->d.SW;
+  *out = t;
+  return CLIFF_OK;
+}
+
+int cliff_tab_unbind(cliff_tab *t) {
+  delete t;
+  return CLIFF_OK;
+}
+
+int cliff_tab_info(const cliff_tab *t, uint32_t *n, uint32_t *shots) {
+  if (!t) return fail(CLIFF_EINVAL, "cliff_tab_info: NULL tableau");
+  if (n) *n = t->d.n;
+  if (shots) *shots = t->d.S;
+  return CLIFF_OK;
+}
+
+int cliff_tab_init_zero(cliff_tab *t) {
+  if (!t) return fail(CLIFF_EINVAL, "cliff_tab_init_zero: NULL tableau");
+  DeviceGuard g(t->ctx->device);
+  HIP_TRY(launch_init_zero(t->dev, t->ctx->stream));
+  return CLIFF_OK;
+}
+
+}  // extern "C"
+
+// ------------------------------------------------------------ gate encoding ---
+
+static inline uint64_t make_op(uint32_t a, uint32_t b, uint64_t flags) {
+  return uint64_t(a) | (uint64_t(b) << kQubitBits) | flags;
+}
+
+static int check_layers(uint32_t n, const uint8_t *h, const uint8_t *s, const uint32_t *ctrl,
+                        const uint32_t *tgt, uint32_t npairs, uint32_t depth) {
+  if (depth == 0) return CLIFF_OK;
+  if (!h || !s) return fail(CLIFF_EINVAL, "layers: NULL h/s");
+  if (npairs && (!ctrl || !tgt)) return fail(CLIFF_EINVAL, "layers: NULL ctrl/tgt");
+  if (2ull * npairs > n) return fail(CLIFF_EINVAL, "layers: %u pairs on %u qubits", npairs, n);
+  std::vector<uint32_t> seen(n, 0xFFFFFFFFu);
+  for (uint32_t l = 0; l < depth; ++l) {
+    for (uint32_t k = 0; k < npairs; ++k) {
+      const uint32_t c = ctrl[size_t(l) * npairs + k], g = tgt[size_t(l) * npairs + k];
+      if (c >= n || g >= n)
+        return fail(CLIFF_EINVAL, "layer %u pair %u: qubit out of range (n=%u)", l, k, n);
+      if (c == g) return fail(CLIFF_EINVAL, "layer %u pair %u: CNOT control == target", l, k);
+      if (seen[c] == l || seen[g] == l)
+        return fail(CLIFF_EINVAL, "layer %u: qubit used by two CNOTs", l);
+      seen[c] = seen[g] = l;
+    }
+  }
+  return CLIFF_OK;
+}
+
+// ops for one layer; returns the number of words written (cap permitting)
+static size_t encode_layer(uint32_t n, const uint8_t *h, const uint8_t *s, const uint32_t *ctrl,
+                           const uint32_t *tgt, uint32_t npairs, std::vector<uint8_t> &paired,
+                           uint64_t *ops, size_t cap) {
+  size_t cnt = 0;
+  auto emit = [&](uint64_t v) {
+    if (ops && cnt < cap) ops[cnt] = v;
+    ++cnt;
+  };
+  std::fill(paired.begin(), paired.end(), 0);
+  for (uint32_t k = 0; k < npairs; ++k) {
+    const uint32_t c = ctrl[k], g = tgt[k];
+    paired[c] = paired[g] = 1;
+    uint64_t f = OPF_PAIR;
+    if (h[c]) f |= OPF_HA;
+    if (s[c]) f |= OPF_SA;
+    if (h[g]) f |= OPF_HB;
+    if (s[g]) f |= OPF_SB;
+    emit(make_op(c, g, f));
+  }
+  for (uint32_t q = 0; q < n; ++q) {
+    if (paired[q] || !(h[q] | s[q])) continue;
+    uint64_t f = 0;
+    if (h[q]) f |= OPF_HA;
+    if (s[q]) f |= OPF_SA;
+    emit(make_op(q, 0, f));
+  }
+  return cnt;
+}
+
+extern "C" int cliff_encode_layers(uint32_t n, const uint8_t *h, const uint8_t *s,
+                                   const uint32_t *ctrl, const uint32_t *tgt, uint32_t npairs,
+                                   uint32_t depth, uint64_t *ops, size_t cap, uint32_t *offs,
+                                   size_t *nops) {
+  if (!nops) return fail(CLIFF_EINVAL, "cliff_encode_layers: nops is NULL");
+  if (n == 0) return fail(CLIFF_EINVAL, "cliff_encode_layers: n == 0");
+  int rc = check_layers(n, h, s, ctrl, tgt, npairs, depth);
+  if (rc) return rc;
+  std::vector<uint8_t> paired(n);
+  size_t total = 0;
+  for (uint32_t l = 0; l < depth; ++l) {
+    if (offs) offs[l] = uint32_t(total);
+    const size_t room = (ops && total < cap) ? cap - total : 0;
+    total += encode_layer(n, h + size_t(l) * n, s + size_t(l) * n,
+                          npairs ? ctrl + size_t(l) * npairs : nullptr,
+                          npairs ? tgt + size_t(l) * npairs : nullptr, npairs, paired,
+                          ops ? ops + std::min(total, cap) : nullptr, room);
+    if (total > 0xFFFFFFF0ull) return fail(CLIFF_EINVAL, "cliff_encode_layers: stream too long");
+  }
+  if (offs) offs[depth] = uint32_t(total);
+  *nops = total;
+  if (ops && total > cap) return fail(CLIFF_ENOMEM, "cliff_encode_layers: need %zu words", total);
+  return CLIFF_OK;
+}
+
+// Upload ops to the context's device buffer (stream-ordered).
+static int upload_ops(cliff_ctx *c, const std::vector<uint64_t> &ops) {
+  const size_t words = ops.size();
+  if (words == 0) return CLIFF_OK;
+  if (c->upload_pending) {
+    HIP_TRY(hipEventSynchronize(c->upload_done));
+    c->upload_pending = false;
+  }
+  if (words > c->dev_ops_cap) {
+    HIP_TRY(hipStreamSynchronize(c->stream));
+    if (c->dev_ops) HIP_TRY(hipFree(c->dev_ops));
+    c->dev_ops = nullptr;
+    c->dev_ops_cap = 0;
+    size_t cap = std::max<size_t>(words, 1 << 16);
+    HIP_TRY(hipMalloc(&c->dev_ops, cap * 8));
+    c->dev_ops_cap = cap;
+  }
+  if (words > c->pinned_cap) {
+    if (c->pinned) HIP_TRY(hipHostFree(c->pinned));
+    c->pinned = nullptr;
+    c->pinned_cap = 0;
+    size_t cap = std::max<size_t>(words, 1 << 16);
+    HIP_TRY(hipHostMalloc(reinterpret_cast<void **>(&c->pinned), cap * 8, hipHostMallocDefault));
+    c->pinned_cap = cap;
+  }
+  memcpy(c->pinned, ops.data(), words * 8);
+  HIP_TRY(hipMemcpyAsync(c->dev_ops, c->pinned, words * 8, hipMemcpyHostToDevice, c->stream));
+  HIP_TRY(hipEventRecord(c->upload_done, c->stream));
+  c->upload_pending = true;
+  return CLIFF_OK;
+}
+
+static int run_encoded(cliff_tab *t, const uint64_t *dev_ops, const uint32_t *offs, uint32_t depth) {
+  for (uint32_t l = 0; l < depth; ++l) {
+    const uint32_t a = offs[l], b = offs[l + 1];
+    if (b < a) return fail(CLIFF_EINVAL, "layer offsets decrease at layer %u", l);
+    HIP_TRY(launch_gate_layer(t->dev, dev_ops + a, b - a, t->ctx->stream));
+  }
+  return CLIFF_OK;
+}
+
+extern "C" int cliff_apply_layers(cliff_tab *t, const uint8_t *h, const uint8_t *s,
+                                  const uint32_t *ctrl, const uint32_t *tgt, uint32_t npairs,
+                                  uint32_t depth) {
+  if (!t) return fail(CLIFF_EINVAL, "cliff_apply_layers: NULL tableau");
+  if (depth == 0) return CLIFF_OK;
+  size_t nops = 0;
+  std::vector<uint32_t> offs(depth + 1);
+  int rc = cliff_encode_layers(t->d.n, h, s, ctrl, tgt, npairs, depth, nullptr, 0, offs.data(), &nops);
+  if (rc) return rc;
+  std::vector<uint64_t> ops(nops);
+  rc = cliff_encode_layers(t->d.n, h, s, ctrl, tgt, npairs, depth, ops.data(), nops, offs.data(), &nops);
+  if (rc) return rc;
+  DeviceGuard g(t->ctx->device);
+  rc = upload_ops(t->ctx, ops);
+  if (rc) return rc;
+  return run_encoded(t, t->ctx->dev_ops, offs.data(), depth);
+}
+
+extern "C" int cliff_apply_encoded(cliff_tab *t, const uint64_t *dev_ops, const uint32_t *offs,
+                                   uint32_t depth) {
+  if (!t || !offs || (!dev_ops && depth)) return fail(CLIFF_EINVAL, "cliff_apply_encoded: NULL argument");
+  DeviceGuard g(t->ctx->device);
+  return run_encoded(t, dev_ops, offs, depth);
+}
+
+extern "C" int cliff_apply_gates(cliff_tab *t, const uint8_t *op, const uint32_t *a,
+                                 const uint32_t *b, size_t count) {
+  if (!t) return fail(CLIFF_EINVAL, "cliff_apply_gates: NULL tableau");
+  if (count == 0) return CLIFF_OK;
+  if (!op || !a || !b) return fail(CLIFF_EINVAL, "cliff_apply_gates: NULL array");
+  const uint32_t n = t->d.n;
+  for (size_t k = 0; k < count; ++k) {
+    if (op[k] > CLIFF_OP_CNOT) return fail(CLIFF_EINVAL, "gate %zu: bad op %u", k, op[k]);
+    if (a[k] >= n) return fail(CLIFF_EINVAL, "gate %zu: qubit %u >= n = %u", k, a[k], n);
+    if (op[k] == CLIFF_OP_CNOT) {
+      if (b[k] >= n) return fail(CLIFF_EINVAL, "gate %zu: target %u >= n = %u", k, b[k], n);
+      if (a[k] == b[k]) return fail(CLIFF_EINVAL, "gate %zu: CNOT control == target", k);
+    }
+  }
+  // Greedy layering: a gate joins the current layer unless one of its qubits
+  // is already used there.  Gates within a layer act on disjoint qubits and
+  // so commute exactly; layer order preserves the list order per qubit.
+  std::vector<uint64_t> ops;
+  std::vector<uint32_t> offs{0};
+  std::vector<uint32_t> used(n, 0);
+  uint32_t layer = 1;
+  ops.reserve(count);
+  for (size_t k = 0; k < count; ++k) {
+    const bool two = op[k] == CLIFF_OP_CNOT;
+    if (used[a[k]] == layer || (two && used[b[k]] == layer)) {
+      offs.push_back(uint32_t(ops.size()));
+      ++layer;
+    }
+    used[a[k]] = layer;
+    if (two) used[b[k]] = layer;
+    uint64_t f = op[k] == CLIFF_OP_H ? OPF_HA : op[k] == CLIFF_OP_S ? OPF_SA : OPF_PAIR;
+    ops.push_back(make_op(a[k], two ? b[k] : 0, f));
+  }
+  offs.push_back(uint32_t(ops.size()));
+  DeviceGuard g(t->ctx->device);
+  int rc = upload_ops(t->ctx, ops);
+  if (rc) return rc;
+  return run_encoded(t, t->ctx->dev_ops, offs.data(), uint32_t(offs.size() - 1));
+}
+
+// ---------------------------------------------------------------- measure ---
+
+static int measure_impl(cliff_tab *t, const uint32_t *qubits, size_t k, uint64_t seed,
+                        uint64_t circuit, uint64_t shot0, uint64_t m0, uint8_t *host_out,
+                        uint8_t *host_random) {
+  const uint32_t n = t->d.n, S = t->d.S;
+  for (size_t i = 0; i < k; ++i)
+    if (qubits[i] >= n) return fail(CLIFF_EINVAL, "measure: qubit %u >= n = %u", qubits[i], n);
+  hipStream_t st = t->ctx->stream;
+  HIP_TRY(launch_fold_pending(t->dev, st));
+  std::vector<uint8_t> out_stage, kind_stage;
+  for (size_t base = 0; base < k; base += n) {
+    const size_t cnt = std::min<size_t>(n, k - base);
+    for (size_t i = 0; i < cnt; ++i)
+      HIP_TRY(launch_measure_one(t->dev, qubits[base + i], uint32_t(i), seed, circuit, shot0,
+                                 m0 + base + i, st));
+    if (host_out || host_random) {
+      out_stage.resize(cnt * S);
+      kind_stage.resize(cnt);
+      HIP_TRY(hipMemcpyAsync(out_stage.data(), t->dev.out, cnt * S, hipMemcpyDeviceToHost, st));
+      HIP_TRY(hipMemcpyAsync(kind_stage.data(), t->dev.kind, cnt, hipMemcpyDeviceToHost, st));
+      HIP_TRY(hipStreamSynchronize(st));
+      if (host_out)
+        for (size_t i = 0; i < cnt; ++i)
+          for (uint32_t s = 0; s < S; ++s) host_out[size_t(s) * k + base + i] = out_stage[i * S + s];
+      if (host_random) memcpy(host_random + base, kind_stage.data(), cnt);
+    }
+  }
+  return CLIFF_OK;
+}
+
+extern "C" int cliff_measure(cliff_tab *t, const uint32_t *qubits, size_t k, uint64_t seed,
+                             uint64_t circuit, uint64_t shot0, uint64_t m0, uint8_t *host_out,
+                             uint8_t *host_random) {
+  if (!t) return fail(CLIFF_EINVAL, "cliff_measure: NULL tableau");
+  if (k == 0) return CLIFF_OK;
+  if (!qubits) return fail(CLIFF_EINVAL, "cliff_measure: NULL qubits");
+  DeviceGuard g(t->ctx->device);
+  return measure_impl(t, qubits, k, seed, circuit, shot0, m0, host_out, host_random);
+}
+
+extern "C" int cliff_sample(cliff_tab *t, cliff_tab *work, const uint32_t *qubits, size_t k,
+                            uint64_t seed, uint64_t circuit, uint64_t shot0, uint8_t *host_out,
+                            uint8_t *host_random) {
+  if (!t || !work) return fail(CLIFF_EINVAL, "cliff_sample: NULL tableau");
+  if (work->d.n != t->d.n) return fail(CLIFF_EINVAL, "cliff_sample: work has n=%u, tab n=%u", work->d.n, t->d.n);
+  if (work->ctx->device != t->ctx->device) return fail(CLIFF_EINVAL, "cliff_sample: different devices");
+  if (work->base == t->base) return fail(CLIFF_EINVAL, "cliff_sample: work aliases tab");
+  if (k && !qubits) return fail(CLIFF_EINVAL, "cliff_sample: NULL qubits");
+  DeviceGuard g(t->ctx->device);
+  if (work->ctx->stream != t->ctx->stream) HIP_TRY(hipStreamSynchronize(t->ctx->stream));
+  HIP_TRY(launch_copy_tab(work->dev, t->dev, work->ctx->stream));
+  if (k == 0) return CLIFF_OK;
+  return measure_impl(work, qubits, k, seed, circuit, shot0, 0, host_out, host_random);
+}
+
+// ------------------------------------------------------------ export/import ---
+
+extern "C" int cliff_tab_export(cliff_tab *t, uint8_t *x, uint8_t *z, uint8_t *r) {
+  if (!t || !x || !z || !r) return fail(CLIFF_EINVAL, "cliff_tab_export: NULL argument");
+  const Dims &d = t->d;
+  DeviceGuard g(t->ctx->device);
+  std::vector<uint64_t> X(size_t(d.n) * d.Wp), Z(size_t(d.n) * d.Wp), R(size_t(d.Wp) * d.S), P(d.Wp);
+  hipStream_t st = t->ctx->stream;
+  HIP_TRY(hipMemcpyAsync(X.data(), t->dev.X, X.size() * 8, hipMemcpyDeviceToHost, st));
+  HIP_TRY(hipMemcpyAsync(Z.data(), t->dev.Z, Z.size() * 8, hipMemcpyDeviceToHost, st));
+  HIP_TRY(hipMemcpyAsync(R.data(), t->dev.R, R.size() * 8, hipMemcpyDeviceToHost, st));
+  HIP_TRY(hipMemcpyAsync(P.data(), t->dev.P, P.size() * 8, hipMemcpyDeviceToHost, st));
+  HIP_TRY(hipStreamSynchronize(st));
+  const uint32_t n = d.n, rows = 2 * n;
+  for (uint32_t j = 0; j < n; ++j) {
+    const uint64_t *cx = &X[size_t(j) * d.Wp], *cz = &Z[size_t(j) * d.Wp];
+    for (uint32_t i = 0; i < rows; ++i) {
+      x[size_t(i) * n + j] = uint8_t((cx[i >> 6] >> (i & 63)) & 1u);
+      z[size_t(i) * n + j] = uint8_t((cz[i >> 6] >> (i & 63)) & 1u);
+    }
+  }
+  for (uint32_t s = 0; s < d.S; ++s)
+    for (uint32_t i = 0; i < rows; ++i)
+      r[size_t(s) * rows + i] = uint8_t(((R[size_t(i >> 6) * d.S + s] ^ P[i >> 6]) >> (i & 63)) & 1u);
+  return CLIFF_OK;
+}
+
+extern "C" int cliff_tab_import(cliff_tab *t, const uint8_t *x, const uint8_t *z, const uint8_t *r) {
+  if (!t || !x || !z || !r) return fail(CLIFF_EINVAL, "cliff_tab_import: NULL argument");
+  const Dims &d = t->d;
+  const uint32_t n = d.n, rows = 2 * n;
+  std::vector<uint64_t> X(size_t(n) * d.Wp, 0), Z(size_t(n) * d.Wp, 0), R(size_t(d.Wp) * d.S, 0),
+      P(d.Wp, 0);
+  for (uint32_t i = 0; i < rows; ++i)
+    for (uint32_t j = 0; j < n; ++j) {
+      if (x[size_t(i) * n + j] & 1u) X[size_t(j) * d.Wp + (i >> 6)] |= 1ull << (i & 63);
+      if (z[size_t(i) * n + j] & 1u) Z[size_t(j) * d.Wp + (i >> 6)] |= 1ull << (i & 63);
+    }
+  for (uint32_t s = 0; s < d.S; ++s)
+    for (uint32_t i = 0; i < rows; ++i)
+      if (r[size_t(s) * rows + i] & 1u) R[size_t(i >> 6) * d.S + s] |= 1ull << (i & 63);
+  DeviceGuard g(t->ctx->device);
+  hipStream_t st = t->ctx->stream;
+  HIP_TRY(hipMemcpyAsync(t->dev.X, X.data(), X.size() * 8, hipMemcpyHostToDevice, st));
+  HIP_TRY(hipMemcpyAsync(t->dev.Z, Z.data(), Z.size() * 8, hipMemcpyHostToDevice, st));
+  HIP_TRY(hipMemcpyAsync(t->dev.R, R.data(), R.size() * 8, hipMemcpyHostToDevice, st));
+  HIP_TRY(hipMemcpyAsync(t->dev.P, P.data(), P.size() * 8, hipMemcpyHostToDevice, st));
+  HIP_TRY(hipStreamSynchronize(st));
+  return CLIFF_OK;
+}
+
+extern "C" int cliff_tab_anomalies(cliff_tab *t, uint64_t *count) {
+  if (!t || !count) return fail(CLIFF_EINVAL, "cliff_tab_anomalies: NULL argument");
+  DeviceGuard g(t->ctx->device);
+  uint32_t v = 0;
+  HIP_TRY(hipMemcpyAsync(&v, t->dev.state + ST_ANOMALY, 4, hipMemcpyDeviceToHost, t->ctx->stream));
+  HIP_TRY(hipStreamSynchronize(t->ctx->stream));
+  *count = v;
+  return CLIFF_OK;
+}

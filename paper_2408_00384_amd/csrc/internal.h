@@ -1,0 +1,122 @@
+// Internal layout and launch helpers of the tableau library (not part of the ABI).
+//
+// HBM layout of one tableau (all regions 256-byte aligned, inside the caller's
+// buffer):
+//   X, Z   : n columns x Wp words (uint64); word w of column j = rows 64w..64w+63
+//            of qubit j, LSB = lowest row.  Column-major so a gate or a rowsum
+//            sweep over one column is a contiguous, coalesced word stream.
+//   R      : Wp x S words; R[w*S + s] = sign bits of rows 64w.. for shot s.
+//   P      : Wp words of sign flips from gates not yet folded into R (gates
+//            act identically on every shot, so they write one plane only).
+//   scratch: measurement snapshot M (Wp), packed pivot row xp/zp (NW each),
+//            pivot signs rp (SW), per-chunk counter partials, small state
+//            words, outcome staging.
+// Padding rows 2n..64W-1 and padding words W..Wp-1 are always zero.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stddef.h>
+#include <stdint.h>
+
+namespace cliff {
+
+constexpr uint32_t kNone = 0xFFFFFFFFu;
+constexpr uint32_t kMaxChunks = 512;   // column chunks of one measurement sweep
+constexpr uint32_t kStateWords = 64;   // uint32 words of measurement state
+
+// Measurement-state word indices (uint32).
+enum : uint32_t {
+  ST_PIVOT = 0,      // pivot row p, or kNone when deterministic
+  ST_ANOMALY = 1,    // count of rows whose phase counter came out odd
+  ST_DET_PAR = 2,    // deterministic branch: XOR of per-column pair parities
+  ST_DET_Y = 3,      // deterministic branch: count of Y entries in the product rows
+  ST_ERROR = 4,      // sticky error bits
+  ST_RANDOM_CNT = 5, // random measurements since bind
+};
+
+// Gate op word: a (28 bits) | b (28 bits) << 28 | flags << 56.
+constexpr uint64_t OPF_HA = 1ull << 56;
+constexpr uint64_t OPF_SA = 1ull << 57;
+constexpr uint64_t OPF_HB = 1ull << 58;
+constexpr uint64_t OPF_SB = 1ull << 59;
+constexpr uint64_t OPF_PAIR = 1ull << 60;  // CNOT(a -> b) after the single-qubit gates
+constexpr uint32_t kQubitBits = 28;
+constexpr uint64_t kQubitMask = (1ull << kQubitBits) - 1;
+
+struct Dims {
+  uint32_t n, S;   // qubits, shot sign columns
+  uint32_t W;      // ceil(2n / 64) row words
+  uint32_t Wp;     // W rounded up to 8 (column stride in words)
+  uint32_t NW;     // ceil(n / 64) words of a packed row
+  uint32_t SW;     // ceil(S / 64) words of packed per-shot bits
+};
+
+struct Offsets {
+  size_t X, Z, R, P, M, xp, zp, rp, part, state, out, kind, total;
+};
+
+// Device view passed by value to kernels.
+struct TabDev {
+  uint64_t *X, *Z, *R, *P;
+  uint64_t *M, *xp, *zp, *rp, *part;
+  uint32_t *state;
+  uint8_t *out, *kind;
+  uint32_t n, S, W, Wp, NW, SW;
+};
+
+inline size_t align256(size_t v) { return (v + 255) & ~size_t(255); }
+
+inline Dims make_dims(uint32_t n, uint32_t S) {
+  Dims d;
+  d.n = n;
+  d.S = S;
+  d.W = (2 * n + 63) / 64;
+  d.Wp = (d.W + 7) & ~7u;
+  d.NW = (n + 63) / 64;
+  d.SW = (S + 63) / 64;
+  return d;
+}
+
+inline uint32_t sweep_chunks(uint32_t n);
+
+inline Offsets make_offsets(const Dims &d) {
+  Offsets o;
+  size_t cur = 0;
+  auto take = [&](size_t bytes) { size_t at = cur; cur = align256(cur + bytes); return at; };
+  const size_t col = size_t(d.n) * d.Wp * 8;
+  o.X = take(col);
+  o.Z = take(col);
+  o.R = take(size_t(d.Wp) * d.S * 8);
+  o.P = take(size_t(d.Wp) * 8);
+  o.M = take(size_t(d.Wp) * 8);
+  o.xp = take(size_t(d.NW) * 8);
+  o.zp = take(size_t(d.NW) * 8);
+  o.rp = take(size_t(d.SW) * 8);
+  o.part = take(size_t(sweep_chunks(d.n)) * d.Wp * 16);
+  o.state = take(kStateWords * 4);
+  o.out = take(size_t(d.n) * d.S);   // staging for up to n measurements per pass
+  o.kind = take(size_t(d.n));
+  o.total = cur;
+  return o;
+}
+
+// Columns per chunk of the multi-kernel measurement sweep, and chunk count.
+inline uint32_t sweep_cols_per_chunk(uint32_t n) {
+  uint32_t cols = n <= 2048 ? 16u : (n <= 8192 ? 32u : 64u);
+  while ((n + cols - 1) / cols > kMaxChunks) cols *= 2;
+  return cols;
+}
+inline uint32_t sweep_chunks(uint32_t n) {
+  const uint32_t cols = sweep_cols_per_chunk(n);
+  return (n + cols - 1) / cols;
+}
+
+// ---- launchers (each defined in the .hip file holding its kernels) ----------
+hipError_t launch_init_zero(const TabDev &t, hipStream_t st);
+hipError_t launch_fold_pending(const TabDev &t, hipStream_t st);
+hipError_t launch_gate_layer(const TabDev &t, const uint64_t *ops, uint32_t nops, hipStream_t st);
+hipError_t launch_measure_one(const TabDev &t, uint32_t a, uint32_t slot, uint64_t seed,
+                              uint64_t circuit, uint64_t shot0, uint64_t m, hipStream_t st);
+hipError_t launch_clear_state(const TabDev &t, hipStream_t st);
+hipError_t launch_copy_tab(const TabDev &dst, const TabDev &src, hipStream_t st);
+
+}  // namespace cliff

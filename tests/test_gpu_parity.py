@@ -1,0 +1,224 @@
+"""GPU parity: the HIP path through the C ABI against the CPU oracle, bit-exact.
+
+Compared: tableau bits (x, z and every shot's signs, via export), outcome bytes
+per shot and the random/deterministic flag of every measurement.  Sizes span
+one word, several words and ragged tails (n = 1, 31..33, 63..65, 127..129, ...).
+"""
+import json
+import os
+
+import numpy as np
+import pytest
+
+import oracle
+from inputs import (layered_circuit, plain_mid, plain_small, random_gate_list)
+
+pytestmark = pytest.mark.gpu
+
+GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    from paper_2408_00384_amd import Context
+    c = Context(0)
+    yield c
+    c.close()
+
+
+def _tab(ctx, n, shots=1):
+    from paper_2408_00384_amd import DeviceTableau
+    return DeviceTableau(ctx, n, shots)
+
+
+def _assert_tab_equal(gpu, ref_tabs):
+    """gpu = (x, z, r[shots]); ref_tabs = list of oracle (x, z, r) per shot."""
+    gx, gz, gr = gpu
+    for s, (x, z, r) in enumerate(ref_tabs):
+        assert np.array_equal(gx, x), "x bits differ"
+        assert np.array_equal(gz, z), "z bits differ"
+        assert np.array_equal(gr[s], r), "sign bits differ (shot %d)" % s
+
+
+RAGGED = [1, 2, 3, 5, 31, 32, 33, 63, 64, 65, 100, 127, 128, 129, 200, 257]
+
+
+@pytest.mark.parametrize("n", RAGGED)
+def test_init_zero(ctx, n):
+    t = _tab(ctx, n, 3)
+    ref = oracle.Tableau(n).get()
+    _assert_tab_equal(t.export(), [ref] * 3)
+
+
+@pytest.mark.parametrize("n", RAGGED)
+def test_layers_match_oracle(ctx, n):
+    c = layered_circuit(n, 7, 2, gen_seed=[11, n])
+    t = _tab(ctx, n, 2).apply_circuit_gates(c)
+    ref = oracle.Tableau(n).apply_circuit_gates(c).get()
+    _assert_tab_equal(t.export(), [ref, ref])
+
+
+@pytest.mark.parametrize("n", [1, 2, 3, 17, 64, 65, 130])
+def test_gate_list_matches_oracle(ctx, n):
+    rng = np.random.default_rng(n)
+    ops, a, b = random_gate_list(rng, n, 400)
+    t = _tab(ctx, n).apply_gates(ops, a, b)
+    ref = oracle.Tableau(n).apply_gates(ops, a, b).get()
+    _assert_tab_equal(t.export(), [ref])
+
+
+def _check_circuit(ctx, c, shots_to_check=None):
+    t = _tab(ctx, c.n, c.shots).apply_circuit_gates(c)
+    out, rnd = t.measure(c.qubits, seed=c.seed, circuit=c.circuit_id)
+    gx, gz, gr = t.export()
+    shots_to_check = range(c.shots) if shots_to_check is None else shots_to_check
+    for s in shots_to_check:
+        o, k, (x, z, r) = oracle.run_shot(c, s, want_tableau=True)
+        assert np.array_equal(out[s], o), "outcomes differ (shot %d)" % s
+        assert np.array_equal(rnd, k), "random flags differ"
+        assert np.array_equal(gx, x) and np.array_equal(gz, z), "x/z differ after measurement"
+        assert np.array_equal(gr[s], r), "signs differ after measurement (shot %d)" % s
+    assert t.anomalies() == 0
+    return out, rnd
+
+
+@pytest.mark.parametrize("n", RAGGED)
+def test_measure_all_matches_oracle(ctx, n):
+    c = layered_circuit(n, 6, 3, gen_seed=[12, n], circuit_id=n)
+    _check_circuit(ctx, c)
+
+
+@pytest.mark.parametrize("n", [2, 9, 40, 70, 140])
+def test_mostly_deterministic_measurements(ctx, n):
+    # shallow circuits with few H gates: most outcomes are determined
+    c = layered_circuit(n, 2, 4, gen_seed=[13, n], circuit_id=3)
+    c.h[:] = 0
+    c.h[0, : max(1, n // 8)] = 1
+    out, rnd = _check_circuit(ctx, c)
+    assert rnd.sum() < n
+
+
+def test_ghz_and_zero_state(ctx):
+    n = 70
+    t = _tab(ctx, n, 8)
+    ops = [0] + [2] * (n - 1)
+    a = [0] + list(range(n - 1))
+    b = [0] + list(range(1, n))
+    t.apply_gates(ops, a, b)
+    out, rnd = t.measure(np.arange(n), seed=5)
+    assert rnd[0] == 1 and rnd[1:].sum() == 0
+    assert all(len(set(row.tolist())) == 1 for row in out)
+    z = _tab(ctx, 33, 2)
+    out, rnd = z.measure(np.arange(33))
+    assert out.sum() == 0 and rnd.sum() == 0
+
+
+@pytest.mark.parametrize("seed", range(6))
+def test_interleaved_gates_and_measurements(ctx, seed):
+    rng = np.random.default_rng(500 + seed)
+    n = int(rng.integers(2, 150))
+    shots = 3
+    t = _tab(ctx, n, shots)
+    refs = [oracle.Tableau(n) for _ in range(shots)]
+    m = 0
+    for _ in range(5):
+        ops, a, b = random_gate_list(rng, n, int(rng.integers(1, 3 * n)))
+        t.apply_gates(ops, a, b)
+        for r in refs:
+            r.apply_gates(ops, a, b)
+        q = rng.integers(0, n, size=int(rng.integers(1, 6)))
+        out, rnd = t.measure(q, seed=77, circuit=seed, m0=m)
+        for s, r in enumerate(refs):
+            o, k = r.measure_list(q, seed=77, circuit=seed, shot=s, m0=m)
+            assert np.array_equal(out[s], o) and np.array_equal(rnd, k)
+        m += len(q)
+    gx, gz, gr = t.export()
+    _assert_tab_equal((gx, gz, gr), [r.get() for r in refs])
+    assert t.anomalies() == 0
+
+
+def test_plain_small_all_shots(ctx):
+    """n = 64, 64 layers, measure all, 16 shots."""
+    _check_circuit(ctx, plain_small())
+
+
+def test_plain_mid_sampled_shots(ctx):
+    """n = 1,024, 100 layers, measure all, 128 shots (checked on sampled shots)."""
+    c = plain_mid()
+    path = os.path.join(GOLDEN, "plain_mid.json")
+    if os.path.exists(path):
+        rec = json.load(open(path))
+        import hashlib
+        t = _tab(ctx, c.n, c.shots).apply_circuit_gates(c)
+        out, rnd = t.measure(c.qubits, seed=c.seed, circuit=c.circuit_id)
+        gx, gz, gr = t.export()
+        for s, v in rec["shots"].items():
+            s = int(s)
+            want = np.unpackbits(np.frombuffer(bytes.fromhex(v["outcomes"]), np.uint8),
+                                 bitorder="little")[: c.n]
+            kinds = np.unpackbits(np.frombuffer(bytes.fromhex(v["random"]), np.uint8),
+                                  bitorder="little")[: c.n]
+            assert np.array_equal(out[s], want)
+            assert np.array_equal(rnd, kinds)
+            h = hashlib.sha256()
+            for arr in (gx, gz, gr[s]):
+                h.update(np.ascontiguousarray(arr, np.uint8).tobytes())
+            assert h.hexdigest() == v["tableau_sha256"]
+        assert t.anomalies() == 0
+    else:
+        _check_circuit(ctx, c, shots_to_check=[0, 127])
+
+
+def test_sample_leaves_state_unchanged(ctx):
+    from paper_2408_00384_amd import cliff_sample
+    c = layered_circuit(90, 8, 1, gen_seed=21, circuit_id=9)
+    t = _tab(ctx, c.n, 1).apply_circuit_gates(c)
+    before = t.export()
+    work = _tab(ctx, c.n, 5)
+    out, rnd = cliff_sample(t.handle, work.handle, c.qubits, seed=c.seed, circuit=9)
+    after = t.export()
+    for A, B in zip(before, after):
+        assert np.array_equal(A, B)
+    for s in range(5):
+        o, k = oracle.run_shot(c, s)
+        assert np.array_equal(out[s], o) and np.array_equal(rnd, k)
+
+
+def test_export_import_resume(ctx):
+    """Checkpoint mid-circuit: export, import into a fresh tableau, continue;
+    the result equals the uninterrupted run bit for bit."""
+    c = layered_circuit(75, 12, 2, gen_seed=31, circuit_id=2)
+    half = 6
+    full = _tab(ctx, c.n, 2).apply_circuit_gates(c)
+    out_full, _ = full.measure(c.qubits, seed=c.seed, circuit=2)
+    a = _tab(ctx, c.n, 2).apply_layers(c.h[:half], c.s[:half], c.ctrl[:half], c.tgt[:half])
+    snap = a.export()
+    b = _tab(ctx, c.n, 2, ).import_(*snap)
+    b.apply_layers(c.h[half:], c.s[half:], c.ctrl[half:], c.tgt[half:])
+    out_b, _ = b.measure(c.qubits, seed=c.seed, circuit=2)
+    assert np.array_equal(out_full, out_b)
+    for A, B in zip(full.export(), b.export()):
+        assert np.array_equal(A, B)
+
+
+def test_error_paths(ctx):
+    from paper_2408_00384_amd import CliffError, CLIFF_EINVAL, CLIFF_ENOMEM, cliff_tab_bind
+    t = _tab(ctx, 10, 1)
+    with pytest.raises(CliffError) as e:
+        t.apply_gates([0], [10], [0])
+    assert e.value.code == CLIFF_EINVAL
+    with pytest.raises(CliffError) as e:
+        t.apply_gates([2], [3], [3])
+    assert e.value.code == CLIFF_EINVAL
+    with pytest.raises(CliffError) as e:
+        t.apply_gates([7], [1], [2])
+    assert e.value.code == CLIFF_EINVAL
+    with pytest.raises(CliffError) as e:
+        t.measure([11])
+    assert e.value.code == CLIFF_EINVAL
+    with pytest.raises(CliffError) as e:
+        cliff_tab_bind(ctx.handle, 10, 1, t.ptr, 64)
+    assert e.value.code == CLIFF_ENOMEM
+    # the tableau is still usable after rejected calls
+    out, rnd = t.measure(np.arange(10))
+    assert out.sum() == 0 and rnd.sum() == 0
