@@ -1,0 +1,204 @@
+#!/usr/bin/env python3
+"""Benchmark of the stabilizer-tableau hot path on one MI355X.
+
+    python bench.py [--steps K] [--warmup W] [--workload large|mid|small]
+
+A step runs one whole circuit of the workload through the C ABI: |0...0>
+init, every gate layer (op stream already resident in HBM), then
+Z-measurement of all qubits for all shots, outcomes copied back to the host.
+Default workload: n = 10,000 qubits, 20 layers of random H/S/CNOT-matching,
+measure all, 1 shot (the rowsum-dominated single-tableau case).
+
+One JSON line is printed with circuits/s, the roofline of the dominant kernel
+(the rowsum sweep: algorithmic bytes from the device-side counters divided by
+the sweep time from HIP events on its stream) and the CPU oracle timed on a
+bounded sample of the same workload.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0   # MI355X HBM3E peak
+
+WORKLOADS = {
+    "small": dict(desc="plain CHP n=64, 64 layers, measure all, 16 shots", steps=20, warmup=3),
+    "mid": dict(desc="plain CHP n=1024, 100 layers, measure all, 128 shots", steps=5, warmup=1),
+    "large": dict(desc="plain CHP n=10000, 20 layers, measure all, 1 shot", steps=3, warmup=1),
+}
+
+
+def make_circuit(name):
+    from inputs import plain_large, plain_mid, plain_small
+    return {"small": plain_small, "mid": plain_mid, "large": plain_large}[name]()
+
+
+def golden_outcomes(name):
+    path = os.path.join(ROOT, "tests", "golden", "plain_%s.json" % name)
+    if not os.path.exists(path):
+        return None
+    import numpy as np
+    rec = json.load(open(path))
+    if "outcomes" not in rec:
+        return None
+    return np.unpackbits(np.frombuffer(bytes.fromhex(rec["outcomes"]), np.uint8),
+                         bitorder="little")
+
+
+def cpu_baseline(c, budget_s: float):
+    """Oracle (as it stands, single thread) on a bounded sample of the workload:
+    the full gate phase, then as many measurements of the measure-all phase as
+    fit the budget; scaled to circuits/s for all shots (the oracle runs shots
+    one after another, each from the post-gate tableau)."""
+    import numpy as np
+    import oracle
+    oracle.build(force=False)
+    t0 = time.perf_counter()
+    t = oracle.Tableau(c.n).apply_circuit_gates(c)
+    t_gates = time.perf_counter() - t0
+    k = 0
+    t1 = time.perf_counter()
+    while k < c.n and (time.perf_counter() - t0) < budget_s:
+        t.measure(int(c.qubits[k]), seed=c.seed, circuit=c.circuit_id, shot=0, m=k)
+        k += 1
+    t_meas = time.perf_counter() - t1
+    per_meas = t_meas / max(1, k)
+    per_circuit = t_gates + c.shots * per_meas * len(c.qubits)
+    return {
+        "value": 1.0 / per_circuit, "unit": "circuits/s", "cores": 1, "kind": "oracle",
+        "sample": "gate phase in full (%.1fs) + first %d of %d measurements of shot 0 "
+                  "(%.3fs each), scaled to %d shot(s) x %d measurements"
+                  % (t_gates, k, len(c.qubits), per_meas, c.shots, len(c.qubits)),
+        "seconds": time.perf_counter() - t0,
+        "host": _host_cpu(),
+    }
+
+
+def _host_cpu():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip() + ", %d logical CPUs" % os.cpu_count()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=None)
+    ap.add_argument("--warmup", type=int, default=None)
+    ap.add_argument("--workload", default="large", choices=sorted(WORKLOADS))
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-budget", type=float, default=20.0, help="seconds of oracle work")
+    args = ap.parse_args()
+
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print("bench.py: this build measures one GPU only (the tableau hot path is "
+              "single-GPU); run with --gpus 1", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+    import paper_2408_00384_amd as P
+
+    wl = WORKLOADS[args.workload]
+    steps = args.steps if args.steps is not None else wl["steps"]
+    warmup = args.warmup if args.warmup is not None else wl["warmup"]
+    c = make_circuit(args.workload)
+    print("# workload %s: %s" % (args.workload, wl["desc"]), file=sys.stderr, flush=True)
+
+    ctx = P.Context(0)
+    tab = P.DeviceTableau(ctx, c.n, c.shots, init=False)
+    ops, offs = P.cliff_encode_layers(c.n, c.h, c.s, c.ctrl, c.tgt)
+    dev_ops = torch.from_numpy(ops.view(np.int64)).to("cuda:0")
+    torch.cuda.synchronize()
+    qubits = c.qubits
+
+    def step():
+        P.cliff_tab_init_zero(tab.handle)
+        P.cliff_apply_encoded(tab.handle, dev_ops.data_ptr(), offs)
+        return P.cliff_measure(tab.handle, qubits, c.seed, c.circuit_id, 0, 0)
+
+    for i in range(warmup):
+        step()
+        print("# warmup %d done" % (i + 1), file=sys.stderr, flush=True)
+    torch.cuda.synchronize()
+    stream = torch.cuda.current_stream()
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    t0 = time.perf_counter()
+    ev0.record(stream)
+    out = rnd = None
+    for i in range(steps):
+        out, rnd = step()
+        print("# step %d done" % (i + 1), file=sys.stderr, flush=True)
+    ev1.record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    ev_ms = ev0.elapsed_time(ev1)
+    ms_per_step = wall * 1e3 / steps
+
+    # parity against stored oracle outcomes (if present) -- bit exact
+    gold = golden_outcomes(args.workload)
+    parity = None
+    if gold is not None and c.shots == 1:
+        parity = bool(np.array_equal(out[0], gold[: c.n]))
+
+    # profiled step: per-kernel HIP-event times and device-side byte counters
+    P.cliff_tab_reset_counters(tab.handle)
+    P.cliff_ctx_profile(ctx.handle, True)
+    step()
+    prof = {k: P.cliff_ctx_profile_read(ctx.handle, k) for k in P.PROF_KINDS}
+    P.cliff_ctx_profile(ctx.handle, False)
+    counters = P.cliff_tab_counters(tab.handle)
+    sweep_ms, sweep_launches = prof["sweep"]
+    sweep_bytes = counters["sweep_bytes"]
+    achieved = sweep_bytes / (sweep_ms * 1e-3) / 1e9 if sweep_ms > 0 else 0.0
+    print("# kernels: " + ", ".join("%s %.2f ms/%d" % (k, v[0], v[1]) for k, v in prof.items()),
+          file=sys.stderr, flush=True)
+
+    result = {
+        "metric": "Clifford circuits/s batched vs plain (bit-exact) + tableau sweep HBM GB/s",
+        "value": 1e3 / ms_per_step,
+        "unit": "circuits/s",
+        "n_gpus": 1,
+        "steps": steps,
+        "warmup": warmup,
+        "ms_per_step": ms_per_step,
+        "ms_per_step_hip_events": ev_ms / steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "u64",
+        "data": "synthetic",
+        "config": {"workload": wl["desc"], "n": c.n, "layers": c.depth, "shots": c.shots,
+                   "measurements": int(len(c.qubits)), "random_measurements": int(rnd.sum()),
+                   "generator_seed": {"small": 0, "mid": 1, "large": 2}[args.workload]},
+        "parity_vs_stored_oracle": parity,
+        "roofline": {
+            "kernel": "rowsum sweep (k_sweep)",
+            "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+            "launches": sweep_launches, "avg_launch_us": 1e3 * sweep_ms / max(1, sweep_launches),
+            "alg_bytes_per_launch": sweep_bytes / max(1, sweep_launches),
+        },
+        "kernel_ms": {k: round(v[0], 3) for k, v in prof.items()},
+        "anomalies": counters["anomalies"],
+    }
+    if not args.no_cpu_baseline:
+        print("# cpu baseline (oracle) ...", file=sys.stderr, flush=True)
+        result["cpu_baseline"] = cpu_baseline(c, args.cpu_budget)
+    print(json.dumps(result), flush=True)
+
+
+if __name__ == "__main__":
+    main()

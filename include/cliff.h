@@ -141,6 +141,22 @@ int cliff_tab_import(cliff_tab *tab, const uint8_t *x, const uint8_t *z, const u
  * came out odd on a row that should commute with the pivot (must stay 0). */
 int cliff_tab_anomalies(cliff_tab *tab, uint64_t *count);
 
+/* Counters since init/reset: out4[0] anomalies (as above), out4[1] random
+ * measurements, out4[2] deterministic measurements, out4[3] algorithmic bytes
+ * of the rowsum sweeps: per random measurement 8 * (update-mask words that
+ * are nonzero) * (2 s + s_x + s_z), s = columns where the pivot row is not I,
+ * s_x / s_z = columns where it has an X / Z part.  Synchronizes. */
+int cliff_tab_counters(cliff_tab *tab, uint64_t *out4);
+int cliff_tab_reset_counters(cliff_tab *tab);
+
+/* Kernel timing (tracing aid): when enabled, every kernel launch made through
+ * the context is bracketed by HIP events on its stream.  Kinds: 0 gate sweep,
+ * 1 pivot select, 2 rowsum sweep, 3 finalize, 4 other (init/fold/copy),
+ * 5 batched circuits.  Enabling (or disabling) resets the totals; reading
+ * synchronizes and returns total milliseconds and launch count of a kind. */
+int cliff_ctx_profile(cliff_ctx *ctx, int enable);
+int cliff_ctx_profile_read(cliff_ctx *ctx, int kind, double *ms, uint64_t *launches);
+
 #ifdef __cplusplus
 }
 #endif

@@ -150,20 +150,32 @@ void orc_s(otab *t, int a) { for (int i = 0; i < 2 * t->n; ++i) s_row(t, i, a); 
 void orc_cnot(otab *t, int a, int b) { for (int i = 0; i < 2 * t->n; ++i) cnot_row(t, i, a, b); }
 
 /* Layered circuit: per qubit H (if h) then S (if s), then every CNOT pair;
- * applied row by row (each row runs through all layers in order). */
+ * applied row by row (each row runs through all layers in order).  Gates on
+ * different qubits commute, so within a layer all H's may precede all S's;
+ * the per-layer qubit lists are built once, outside the row loop. */
 void orc_apply_layers(otab *t, int depth, const uint8_t *h, const uint8_t *s,
                       const uint32_t *ctrl, const uint32_t *tgt, int npairs) {
     int n = t->n;
+    int *hl = (int *)malloc(sizeof(int) * ((size_t)depth * n + 1));
+    int *sl = (int *)malloc(sizeof(int) * ((size_t)depth * n + 1));
+    int *hc = (int *)calloc((size_t)depth + 1, sizeof(int));
+    int *sc = (int *)calloc((size_t)depth + 1, sizeof(int));
+    if (!hl || !sl || !hc || !sc) { free(hl); free(sl); free(hc); free(sc); return; }
+    for (int l = 0; l < depth; ++l)
+        for (int q = 0; q < n; ++q) {
+            if (h[(size_t)l * n + q]) hl[(size_t)l * n + hc[l]++] = q;
+            if (s[(size_t)l * n + q]) sl[(size_t)l * n + sc[l]++] = q;
+        }
     for (int i = 0; i < 2 * n; ++i) {
         for (int l = 0; l < depth; ++l) {
-            for (int q = 0; q < n; ++q) {
-                if (h[(size_t)l * n + q]) h_row(t, i, q);
-                if (s[(size_t)l * n + q]) s_row(t, i, q);
-            }
+            const int *hq = hl + (size_t)l * n, *sq = sl + (size_t)l * n;
+            for (int k = 0; k < hc[l]; ++k) h_row(t, i, hq[k]);
+            for (int k = 0; k < sc[l]; ++k) s_row(t, i, sq[k]);
             for (int k = 0; k < npairs; ++k)
                 cnot_row(t, i, (int)ctrl[(size_t)l * npairs + k], (int)tgt[(size_t)l * npairs + k]);
         }
     }
+    free(hl); free(sl); free(hc); free(sc);
 }
 
 /* Gate list: op 0 = H(a), 1 = S(a), 2 = CNOT(a -> b). */

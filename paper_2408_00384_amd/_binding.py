@@ -40,7 +40,7 @@ except ImportError:  # standalone use without PyTorch: /opt/rocm's runtime
 
 if not os.path.exists(LIB_PATH):
     raise ImportError("libcliff.so not built (expected %s); run "
-                      "`python -m paper_2408_00384_amd.build`" % LIB_PATH)
+                      "`python paper_2408_00384_amd/build.py`" % LIB_PATH)
 
 _lib = ctypes.CDLL(LIB_PATH)
 _vp = ctypes.c_void_p
@@ -73,6 +73,10 @@ _SIGS = {
     "cliff_tab_export": (ctypes.c_int, [_vp, _u8p, _u8p, _u8p]),
     "cliff_tab_import": (ctypes.c_int, [_vp, _u8p, _u8p, _u8p]),
     "cliff_tab_anomalies": (ctypes.c_int, [_vp, _u64p]),
+    "cliff_tab_counters": (ctypes.c_int, [_vp, _u64p]),
+    "cliff_tab_reset_counters": (ctypes.c_int, [_vp]),
+    "cliff_ctx_profile": (ctypes.c_int, [_vp, ctypes.c_int]),
+    "cliff_ctx_profile_read": (ctypes.c_int, [_vp, ctypes.c_int, ctypes.POINTER(ctypes.c_double), _u64p]),
 }
 
 for _name, (_res, _args) in _SIGS.items():
@@ -234,6 +238,35 @@ def cliff_tab_anomalies(tab) -> int:
     return int(v.value)
 
 
+def cliff_tab_counters(tab):
+    """dict(anomalies, random, deterministic, sweep_bytes)."""
+    out = np.zeros(4, np.uint64)
+    _check(_lib.cliff_tab_counters(tab, _ptr(out, _u64p)), "cliff_tab_counters")
+    return dict(anomalies=int(out[0]), random=int(out[1]), deterministic=int(out[2]),
+                sweep_bytes=int(out[3]))
+
+
+def cliff_tab_reset_counters(tab):
+    _check(_lib.cliff_tab_reset_counters(tab), "cliff_tab_reset_counters")
+
+
+PROF_KINDS = ("gate", "select", "sweep", "final", "other", "batch")
+
+
+def cliff_ctx_profile(ctx, enable: bool):
+    _check(_lib.cliff_ctx_profile(ctx, 1 if enable else 0), "cliff_ctx_profile")
+
+
+def cliff_ctx_profile_read(ctx, kind):
+    k = PROF_KINDS.index(kind) if isinstance(kind, str) else int(kind)
+    ms = ctypes.c_double()
+    n = _u64()
+    _check(_lib.cliff_ctx_profile_read(ctx, k, ctypes.byref(ms), ctypes.byref(n)),
+           "cliff_ctx_profile_read")
+    return float(ms.value), int(n.value)
+
+
 __all__ = [n for n in list(globals()) if n.startswith("cliff_")] + [
     "CLIFF_OK", "CLIFF_EINVAL", "CLIFF_ENOMEM", "CLIFF_EDEVICE", "CLIFF_EBUSY",
-    "CLIFF_EINTERNAL", "OP_H", "OP_S", "OP_CNOT", "CliffError", "LIB_PATH", "exported_symbols"]
+    "CLIFF_EINTERNAL", "OP_H", "OP_S", "OP_CNOT", "CliffError", "LIB_PATH", "exported_symbols",
+    "PROF_KINDS"]

@@ -1,6 +1,8 @@
 """Build libcliff.so (HIP, gfx950) in-tree with hipcc.
 
-    python -m paper_2408_00384_amd.build
+    python paper_2408_00384_amd/build.py
+
+(Run it by path: importing the package first would load the library it builds.)
 
 Each .hip source under csrc/ is compiled to an object in parallel, then linked
 into paper_2408_00384_amd/_lib/libcliff.so.

@@ -3,6 +3,7 @@
 // the kernels of gates.hip / measure.hip / batch.hip.
 #include <stdarg.h>
 #include <stdio.h>
+#include <stdlib.h>
 #include <string.h>
 
 #include <algorithm>
@@ -46,7 +47,72 @@ struct DeviceGuard {
   }
 };
 
+// ---------------------------------------------------------------- profiler ---
+namespace cliff {
+
+static hipEvent_t take_event(Profiler &p) {
+  if (!p.pool.empty()) {
+    hipEvent_t e = p.pool.back();
+    p.pool.pop_back();
+    return e;
+  }
+  hipEvent_t e = nullptr;
+  if (hipEventCreate(&e) != hipSuccess) return nullptr;
+  return e;
+}
+
+void Profiler::begin(int kind, hipStream_t st) {
+  (void)kind;
+  if (!on) return;
+  open_ev = take_event(*this);
+  if (open_ev) (void)hipEventRecord(open_ev, st);
+}
+
+void Profiler::end(int kind, hipStream_t st) {
+  if (!on || !open_ev) return;
+  hipEvent_t b = take_event(*this);
+  if (!b) return;
+  (void)hipEventRecord(b, st);
+  pending.push_back({kind, open_ev, b});
+  open_ev = nullptr;
+}
+
+hipError_t Profiler::resolve() {
+  for (const Rec &r : pending) {
+    hipError_t e = hipEventSynchronize(r.b);
+    if (e != hipSuccess) return e;
+    float ms_ = 0.f;
+    e = hipEventElapsedTime(&ms_, r.a, r.b);
+    if (e != hipSuccess) return e;
+    ms[r.kind] += ms_;
+    launches[r.kind] += 1;
+    pool.push_back(r.a);
+    pool.push_back(r.b);
+  }
+  pending.clear();
+  return hipSuccess;
+}
+
+void Profiler::reset() {
+  (void)resolve();
+  for (int k = 0; k < kProfKinds; ++k) {
+    ms[k] = 0;
+    launches[k] = 0;
+  }
+}
+
+Profiler::~Profiler() {
+  for (const Rec &r : pending) {
+    (void)hipEventDestroy(r.a);
+    (void)hipEventDestroy(r.b);
+  }
+  for (hipEvent_t e : pool) (void)hipEventDestroy(e);
+}
+
+}  // namespace cliff
+
 struct cliff_ctx {
+  Profiler prof;
   int device = 0;
   hipStream_t stream = nullptr;
   int num_cus = 0;
@@ -132,7 +198,7 @@ int cliff_sync(cliff_ctx *c) {
 int cliff_ctx_num_cus(const cliff_ctx *c) { return c ? c->num_cus : 0; }
 
 size_t cliff_tab_bytes(uint32_t n, uint32_t shots) {
-  if (n == 0 || shots == 0 || n > (1u << 26)) return 0;
+  if (n == 0 || shots == 0 || n > kMaxQubits) return 0;
   return make_offsets(make_dims(n, shots)).total;
 }
 
@@ -141,7 +207,7 @@ int cliff_tab_bind(cliff_ctx *ctx, uint32_t n, uint32_t shots, void *dev, size_t
   if (!ctx || !dev || !out) return fail(CLIFF_EINVAL, "cliff_tab_bind: NULL argument");
   *out = nullptr;
   if (n == 0 || shots == 0) return fail(CLIFF_EINVAL, "cliff_tab_bind: n and shots must be > 0");
-  if (n > (1u << 26)) return fail(CLIFF_EINVAL, "cliff_tab_bind: n = %u too large", n);
+  if (n > kMaxQubits) return fail(CLIFF_EINVAL, "cliff_tab_bind: n = %u > %u", n, kMaxQubits);
   if (reinterpret_cast<uintptr_t>(dev) & 255)
     return fail(CLIFF_EINVAL, "cliff_tab_bind: device buffer not 256-byte aligned");
   const size_t need = cliff_tab_bytes(n, shots);
@@ -167,6 +233,12 @@ int cliff_tab_bind(cliff_ctx *ctx, uint32_t n, uint32_t shots, void *dev, size_t
   v.state = reinterpret_cast<uint32_t *>(at(t->o.state));
   v.out = at(t->o.out);
   v.kind = at(t->o.kind);
+  v.SN = reinterpret_cast<uint64_t *>(at(t->o.SN));
+  v.piv = reinterpret_cast<uint32_t *>(at(t->o.piv));
+  v.rps = reinterpret_cast<uint64_t *>(at(t->o.rps));
+  v.detpar = reinterpret_cast<uint32_t *>(at(t->o.detpar));
+  v.detY = reinterpret_cast<uint32_t *>(at(t->o.detY));
+  v.detr = reinterpret_cast<uint64_t *>(at(t->o.detr));
   v.n = n;
   v.S = shots;
   v.W = t->d.W;
@@ -316,7 +388,10 @@ static int run_encoded(cliff_tab *t, const uint64_t *dev_ops, const uint32_t *of
   for (uint32_t l = 0; l < depth; ++l) {
     const uint32_t a = offs[l], b = offs[l + 1];
     if (b < a) return fail(CLIFF_EINVAL, "layer offsets decrease at layer %u", l);
-    HIP_TRY(launch_gate_layer(t->dev, dev_ops + a, b - a, t->ctx->stream));
+    t->ctx->prof.begin(PK_GATE, t->ctx->stream);
+    hipError_t e = launch_gate_layer(t->dev, dev_ops + a, b - a, t->ctx->stream);
+    t->ctx->prof.end(PK_GATE, t->ctx->stream);
+    HIP_TRY(e);
   }
   return CLIFF_OK;
 }
@@ -388,6 +463,15 @@ extern "C" int cliff_apply_gates(cliff_tab *t, const uint8_t *op, const uint32_t
 
 // ---------------------------------------------------------------- measure ---
 
+static bool use_v1_path() {
+  static int v = -1;
+  if (v < 0) {
+    const char *e = getenv("CLIFF_MEASURE_V1");
+    v = (e && e[0] == '1') ? 1 : 0;
+  }
+  return v == 1;
+}
+
 static int measure_impl(cliff_tab *t, const uint32_t *qubits, size_t k, uint64_t seed,
                         uint64_t circuit, uint64_t shot0, uint64_t m0, uint8_t *host_out,
                         uint8_t *host_random) {
@@ -395,13 +479,21 @@ static int measure_impl(cliff_tab *t, const uint32_t *qubits, size_t k, uint64_t
   for (size_t i = 0; i < k; ++i)
     if (qubits[i] >= n) return fail(CLIFF_EINVAL, "measure: qubit %u >= n = %u", qubits[i], n);
   hipStream_t st = t->ctx->stream;
-  HIP_TRY(launch_fold_pending(t->dev, st));
+  t->ctx->prof.begin(PK_OTHER, st);
+  hipError_t fe = launch_fold_pending(t->dev, st);
+  t->ctx->prof.end(PK_OTHER, st);
+  HIP_TRY(fe);
   std::vector<uint8_t> out_stage, kind_stage;
   for (size_t base = 0; base < k; base += n) {
     const size_t cnt = std::min<size_t>(n, k - base);
-    for (size_t i = 0; i < cnt; ++i)
-      HIP_TRY(launch_measure_one(t->dev, qubits[base + i], uint32_t(i), seed, circuit, shot0,
-                                 m0 + base + i, st));
+    if (use_v1_path()) {
+      for (size_t i = 0; i < cnt; ++i)
+        HIP_TRY(launch_measure_one(t->dev, qubits[base + i], uint32_t(i), seed, circuit, shot0,
+                                   m0 + base + i, st, &t->ctx->prof));
+    } else {
+      HIP_TRY(launch_measure_list(t->dev, qubits + base, uint32_t(cnt), seed, circuit, shot0,
+                                  m0 + base, st, &t->ctx->prof));
+    }
     if (host_out || host_random) {
       out_stage.resize(cnt * S);
       kind_stage.resize(cnt);
@@ -500,5 +592,48 @@ extern "C" int cliff_tab_anomalies(cliff_tab *t, uint64_t *count) {
   HIP_TRY(hipMemcpyAsync(&v, t->dev.state + ST_ANOMALY, 4, hipMemcpyDeviceToHost, t->ctx->stream));
   HIP_TRY(hipStreamSynchronize(t->ctx->stream));
   *count = v;
+  return CLIFF_OK;
+}
+
+// ------------------------------------------------------- profiling/counters ---
+
+extern "C" int cliff_ctx_profile(cliff_ctx *c, int enable) {
+  if (!c) return fail(CLIFF_EINVAL, "cliff_ctx_profile: NULL context");
+  DeviceGuard g(c->device);
+  HIP_TRY(c->prof.resolve());
+  c->prof.reset();
+  c->prof.on = enable != 0;
+  return CLIFF_OK;
+}
+
+extern "C" int cliff_ctx_profile_read(cliff_ctx *c, int kind, double *ms, uint64_t *launches) {
+  if (!c || !ms || !launches) return fail(CLIFF_EINVAL, "cliff_ctx_profile_read: NULL argument");
+  if (kind < 0 || kind >= kProfKinds) return fail(CLIFF_EINVAL, "cliff_ctx_profile_read: kind %d", kind);
+  DeviceGuard g(c->device);
+  HIP_TRY(c->prof.resolve());
+  *ms = c->prof.ms[kind];
+  *launches = c->prof.launches[kind];
+  return CLIFF_OK;
+}
+
+extern "C" int cliff_tab_counters(cliff_tab *t, uint64_t *out4) {
+  if (!t || !out4) return fail(CLIFF_EINVAL, "cliff_tab_counters: NULL argument");
+  DeviceGuard g(t->ctx->device);
+  uint32_t st[kStateWords];
+  HIP_TRY(hipMemcpyAsync(st, t->dev.state, sizeof st, hipMemcpyDeviceToHost, t->ctx->stream));
+  HIP_TRY(hipStreamSynchronize(t->ctx->stream));
+  uint64_t bytes;
+  memcpy(&bytes, st + ST_SWEEP_BYTES, 8);
+  out4[0] = st[ST_ANOMALY];
+  out4[1] = st[ST_RANDOM_CNT];
+  out4[2] = st[ST_DET_CNT];
+  out4[3] = bytes;
+  return CLIFF_OK;
+}
+
+extern "C" int cliff_tab_reset_counters(cliff_tab *t) {
+  if (!t) return fail(CLIFF_EINVAL, "cliff_tab_reset_counters: NULL tableau");
+  DeviceGuard g(t->ctx->device);
+  HIP_TRY(launch_clear_state(t->dev, t->ctx->stream));
   return CLIFF_OK;
 }

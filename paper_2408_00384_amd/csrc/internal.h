@@ -17,6 +17,8 @@
 #include <stddef.h>
 #include <stdint.h>
 
+#include <vector>
+
 namespace cliff {
 
 constexpr uint32_t kNone = 0xFFFFFFFFu;
@@ -31,6 +33,32 @@ enum : uint32_t {
   ST_DET_Y = 3,      // deterministic branch: count of Y entries in the product rows
   ST_ERROR = 4,      // sticky error bits
   ST_RANDOM_CNT = 5, // random measurements since bind
+  ST_DET_CNT = 6,    // deterministic measurements since bind
+  ST_SWEEP_BYTES = 8,  // uint64 (words 8..9): algorithmic bytes of the rowsum sweeps
+};
+
+// Kernel classes timed by the profiler.
+enum ProfKind : int { PK_GATE = 0, PK_SELECT, PK_SWEEP, PK_FINAL, PK_OTHER, PK_BATCH, kProfKinds };
+
+// Optional hipEvent timing of kernel launches, per kernel class: events are
+// recorded on the launch stream right before and after each launch and
+// resolved on demand (defined in api.hip).
+struct Profiler {
+  bool on = false;
+  struct Rec {
+    int kind;
+    hipEvent_t a, b;
+  };
+  std::vector<hipEvent_t> pool;
+  std::vector<Rec> pending;
+  hipEvent_t open_ev = nullptr;
+  double ms[kProfKinds] = {};
+  unsigned long long launches[kProfKinds] = {};
+  void begin(int kind, hipStream_t st);
+  void end(int kind, hipStream_t st);
+  hipError_t resolve();
+  void reset();
+  ~Profiler();
 };
 
 // Gate op word: a (28 bits) | b (28 bits) << 28 | flags << 56.
@@ -51,7 +79,8 @@ struct Dims {
 };
 
 struct Offsets {
-  size_t X, Z, R, P, M, xp, zp, rp, part, state, out, kind, total;
+  size_t X, Z, R, P, M, xp, zp, rp, part, state, out, kind;
+  size_t SN, piv, rps, detpar, detY, detr, total;
 };
 
 // Device view passed by value to kernels.
@@ -60,8 +89,24 @@ struct TabDev {
   uint64_t *M, *xp, *zp, *rp, *part;
   uint32_t *state;
   uint8_t *out, *kind;
+  uint64_t *SN;              // 3 x Wp: snapshots of the measured columns
+  uint32_t *piv;             // 4: pivot rows of consecutive measurements
+  uint64_t *rps;             // 2 x SW: pivot-row signs handed to the next step
+  uint32_t *detpar, *detY;   // n: deterministic-outcome accumulators
+  uint64_t *detr;            // n x SW
   uint32_t n, S, W, Wp, NW, SW;
 };
+
+// Largest supported qubit count (pivot bits of a workgroup's columns in LDS).
+constexpr uint32_t kMaxQubits = 1u << 20;
+
+// Launch shape of the per-measurement step kernel for n qubits.
+inline uint32_t step_grid(uint32_t n) {
+  uint32_t g = (n + 31) / 32;
+  if (g > 256) g = 256;
+  return g < 1 ? 1 : g;
+}
+inline uint32_t step_block(uint32_t n) { return n >= 2048 ? 1024u : 256u; }
 
 inline size_t align256(size_t v) { return (v + 255) & ~size_t(255); }
 
@@ -91,10 +136,19 @@ inline Offsets make_offsets(const Dims &d) {
   o.xp = take(size_t(d.NW) * 8);
   o.zp = take(size_t(d.NW) * 8);
   o.rp = take(size_t(d.SW) * 8);
-  o.part = take(size_t(sweep_chunks(d.n)) * d.Wp * 16);
+  {
+    const size_t a = size_t(sweep_chunks(d.n)), b = 2 * size_t(step_grid(d.n));
+    o.part = take((a > b ? a : b) * d.Wp * 16);
+  }
   o.state = take(kStateWords * 4);
   o.out = take(size_t(d.n) * d.S);   // staging for up to n measurements per pass
   o.kind = take(size_t(d.n));
+  o.SN = take(3 * size_t(d.Wp) * 8);
+  o.piv = take(4 * 4);
+  o.rps = take(2 * size_t(d.SW) * 8);
+  o.detpar = take(size_t(d.n) * 4);
+  o.detY = take(size_t(d.n) * 4);
+  o.detr = take(size_t(d.n) * d.SW * 8);
   o.total = cur;
   return o;
 }
@@ -115,7 +169,11 @@ hipError_t launch_init_zero(const TabDev &t, hipStream_t st);
 hipError_t launch_fold_pending(const TabDev &t, hipStream_t st);
 hipError_t launch_gate_layer(const TabDev &t, const uint64_t *ops, uint32_t nops, hipStream_t st);
 hipError_t launch_measure_one(const TabDev &t, uint32_t a, uint32_t slot, uint64_t seed,
-                              uint64_t circuit, uint64_t shot0, uint64_t m, hipStream_t st);
+                              uint64_t circuit, uint64_t shot0, uint64_t m, hipStream_t st,
+                              Profiler *prof);
+hipError_t launch_measure_list(const TabDev &t, const uint32_t *qubits, uint32_t k, uint64_t seed,
+                               uint64_t circuit, uint64_t shot0, uint64_t m0, hipStream_t st,
+                               Profiler *prof);
 hipError_t launch_clear_state(const TabDev &t, hipStream_t st);
 hipError_t launch_copy_tab(const TabDev &dst, const TabDev &src, hipStream_t st);
 

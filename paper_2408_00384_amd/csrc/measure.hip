@@ -31,9 +31,12 @@ namespace cliff {
 // the update mask M, packed pivot row and packed pivot signs; or, when
 // deterministic, the product-row mask T (stabilizer rows n+i with x_ia = 1).
 __global__ void __launch_bounds__(1024) k_select(TabDev t, uint32_t a, uint32_t slot) {
-  __shared__ uint32_t s_p;
+  __shared__ uint32_t s_p, s_nzw, s_sx, s_sz, s_s;
   const uint32_t tid = threadIdx.x, bd = blockDim.x;
-  if (tid == 0) s_p = kNone;
+  if (tid == 0) {
+    s_p = kNone;
+    s_nzw = s_sx = s_sz = s_s = 0;
+  }
   __syncthreads();
   const uint64_t *colX = t.X + size_t(a) * t.Wp;
   const uint32_t n = t.n;
@@ -51,6 +54,7 @@ __global__ void __launch_bounds__(1024) k_select(TabDev t, uint32_t a, uint32_t 
       uint64_t v = w < t.W ? colX[w] : 0ull;
       if (w == wp) v &= ~(1ull << bp);
       t.M[w] = v;
+      if (v) atomicAdd(&s_nzw, 1u);
     }
     for (uint32_t j = tid; j < t.NW * 64; j += bd) {   // 64 consecutive columns per wave
       uint32_t xb = 0, zb = 0;
@@ -59,7 +63,13 @@ __global__ void __launch_bounds__(1024) k_select(TabDev t, uint32_t a, uint32_t 
         zb = uint32_t(t.Z[size_t(j) * t.Wp + wp] >> bp) & 1u;
       }
       const uint64_t bx = __ballot(xb), bz = __ballot(zb);
-      if ((tid & 63) == 0) { t.xp[j >> 6] = bx; t.zp[j >> 6] = bz; }
+      if ((tid & 63) == 0) {
+        t.xp[j >> 6] = bx;
+        t.zp[j >> 6] = bz;
+        atomicAdd(&s_sx, uint32_t(__popcll(bx)));
+        atomicAdd(&s_sz, uint32_t(__popcll(bz)));
+        atomicAdd(&s_s, uint32_t(__popcll(bx | bz)));
+      }
     }
     for (uint32_t s = tid; s < t.SW * 64; s += bd) {
       const uint32_t rb = s < t.S ? uint32_t(t.R[size_t(wp) * t.S + s] >> bp) & 1u : 0u;
@@ -86,9 +96,20 @@ __global__ void __launch_bounds__(1024) k_select(TabDev t, uint32_t a, uint32_t 
       t.state[ST_DET_Y] = 0;
     }
   }
+  __syncthreads();
   if (tid == 0) {
     t.state[ST_PIVOT] = p;
     t.kind[slot] = p != kNone ? 1 : 0;
+    if (p != kNone) {
+      // bytes the rowsum sweep must move: read x and z of every supported
+      // column word with rows to update, write x (z) where the pivot has x (z)
+      const uint64_t bytes = 8ull * s_nzw * (2ull * s_s + s_sx + s_sz);
+      atomicAdd(reinterpret_cast<unsigned long long *>(t.state + ST_SWEEP_BYTES),
+                (unsigned long long)bytes);
+      atomicAdd(&t.state[ST_RANDOM_CNT], 1u);
+    } else {
+      atomicAdd(&t.state[ST_DET_CNT], 1u);
+    }
   }
 }
 
@@ -286,17 +307,24 @@ __global__ void __launch_bounds__(1024) k_final(TabDev t, uint32_t slot, uint32_
 }
 
 hipError_t launch_measure_one(const TabDev &t, uint32_t a, uint32_t slot, uint64_t seed,
-                              uint64_t circuit, uint64_t shot0, uint64_t m, hipStream_t st) {
+                              uint64_t circuit, uint64_t shot0, uint64_t m, hipStream_t st,
+                              Profiler *prof) {
   const uint32_t cols = sweep_cols_per_chunk(t.n);
   const uint32_t chunks = (t.n + cols - 1) / cols;
   const uint32_t tiles = (t.W + 63) / 64;
+  if (prof) prof->begin(PK_SELECT, st);
   k_select<<<1, 1024, 0, st>>>(t, a, slot);
+  if (prof) prof->end(PK_SELECT, st);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
+  if (prof) prof->begin(PK_SWEEP, st);
   k_sweep<<<dim3(chunks, tiles), 256, 0, st>>>(t, a, cols);
+  if (prof) prof->end(PK_SWEEP, st);
   e = hipGetLastError();
   if (e != hipSuccess) return e;
+  if (prof) prof->begin(PK_FINAL, st);
   k_final<<<tiles, 1024, 0, st>>>(t, slot, chunks, seed, circuit, shot0, m);
+  if (prof) prof->end(PK_FINAL, st);
   return hipGetLastError();
 }
 
