@@ -153,7 +153,7 @@ __device__ void finish_prev(const TabDev &t, const StepArgs &s, uint32_t G, uint
 __global__ void __launch_bounds__(1024) k_step(TabDev t, StepArgs s) {
   __shared__ uint64_t s_c0[1024], s_c1[1024];
   __shared__ uint64_t s_xp[kMaxOwnCols / 64], s_zp[kMaxOwnCols / 64];
-  __shared__ uint32_t s_pnext;
+  __shared__ uint32_t s_pnext, s_nzw;
   const uint32_t tid = threadIdx.x, lane = tid & 63;
   const uint32_t wave = __builtin_amdgcn_readfirstlane(tid >> 6);
   const uint32_t nw = blockDim.x >> 6;   // >= 2
@@ -164,7 +164,10 @@ __global__ void __launch_bounds__(1024) k_step(TabDev t, StepArgs s) {
     if (wave == 0 && s.has_prev) finish_prev(t, s, G, g, lane);
     return;
   }
-  if (tid == 0) s_pnext = kNone;
+  if (tid == 0) {
+    s_pnext = kNone;
+    s_nzw = 0;
+  }
   const uint32_t rwave = nw - 1;         // finishes the previous measurement
   const uint32_t nsw = nw - 1;           // sweep waves
   const uint32_t p = t.piv[s.slot % 4];
@@ -210,55 +213,66 @@ __global__ void __launch_bounds__(1024) k_step(TabDev t, StepArgs s) {
     if (whole_tiles) { cgi = 0; tfirst = wave; tstep = nsw; }
     else { cgi = wave / T; tfirst = cgi < ncg ? wave % T : T; tstep = T; }
     const uint32_t cslot = cgi * cpw + sub, cstride = ncg * cpw;
+    constexpr uint32_t U = 8;   // columns in flight per lane
     for (uint32_t tile = tfirst; tile < T; tile += tstep) {
       const uint32_t w = tile * Wl + wl;
       const bool live = w < W;
       const uint64_t m = live ? upd_mask(t, s.slot, p, w) : 0ull;
       const bool touch = live && (m != 0 || w == wpn || w == wp);
+      if (cgi == 0 && sub == 0 && m != 0) atomicAdd(&s_nzw, 1u);
       uint64_t c0 = 0, c1 = 0;
-      for (uint32_t j = j0 + cslot; j < j1; j += cstride) {
-        const uint32_t c = j - j0;
-        const uint32_t xpj = uint32_t(s_xp[c >> 6] >> (c & 63)) & 1u;
-        const uint32_t zpj = uint32_t(s_zp[c >> 6] >> (c & 63)) & 1u;
-        const bool is_next = own_next && j == s.a_next;
-        uint64_t *qx = t.X + size_t(j) * t.Wp + w;
-        uint64_t *qz = t.Z + size_t(j) * t.Wp + w;
-        if (!(xpj | zpj)) {
-          // the pivot is I here: only row p-n changes (to the pivot's zeros)
-          if (live && (w == wpn || is_next)) {
-            uint64_t x = *qx;
-            if (w == wpn) {
-              const uint64_t z = *qz;
-              if (z & bpn) *qz = z & ~bpn;
-              if (x & bpn) { x &= ~bpn; *qx = x; }
-            }
-            if (is_next) { SNn[w] = x; note_pivot(&s_pnext, n, w, x); }
+      for (uint32_t jb = j0 + cslot; jb < j1; jb += U * cstride) {
+        uint64_t xv[U], zv[U];
+        uint32_t ty[U];
+        bool need[U];
+        // issue the loads of U columns first ...
+#pragma unroll
+        for (uint32_t u = 0; u < U; ++u) {
+          const uint32_t j = jb + u * cstride;
+          uint32_t tj = 0;
+          if (j < j1) {
+            const uint32_t c = j - j0;
+            tj = (uint32_t(s_xp[c >> 6] >> (c & 63)) & 1u) | ((uint32_t(s_zp[c >> 6] >> (c & 63)) & 1u) << 1);
           }
-          continue;
+          const bool nxt = own_next && j == s.a_next;
+          // supported column: every word with rows to update; pivot I here:
+          // only the word of row p-n (it becomes the pivot's zeros)
+          need[u] = j < j1 && live && (nxt || (tj ? touch : (w == wpn)));
+          ty[u] = tj;
+          xv[u] = need[u] ? t.X[size_t(j) * t.Wp + w] : 0ull;
+          zv[u] = need[u] ? t.Z[size_t(j) * t.Wp + w] : 0ull;
         }
-        if (!touch && !(is_next && live)) continue;
-        const uint64_t x = *qx, z = *qz;
-        const uint64_t X1 = xpj ? ~0ull : 0ull, Z1 = zpj ? ~0ull : 0ull;
-        const uint64_t yc = X1 & Z1, xc = X1 & ~Z1, zc = ~X1 & Z1;
-        // g = +1 / -1 per row: pivot Y: z-x;  pivot X: z(2x-1);  pivot Z: x(1-2z)
-        const uint64_t plus = ((yc & z & ~x) | (xc & z & x) | (zc & x & ~z)) & m;
-        const uint64_t minus = ((yc & x & ~z) | (xc & z & ~x) | (zc & x & z)) & m;
-        c1 ^= c0 & plus;
-        c0 ^= plus;
-        c1 ^= ~c0 & minus;
-        c0 ^= minus;
-        uint64_t nx = x ^ (X1 & m), nz = z ^ (Z1 & m);
-        if (w == wpn) {   // row p-n <- pivot row
-          nx = xpj ? (nx | bpn) : (nx & ~bpn);
-          nz = zpj ? (nz | bpn) : (nz & ~bpn);
+        // ... then update them
+#pragma unroll
+        for (uint32_t u = 0; u < U; ++u) {
+          if (!need[u]) continue;
+          const uint32_t j = jb + u * cstride;
+          const uint64_t x = xv[u], z = zv[u];
+          const uint64_t X1 = (ty[u] & 1u) ? ~0ull : 0ull, Z1 = (ty[u] & 2u) ? ~0ull : 0ull;
+          const uint64_t yc = X1 & Z1, xc = X1 & ~Z1, zc = ~X1 & Z1;
+          // g = +1 / -1 per row: pivot Y: z-x;  pivot X: z(2x-1);  pivot Z: x(1-2z)
+          const uint64_t plus = ((yc & z & ~x) | (xc & z & x) | (zc & x & ~z)) & m;
+          const uint64_t minus = ((yc & x & ~z) | (xc & z & ~x) | (zc & x & z)) & m;
+          c1 ^= c0 & plus;
+          c0 ^= plus;
+          c1 ^= ~c0 & minus;
+          c0 ^= minus;
+          uint64_t nx = x ^ (X1 & m), nz = z ^ (Z1 & m);
+          if (w == wpn) {   // row p-n <- pivot row
+            nx = (ty[u] & 1u) ? (nx | bpn) : (nx & ~bpn);
+            nz = (ty[u] & 2u) ? (nz | bpn) : (nz & ~bpn);
+          }
+          if (w == wp) {    // row p <- Z_a
+            nx &= ~bpb;
+            nz = (j == s.a) ? (nz | bpb) : (nz & ~bpb);
+          }
+          if (nx != x) t.X[size_t(j) * t.Wp + w] = nx;
+          if (nz != z) t.Z[size_t(j) * t.Wp + w] = nz;
+          if (own_next && j == s.a_next) {
+            SNn[w] = nx;
+            note_pivot(&s_pnext, n, w, nx);
+          }
         }
-        if (w == wp) {    // row p <- Z_a
-          nx &= ~bpb;
-          nz = (j == s.a) ? (nz | bpb) : (nz & ~bpb);
-        }
-        if (nx != x) *qx = nx;
-        if (nz != z) *qz = nz;
-        if (is_next) { SNn[w] = nx; note_pivot(&s_pnext, n, w, nx); }
       }
       if (whole_tiles) {
         if (live) {   // complete over the workgroup's columns: store directly
@@ -325,6 +339,23 @@ __global__ void __launch_bounds__(1024) k_step(TabDev t, StepArgs s) {
     }
   }
   if (tid == 0 && own_next) t.piv[(s.slot + 1) % 4] = s_pnext;
+  if (tid == 0) {
+    if (p != kNone) {
+      // algorithmic bytes of this workgroup's share of the rowsum sweep:
+      // 8 * (nonzero update-mask words) * (2 s + s_x + s_z) over its columns
+      uint32_t sx = 0, sz = 0, sxz = 0;
+      for (uint32_t k = 0; k < (j1 - j0 + 63) / 64; ++k) {
+        sx += uint32_t(__popcll(s_xp[k]));
+        sz += uint32_t(__popcll(s_zp[k]));
+        sxz += uint32_t(__popcll(s_xp[k] | s_zp[k]));
+      }
+      const uint64_t bytes = 8ull * s_nzw * (2ull * sxz + sx + sz);
+      if (bytes)
+        atomicAdd(reinterpret_cast<unsigned long long *>(t.state + ST_SWEEP_BYTES),
+                  (unsigned long long)bytes);
+    }
+    if (g == 0) atomicAdd(&t.state[p != kNone ? ST_RANDOM_CNT : ST_DET_CNT], 1u);
+  }
 }
 
 // ---------------------------------------------------------- call prologue ---
