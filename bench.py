@@ -81,6 +81,64 @@ def cpu_baseline(c, budget_s: float):
     }
 
 
+def bench_batch(P, torch, np, count=4096, plain_sample=48, reps=5):
+    """Batched workload: all circuits in one graph-captured sequence of
+    persistent launches vs the plain path (one circuit at a time through the
+    HBM kernels) on a sample of the same circuits; outcomes compared bit-exact."""
+    from inputs import batch_workload
+    from paper_2408_00384_amd.batch import BatchPlan, load_tuning
+    t0 = time.perf_counter()
+    circs = batch_workload(count)
+    gen_s = time.perf_counter() - t0
+    stream = torch.cuda.Stream()
+    ctx = P.Context(0, stream)
+    with torch.cuda.stream(stream):
+        plan = BatchPlan(ctx, circs).capture()
+        plan.run()
+        ctx.sync()
+        ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        t1 = time.perf_counter()
+        ev0.record(stream)
+        for _ in range(reps):
+            plan.run()
+        ev1.record(stream)
+        ctx.sync()
+        wall = (time.perf_counter() - t1) / reps
+        ev_ms = ev0.elapsed_time(ev1) / reps
+        outs = plan.outcomes()
+    status = plan.status()
+    # plain path on an evenly spaced sample
+    idx = np.linspace(0, count - 1, plain_sample).astype(int)
+    pctx = P.Context(0)
+    parity = True
+    t2 = time.perf_counter()
+    for i in idx:
+        c = circs[i]
+        tab = P.DeviceTableau(pctx, c.n, c.shots)
+        tab.apply_circuit_gates(c)
+        o, _ = tab.measure(c.qubits, seed=c.seed, circuit=c.circuit_id)
+        parity &= bool(np.array_equal(o, outs[i]))
+        tab.close()
+    torch.cuda.synchronize()
+    plain_s = (time.perf_counter() - t2) / len(idx)
+    # the plain path's time depends on n: weight the sample to the whole batch
+    ns = np.array([c.n for c in circs])
+    plan.close()
+    return {
+        "workload": "%d circuits, n ~ U{8..256}, depth ~ U{n..4n}, measure all, 4 shots" % count,
+        "circuits_per_s": count / (ev_ms * 1e-3),
+        "ms_per_batch": ev_ms, "ms_per_batch_wall": wall * 1e3,
+        "plain_circuits_per_s": 1.0 / plain_s,
+        "plain_sample": "%d evenly spaced circuits (mean n %.0f vs %.0f in the batch), one at a time"
+                        % (len(idx), ns[idx].mean(), ns.mean()),
+        "batched_vs_plain": (count / (ev_ms * 1e-3)) * plain_s,
+        "bit_exact_vs_plain": parity,
+        "device_checks": status,
+        "teams": {str(k): v for k, v in load_tuning().items()},
+        "generate_s": gen_s,
+    }
+
+
 def _host_cpu():
     try:
         for line in open("/proc/cpuinfo"):
@@ -99,6 +157,7 @@ def main():
     ap.add_argument("--workload", default="large", choices=sorted(WORKLOADS))
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-budget", type=float, default=20.0, help="seconds of oracle work")
+    ap.add_argument("--no-batch", action="store_true", help="skip the batched-circuits leg")
     args = ap.parse_args()
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -194,6 +253,9 @@ def main():
         "kernel_ms": {k: round(v[0], 3) for k, v in prof.items()},
         "anomalies": counters["anomalies"],
     }
+    if not args.no_batch:
+        print("# batched circuits ...", file=sys.stderr, flush=True)
+        result["batched"] = bench_batch(P, torch, np)
     if not args.no_cpu_baseline:
         print("# cpu baseline (oracle) ...", file=sys.stderr, flush=True)
         result["cpu_baseline"] = cpu_baseline(c, args.cpu_budget)

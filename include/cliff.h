@@ -157,6 +157,46 @@ int cliff_tab_reset_counters(cliff_tab *tab);
 int cliff_ctx_profile(cliff_ctx *ctx, int enable);
 int cliff_ctx_profile_read(cliff_ctx *ctx, int kind, double *ms, uint64_t *launches);
 
+/* ------------------------------------------------------------ batching ---
+ * Thousands of independent small circuits in one persistent launch (the
+ * phase-space method of Sec. 2 applied per circuit, each circuit held in the
+ * LDS of one workgroup).  Circuit i is described by descs[i]: n qubits
+ * (1 <= n <= maxn of the launch), `depth` layers whose encoded ops (see
+ * cliff_encode_layers) start at word ops_off of dev_ops, with the layer
+ * boundaries offs[offs_off .. offs_off+depth] (relative to ops_off), `shots`
+ * sign columns (1..64), and outcomes written as uint8 [shots][n] at byte
+ * out_off of dev_out after measuring qubits 0..n-1 in order (measurement index
+ * m = qubit, shot index 0..shots-1, circuit index circuit_id for the random
+ * bit).  Workgroups take circuits in the order dev_order[0..count) from a
+ * device queue.  team (threads per circuit) and maxn select the kernel
+ * instance: (64,64) (128,64) (64,128) (128,128) (256,128) (128,256) (256,256)
+ * (512,256).  dev_work: cliff_batch_work_bytes() bytes of device scratch,
+ * reset by the launch.  All pointers are device pointers; nothing is copied
+ * to the host and the call only enqueues work. */
+typedef struct {
+    uint32_t n, depth, shots, reserved;
+    uint64_t ops_off, offs_off, out_off, circuit_id;
+} cliff_batch_desc;
+
+size_t cliff_batch_work_bytes(void);
+int cliff_batch_run(cliff_ctx *ctx, const cliff_batch_desc *dev_descs, const uint64_t *dev_ops,
+                    const uint32_t *dev_offs, uint8_t *dev_out, const uint32_t *dev_order,
+                    uint32_t count, uint64_t seed, void *dev_work, uint32_t team, uint32_t maxn);
+/* out2[0] = descriptors rejected (n or shots out of range), out2[1] = device
+ * consistency-check failures, of the last launch using dev_work.  Synchronizes. */
+int cliff_batch_status(cliff_ctx *ctx, const void *dev_work, uint64_t *out2);
+
+/* --------------------------------------------------------------- graphs ---
+ * Capture everything the context enqueues between begin and end into a HIP
+ * graph, replayable with cliff_graph_launch on the same stream.  The context
+ * must use a non-default stream.  Captured work must not change shape between
+ * replays (the same pointers and sizes are reused). */
+typedef struct cliff_graph cliff_graph;
+int cliff_graph_begin(cliff_ctx *ctx);
+int cliff_graph_end(cliff_ctx *ctx, cliff_graph **out);
+int cliff_graph_launch(cliff_graph *graph);
+int cliff_graph_destroy(cliff_graph *graph);
+
 #ifdef __cplusplus
 }
 #endif

@@ -77,6 +77,13 @@ _SIGS = {
     "cliff_tab_reset_counters": (ctypes.c_int, [_vp]),
     "cliff_ctx_profile": (ctypes.c_int, [_vp, ctypes.c_int]),
     "cliff_ctx_profile_read": (ctypes.c_int, [_vp, ctypes.c_int, ctypes.POINTER(ctypes.c_double), _u64p]),
+    "cliff_batch_work_bytes": (_sz, []),
+    "cliff_batch_run": (ctypes.c_int, [_vp, _vp, _vp, _vp, _vp, _vp, _u32, _u64, _vp, _u32, _u32]),
+    "cliff_batch_status": (ctypes.c_int, [_vp, _vp, _u64p]),
+    "cliff_graph_begin": (ctypes.c_int, [_vp]),
+    "cliff_graph_end": (ctypes.c_int, [_vp, ctypes.POINTER(_vp)]),
+    "cliff_graph_launch": (ctypes.c_int, [_vp]),
+    "cliff_graph_destroy": (ctypes.c_int, [_vp]),
 }
 
 for _name, (_res, _args) in _SIGS.items():
@@ -266,7 +273,48 @@ def cliff_ctx_profile_read(ctx, kind):
     return float(ms.value), int(n.value)
 
 
+BATCH_DESC_DTYPE = np.dtype([("n", np.uint32), ("depth", np.uint32), ("shots", np.uint32),
+                             ("reserved", np.uint32), ("ops_off", np.uint64), ("offs_off", np.uint64),
+                             ("out_off", np.uint64), ("circuit_id", np.uint64)])
+BATCH_CONFIGS = ((64, 64), (128, 64), (64, 128), (128, 128), (256, 128), (128, 256), (256, 256),
+                 (512, 256))
+
+
+def cliff_batch_work_bytes() -> int:
+    return int(_lib.cliff_batch_work_bytes())
+
+
+def cliff_batch_run(ctx, descs_ptr, ops_ptr, offs_ptr, out_ptr, order_ptr, count, seed, work_ptr,
+                    team, maxn):
+    _check(_lib.cliff_batch_run(ctx, descs_ptr, ops_ptr, offs_ptr, out_ptr, order_ptr, count, seed,
+                                work_ptr, team, maxn), "cliff_batch_run")
+
+
+def cliff_batch_status(ctx, work_ptr):
+    out = np.zeros(2, np.uint64)
+    _check(_lib.cliff_batch_status(ctx, work_ptr, _ptr(out, _u64p)), "cliff_batch_status")
+    return dict(rejected=int(out[0]), anomalies=int(out[1]))
+
+
+def cliff_graph_begin(ctx):
+    _check(_lib.cliff_graph_begin(ctx), "cliff_graph_begin")
+
+
+def cliff_graph_end(ctx):
+    out = _vp()
+    _check(_lib.cliff_graph_end(ctx, ctypes.byref(out)), "cliff_graph_end")
+    return out
+
+
+def cliff_graph_launch(graph):
+    _check(_lib.cliff_graph_launch(graph), "cliff_graph_launch")
+
+
+def cliff_graph_destroy(graph):
+    _check(_lib.cliff_graph_destroy(graph), "cliff_graph_destroy")
+
+
 __all__ = [n for n in list(globals()) if n.startswith("cliff_")] + [
     "CLIFF_OK", "CLIFF_EINVAL", "CLIFF_ENOMEM", "CLIFF_EDEVICE", "CLIFF_EBUSY",
     "CLIFF_EINTERNAL", "OP_H", "OP_S", "OP_CNOT", "CliffError", "LIB_PATH", "exported_symbols",
-    "PROF_KINDS"]
+    "PROF_KINDS", "BATCH_DESC_DTYPE", "BATCH_CONFIGS"]

@@ -637,3 +637,98 @@ extern "C" int cliff_tab_reset_counters(cliff_tab *t) {
   HIP_TRY(launch_clear_state(t->dev, t->ctx->stream));
   return CLIFF_OK;
 }
+
+// ------------------------------------------------------------------ batch ---
+
+static_assert(sizeof(cliff_batch_desc) == 48, "descriptor layout");
+
+extern "C" size_t cliff_batch_work_bytes(void) { return 256; }
+
+extern "C" int cliff_batch_run(cliff_ctx *c, const cliff_batch_desc *dev_descs,
+                               const uint64_t *dev_ops, const uint32_t *dev_offs, uint8_t *dev_out,
+                               const uint32_t *dev_order, uint32_t count, uint64_t seed,
+                               void *dev_work, uint32_t team, uint32_t maxn) {
+  if (!c || !dev_work || (count && (!dev_descs || !dev_ops || !dev_offs || !dev_out || !dev_order)))
+    return fail(CLIFF_EINVAL, "cliff_batch_run: NULL argument");
+  if (count == 0) return CLIFF_OK;
+  DeviceGuard g(c->device);
+  c->prof.begin(PK_BATCH, c->stream);
+  hipError_t e = launch_batch(dev_descs, dev_ops, dev_offs, dev_out, dev_order, count, seed,
+                              reinterpret_cast<uint32_t *>(dev_work), team, maxn, c->num_cus, c->stream);
+  c->prof.end(PK_BATCH, c->stream);
+  if (e == hipErrorInvalidValue)
+    return fail(CLIFF_EINVAL, "cliff_batch_run: no kernel for team=%u maxn=%u", team, maxn);
+  HIP_TRY(e);
+  return CLIFF_OK;
+}
+
+extern "C" int cliff_batch_status(cliff_ctx *c, const void *dev_work, uint64_t *out2) {
+  if (!c || !dev_work || !out2) return fail(CLIFF_EINVAL, "cliff_batch_status: NULL argument");
+  DeviceGuard g(c->device);
+  uint32_t v[4];
+  HIP_TRY(hipMemcpyAsync(v, dev_work, sizeof v, hipMemcpyDeviceToHost, c->stream));
+  HIP_TRY(hipStreamSynchronize(c->stream));
+  out2[0] = v[1];
+  out2[1] = v[2];
+  return CLIFF_OK;
+}
+
+// ------------------------------------------------------------------ graphs ---
+
+struct cliff_graph {
+  int device = 0;
+  hipStream_t stream = nullptr;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+};
+
+extern "C" int cliff_graph_begin(cliff_ctx *c) {
+  if (!c) return fail(CLIFF_EINVAL, "cliff_graph_begin: NULL context");
+  if (!c->stream) return fail(CLIFF_EINVAL, "cliff_graph_begin: the default stream cannot be captured");
+  DeviceGuard g(c->device);
+  HIP_TRY(hipStreamBeginCapture(c->stream, hipStreamCaptureModeThreadLocal));
+  return CLIFF_OK;
+}
+
+extern "C" int cliff_graph_end(cliff_ctx *c, cliff_graph **out) {
+  if (!c || !out) return fail(CLIFF_EINVAL, "cliff_graph_end: NULL argument");
+  *out = nullptr;
+  DeviceGuard g(c->device);
+  hipGraph_t graph = nullptr;
+  HIP_TRY(hipStreamEndCapture(c->stream, &graph));
+  hipGraphExec_t exec = nullptr;
+  hipError_t e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+  if (e != hipSuccess) {
+    (void)hipGraphDestroy(graph);
+    return fail(CLIFF_EDEVICE, "hipGraphInstantiate: %s", hipGetErrorString(e));
+  }
+  cliff_graph *gr = new (std::nothrow) cliff_graph();
+  if (!gr) {
+    (void)hipGraphExecDestroy(exec);
+    (void)hipGraphDestroy(graph);
+    return fail(CLIFF_ENOMEM, "cliff_graph_end: host allocation failed");
+  }
+  gr->device = c->device;
+  gr->stream = c->stream;
+  gr->graph = graph;
+  gr->exec = exec;
+  *out = gr;
+  return CLIFF_OK;
+}
+
+extern "C" int cliff_graph_launch(cliff_graph *gr) {
+  if (!gr) return fail(CLIFF_EINVAL, "cliff_graph_launch: NULL graph");
+  DeviceGuard g(gr->device);
+  HIP_TRY(hipGraphLaunch(gr->exec, gr->stream));
+  return CLIFF_OK;
+}
+
+extern "C" int cliff_graph_destroy(cliff_graph *gr) {
+  if (!gr) return CLIFF_OK;
+  DeviceGuard g(gr->device);
+  (void)hipStreamSynchronize(gr->stream);
+  if (gr->exec) (void)hipGraphExecDestroy(gr->exec);
+  if (gr->graph) (void)hipGraphDestroy(gr->graph);
+  delete gr;
+  return CLIFF_OK;
+}

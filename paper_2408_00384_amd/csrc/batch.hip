@@ -1,0 +1,318 @@
+// Batched circuits: one persistent launch runs thousands of independent small
+// circuits, each held entirely in LDS by one workgroup ("team").
+//
+// Per circuit (phase-space method of the paper's Sec. 2, after Aaronson &
+// Gottesman 2004): |0...0> tableau, every gate layer, then Z-measurement of
+// every qubit in ascending order for all shots at once (x/z evolve once, the
+// signs of each shot sit in their own bit column).  Rules are those of the
+// HBM path: H/S/CNOT column updates; rowsum with the phase function g counted
+// in bit-sliced mod-4 counters; smallest-pivot random branch with Philox
+// outcomes keyed by (seed; measurement, shot, circuit); deterministic branch
+// from the sign of the product of the selected stabilizers.
+//
+// Work distribution: workgroups pull circuit indices from a device counter in
+// the order given by the host (largest first), until the list is exhausted.
+// LDS layout per team: X[j][w], Z[j][w] (column-major, W <= MAXN/32 words per
+// column), signs R[w][s] (s < 64), pending gate signs, measurement scratch.
+#include "internal.h"
+#include "philox.h"
+
+namespace cliff {
+
+struct BatchDescDev {
+  uint32_t n, depth, shots, reserved;
+  uint64_t ops_off, offs_off, out_off, circuit_id;
+};
+
+template <int TEAM, int MAXN>
+__global__ void __launch_bounds__(TEAM) k_batch(const BatchDescDev *__restrict__ descs,
+                                               const uint64_t *__restrict__ ops,
+                                               const uint32_t *__restrict__ offs,
+                                               uint8_t *__restrict__ out,
+                                               const uint32_t *__restrict__ order, uint32_t count,
+                                               uint64_t seed, uint32_t *queue, uint32_t *errors) {
+  constexpr int MAXW = (2 * MAXN + 63) / 64;
+  constexpr int NWAVE = TEAM / 64;
+  __shared__ uint64_t sX[MAXN * MAXW], sZ[MAXN * MAXW];
+  __shared__ uint64_t sR[MAXW * 64];        // signs, stride 64 shots
+  __shared__ uint64_t sP[MAXW];             // gate sign flips (same for every shot)
+  __shared__ uint64_t sC0[TEAM], sC1[TEAM]; // counter slots
+  __shared__ uint32_t s_circ, s_par, s_y;
+  const uint32_t tid = threadIdx.x, lane = tid & 63;
+  const uint32_t wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+
+  for (;;) {
+    if (tid == 0) {
+      const uint32_t q = atomicAdd(queue, 1u);
+      s_circ = q < count ? order[q] : kNone;
+    }
+    __syncthreads();
+    const uint32_t ci = s_circ;
+    if (ci == kNone) return;
+    const BatchDescDev d = descs[ci];
+    const uint32_t n = d.n, S = d.shots;
+    if (n == 0 || n > uint32_t(MAXN) || S == 0 || S > 64) {
+      if (tid == 0) atomicAdd(errors, 1u);
+      __syncthreads();
+      continue;
+    }
+    const uint32_t W = (2 * n + 63) / 64;
+    const uint32_t Wl = W <= 1 ? 1u : (1u << (32 - __builtin_clz(W - 1)));   // pow2 >= W
+    // ---- |0...0>
+    for (uint32_t i = tid; i < n * W; i += TEAM) {
+      const uint32_t j = i / W, w = i % W, zr = n + j;
+      sX[i] = (w == (j >> 6)) ? (1ull << (j & 63)) : 0ull;
+      sZ[i] = (w == (zr >> 6)) ? (1ull << (zr & 63)) : 0ull;
+    }
+    for (uint32_t i = tid; i < W * 64; i += TEAM) sR[i] = 0;
+    if (tid < MAXW) sP[tid] = 0;
+    __syncthreads();
+    // ---- gate layers: thread <-> (op, word); its word is fixed, so the sign
+    // flips it produces accumulate in one register for the whole circuit
+    {
+      const uint64_t *cops = ops + d.ops_off;
+      const uint32_t *coffs = offs + d.offs_off;
+      const uint32_t w = tid % Wl, k0 = tid / Wl, kst = TEAM / Wl;
+      uint64_t racc = 0;
+      for (uint32_t l = 0; l < d.depth; ++l) {
+        const uint32_t a0 = coffs[l], a1 = coffs[l + 1];
+        if (w < W) {
+          for (uint32_t k = a0 + k0; k < a1; k += kst) {
+            const uint64_t op = cops[k];
+            const uint32_t a = uint32_t(op & kQubitMask);
+            const uint32_t bq = uint32_t((op >> kQubitBits) & kQubitMask);
+            if (a >= n || ((op & OPF_PAIR) && (bq >= n || bq == a))) {   // malformed op
+              atomicAdd(errors, 1u);
+              continue;
+            }
+            uint64_t xa = sX[a * W + w], za = sZ[a * W + w];
+            if (op & OPF_HA) { racc ^= xa & za; const uint64_t t = xa; xa = za; za = t; }
+            if (op & OPF_SA) { racc ^= xa & za; za ^= xa; }
+            if (op & OPF_PAIR) {
+              const uint32_t b = bq;
+              uint64_t xb = sX[b * W + w], zb = sZ[b * W + w];
+              if (op & OPF_HB) { racc ^= xb & zb; const uint64_t t = xb; xb = zb; zb = t; }
+              if (op & OPF_SB) { racc ^= xb & zb; zb ^= xb; }
+              racc ^= xa & zb & ~(xb ^ za);
+              xb ^= xa;
+              za ^= zb;
+              sX[b * W + w] = xb;
+              sZ[b * W + w] = zb;
+            }
+            sX[a * W + w] = xa;
+            sZ[a * W + w] = za;
+          }
+        }
+        __syncthreads();
+      }
+      if (w < W && racc) atomicXor(reinterpret_cast<unsigned long long *>(&sP[w]), (unsigned long long)racc);
+      __syncthreads();
+      for (uint32_t i = tid; i < W * 64; i += TEAM) sR[i] ^= sP[i / 64];
+      __syncthreads();
+    }
+    // ---- measure every qubit
+    const uint32_t cpw = 64 / Wl;                  // columns per wave instruction
+    const uint32_t sub = lane / Wl, wl = lane % Wl;
+    const uint32_t slots = NWAVE * cpw;            // column slots per pass
+    const uint32_t slot = wave * cpw + sub;
+    uint8_t *cout = out + d.out_off;
+    for (uint32_t a = 0; a < n; ++a) {
+      // pivot: smallest stabilizer row with x_a = 1 (every wave computes it)
+      uint32_t p = kNone;
+      {
+        uint32_t cand = kNone;
+        if (lane < W && lane >= (n >> 6)) {
+          uint64_t v = sX[a * W + lane];
+          if (lane == (n >> 6)) v &= ~0ull << (n & 63);
+          if (v) cand = lane * 64 + uint32_t(__builtin_ctzll(v));
+        }
+        for (int off = 32; off > 0; off >>= 1) cand = min(cand, uint32_t(__shfl_xor(int(cand), off)));
+        p = __builtin_amdgcn_readfirstlane(cand);
+      }
+      // update mask (random) or product-row mask T (deterministic), per lane word
+      uint64_t m = 0;
+      if (wl < W) {
+        if (p != kNone) {
+          m = sX[a * W + wl];
+          if (wl == (p >> 6)) m &= ~(1ull << (p & 63));
+        } else {
+          const uint32_t q = n >> 6, sh = n & 63;
+          auto src = [&](int32_t i) -> uint64_t {
+            if (i < 0 || i >= int32_t((n + 63) / 64)) return 0ull;
+            uint64_t v = sX[a * W + i];
+            if (uint32_t(i) == q && sh) v &= (1ull << sh) - 1;
+            return v;
+          };
+          const int32_t i = int32_t(wl) - int32_t(q);
+          m = src(i) << sh;
+          if (sh) m |= src(i - 1) >> (64 - sh);
+        }
+      }
+      // pivot signs of every shot, read before any update
+      uint64_t rpw = 0;   // bit s = r_p of shot s (wave-uniform)
+      if (p != kNone) {
+        const uint32_t b = lane < S ? uint32_t(sR[(p >> 6) * 64 + lane] >> (p & 63)) & 1u : 0u;
+        rpw = __ballot(b);
+      }
+      if (tid == 0) { s_par = 0; s_y = 0; }
+      __syncthreads();   // everyone has column a and r_p before any write
+      if (p != kNone) {
+        const uint32_t pn = p - n, wpn = pn >> 6, wp = p >> 6;
+        const uint64_t bpn = 1ull << (pn & 63), bpb = 1ull << (p & 63);
+        uint64_t c0 = 0, c1 = 0;
+        if (wl < W) {
+          for (uint32_t j = slot; j < n; j += slots) {
+            const uint32_t xpj = uint32_t(sX[j * W + wp] >> (p & 63)) & 1u;
+            const uint32_t zpj = uint32_t(sZ[j * W + wp] >> (p & 63)) & 1u;
+            const uint64_t x = sX[j * W + wl], z = sZ[j * W + wl];
+            const uint64_t X1 = xpj ? ~0ull : 0ull, Z1 = zpj ? ~0ull : 0ull;
+            const uint64_t yc = X1 & Z1, xc = X1 & ~Z1, zc = ~X1 & Z1;
+            const uint64_t plus = ((yc & z & ~x) | (xc & z & x) | (zc & x & ~z)) & m;
+            const uint64_t minus = ((yc & x & ~z) | (xc & z & ~x) | (zc & x & z)) & m;
+            c1 ^= c0 & plus;
+            c0 ^= plus;
+            c1 ^= ~c0 & minus;
+            c0 ^= minus;
+            uint64_t nx = x ^ (X1 & m), nz = z ^ (Z1 & m);
+            if (wl == wpn) {
+              nx = xpj ? (nx | bpn) : (nx & ~bpn);
+              nz = zpj ? (nz | bpn) : (nz & ~bpn);
+            }
+            if (wl == wp) {
+              nx &= ~bpb;
+              nz = (j == a) ? (nz | bpb) : (nz & ~bpb);
+            }
+            sX[j * W + wl] = nx;
+            sZ[j * W + wl] = nz;
+          }
+        }
+        sC0[tid] = c0;
+        sC1[tid] = c1;
+        __syncthreads();
+        // reduce counters per word (wave 0), then update the signs of all shots
+        if (wave == 0) {
+          uint64_t t0 = 0, t1 = 0;
+          if (lane < Wl && lane < W) {
+            for (uint32_t sl = 0; sl < slots; ++sl) {
+              const uint32_t th = (sl / cpw) * 64 + (sl % cpw) * Wl + lane;
+              const uint64_t b0 = sC0[th], b1 = sC1[th];
+              t1 ^= b1 ^ (t0 & b0);
+              t0 ^= b0;
+            }
+          }
+          // one lane per shot; word values via shuffles
+          for (uint32_t w = 0; w < W; ++w) {
+            const uint64_t mw = __shfl(m, int(w));           // lane w holds word w
+            const uint64_t c1w = __shfl(t1, int(w));
+            if (lane < S) {
+              const uint32_t rpb = uint32_t(rpw >> lane) & 1u;
+              uint64_t rv = sR[w * 64 + lane];
+              rv ^= mw & (c1w ^ (rpb ? ~0ull : 0ull));
+              if (w == wpn) rv = rpb ? (rv | bpn) : (rv & ~bpn);
+              if (w == wp) {
+                const uint32_t o = outcome_bit(seed, d.circuit_id, lane, a);
+                rv = o ? (rv | bpb) : (rv & ~bpb);
+                cout[size_t(lane) * n + a] = uint8_t(o);
+              }
+              sR[w * 64 + lane] = rv;
+            }
+          }
+          const uint64_t bad = (lane < W) ? (t0 & m & ~(lane == wpn ? bpn : 0ull)) : 0ull;
+          if (bad) atomicAdd(errors + 1, 1u);
+        }
+      } else {
+        // deterministic: per column, pairs s < t in T with z_s x_t, and Y count
+        uint32_t par = 0, ycnt = 0;
+        for (uint32_t j = tid; j < n; j += TEAM) {
+          uint32_t carry = 0;
+          for (uint32_t w = 0; w < W; ++w) {
+            // T mask of word w: lane w of every wave holds it
+            const uint32_t q = n >> 6, sh = n & 63;
+            uint64_t Tw = 0;
+            {
+              const int32_t i = int32_t(w) - int32_t(q);
+              auto src = [&](int32_t ii) -> uint64_t {
+                if (ii < 0 || ii >= int32_t((n + 63) / 64)) return 0ull;
+                uint64_t v = sX[a * W + ii];
+                if (uint32_t(ii) == q && sh) v &= (1ull << sh) - 1;
+                return v;
+              };
+              Tw = src(i) << sh;
+              if (sh) Tw |= src(i - 1) >> (64 - sh);
+            }
+            const uint64_t xt = sX[j * W + w] & Tw, zt = sZ[j * W + w] & Tw;
+            ycnt += uint32_t(__popcll(xt & zt));
+            uint64_t pre = zt << 1;
+            pre ^= pre << 1; pre ^= pre << 2; pre ^= pre << 4;
+            pre ^= pre << 8; pre ^= pre << 16; pre ^= pre << 32;
+            par ^= (uint32_t(__popcll(xt & pre)) & 1u) ^ (carry & uint32_t(__popcll(xt)) & 1u);
+            carry ^= uint32_t(__popcll(zt)) & 1u;
+          }
+        }
+        if (par & 1u) atomicXor(&s_par, 1u);
+        if (ycnt) atomicAdd(&s_y, ycnt);
+        __syncthreads();
+        if (wave == 0) {
+          // shuffles with the whole wave active (lane w holds mask word w)
+          uint32_t rt = 0;
+          for (uint32_t w = 0; w < W; ++w) {
+            const uint64_t Tw = __shfl(m, int(w));
+            if (lane < S) rt ^= uint32_t(__popcll(Tw & sR[w * 64 + lane])) & 1u;
+          }
+          if (lane < S) cout[size_t(lane) * n + a] = uint8_t(rt ^ (s_par & 1u) ^ ((s_y >> 1) & 1u));
+        }
+        if (wave == 0 && lane == 0 && (s_y & 1u)) atomicAdd(errors + 1, 1u);
+      }
+      __syncthreads();
+    }
+  }
+}
+
+template <int TEAM, int MAXN>
+static hipError_t launch_batch_t(const BatchDescDev *descs, const uint64_t *ops, const uint32_t *offs,
+                                 uint8_t *out, const uint32_t *order, uint32_t count, uint64_t seed,
+                                 uint32_t *queue, uint32_t *errors, uint32_t grid, hipStream_t st) {
+  k_batch<TEAM, MAXN><<<grid, TEAM, 0, st>>>(descs, ops, offs, out, order, count, seed, queue, errors);
+  return hipGetLastError();
+}
+
+// work[0] = queue head, work[1] = rejected descriptors, work[2] = anomalies
+__global__ void k_reset_queue(uint32_t *work) {
+  if (threadIdx.x < 4) work[threadIdx.x] = 0;
+}
+
+// Occupancy-limited grid for a team configuration.
+template <int TEAM, int MAXN>
+static uint32_t batch_grid(int num_cus) {
+  int per = 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k_batch<TEAM, MAXN>, TEAM, 0) != hipSuccess ||
+      per < 1)
+    per = 1;
+  return uint32_t(per) * uint32_t(num_cus);
+}
+
+hipError_t launch_batch(const void *descs, const uint64_t *ops, const uint32_t *offs, uint8_t *out,
+                        const uint32_t *order, uint32_t count, uint64_t seed, uint32_t *work,
+                        uint32_t team, uint32_t maxn, int num_cus, hipStream_t st) {
+  const BatchDescDev *d = reinterpret_cast<const BatchDescDev *>(descs);
+  k_reset_queue<<<1, 64, 0, st>>>(work);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  uint32_t *q = work, *err = work + 1;
+#define CLIFF_BATCH_CASE(T_, N_)                                                              \
+  if (team == T_ && maxn == N_)                                                               \
+    return launch_batch_t<T_, N_>(d, ops, offs, out, order, count, seed, q, err,              \
+                                  batch_grid<T_, N_>(num_cus), st);
+  CLIFF_BATCH_CASE(64, 64)
+  CLIFF_BATCH_CASE(128, 64)
+  CLIFF_BATCH_CASE(64, 128)
+  CLIFF_BATCH_CASE(128, 128)
+  CLIFF_BATCH_CASE(256, 128)
+  CLIFF_BATCH_CASE(128, 256)
+  CLIFF_BATCH_CASE(256, 256)
+  CLIFF_BATCH_CASE(512, 256)
+#undef CLIFF_BATCH_CASE
+  return hipErrorInvalidValue;
+}
+
+}  // namespace cliff

@@ -175,6 +175,9 @@ hipError_t launch_measure_list(const TabDev &t, const uint32_t *qubits, uint32_t
                                uint64_t circuit, uint64_t shot0, uint64_t m0, hipStream_t st,
                                Profiler *prof);
 hipError_t launch_clear_state(const TabDev &t, hipStream_t st);
+hipError_t launch_batch(const void *descs, const uint64_t *ops, const uint32_t *offs, uint8_t *out,
+                        const uint32_t *order, uint32_t count, uint64_t seed, uint32_t *work,
+                        uint32_t team, uint32_t maxn, int num_cus, hipStream_t st);
 hipError_t launch_copy_tab(const TabDev &dst, const TabDev &src, hipStream_t st);
 
 }  // namespace cliff

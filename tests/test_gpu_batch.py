@@ -1,0 +1,107 @@
+"""Batched persistent kernel vs the CPU oracle (bit-exact outcome bytes)."""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from inputs import batch_circuit, layered_circuit
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    from paper_2408_00384_amd import Context
+    stream = torch.cuda.Stream()
+    c = Context(0, stream)
+    yield c
+    c.close()
+
+
+def _mixed_circuits(count=36, seed=7):
+    rng = np.random.default_rng(seed)
+    ns = list(rng.integers(1, 257, size=count - 8)) + [1, 2, 31, 32, 33, 64, 65, 256]
+    out = []
+    for i, n in enumerate(ns):
+        n = int(n)
+        depth = int(rng.integers(0, 12))
+        shots = int(rng.choice([1, 3, 4, 17, 64]))
+        out.append(layered_circuit(n, depth, shots, gen_seed=[seed, i], circuit_id=1000 + i))
+    return out
+
+
+def _check(circs, outs):
+    for c, o in zip(circs, outs):
+        for s in range(c.shots):
+            ref, _ = oracle.run_shot(c, s)
+            assert np.array_equal(o[s], ref), "circuit %d (n=%d) shot %d" % (c.circuit_id, c.n, s)
+
+
+def test_batch_matches_oracle_default_teams(ctx):
+    from paper_2408_00384_amd.batch import BatchPlan
+    circs = _mixed_circuits()
+    with torch.cuda.stream(ctx.stream):
+        plan = BatchPlan(ctx, circs).run()
+        outs = plan.outcomes()
+    assert plan.status() == dict(rejected=0, anomalies=0)
+    _check(circs, outs)
+
+
+@pytest.mark.parametrize("cfg", [(64, 64), (128, 64), (64, 128), (128, 128), (256, 128),
+                                 (128, 256), (256, 256), (512, 256)])
+def test_every_team_config_is_bit_identical(ctx, cfg):
+    from paper_2408_00384_amd.batch import BatchPlan
+    team, maxn = cfg
+    rng = np.random.default_rng(maxn)
+    lo = {64: 1, 128: 65, 256: 129}[maxn]
+    circs = [layered_circuit(int(n), int(rng.integers(1, 8)), 4, gen_seed=[3, maxn, i], circuit_id=i)
+             for i, n in enumerate(rng.integers(lo, maxn + 1, size=6))]
+    with torch.cuda.stream(ctx.stream):
+        plan = BatchPlan(ctx, circs, teams={maxn: team}).run()
+        outs = plan.outcomes()
+    assert plan.status() == dict(rejected=0, anomalies=0)
+    _check(circs, outs)
+
+
+def test_batched_workload_sample_and_graph_replay(ctx):
+    """Circuits of the 4,096-circuit workload (n in [8, 256], depth in [n, 4n],
+    4 shots): a sample checked against the oracle, replayed from a HIP graph."""
+    from inputs import batch_sizes
+    from paper_2408_00384_amd.batch import BatchPlan
+    ns, depths = batch_sizes()
+    idx = [0, 1, 2, 3, 5, 8, 13, 21, 34, 55, 89, 144]
+    circs = [batch_circuit(i, ns, depths) for i in idx]
+    with torch.cuda.stream(ctx.stream):
+        plan = BatchPlan(ctx, circs).capture()
+        outs = []
+        for rep in range(3):
+            plan.d_out.zero_()
+            torch.cuda.current_stream().synchronize()
+            plan.run()
+            outs.append(plan.outcomes())
+    for rep in (1, 2):
+        assert all(np.array_equal(a, b) for a, b in zip(outs[0], outs[rep]))
+    assert plan.status() == dict(rejected=0, anomalies=0)
+    _check(circs, outs[0])
+    plan.close()
+
+
+def test_rejects_oversized_descriptors(ctx):
+    from paper_2408_00384_amd import _binding as B
+    from paper_2408_00384_amd.batch import BatchPlan
+    circs = [layered_circuit(100, 2, 2, gen_seed=1, circuit_id=0),
+             layered_circuit(20, 2, 2, gen_seed=2, circuit_id=1)]
+    with torch.cuda.stream(ctx.stream):
+        plan = BatchPlan(ctx, circs)
+        order = torch.tensor([0, 1], dtype=torch.int32, device="cuda:0")
+        torch.cuda.synchronize()
+        B.cliff_batch_run(ctx.handle, plan.d_descs.data_ptr(), plan.d_ops.data_ptr(),
+                          plan.d_offs.data_ptr(), plan.d_out.data_ptr(), order.data_ptr(), 2,
+                          plan.seed, plan.d_work.data_ptr(), 64, 64)
+        st = B.cliff_batch_status(ctx.handle, plan.d_work.data_ptr())
+    assert st["rejected"] == 1
+    out = plan.d_out.cpu().numpy()
+    d = plan.descs[1]
+    got = out[int(d["out_off"]): int(d["out_off"]) + 2 * 20].reshape(2, 20)
+    for s in range(2):
+        assert np.array_equal(got[s], oracle.run_shot(circs[1], s)[0])
