@@ -139,6 +139,40 @@ def bench_batch(P, torch, np, count=4096, plain_sample=48, reps=5):
     }
 
 
+def bench_serving(P, np, count=96, seed=4, budget=64 << 30, lanes=8):
+    """Serving workload: n log-uniform in [16, 4096], depth 2n, shots in
+    [1, 1024], admission by tableau bytes against a 64 GB budget.  First a
+    closed-loop pass (every request admitted at once) gives the saturated
+    throughput; then Poisson arrivals at 70% of it give the latencies."""
+    from inputs import serving_params, serving_request
+    from paper_2408_00384_amd.serving import Server, summarize
+    arrivals, ns, shots = serving_params(count, 1.0, seed=seed)
+    circs = [serving_request(i, arrivals, ns, shots, seed=seed).circuit for i in range(count)]
+    srv = Server(budget_bytes=budget, lanes=lanes)
+    t0 = time.perf_counter()
+    sat = srv.run(circs, np.zeros(count), realtime=False)
+    sat_s = time.perf_counter() - t0
+    sat_rate = count / sat_s
+    rate = 0.7 * sat_rate
+    arrivals, _, _ = serving_params(count, rate, seed=seed)
+    mix = srv.run(circs, arrivals, realtime=True)
+    same = all(np.array_equal(sat[i].outcomes, mix[i].outcomes) for i in range(count)
+               if sat[i].error is None)
+    st = summarize(mix)
+    srv.close()
+    return {
+        "workload": "%d requests, n log-uniform [16, 4096], depth 2n, shots U{1..1024}, "
+                    "64 GB admission budget, %d HBM lanes + 1 batch lane" % (count, lanes),
+        "saturated_circuits_per_s": sat_rate,
+        "poisson_rate_hz": rate,
+        "p50_ms": st["p50_ms"], "p99_ms": st["p99_ms"], "mean_ms": st["mean_ms"],
+        "circuits_per_s": st["circuits_per_s"],
+        "paths": st["paths"], "rejected": st["rejected"],
+        "outcomes_same_as_closed_loop": same,
+        "max_n": int(max(ns)), "total_shots": int(sum(shots)),
+    }
+
+
 def _host_cpu():
     try:
         for line in open("/proc/cpuinfo"):
@@ -158,6 +192,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-budget", type=float, default=20.0, help="seconds of oracle work")
     ap.add_argument("--no-batch", action="store_true", help="skip the batched-circuits leg")
+    ap.add_argument("--no-serving", action="store_true", help="skip the serving leg")
     args = ap.parse_args()
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -256,6 +291,9 @@ def main():
     if not args.no_batch:
         print("# batched circuits ...", file=sys.stderr, flush=True)
         result["batched"] = bench_batch(P, torch, np)
+    if not args.no_serving:
+        print("# serving ...", file=sys.stderr, flush=True)
+        result["serving"] = bench_serving(P, np)
     if not args.no_cpu_baseline:
         print("# cpu baseline (oracle) ...", file=sys.stderr, flush=True)
         result["cpu_baseline"] = cpu_baseline(c, args.cpu_budget)

@@ -67,6 +67,15 @@ int cliff_sync(cliff_ctx *ctx);
 /* Number of compute units of the context's device. */
 int cliff_ctx_num_cus(const cliff_ctx *ctx);
 
+/* Gate-stream strategy.  AUTO: one launch for all layers when 8n bytes (32
+ * rows of every column) fit in LDS, else one launch per layer.  PER_LAYER:
+ * always one launch per layer.  FUSED: always one launch (EINVAL if n is too
+ * large).  Results are identical; only speed differs. */
+#define CLIFF_GATES_AUTO 0
+#define CLIFF_GATES_PER_LAYER 1
+#define CLIFF_GATES_FUSED 2
+int cliff_ctx_set_gate_mode(cliff_ctx *ctx, int mode);
+
 /* Bytes of device memory a tableau of n qubits with `shots` sign columns needs,
  * scratch included (X, Z, signs, measurement scratch, outcome staging). */
 size_t cliff_tab_bytes(uint32_t n, uint32_t shots);
@@ -123,6 +132,14 @@ int cliff_apply_encoded(cliff_tab *tab, const uint64_t *dev_ops, const uint32_t 
 int cliff_measure(cliff_tab *tab, const uint32_t *qubits, size_t k, uint64_t seed,
                   uint64_t circuit, uint64_t shot0, uint64_t m0, uint8_t *host_out,
                   uint8_t *host_random);
+
+/* Asynchronous form of cliff_measure for k <= n measurements: only enqueues
+ * the work on the context stream.  The outcomes stay in the tableau's device
+ * staging until cliff_tab_read_outcomes (same k, same layout as cliff_measure,
+ * synchronizes the stream) or the next measurement on this tableau. */
+int cliff_measure_async(cliff_tab *tab, const uint32_t *qubits, size_t k, uint64_t seed,
+                        uint64_t circuit, uint64_t shot0, uint64_t m0);
+int cliff_tab_read_outcomes(cliff_tab *tab, size_t k, uint8_t *host_out, uint8_t *host_random);
 
 /* Sampling without disturbing the state: copy `tab` into `work` (bound with
  * the same n and at least `shots` sign columns; every sign column of work

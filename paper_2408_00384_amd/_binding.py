@@ -58,6 +58,7 @@ _SIGS = {
     "cliff_ctx_destroy": (ctypes.c_int, [_vp]),
     "cliff_sync": (ctypes.c_int, [_vp]),
     "cliff_ctx_num_cus": (ctypes.c_int, [_vp]),
+    "cliff_ctx_set_gate_mode": (ctypes.c_int, [_vp, ctypes.c_int]),
     "cliff_tab_bytes": (_sz, [_u32, _u32]),
     "cliff_tab_bind": (ctypes.c_int, [_vp, _u32, _u32, _vp, _sz, ctypes.POINTER(_vp)]),
     "cliff_tab_unbind": (ctypes.c_int, [_vp]),
@@ -70,6 +71,8 @@ _SIGS = {
     "cliff_apply_encoded": (ctypes.c_int, [_vp, _vp, _u32p, _u32]),
     "cliff_measure": (ctypes.c_int, [_vp, _u32p, _sz, _u64, _u64, _u64, _u64, _u8p, _u8p]),
     "cliff_sample": (ctypes.c_int, [_vp, _vp, _u32p, _sz, _u64, _u64, _u64, _u8p, _u8p]),
+    "cliff_measure_async": (ctypes.c_int, [_vp, _u32p, _sz, _u64, _u64, _u64, _u64]),
+    "cliff_tab_read_outcomes": (ctypes.c_int, [_vp, _sz, _u8p, _u8p]),
     "cliff_tab_export": (ctypes.c_int, [_vp, _u8p, _u8p, _u8p]),
     "cliff_tab_import": (ctypes.c_int, [_vp, _u8p, _u8p, _u8p]),
     "cliff_tab_anomalies": (ctypes.c_int, [_vp, _u64p]),
@@ -136,6 +139,13 @@ def cliff_sync(ctx):
 
 def cliff_ctx_num_cus(ctx) -> int:
     return int(_lib.cliff_ctx_num_cus(ctx))
+
+
+GATES_AUTO, GATES_PER_LAYER, GATES_FUSED = 0, 1, 2
+
+
+def cliff_ctx_set_gate_mode(ctx, mode: int):
+    _check(_lib.cliff_ctx_set_gate_mode(ctx, mode), "cliff_ctx_set_gate_mode")
 
 
 def cliff_tab_bytes(n: int, shots: int) -> int:
@@ -208,6 +218,21 @@ def cliff_measure(tab, qubits, seed=0, circuit=0, shot0=0, m0=0, want_out=True):
     rnd = np.zeros(len(q), np.uint8)
     _check(_lib.cliff_measure(tab, _ptr(q, _u32p), len(q), seed, circuit, shot0, m0,
                               _ptr(out, _u8p), _ptr(rnd, _u8p)), "cliff_measure")
+    return out, rnd
+
+
+def cliff_measure_async(tab, qubits, seed=0, circuit=0, shot0=0, m0=0):
+    q = _arr(qubits, np.uint32)
+    _check(_lib.cliff_measure_async(tab, _ptr(q, _u32p), len(q), seed, circuit, shot0, m0),
+           "cliff_measure_async")
+
+
+def cliff_tab_read_outcomes(tab, k):
+    _, shots = cliff_tab_info(tab)
+    out = np.zeros((shots, k), np.uint8)
+    rnd = np.zeros(k, np.uint8)
+    _check(_lib.cliff_tab_read_outcomes(tab, k, _ptr(out, _u8p), _ptr(rnd, _u8p)),
+           "cliff_tab_read_outcomes")
     return out, rnd
 
 
@@ -317,4 +342,5 @@ def cliff_graph_destroy(graph):
 __all__ = [n for n in list(globals()) if n.startswith("cliff_")] + [
     "CLIFF_OK", "CLIFF_EINVAL", "CLIFF_ENOMEM", "CLIFF_EDEVICE", "CLIFF_EBUSY",
     "CLIFF_EINTERNAL", "OP_H", "OP_S", "OP_CNOT", "CliffError", "LIB_PATH", "exported_symbols",
-    "PROF_KINDS", "BATCH_DESC_DTYPE", "BATCH_CONFIGS"]
+    "PROF_KINDS", "BATCH_DESC_DTYPE", "BATCH_CONFIGS", "GATES_AUTO", "GATES_PER_LAYER",
+    "GATES_FUSED"]

@@ -97,8 +97,11 @@ class BatchPlan:
         self.d_work = torch.zeros(self.work_stride * max(1, len(self.buckets)), dtype=torch.uint8,
                                   device=device)
         self.graph = None
-        # uploads ran on torch's stream; the batch kernels run on the context's
-        torch.cuda.synchronize()
+        # uploads ran on torch's current stream; the batch kernels run on the
+        # context's stream, which waits for them (no device-wide sync)
+        cur = torch.cuda.current_stream()
+        if cur != ctx.stream:
+            ctx.stream.wait_stream(cur)
 
     def launch(self):
         """Enqueue every bucket on the context stream (no host sync)."""
@@ -135,7 +138,8 @@ class BatchPlan:
     def outcomes(self):
         """List of uint8 [shots, n] outcome arrays, one per circuit (synchronizes)."""
         self.ctx.sync()
-        host = self.d_out.cpu().numpy()
+        with torch.cuda.stream(self.ctx.stream):   # copy on this plan's stream only
+            host = self.d_out.cpu().numpy()
         res = []
         for d in self.descs:
             o, s, n = int(d["out_off"]), int(d["shots"]), int(d["n"])

@@ -122,6 +122,7 @@ struct cliff_ctx {
   size_t pinned_cap = 0;         // words
   hipEvent_t upload_done = nullptr;
   bool upload_pending = false;
+  int gate_mode = CLIFF_GATES_AUTO;
 };
 
 struct cliff_tab {
@@ -196,6 +197,14 @@ int cliff_sync(cliff_ctx *c) {
 }
 
 int cliff_ctx_num_cus(const cliff_ctx *c) { return c ? c->num_cus : 0; }
+
+int cliff_ctx_set_gate_mode(cliff_ctx *c, int mode) {
+  if (!c) return fail(CLIFF_EINVAL, "cliff_ctx_set_gate_mode: NULL context");
+  if (mode < CLIFF_GATES_AUTO || mode > CLIFF_GATES_FUSED)
+    return fail(CLIFF_EINVAL, "cliff_ctx_set_gate_mode: bad mode %d", mode);
+  c->gate_mode = mode;
+  return CLIFF_OK;
+}
 
 size_t cliff_tab_bytes(uint32_t n, uint32_t shots) {
   if (n == 0 || shots == 0 || n > kMaxQubits) return 0;
@@ -352,9 +361,12 @@ extern "C" int cliff_encode_layers(uint32_t n, const uint8_t *h, const uint8_t *
   return CLIFF_OK;
 }
 
-// Upload ops to the context's device buffer (stream-ordered).
-static int upload_ops(cliff_ctx *c, const std::vector<uint64_t> &ops) {
-  const size_t words = ops.size();
+// Upload [ops | layer offsets] to the context's device buffer (stream-ordered).
+// Returns device pointers to both parts.
+static int upload_stream(cliff_ctx *c, const uint64_t *ops, size_t nops, const uint32_t *offs,
+                         size_t noffs, const uint64_t **dev_ops, const uint32_t **dev_offs) {
+  const size_t offs_words = (noffs + 1) / 2;
+  const size_t words = nops + offs_words;
   if (words == 0) return CLIFF_OK;
   if (c->upload_pending) {
     HIP_TRY(hipEventSynchronize(c->upload_done));
@@ -377,20 +389,42 @@ static int upload_ops(cliff_ctx *c, const std::vector<uint64_t> &ops) {
     HIP_TRY(hipHostMalloc(reinterpret_cast<void **>(&c->pinned), cap * 8, hipHostMallocDefault));
     c->pinned_cap = cap;
   }
-  memcpy(c->pinned, ops.data(), words * 8);
+  if (nops) memcpy(c->pinned, ops, nops * 8);
+  if (noffs) {
+    c->pinned[nops + offs_words - 1] = 0;
+    memcpy(c->pinned + nops, offs, noffs * 4);
+  }
   HIP_TRY(hipMemcpyAsync(c->dev_ops, c->pinned, words * 8, hipMemcpyHostToDevice, c->stream));
   HIP_TRY(hipEventRecord(c->upload_done, c->stream));
   c->upload_pending = true;
+  if (dev_ops) *dev_ops = c->dev_ops;
+  if (dev_offs) *dev_offs = reinterpret_cast<const uint32_t *>(c->dev_ops + nops);
   return CLIFF_OK;
 }
 
-static int run_encoded(cliff_tab *t, const uint64_t *dev_ops, const uint32_t *offs, uint32_t depth) {
+// Run an encoded gate stream: all layers in one launch when the 32-row LDS
+// slice of every column fits, otherwise one launch per layer.
+static int run_encoded(cliff_tab *t, const uint64_t *dev_ops, const uint32_t *host_offs,
+                       const uint32_t *dev_offs, uint32_t depth) {
+  for (uint32_t l = 0; l < depth; ++l)
+    if (host_offs[l + 1] < host_offs[l])
+      return fail(CLIFF_EINVAL, "layer offsets decrease at layer %u", l);
+  hipStream_t st = t->ctx->stream;
+  const int mode = t->ctx->gate_mode;
+  if (mode == CLIFF_GATES_FUSED && !(dev_offs && fused_gates_fit(t->d.n)))
+    return fail(CLIFF_EINVAL, "fused gates need 8n <= %zu bytes of LDS (n = %u)", kFusedGateLds, t->d.n);
+  if (mode != CLIFF_GATES_PER_LAYER && dev_offs && fused_gates_fit(t->d.n)) {
+    t->ctx->prof.begin(PK_GATE, st);
+    hipError_t e = launch_gates_fused(t->dev, dev_ops, dev_offs, depth, st);
+    t->ctx->prof.end(PK_GATE, st);
+    HIP_TRY(e);
+    return CLIFF_OK;
+  }
   for (uint32_t l = 0; l < depth; ++l) {
-    const uint32_t a = offs[l], b = offs[l + 1];
-    if (b < a) return fail(CLIFF_EINVAL, "layer offsets decrease at layer %u", l);
-    t->ctx->prof.begin(PK_GATE, t->ctx->stream);
-    hipError_t e = launch_gate_layer(t->dev, dev_ops + a, b - a, t->ctx->stream);
-    t->ctx->prof.end(PK_GATE, t->ctx->stream);
+    const uint32_t a = host_offs[l], b = host_offs[l + 1];
+    t->ctx->prof.begin(PK_GATE, st);
+    hipError_t e = launch_gate_layer(t->dev, dev_ops + a, b - a, st);
+    t->ctx->prof.end(PK_GATE, st);
     HIP_TRY(e);
   }
   return CLIFF_OK;
@@ -409,16 +443,24 @@ extern "C" int cliff_apply_layers(cliff_tab *t, const uint8_t *h, const uint8_t 
   rc = cliff_encode_layers(t->d.n, h, s, ctrl, tgt, npairs, depth, ops.data(), nops, offs.data(), &nops);
   if (rc) return rc;
   DeviceGuard g(t->ctx->device);
-  rc = upload_ops(t->ctx, ops);
+  const uint64_t *dops = nullptr;
+  const uint32_t *doffs = nullptr;
+  rc = upload_stream(t->ctx, ops.data(), ops.size(), offs.data(), offs.size(), &dops, &doffs);
   if (rc) return rc;
-  return run_encoded(t, t->ctx->dev_ops, offs.data(), depth);
+  return run_encoded(t, dops, offs.data(), doffs, depth);
 }
 
 extern "C" int cliff_apply_encoded(cliff_tab *t, const uint64_t *dev_ops, const uint32_t *offs,
                                    uint32_t depth) {
   if (!t || !offs || (!dev_ops && depth)) return fail(CLIFF_EINVAL, "cliff_apply_encoded: NULL argument");
+  if (depth == 0) return CLIFF_OK;
   DeviceGuard g(t->ctx->device);
-  return run_encoded(t, dev_ops, offs, depth);
+  const uint32_t *doffs = nullptr;
+  if (fused_gates_fit(t->d.n) && t->ctx->gate_mode != CLIFF_GATES_PER_LAYER) {
+    int rc = upload_stream(t->ctx, nullptr, 0, offs, size_t(depth) + 1, nullptr, &doffs);
+    if (rc) return rc;
+  }
+  return run_encoded(t, dev_ops, offs, doffs, depth);
 }
 
 extern "C" int cliff_apply_gates(cliff_tab *t, const uint8_t *op, const uint32_t *a,
@@ -456,21 +498,14 @@ extern "C" int cliff_apply_gates(cliff_tab *t, const uint8_t *op, const uint32_t
   }
   offs.push_back(uint32_t(ops.size()));
   DeviceGuard g(t->ctx->device);
-  int rc = upload_ops(t->ctx, ops);
+  const uint64_t *dops = nullptr;
+  const uint32_t *doffs = nullptr;
+  int rc = upload_stream(t->ctx, ops.data(), ops.size(), offs.data(), offs.size(), &dops, &doffs);
   if (rc) return rc;
-  return run_encoded(t, t->ctx->dev_ops, offs.data(), uint32_t(offs.size() - 1));
+  return run_encoded(t, dops, offs.data(), doffs, uint32_t(offs.size() - 1));
 }
 
 // ---------------------------------------------------------------- measure ---
-
-static bool use_v1_path() {
-  static int v = -1;
-  if (v < 0) {
-    const char *e = getenv("CLIFF_MEASURE_V1");
-    v = (e && e[0] == '1') ? 1 : 0;
-  }
-  return v == 1;
-}
 
 static int measure_impl(cliff_tab *t, const uint32_t *qubits, size_t k, uint64_t seed,
                         uint64_t circuit, uint64_t shot0, uint64_t m0, uint8_t *host_out,
@@ -486,14 +521,8 @@ static int measure_impl(cliff_tab *t, const uint32_t *qubits, size_t k, uint64_t
   std::vector<uint8_t> out_stage, kind_stage;
   for (size_t base = 0; base < k; base += n) {
     const size_t cnt = std::min<size_t>(n, k - base);
-    if (use_v1_path()) {
-      for (size_t i = 0; i < cnt; ++i)
-        HIP_TRY(launch_measure_one(t->dev, qubits[base + i], uint32_t(i), seed, circuit, shot0,
-                                   m0 + base + i, st, &t->ctx->prof));
-    } else {
-      HIP_TRY(launch_measure_list(t->dev, qubits + base, uint32_t(cnt), seed, circuit, shot0,
-                                  m0 + base, st, &t->ctx->prof));
-    }
+    HIP_TRY(launch_measure_list(t->dev, qubits + base, uint32_t(cnt), seed, circuit, shot0,
+                                m0 + base, st, &t->ctx->prof));
     if (host_out || host_random) {
       out_stage.resize(cnt * S);
       kind_stage.resize(cnt);
@@ -517,6 +546,35 @@ extern "C" int cliff_measure(cliff_tab *t, const uint32_t *qubits, size_t k, uin
   if (!qubits) return fail(CLIFF_EINVAL, "cliff_measure: NULL qubits");
   DeviceGuard g(t->ctx->device);
   return measure_impl(t, qubits, k, seed, circuit, shot0, m0, host_out, host_random);
+}
+
+extern "C" int cliff_measure_async(cliff_tab *t, const uint32_t *qubits, size_t k, uint64_t seed,
+                                   uint64_t circuit, uint64_t shot0, uint64_t m0) {
+  if (!t) return fail(CLIFF_EINVAL, "cliff_measure_async: NULL tableau");
+  if (k == 0) return CLIFF_OK;
+  if (!qubits) return fail(CLIFF_EINVAL, "cliff_measure_async: NULL qubits");
+  if (k > t->d.n) return fail(CLIFF_EINVAL, "cliff_measure_async: k = %zu > n = %u", k, t->d.n);
+  DeviceGuard g(t->ctx->device);
+  return measure_impl(t, qubits, k, seed, circuit, shot0, m0, nullptr, nullptr);
+}
+
+extern "C" int cliff_tab_read_outcomes(cliff_tab *t, size_t k, uint8_t *host_out,
+                                       uint8_t *host_random) {
+  if (!t) return fail(CLIFF_EINVAL, "cliff_tab_read_outcomes: NULL tableau");
+  if (k > t->d.n) return fail(CLIFF_EINVAL, "cliff_tab_read_outcomes: k = %zu > n = %u", k, t->d.n);
+  if (k == 0) return CLIFF_OK;
+  DeviceGuard g(t->ctx->device);
+  const uint32_t S = t->d.S;
+  hipStream_t st = t->ctx->stream;
+  std::vector<uint8_t> out_stage(k * S), kind_stage(k);
+  HIP_TRY(hipMemcpyAsync(out_stage.data(), t->dev.out, k * S, hipMemcpyDeviceToHost, st));
+  HIP_TRY(hipMemcpyAsync(kind_stage.data(), t->dev.kind, k, hipMemcpyDeviceToHost, st));
+  HIP_TRY(hipStreamSynchronize(st));
+  if (host_out)
+    for (size_t i = 0; i < k; ++i)
+      for (uint32_t s = 0; s < S; ++s) host_out[size_t(s) * k + i] = out_stage[i * S + s];
+  if (host_random) memcpy(host_random, kind_stage.data(), k);
+  return CLIFF_OK;
 }
 
 extern "C" int cliff_sample(cliff_tab *t, cliff_tab *work, const uint32_t *qubits, size_t k,

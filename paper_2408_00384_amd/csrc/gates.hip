@@ -63,13 +63,15 @@ __global__ void __launch_bounds__(256) k_gate_layer(TabDev t, const uint64_t *__
   for (uint32_t o = o0 + wave; o < o1; o += 4) {
     const uint64_t op = ops[o];
     const uint32_t a = uint32_t(op & kQubitMask);
+    const uint32_t bq = uint32_t((op >> kQubitBits) & kQubitMask);
+    if (a >= t.n || ((op & OPF_PAIR) && (bq >= t.n || bq == a))) continue;   // malformed op
     uint64_t *pxa = t.X + a * Wp + w;
     uint64_t *pza = t.Z + a * Wp + w;
     uint64_t xa = *pxa, za = *pza;
     if (op & OPF_HA) { racc ^= xa & za; const uint64_t tmp = xa; xa = za; za = tmp; }
     if (op & OPF_SA) { racc ^= xa & za; za ^= xa; }
     if (op & OPF_PAIR) {
-      const uint32_t b = uint32_t((op >> kQubitBits) & kQubitMask);
+      const uint32_t b = bq;
       uint64_t *pxb = t.X + b * Wp + w;
       uint64_t *pzb = t.Z + b * Wp + w;
       uint64_t xb = *pxb, zb = *pzb;
@@ -85,6 +87,70 @@ __global__ void __launch_bounds__(256) k_gate_layer(TabDev t, const uint64_t *__
     *pza = za;
   }
   if (racc) atomicXor(reinterpret_cast<unsigned long long *>(t.P + w), (unsigned long long)racc);
+}
+
+// All layers of a gate stream in one launch.  Gates act row by row, so a
+// workgroup that owns 32 rows (one half of a 64-row word) of every column can
+// apply every layer to them without talking to any other workgroup: it loads
+// its half-words of X and Z into LDS (8n bytes), runs the layers with a
+// workgroup barrier between consecutive layers, and writes them back once.
+// Its sign flips stay in registers and land in its own half of P.
+__global__ void __launch_bounds__(256) k_gates_fused(TabDev t, const uint64_t *__restrict__ ops,
+                                                     const uint32_t *__restrict__ offs, uint32_t depth) {
+  extern __shared__ uint32_t lds_u32[];
+  const uint32_t n = t.n;
+  uint32_t *sx = lds_u32, *sz = lds_u32 + n;
+  __shared__ uint32_t s_r;
+  const uint32_t h = blockIdx.x;                  // half-word index: rows 32h .. 32h+31
+  const uint32_t tid = threadIdx.x;
+  const size_t hs = size_t(t.Wp) * 2;             // column stride in half-words
+  const uint32_t *X32 = reinterpret_cast<const uint32_t *>(t.X);
+  const uint32_t *Z32 = reinterpret_cast<const uint32_t *>(t.Z);
+  for (uint32_t j = tid; j < n; j += blockDim.x) {
+    sx[j] = X32[j * hs + h];
+    sz[j] = Z32[j * hs + h];
+  }
+  if (tid == 0) s_r = 0;
+  __syncthreads();
+  uint32_t racc = 0;
+  for (uint32_t l = 0; l < depth; ++l) {
+    const uint32_t o1 = offs[l + 1];
+    for (uint32_t k = offs[l] + tid; k < o1; k += blockDim.x) {
+      const uint64_t op = ops[k];
+      const uint32_t a = uint32_t(op & kQubitMask);
+      const uint32_t bq = uint32_t((op >> kQubitBits) & kQubitMask);
+      if (a >= n || ((op & OPF_PAIR) && (bq >= n || bq == a))) continue;   // malformed op
+      uint32_t xa = sx[a], za = sz[a];
+      if (op & OPF_HA) { racc ^= xa & za; const uint32_t tmp = xa; xa = za; za = tmp; }
+      if (op & OPF_SA) { racc ^= xa & za; za ^= xa; }
+      if (op & OPF_PAIR) {
+        const uint32_t b = bq;
+        uint32_t xb = sx[b], zb = sz[b];
+        if (op & OPF_HB) { racc ^= xb & zb; const uint32_t tmp = xb; xb = zb; zb = tmp; }
+        if (op & OPF_SB) { racc ^= xb & zb; zb ^= xb; }
+        racc ^= xa & zb & ~(xb ^ za);
+        xb ^= xa;
+        za ^= zb;
+        sx[b] = xb;
+        sz[b] = zb;
+      }
+      sx[a] = xa;
+      sz[a] = za;
+    }
+    __syncthreads();
+  }
+  if (racc) atomicXor(&s_r, racc);
+  uint32_t *X32w = reinterpret_cast<uint32_t *>(t.X);
+  uint32_t *Z32w = reinterpret_cast<uint32_t *>(t.Z);
+  for (uint32_t j = tid; j < n; j += blockDim.x) {
+    X32w[j * hs + h] = sx[j];
+    Z32w[j * hs + h] = sz[j];
+  }
+  __syncthreads();
+  if (tid == 0 && s_r) {
+    uint32_t *P32 = reinterpret_cast<uint32_t *>(t.P);
+    P32[h] ^= s_r;   // this half of P belongs to this workgroup alone
+  }
 }
 
 // dst <- src with every sign column of dst set to src's column 0 (+ pending).
@@ -139,6 +205,24 @@ hipError_t launch_gate_layer(const TabDev &t, const uint64_t *ops, uint32_t nops
   while (size_t(tiles) * ((nops + per - 1) / per) > 2048 && per < 4096) per *= 2;
   dim3 grid(tiles, (nops + per - 1) / per);
   k_gate_layer<<<grid, 256, 0, st>>>(t, ops, nops, per);
+  return hipGetLastError();
+}
+
+bool fused_gates_fit(uint32_t n) { return size_t(n) * 8 <= kFusedGateLds; }
+
+hipError_t launch_gates_fused(const TabDev &t, const uint64_t *ops, const uint32_t *dev_offs,
+                              uint32_t depth, hipStream_t st) {
+  if (depth == 0) return hipSuccess;
+  const size_t lds = size_t(t.n) * 8;
+  static bool attr_set = false;
+  if (!attr_set) {
+    hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(k_gates_fused),
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, int(kFusedGateLds));
+    if (e != hipSuccess) return e;
+    attr_set = true;
+  }
+  const uint32_t halves = (2 * t.n + 31) / 32;
+  k_gates_fused<<<halves, 256, lds, st>>>(t, ops, dev_offs, depth);
   return hipGetLastError();
 }
 

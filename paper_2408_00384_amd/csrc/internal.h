@@ -8,9 +8,9 @@
 //   R      : Wp x S words; R[w*S + s] = sign bits of rows 64w.. for shot s.
 //   P      : Wp words of sign flips from gates not yet folded into R (gates
 //            act identically on every shot, so they write one plane only).
-//   scratch: measurement snapshot M (Wp), packed pivot row xp/zp (NW each),
-//            pivot signs rp (SW), per-chunk counter partials, small state
-//            words, outcome staging.
+//   scratch: snapshots of measured columns, pivot ring, pivot signs, per-
+//            workgroup counter partials of two consecutive measurements,
+//            deterministic-outcome accumulators, state words, outcome staging.
 // Padding rows 2n..64W-1 and padding words W..Wp-1 are always zero.
 #pragma once
 #include <hip/hip_runtime.h>
@@ -22,7 +22,6 @@
 namespace cliff {
 
 constexpr uint32_t kNone = 0xFFFFFFFFu;
-constexpr uint32_t kMaxChunks = 512;   // column chunks of one measurement sweep
 constexpr uint32_t kStateWords = 64;   // uint32 words of measurement state
 
 // Measurement-state word indices (uint32).
@@ -97,6 +96,8 @@ struct TabDev {
   uint32_t n, S, W, Wp, NW, SW;
 };
 
+
+
 // Largest supported qubit count (pivot bits of a workgroup's columns in LDS).
 constexpr uint32_t kMaxQubits = 1u << 20;
 
@@ -121,8 +122,6 @@ inline Dims make_dims(uint32_t n, uint32_t S) {
   return d;
 }
 
-inline uint32_t sweep_chunks(uint32_t n);
-
 inline Offsets make_offsets(const Dims &d) {
   Offsets o;
   size_t cur = 0;
@@ -136,10 +135,7 @@ inline Offsets make_offsets(const Dims &d) {
   o.xp = take(size_t(d.NW) * 8);
   o.zp = take(size_t(d.NW) * 8);
   o.rp = take(size_t(d.SW) * 8);
-  {
-    const size_t a = size_t(sweep_chunks(d.n)), b = 2 * size_t(step_grid(d.n));
-    o.part = take((a > b ? a : b) * d.Wp * 16);
-  }
+  o.part = take(2 * size_t(step_grid(d.n)) * d.Wp * 16);   // partials of two steps
   o.state = take(kStateWords * 4);
   o.out = take(size_t(d.n) * d.S);   // staging for up to n measurements per pass
   o.kind = take(size_t(d.n));
@@ -153,24 +149,16 @@ inline Offsets make_offsets(const Dims &d) {
   return o;
 }
 
-// Columns per chunk of the multi-kernel measurement sweep, and chunk count.
-inline uint32_t sweep_cols_per_chunk(uint32_t n) {
-  uint32_t cols = n <= 2048 ? 16u : (n <= 8192 ? 32u : 64u);
-  while ((n + cols - 1) / cols > kMaxChunks) cols *= 2;
-  return cols;
-}
-inline uint32_t sweep_chunks(uint32_t n) {
-  const uint32_t cols = sweep_cols_per_chunk(n);
-  return (n + cols - 1) / cols;
-}
 
 // ---- launchers (each defined in the .hip file holding its kernels) ----------
 hipError_t launch_init_zero(const TabDev &t, hipStream_t st);
 hipError_t launch_fold_pending(const TabDev &t, hipStream_t st);
 hipError_t launch_gate_layer(const TabDev &t, const uint64_t *ops, uint32_t nops, hipStream_t st);
-hipError_t launch_measure_one(const TabDev &t, uint32_t a, uint32_t slot, uint64_t seed,
-                              uint64_t circuit, uint64_t shot0, uint64_t m, hipStream_t st,
-                              Profiler *prof);
+// LDS budget of the fused all-layers gate kernel (8 bytes per qubit).
+constexpr size_t kFusedGateLds = 160 * 1024 - 1024;
+bool fused_gates_fit(uint32_t n);
+hipError_t launch_gates_fused(const TabDev &t, const uint64_t *ops, const uint32_t *dev_offs,
+                              uint32_t depth, hipStream_t st);
 hipError_t launch_measure_list(const TabDev &t, const uint32_t *qubits, uint32_t k, uint64_t seed,
                                uint64_t circuit, uint64_t shot0, uint64_t m0, hipStream_t st,
                                Profiler *prof);

@@ -50,8 +50,17 @@ def test_init_zero(ctx, n):
     _assert_tab_equal(t.export(), [ref] * 3)
 
 
+@pytest.fixture(params=["per_layer", "fused"])
+def gate_mode(request, ctx):
+    from paper_2408_00384_amd import (GATES_AUTO, GATES_FUSED, GATES_PER_LAYER,
+                                      cliff_ctx_set_gate_mode)
+    cliff_ctx_set_gate_mode(ctx.handle, GATES_PER_LAYER if request.param == "per_layer" else GATES_FUSED)
+    yield request.param
+    cliff_ctx_set_gate_mode(ctx.handle, GATES_AUTO)
+
+
 @pytest.mark.parametrize("n", RAGGED)
-def test_layers_match_oracle(ctx, n):
+def test_layers_match_oracle(ctx, gate_mode, n):
     c = layered_circuit(n, 7, 2, gen_seed=[11, n])
     t = _tab(ctx, n, 2).apply_circuit_gates(c)
     ref = oracle.Tableau(n).apply_circuit_gates(c).get()
@@ -59,11 +68,25 @@ def test_layers_match_oracle(ctx, n):
 
 
 @pytest.mark.parametrize("n", [1, 2, 3, 17, 64, 65, 130])
-def test_gate_list_matches_oracle(ctx, n):
+def test_gate_list_matches_oracle(ctx, gate_mode, n):
     rng = np.random.default_rng(n)
     ops, a, b = random_gate_list(rng, n, 400)
     t = _tab(ctx, n).apply_gates(ops, a, b)
     ref = oracle.Tableau(n).apply_gates(ops, a, b).get()
+    _assert_tab_equal(t.export(), [ref])
+
+
+def test_encoded_stream_from_device_memory(ctx, gate_mode):
+    """Pre-encoded ops resident in HBM (cliff_apply_encoded), both strategies."""
+    import torch
+    from paper_2408_00384_amd import cliff_apply_encoded, cliff_encode_layers
+    c = layered_circuit(300, 9, 1, gen_seed=99)
+    ops, offs = cliff_encode_layers(c.n, c.h, c.s, c.ctrl, c.tgt)
+    dev = torch.from_numpy(ops.view(np.int64)).to("cuda:0")
+    torch.cuda.synchronize()
+    t = _tab(ctx, c.n)
+    cliff_apply_encoded(t.handle, dev.data_ptr(), offs)
+    ref = oracle.Tableau(c.n).apply_circuit_gates(c).get()
     _assert_tab_equal(t.export(), [ref])
 
 

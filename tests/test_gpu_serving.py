@@ -1,0 +1,59 @@
+"""Serving loop: continuous batching with admission by tableau bytes.
+
+Each request's outcome bytes must be identical when served alone and when
+served in a mix of overlapping requests (tolerance 0), and agree with the CPU
+oracle on a small subset."""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from inputs import serving_workload
+
+pytestmark = pytest.mark.gpu
+
+
+def _workload(count=20, rate=400.0, n_hi=384, shots_hi=200, seed=4):
+    reqs = serving_workload(count, rate, seed=seed, n_hi=n_hi, shots_hi=shots_hi)
+    return [r.circuit for r in reqs], [r.arrival for r in reqs]
+
+
+def test_mix_equals_alone_and_oracle():
+    from paper_2408_00384_amd.serving import Server, summarize
+    circs, arr = _workload()
+    srv = Server(budget_bytes=256 << 20, lanes=4)
+    alone = srv.run(circs, arr, realtime=False, one_at_a_time=True)
+    alone_out = {i: r.outcomes.copy() for i, r in alone.items()}
+    mix = srv.run(circs, arr, realtime=True)
+    st = summarize(mix)
+    assert st["completed"] == len(circs)
+    for i in range(len(circs)):
+        assert np.array_equal(alone_out[i], mix[i].outcomes), "request %d differs in the mix" % i
+    # small ones against the oracle (every shot)
+    for i, c in enumerate(circs):
+        if c.n <= 48:
+            for s in range(c.shots):
+                ref, _ = oracle.run_shot(c, s)
+                assert np.array_equal(mix[i].outcomes[s], ref), (i, s)
+    assert set(st["paths"]) == {"hbm", "batch"}
+    srv.close()
+
+
+def test_admission_respects_budget_and_rejects_oversized():
+    from paper_2408_00384_amd import cliff_tab_bytes
+    from paper_2408_00384_amd.serving import Server
+    circs, arr = _workload(count=12, rate=1e6, n_hi=300, shots_hi=150, seed=9)
+    biggest = max(cliff_tab_bytes(c.n, c.shots) for c in circs)
+    budget = 2 * biggest + 4096
+    srv = Server(budget_bytes=budget, lanes=6)
+    res = srv.run(circs, arr, realtime=False)
+    assert all(r.error is None for r in res.values())
+    assert srv.alloc.peak <= srv.alloc.size
+    assert srv.alloc.used == 0
+    # a request larger than the whole budget is rejected, the rest still served
+    from inputs import layered_circuit
+    big = layered_circuit(2048, 2, 512, gen_seed=1)
+    res = srv.run(circs[:3] + [big], arr[:3] + [0.0], realtime=False)
+    assert res[3].error is not None
+    assert all(res[i].error is None and res[i].outcomes is not None for i in range(3))
+    srv.close()
