@@ -76,6 +76,16 @@ int cliff_ctx_num_cus(const cliff_ctx *ctx);
 #define CLIFF_GATES_FUSED 2
 int cliff_ctx_set_gate_mode(cliff_ctx *ctx, int mode);
 
+/* Measurement strategy.  AUTO: the register-resident path when the tableau
+ * shape allows it (64 <= ceil(2n/64) <= 1024 and the columns fit the
+ * registers of the device's compute units), else one kernel per measurement.
+ * STEP: always one kernel per measurement.  PERSISTENT: always the
+ * register-resident path (EINVAL if n does not fit).  Results are identical. */
+#define CLIFF_MEASURE_AUTO 0
+#define CLIFF_MEASURE_STEP 1
+#define CLIFF_MEASURE_PERSISTENT 2
+int cliff_ctx_set_measure_mode(cliff_ctx *ctx, int mode);
+
 /* Bytes of device memory a tableau of n qubits with `shots` sign columns needs,
  * scratch included (X, Z, signs, measurement scratch, outcome staging). */
 size_t cliff_tab_bytes(uint32_t n, uint32_t shots);

@@ -59,6 +59,7 @@ _SIGS = {
     "cliff_sync": (ctypes.c_int, [_vp]),
     "cliff_ctx_num_cus": (ctypes.c_int, [_vp]),
     "cliff_ctx_set_gate_mode": (ctypes.c_int, [_vp, ctypes.c_int]),
+    "cliff_ctx_set_measure_mode": (ctypes.c_int, [_vp, ctypes.c_int]),
     "cliff_tab_bytes": (_sz, [_u32, _u32]),
     "cliff_tab_bind": (ctypes.c_int, [_vp, _u32, _u32, _vp, _sz, ctypes.POINTER(_vp)]),
     "cliff_tab_unbind": (ctypes.c_int, [_vp]),
@@ -142,6 +143,11 @@ def cliff_ctx_num_cus(ctx) -> int:
 
 
 GATES_AUTO, GATES_PER_LAYER, GATES_FUSED = 0, 1, 2
+MEASURE_AUTO, MEASURE_STEP, MEASURE_PERSISTENT = 0, 1, 2
+
+
+def cliff_ctx_set_measure_mode(ctx, mode: int):
+    _check(_lib.cliff_ctx_set_measure_mode(ctx, mode), "cliff_ctx_set_measure_mode")
 
 
 def cliff_ctx_set_gate_mode(ctx, mode: int):
@@ -343,4 +349,4 @@ __all__ = [n for n in list(globals()) if n.startswith("cliff_")] + [
     "CLIFF_OK", "CLIFF_EINVAL", "CLIFF_ENOMEM", "CLIFF_EDEVICE", "CLIFF_EBUSY",
     "CLIFF_EINTERNAL", "OP_H", "OP_S", "OP_CNOT", "CliffError", "LIB_PATH", "exported_symbols",
     "PROF_KINDS", "BATCH_DESC_DTYPE", "BATCH_CONFIGS", "GATES_AUTO", "GATES_PER_LAYER",
-    "GATES_FUSED"]
+    "GATES_FUSED", "MEASURE_AUTO", "MEASURE_STEP", "MEASURE_PERSISTENT"]

@@ -123,9 +123,11 @@ struct cliff_ctx {
   hipEvent_t upload_done = nullptr;
   bool upload_pending = false;
   int gate_mode = CLIFF_GATES_AUTO;
+  int measure_mode = CLIFF_MEASURE_AUTO;
 };
 
 struct cliff_tab {
+  bool persist_used = false;   // a register-resident pass ran (abort flag is meaningful)
   cliff_ctx *ctx = nullptr;
   Dims d{};
   Offsets o{};
@@ -198,6 +200,14 @@ int cliff_sync(cliff_ctx *c) {
 
 int cliff_ctx_num_cus(const cliff_ctx *c) { return c ? c->num_cus : 0; }
 
+int cliff_ctx_set_measure_mode(cliff_ctx *c, int mode) {
+  if (!c) return fail(CLIFF_EINVAL, "cliff_ctx_set_measure_mode: NULL context");
+  if (mode < CLIFF_MEASURE_AUTO || mode > CLIFF_MEASURE_PERSISTENT)
+    return fail(CLIFF_EINVAL, "cliff_ctx_set_measure_mode: bad mode %d", mode);
+  c->measure_mode = mode;
+  return CLIFF_OK;
+}
+
 int cliff_ctx_set_gate_mode(cliff_ctx *c, int mode) {
   if (!c) return fail(CLIFF_EINVAL, "cliff_ctx_set_gate_mode: NULL context");
   if (mode < CLIFF_GATES_AUTO || mode > CLIFF_GATES_FUSED)
@@ -248,6 +258,14 @@ int cliff_tab_bind(cliff_ctx *ctx, uint32_t n, uint32_t shots, void *dev, size_t
   v.detpar = reinterpret_cast<uint32_t *>(at(t->o.detpar));
   v.detY = reinterpret_cast<uint32_t *>(at(t->o.detY));
   v.detr = reinterpret_cast<uint64_t *>(at(t->o.detr));
+  v.SNall = reinterpret_cast<uint64_t *>(at(t->o.SNall));
+  v.C1all = reinterpret_cast<uint64_t *>(at(t->o.C1all));
+  v.ring = reinterpret_cast<uint64_t *>(at(t->o.ring));
+  v.pivall = reinterpret_cast<uint32_t *>(at(t->o.pivall));
+  v.flags = reinterpret_cast<uint32_t *>(at(t->o.flags));
+  v.wr = reinterpret_cast<uint32_t *>(at(t->o.wr));
+  v.cons = reinterpret_cast<uint32_t *>(at(t->o.cons));
+  v.abort_flag = reinterpret_cast<uint32_t *>(at(t->o.abort_flag));
   v.n = n;
   v.S = shots;
   v.W = t->d.W;
@@ -507,6 +525,48 @@ extern "C" int cliff_apply_gates(cliff_tab *t, const uint8_t *op, const uint32_t
 
 // ---------------------------------------------------------------- measure ---
 
+// One pass of up to n measurements: the register-resident path when the
+// tableau shape allows it (and the device takes the cooperative launch),
+// else one step kernel per measurement.
+static int measure_pass(cliff_tab *t, const uint32_t *qubits, size_t cnt, uint64_t seed,
+                        uint64_t circuit, uint64_t shot0, uint64_t m0) {
+  cliff_ctx *c = t->ctx;
+  hipStream_t st = c->stream;
+  uint32_t G, T, NCG, CW;
+  const bool shape_ok = persist_layout(t->d.n) &&
+                        persist_shape(t->d.n, uint32_t(c->num_cus), &G, &T, &NCG, &CW);
+  if (c->measure_mode == CLIFF_MEASURE_PERSISTENT && !shape_ok)
+    return fail(CLIFF_EINVAL, "register-resident measurement does not fit n = %u", t->d.n);
+  if (c->measure_mode != CLIFF_MEASURE_STEP && shape_ok) {
+    const uint32_t *dq = nullptr;
+    int rc = upload_stream(c, nullptr, 0, qubits, cnt, nullptr, &dq);
+    if (rc) return rc;
+    hipError_t e = launch_measure_persist(t->dev, dq, uint32_t(cnt), seed, circuit, shot0, m0,
+                                          c->num_cus, st, &c->prof);
+    if (e == hipSuccess) {
+      t->persist_used = true;
+      return CLIFF_OK;
+    }
+    (void)hipGetLastError();
+    if (c->measure_mode == CLIFF_MEASURE_PERSISTENT)
+      return fail(CLIFF_EDEVICE, "cooperative launch failed: %s", hipGetErrorString(e));
+    // fall through: the step kernels need no co-residency
+  }
+  HIP_TRY(launch_measure_list(t->dev, qubits, uint32_t(cnt), seed, circuit, shot0, m0, st, &c->prof));
+  return CLIFF_OK;
+}
+
+// After a synchronizing readout: a register-resident pass that timed out
+// leaves the abort flag set.
+static int check_abort(cliff_tab *t) {
+  if (!t->persist_used) return CLIFF_OK;
+  uint32_t v = 0;
+  HIP_TRY(hipMemcpyAsync(&v, t->dev.abort_flag, 4, hipMemcpyDeviceToHost, t->ctx->stream));
+  HIP_TRY(hipStreamSynchronize(t->ctx->stream));
+  if (v) return fail(CLIFF_EINTERNAL, "register-resident measurement timed out waiting for a peer");
+  return CLIFF_OK;
+}
+
 static int measure_impl(cliff_tab *t, const uint32_t *qubits, size_t k, uint64_t seed,
                         uint64_t circuit, uint64_t shot0, uint64_t m0, uint8_t *host_out,
                         uint8_t *host_random) {
@@ -521,14 +581,16 @@ static int measure_impl(cliff_tab *t, const uint32_t *qubits, size_t k, uint64_t
   std::vector<uint8_t> out_stage, kind_stage;
   for (size_t base = 0; base < k; base += n) {
     const size_t cnt = std::min<size_t>(n, k - base);
-    HIP_TRY(launch_measure_list(t->dev, qubits + base, uint32_t(cnt), seed, circuit, shot0,
-                                m0 + base, st, &t->ctx->prof));
+    int rc = measure_pass(t, qubits + base, cnt, seed, circuit, shot0, m0 + base);
+    if (rc) return rc;
     if (host_out || host_random) {
       out_stage.resize(cnt * S);
       kind_stage.resize(cnt);
       HIP_TRY(hipMemcpyAsync(out_stage.data(), t->dev.out, cnt * S, hipMemcpyDeviceToHost, st));
       HIP_TRY(hipMemcpyAsync(kind_stage.data(), t->dev.kind, cnt, hipMemcpyDeviceToHost, st));
       HIP_TRY(hipStreamSynchronize(st));
+      int arc = check_abort(t);
+      if (arc) return arc;
       if (host_out)
         for (size_t i = 0; i < cnt; ++i)
           for (uint32_t s = 0; s < S; ++s) host_out[size_t(s) * k + base + i] = out_stage[i * S + s];
@@ -570,6 +632,8 @@ extern "C" int cliff_tab_read_outcomes(cliff_tab *t, size_t k, uint8_t *host_out
   HIP_TRY(hipMemcpyAsync(out_stage.data(), t->dev.out, k * S, hipMemcpyDeviceToHost, st));
   HIP_TRY(hipMemcpyAsync(kind_stage.data(), t->dev.kind, k, hipMemcpyDeviceToHost, st));
   HIP_TRY(hipStreamSynchronize(st));
+  int arc = check_abort(t);
+  if (arc) return arc;
   if (host_out)
     for (size_t i = 0; i < k; ++i)
       for (uint32_t s = 0; s < S; ++s) host_out[size_t(s) * k + i] = out_stage[i * S + s];

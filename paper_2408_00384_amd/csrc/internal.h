@@ -79,7 +79,8 @@ struct Dims {
 
 struct Offsets {
   size_t X, Z, R, P, M, xp, zp, rp, part, state, out, kind;
-  size_t SN, piv, rps, detpar, detY, detr, total;
+  size_t SN, piv, rps, detpar, detY, detr;
+  size_t SNall, pivall, flags, C1all, ring, wr, cons, abort_flag, total;
 };
 
 // Device view passed by value to kernels.
@@ -93,8 +94,17 @@ struct TabDev {
   uint64_t *rps;             // 2 x SW: pivot-row signs handed to the next step
   uint32_t *detpar, *detY;   // n: deterministic-outcome accumulators
   uint64_t *detr;            // n x SW
+  // register-resident path (n >= 2048): published columns, pivots and flags
+  // of every measurement of a call, per-measurement sign corrections, ring of
+  // per-workgroup counter partials with its written / consumed counters
+  uint64_t *SNall, *C1all, *ring;
+  uint32_t *pivall, *flags, *wr, *cons, *abort_flag;
   uint32_t n, S, W, Wp, NW, SW;
 };
+
+constexpr uint32_t kPersistMaxGroups = 256;
+constexpr uint32_t kPersistRing = 16;
+inline bool persist_layout(uint32_t n) { return (2 * n + 63) / 64 >= 64 && (2 * n + 63) / 64 <= 1024; }
 
 
 
@@ -145,6 +155,15 @@ inline Offsets make_offsets(const Dims &d) {
   o.detpar = take(size_t(d.n) * 4);
   o.detY = take(size_t(d.n) * 4);
   o.detr = take(size_t(d.n) * d.SW * 8);
+  const bool pl = persist_layout(d.n);
+  o.SNall = take(pl ? size_t(d.n) * d.Wp * 8 : 0);
+  o.pivall = take(pl ? size_t(d.n) * 4 : 0);
+  o.flags = take(pl ? size_t(d.n) * 4 : 0);
+  o.C1all = take(pl ? size_t(d.n) * d.Wp * 8 : 0);
+  o.ring = take(pl ? size_t(kPersistRing) * kPersistMaxGroups * d.Wp * 16 : 0);
+  o.wr = take(pl ? kPersistRing * 4 : 0);
+  o.cons = take(pl ? kPersistRing * 4 : 0);
+  o.abort_flag = take(pl ? 4 : 0);
   o.total = cur;
   return o;
 }
@@ -163,6 +182,10 @@ hipError_t launch_measure_list(const TabDev &t, const uint32_t *qubits, uint32_t
                                uint64_t circuit, uint64_t shot0, uint64_t m0, hipStream_t st,
                                Profiler *prof);
 hipError_t launch_clear_state(const TabDev &t, hipStream_t st);
+bool persist_shape(uint32_t n, uint32_t num_cus, uint32_t *G, uint32_t *T, uint32_t *NCG, uint32_t *CW);
+hipError_t launch_measure_persist(const TabDev &t, const uint32_t *dev_qubits, uint32_t k,
+                                  uint64_t seed, uint64_t circuit, uint64_t shot0, uint64_t m0,
+                                  int num_cus, hipStream_t st, Profiler *prof);
 hipError_t launch_batch(const void *descs, const uint64_t *ops, const uint32_t *offs, uint8_t *out,
                         const uint32_t *order, uint32_t count, uint64_t seed, uint32_t *work,
                         uint32_t team, uint32_t maxn, int num_cus, hipStream_t st);

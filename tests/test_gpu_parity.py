@@ -245,3 +245,54 @@ def test_error_paths(ctx):
     # the tableau is still usable after rejected calls
     out, rnd = t.measure(np.arange(10))
     assert out.sum() == 0 and rnd.sum() == 0
+
+
+@pytest.fixture(params=["step", "persistent"])
+def measure_mode(request, ctx):
+    from paper_2408_00384_amd import (MEASURE_AUTO, MEASURE_PERSISTENT, MEASURE_STEP,
+                                      cliff_ctx_set_measure_mode)
+    cliff_ctx_set_measure_mode(ctx.handle, MEASURE_STEP if request.param == "step" else MEASURE_PERSISTENT)
+    yield request.param
+    cliff_ctx_set_measure_mode(ctx.handle, MEASURE_AUTO)
+
+
+@pytest.mark.parametrize("n", [2048, 2111, 3000, 4096, 6000])
+def test_large_n_partial_measure_vs_oracle(ctx, measure_mode, n):
+    """Both measurement strategies against the oracle on the first qubits of a
+    dense state (a prefix of measure-all, so the oracle finishes quickly),
+    with a repeated qubit and a deterministic re-measurement in the list."""
+    c = layered_circuit(n, 14, 3, gen_seed=[40, n], circuit_id=5)
+    q = np.concatenate([np.arange(0, 24), [3, 7], np.arange(n - 10, n)]).astype(np.uint32)
+    t = _tab(ctx, n, 3).apply_circuit_gates(c)
+    out, rnd = t.measure(q, seed=c.seed, circuit=5)
+    gx, gz, gr = t.export()
+    ref = oracle.Tableau(n).apply_circuit_gates(c)
+    refs = [ref.clone() for _ in range(3)]
+    for s in range(3):
+        o, k = refs[s].measure_list(q, seed=c.seed, circuit=5, shot=s)
+        assert np.array_equal(out[s], o), "outcomes (shot %d)" % s
+        assert np.array_equal(rnd, k)
+    _assert_tab_equal((gx, gz, gr), [r.get() for r in refs])
+    assert t.anomalies() == 0
+
+
+@pytest.mark.parametrize("n", [2048, 4096, 10000])
+def test_persistent_equals_step_measure_all(ctx, n):
+    """Register-resident and per-measurement-kernel paths agree bit for bit
+    on a full measure-all (tableau and every shot's outcomes)."""
+    from paper_2408_00384_amd import (MEASURE_AUTO, MEASURE_PERSISTENT, MEASURE_STEP,
+                                      cliff_ctx_set_measure_mode)
+    c = layered_circuit(n, 20 if n > 4096 else 12, 2, gen_seed=[41, n], circuit_id=6)
+    res = {}
+    for mode in (MEASURE_STEP, MEASURE_PERSISTENT):
+        cliff_ctx_set_measure_mode(ctx.handle, mode)
+        t = _tab(ctx, n, 2).apply_circuit_gates(c)
+        out, rnd = t.measure(c.qubits, seed=c.seed, circuit=6)
+        res[mode] = (out, rnd, t.export(), t.anomalies())
+        t.close()
+    cliff_ctx_set_measure_mode(ctx.handle, MEASURE_AUTO)
+    a, b = res[MEASURE_STEP], res[MEASURE_PERSISTENT]
+    assert np.array_equal(a[0], b[0]) and np.array_equal(a[1], b[1])
+    for A, B in zip(a[2], b[2]):
+        assert np.array_equal(A, B)
+    assert a[3] == 0 and b[3] == 0
