@@ -29,6 +29,14 @@ FLAGS = [
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
 ]
 
+# Per-source extra flags.  The register-resident measurement kernel keeps an
+# unrolled array of row words in registers; promoting that array to one LLVM
+# vector (done before unrolling) makes every conditional update copy the whole
+# register tuple and spill; without it the array splits into scalars.
+FILE_FLAGS = {
+    "measure_persist.hip": ["-mllvm", "-disable-promote-alloca-to-vector"],
+}
+
 
 def sources():
     return sorted(os.path.join(CSRC, f) for f in os.listdir(CSRC) if f.endswith(".hip"))
@@ -36,7 +44,7 @@ def sources():
 
 def _compile(src: str) -> str:
     obj = os.path.join(OBJ, os.path.basename(src)[:-4] + ".o")
-    cmd = [HIPCC, *FLAGS, "-c", src, "-o", obj]
+    cmd = [HIPCC, *FLAGS, *FILE_FLAGS.get(os.path.basename(src), []), "-c", src, "-o", obj]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         raise RuntimeError("hipcc failed for %s:\n%s\n%s" % (src, r.stdout, r.stderr))

@@ -94,17 +94,28 @@ struct TabDev {
   uint64_t *rps;             // 2 x SW: pivot-row signs handed to the next step
   uint32_t *detpar, *detY;   // n: deterministic-outcome accumulators
   uint64_t *detr;            // n x SW
-  // register-resident path (n >= 2048): published columns, pivots and flags
-  // of every measurement of a call, per-measurement sign corrections, ring of
-  // per-workgroup counter partials with its written / consumed counters
+  // register-resident path (n >= 2048), per chunk of measurements: published
+  // columns, pivots and flags, per-workgroup counter partials, and the
+  // reduced sign corrections
   uint64_t *SNall, *C1all, *ring;
   uint32_t *pivall, *flags, *wr, *cons, *abort_flag;
   uint32_t n, S, W, Wp, NW, SW;
 };
 
 constexpr uint32_t kPersistMaxGroups = 256;
-constexpr uint32_t kPersistRing = 16;
+constexpr uint32_t kPersistMaxChunk = 1024;   // measurements per chunk (qubit list held in LDS)
 inline bool persist_layout(uint32_t n) { return (2 * n + 63) / 64 >= 64 && (2 * n + 63) / 64 <= 1024; }
+// Measurements per chunk of the register-resident path: bounded by the HBM
+// kept for per-workgroup counter partials (256 MB for n >= 8192, else 64 MB).
+inline uint32_t persist_chunk(uint32_t n) {
+  const uint32_t Wp = (((2 * n + 63) / 64) + 7) & ~7u;
+  const size_t budget = n >= 8192 ? (size_t(256) << 20) : (size_t(64) << 20);
+  size_t kc = budget / (size_t(kPersistMaxGroups) * Wp * 16);
+  if (kc < 16) kc = 16;
+  if (kc > kPersistMaxChunk) kc = kPersistMaxChunk;
+  if (kc > n) kc = n;
+  return uint32_t(kc);
+}
 
 
 
@@ -156,13 +167,14 @@ inline Offsets make_offsets(const Dims &d) {
   o.detY = take(size_t(d.n) * 4);
   o.detr = take(size_t(d.n) * d.SW * 8);
   const bool pl = persist_layout(d.n);
-  o.SNall = take(pl ? size_t(d.n) * d.Wp * 8 : 0);
-  o.pivall = take(pl ? size_t(d.n) * 4 : 0);
-  o.flags = take(pl ? size_t(d.n) * 4 : 0);
-  o.C1all = take(pl ? size_t(d.n) * d.Wp * 8 : 0);
-  o.ring = take(pl ? size_t(kPersistRing) * kPersistMaxGroups * d.Wp * 16 : 0);
-  o.wr = take(pl ? kPersistRing * 4 : 0);
-  o.cons = take(pl ? kPersistRing * 4 : 0);
+  const size_t kc = pl ? persist_chunk(d.n) : 0;
+  o.SNall = take(kc * d.Wp * 8);
+  o.pivall = take(kc * 4);
+  o.flags = take(kc * 4);
+  o.C1all = take(kc * d.Wp * 8);
+  o.ring = take(kc * kPersistMaxGroups * d.Wp * 16);   // partials [m][workgroup][word][2]
+  o.wr = take(0);
+  o.cons = take(0);
   o.abort_flag = take(pl ? 4 : 0);
   o.total = cur;
   return o;

@@ -1,6 +1,7 @@
-// Measuring a list of qubits with the tableau held in registers: one
-// cooperative launch for all measurements of the list, then one small launch
-// for the signs of every shot.
+// Measuring a list of qubits with the tableau held in registers and LDS,
+// in chunks of up to Kc measurements; per chunk four launches: publish the
+// first measured column, the cooperative x/z kernel, a parallel reduction of
+// the sign counters, and a per-shot sign walk.
 //
 // The method is that of measure_step.hip (paper Sec. 2, after Aaronson &
 // Gottesman 2004: smallest-pivot random branch with rowsum and the phase
@@ -8,37 +9,34 @@
 // the sign of the product of the selected stabilizers).  Only where the data
 // lives and how workgroups meet differs:
 //
-//  * x/z kernel (k_meas_xz): G workgroups of 16 waves, each owning whole
-//    columns.  A data wave holds, for one 64-row word tile, up to CW of the
-//    workgroup's columns in registers for the whole list, so the rowsum sweep
-//    reads and writes no memory.  Per measurement m the only thing that must
-//    travel between workgroups is the measured column a_m after measurement
-//    m-1 and its pivot row p_m: the owner of a_m publishes both (then a flag)
-//    as soon as it has applied measurement m-1 to that one column, and every
-//    workgroup waits for that flag only.  Sign corrections need a sum over all
-//    columns: each workgroup writes one (c0, c1) pair per row word into a ring
-//    of partials, and the partials of measurement r are reduced later (mod 4)
-//    by the workgroups, each for a slice of row words, into c1[r][w].
-//    Writers wait until a ring slot has been consumed; every wait also does
-//    pending reductions, so no wait can block the one it waits for.
-//  * sign kernel (k_meas_signs): one workgroup per shot walks the list in
-//    order with that shot's sign column in LDS: r ^= M & (c1 ^ r_p), rows p-n
-//    and p rewritten, outcome = Philox bit; deterministic outcomes from the
-//    XOR of the product rows' signs and the two x/z terms accumulated by the
-//    x/z kernel.
+//  * x/z kernel (k_meas_xz): G workgroups of 16 waves; workgroup g owns the
+//    columns j = g (mod G), so consecutive qubits belong to different
+//    workgroups.  A data wave holds, for one 64-row word tile, up to CW of the
+//    workgroup's columns: x bits in registers, z bits in LDS, for the whole
+//    chunk, so the rowsum sweep touches no HBM.  Per measurement m the only
+//    thing that travels between workgroups is the measured column a_m after
+//    measurement m-1 and its pivot row p_m: the owner of a_m publishes both
+//    (then a flag) as soon as it has seen measurement m-1 published, and
+//    every workgroup waits for that flag only.  Each workgroup writes its
+//    (c0, c1) counter pair per row word for every measurement of the chunk to
+//    HBM with write-through stores.
+//  * reduce kernel: c1[m][w] = mod-4 sum of the partials of all workgroups.
+//  * sign kernel: one workgroup per shot walks the chunk in order with that
+//    shot's sign column in LDS: r ^= M & (c1 ^ r_p), rows p-n and p rewritten,
+//    outcome = Philox bit; deterministic outcomes from the XOR of the product
+//    rows' signs and the two x/z terms accumulated by the x/z kernel.
 //
-// Every spin is bounded; a timeout raises a device-wide abort flag that every
-// wait checks, so all waves leave the kernel; the host reports the error.
+// Every wait is bounded; a timeout raises a device-wide abort flag that every
+// wait checks, so all waves leave the kernel and the host reports the error.
 #include "internal.h"
 #include "philox.h"
 
 namespace cliff {
 
-constexpr uint32_t kRing = kPersistRing;   // partial slots
-constexpr uint32_t kSpinLimit = 1u << 21;  // polls before giving up (each polls ~1 us apart at worst)
+constexpr uint32_t kSpinLimit = 1u << 21;   // polls before giving up (~seconds)
 
 struct PersistArgs {
-  const uint32_t *qubits;   // device, k entries
+  const uint32_t *qubits;   // device, this chunk's k entries
   uint32_t k, G, T, NCG;
 };
 
@@ -74,60 +72,29 @@ __device__ __forceinline__ uint64_t det_word(const uint64_t *col, uint32_t n, ui
   return v;
 }
 
-// Reduce the partials of measurement r for this workgroup's row-word slice.
-__device__ void reduce_slice(const TabDev &t, const PersistArgs &a, uint32_t r, uint32_t g,
-                             uint32_t wave, uint32_t lane) {
-  const uint32_t W = t.W, G = a.G;
-  const uint32_t p = ld_relaxed(t.pivall + r);
-  if (p == kNone) return;
-  const uint64_t *part = t.ring + size_t(r % kRing) * G * t.Wp * 2;
-  const uint64_t *col = t.SNall + size_t(r) * t.Wp;
-  // one wave per word of the slice
-  for (uint32_t w = g + wave * G; w < W; w += 16 * G) {
-    uint64_t c0 = 0, c1 = 0;
-    for (uint32_t q = lane; q < G; q += 64) {
-      const uint64_t b0 = ld_relaxed64(part + (size_t(q) * t.Wp + w) * 2);
-      const uint64_t b1 = ld_relaxed64(part + (size_t(q) * t.Wp + w) * 2 + 1);
-      c1 ^= b1 ^ (c0 & b0);
-      c0 ^= b0;
-    }
-    for (int off = 32; off > 0; off >>= 1) {
-      const uint64_t b0 = __shfl_xor(c0, off), b1 = __shfl_xor(c1, off);
-      c1 ^= b1 ^ (c0 & b0);
-      c0 ^= b0;
-    }
-    if (lane == 0) {
-      uint64_t mw = ld_relaxed64(col + w);
-      if (w == (p >> 6)) mw &= ~pbit(p);
-      uint64_t bad = c0 & mw;
-      const uint32_t pn = p - t.n;
-      if (w == (pn >> 6)) bad &= ~pbit(pn);   // row p-n anticommutes with the pivot
-      if (bad) atomicAdd(&t.state[ST_ANOMALY], uint32_t(__popcll(bad)));
-      t.C1all[size_t(r) * t.Wp + w] = c1;
-    }
-  }
-}
-
 template <int CW>
 __global__ void __launch_bounds__(1024) k_meas_xz(TabDev t, PersistArgs a) {
   // x bits of the owned columns live in registers, z bits in LDS
   __shared__ uint64_t sZ[16 * CW * 64];
   __shared__ uint64_t s_c0[16 * 64], s_c1[16 * 64];
-  __shared__ uint8_t s_xp[16 * CW], s_zp[16 * CW];
+  __shared__ uint32_t s_q[kPersistMaxChunk];                // this chunk's measured qubits
+  __shared__ uint32_t s_xpm[16], s_zpm[16];                 // per column group: bit k = pivot-row x/z of slot k
   __shared__ uint32_t s_ztile[16 * CW], s_xtile[16 * CW];   // per column: bit = tile parity
-  __shared__ uint32_t s_flag, s_red, s_pn, s_abort, s_nzw;
+  __shared__ uint32_t s_flag, s_pn, s_abort, s_nzw;
   __shared__ uint32_t s_par, s_y;
   const uint32_t tid = threadIdx.x, lane = tid & 63;
   const uint32_t wave = __builtin_amdgcn_readfirstlane(tid >> 6);
   const uint32_t g = blockIdx.x, G = a.G, T = a.T, NCG = a.NCG;
   const uint32_t n = t.n, W = t.W;
-  const uint32_t j0 = uint32_t(uint64_t(g) * n / G), j1 = uint32_t(uint64_t(g + 1) * n / G);
-  const uint32_t C = j1 - j0;
+  const uint32_t C = g < n ? (n - g + G - 1) / G : 0;   // owned columns g, g+G, g+2G, ...
   const bool data = wave < T * NCG;
   const uint32_t tile = data ? wave % T : 0, cg = data ? wave / T : 0;
+  // slots k < ns of this wave hold columns c = cg + k * NCG < C (wave-uniform)
+  const uint32_t ns = data && C > cg ? (C - cg + NCG - 1) / NCG : 0;
   const uint32_t w = tile * 64 + lane;
   const bool live = data && w < W;
 
+  for (uint32_t i = tid; i < a.k; i += blockDim.x) s_q[i] = a.qubits[i];
   // ---- load the owned columns: x into registers, z into LDS
   uint64_t xr[CW];
   uint64_t *zl = sZ + size_t(wave) * CW * 64 + lane;   // z of slot k at zl[k * 64]
@@ -136,28 +103,24 @@ __global__ void __launch_bounds__(1024) k_meas_xz(TabDev t, PersistArgs a) {
     const uint32_t c = cg + uint32_t(k) * NCG;
     xr[k] = 0;
     if (data) zl[k * 64] = 0;
-    if (live && c < C) {
-      xr[k] = t.X[size_t(j0 + c) * t.Wp + w];
-      zl[k * 64] = t.Z[size_t(j0 + c) * t.Wp + w];
+    if (live && uint32_t(k) < ns) {
+      xr[k] = t.X[size_t(g + c * G) * t.Wp + w];
+      zl[k * 64] = t.Z[size_t(g + c * G) * t.Wp + w];
     }
   }
-  uint32_t r_next = 0;   // next measurement whose partials this workgroup reduces
   unsigned long long bytes_acc = 0;   // algorithmic sweep bytes of this workgroup (thread 0)
   uint32_t n_random = 0, n_det = 0;
   if (tid == 0) s_nzw = 0;
 
   for (uint32_t m = 0; m < a.k; ++m) {
-    // ---- wait: measurement m published and its partial slot free;
-    //      reduce pending partials meanwhile
+    // ---- wait until measurement m is published; the flag word carries
+    // the pivot row as p + 2 (kNone + 2 wraps to 1), so it is never zero
     uint32_t spins = 0;
     for (;;) {
       if (tid == 0) {
-        const uint32_t f = ld_relaxed(t.flags + m);
-        const uint32_t slot_ok = ld_relaxed(t.cons + (m % kRing)) >= G * (m / kRing);
-        s_flag = (f && slot_ok) ? 1u : 0u;
-        s_red = (r_next < m && ld_relaxed(t.wr + (r_next % kRing)) >= G * (r_next / kRing + 1)) ? 1u : 0u;
+        s_flag = ld_relaxed(t.flags + m);
         s_abort = ld_relaxed(t.abort_flag);
-        if (!s_flag && !s_red && ++spins > kSpinLimit) {
+        if (!s_flag && ++spins > kSpinLimit) {
           atomicOr(t.abort_flag, 1u);
           s_abort = 1;
         }
@@ -165,22 +128,15 @@ __global__ void __launch_bounds__(1024) k_meas_xz(TabDev t, PersistArgs a) {
       __syncthreads();
       if (s_abort) return;
       if (s_flag) break;
-      if (s_red) {
-        reduce_slice(t, a, r_next, g, wave, lane);
-        __syncthreads();
-        if (tid == 0) atomicAdd(t.cons + (r_next % kRing), 1u);
-        ++r_next;
-      } else {
-        __builtin_amdgcn_s_sleep(2);
-      }
+      __builtin_amdgcn_s_sleep(1);
       __syncthreads();
     }
-    const uint32_t p = ld_relaxed(t.pivall + m);
+    const uint32_t p = s_flag - 2u;
     const uint64_t *col = t.SNall + size_t(m) * t.Wp;
-    const uint32_t am = a.qubits[m];
-    const uint32_t a_next = m + 1 < a.k ? a.qubits[m + 1] : kNone;
-    const bool own_next = a_next != kNone && a_next >= j0 && a_next < j1;
-    const uint32_t cn = own_next ? a_next - j0 : 0;
+    const uint32_t am = s_q[m];
+    const uint32_t a_next = m + 1 < a.k ? s_q[m + 1] : kNone;
+    const bool own_next = a_next != kNone && (a_next % G) == g;
+    const uint32_t cn = own_next ? a_next / G : 0;
     const uint32_t pn = p - n, wpn = pn >> 6, wp = p >> 6;
     const uint64_t bpn = pbit(pn), bpb = pbit(p);
     uint64_t mw = 0;
@@ -188,18 +144,18 @@ __global__ void __launch_bounds__(1024) k_meas_xz(TabDev t, PersistArgs a) {
       mw = ld_relaxed64(col + w);
       if (p != kNone && w == wp) mw &= ~bpb;
     }
-    if (p != kNone) {
-      // ---- pivot-row bits of the owned columns (the lane holding row p)
-      if (live && w == wp) {
+    if (p != kNone && live && w == wp) {
+      // the lane holding row p: pivot-row bits of this wave's slots
+      uint32_t xm = 0, zm = 0;
 #pragma unroll
-        for (int k = 0; k < CW; ++k) {
-          const uint32_t c = cg + uint32_t(k) * NCG;
-          if (c < C) {
-            s_xp[c] = uint8_t((xr[k] >> (p & 63)) & 1u);
-            s_zp[c] = uint8_t((zl[k * 64] >> (p & 63)) & 1u);
-          }
+      for (int k = 0; k < CW; ++k) {
+        if (uint32_t(k) < ns) {
+          xm |= uint32_t((xr[k] >> (p & 63)) & 1u) << k;
+          zm |= uint32_t((zl[k * 64] >> (p & 63)) & 1u) << k;
         }
       }
+      s_xpm[cg] = xm;
+      s_zpm[cg] = zm;
     }
     if (tid == 0) s_pn = kNone;
     if (tid < 16 * CW) {
@@ -207,69 +163,74 @@ __global__ void __launch_bounds__(1024) k_meas_xz(TabDev t, PersistArgs a) {
       s_xtile[tid] = 0;
     }
     __syncthreads();
+    const uint32_t xm = p != kNone ? __builtin_amdgcn_readfirstlane(s_xpm[cg]) : 0u;
+    const uint32_t zm = p != kNone ? __builtin_amdgcn_readfirstlane(s_zpm[cg]) : 0u;
     // ---- publish the next measured column first (only its owner)
-    if (own_next && live && (cn % NCG) == cg) {
+    const bool pub = own_next && data && (cn % NCG) == cg;
+    if (pub && live) {
       const uint32_t kn = cn / NCG;
-      uint64_t x = 0;
+      // one uniform branch per slot (a select chain over xr would make the
+      // compiler index the register array dynamically and spill it)
 #pragma unroll
-      for (int k = 0; k < CW; ++k) x = (uint32_t(k) == kn) ? xr[k] : x;
-      if (p != kNone) {
-        const uint32_t xpj = s_xp[cn];
-        uint64_t nx = xpj ? (x ^ mw) : x;
-        if (w == wpn) nx = xpj ? (nx | bpn) : (nx & ~bpn);
-        if (w == wp) nx &= ~bpb;
-        x = nx;
-      }
-      st_relaxed64(t.SNall + size_t(m + 1) * t.Wp + w, x);
-      uint64_t v = x;
-      if (w >= (n >> 6)) {
-        if (w == (n >> 6)) v &= ~0ull << (n & 63);
-        if (v) atomicMin(&s_pn, w * 64 + uint32_t(__builtin_ctzll(v)));
+      for (int k = 0; k < CW; ++k) {
+        if (uint32_t(k) != kn) continue;
+        uint64_t x = xr[k];
+        if (p != kNone) {
+          const uint32_t xpj = (xm >> k) & 1u;
+          uint64_t nx = xpj ? (x ^ mw) : x;
+          if (w == wpn) nx = xpj ? (nx | bpn) : (nx & ~bpn);
+          if (w == wp) nx &= ~bpb;
+          x = nx;
+        }
+        st_relaxed64(t.SNall + size_t(m + 1) * t.Wp + w, x);
+        uint64_t v = x;
+        if (w >= (n >> 6)) {
+          if (w == (n >> 6)) v &= ~0ull << (n & 63);
+          if (v) atomicMin(&s_pn, w * 64 + uint32_t(__builtin_ctzll(v)));
+        }
       }
     }
-    if (own_next && data && (cn % NCG) == cg)
-      __atomic_thread_fence(__ATOMIC_RELEASE);   // each storing wave fences its own stores
+    if (pub) __atomic_thread_fence(__ATOMIC_RELEASE);   // each storing wave fences its own stores
     __syncthreads();
     if (own_next && tid == 0) {
-      st_relaxed(t.pivall + m + 1, s_pn);
+      const uint32_t pnext = s_pn;
       __atomic_thread_fence(__ATOMIC_RELEASE);
-      st_relaxed(t.flags + m + 1, 1u);
+      st_relaxed(t.flags + m + 1, pnext + 2u);
+      t.pivall[m + 1] = pnext;   // read only by the kernels after this one
     }
     // ---- the sweep (random) or the x/z terms of the sign (deterministic)
     uint64_t c0 = 0, c1 = 0;
     if (p != kNone) {
       if (live) {
+        // Branch-free per slot, with the pivot-row bits (xp, zp) of the
+        // column as wave-uniform all-ones/zero masks XP, ZP.  Row i and the
+        // pivot row anticommute on this column iff x zp ^ z xp; then g is +1
+        // when f = x ^ (xp ? zp : z) is set and -1 otherwise (the three
+        // pivot cases Y: g = z - x, X: g = z(2x - 1), Z: g = x(1 - 2z)).
 #pragma unroll
         for (int k = 0; k < CW; ++k) {
+          if (uint32_t(k) >= ns) continue;   // wave-uniform
           const uint32_t c = cg + uint32_t(k) * NCG;
-          if (c >= C) continue;
-          const uint32_t xpj = s_xp[c], zpj = s_zp[c];
-          if (!(xpj | zpj)) {
-            if (w == wpn) { xr[k] &= ~bpn; zl[k * 64] &= ~bpn; }
-            continue;
-          }
+          const uint64_t XP = 0ull - ((xm >> k) & 1u), ZP = 0ull - ((zm >> k) & 1u);
           const uint64_t x = xr[k], z = zl[k * 64];
-          uint64_t plus, minus;
-          if (xpj & zpj) { plus = z & ~x; minus = x & ~z; }        // pivot Y: g = z - x
-          else if (xpj) { plus = z & x; minus = z & ~x; }          // pivot X: g = z(2x - 1)
-          else { plus = x & ~z; minus = x & z; }                   // pivot Z: g = x(1 - 2z)
-          plus &= mw;
-          minus &= mw;
+          const uint64_t anti = ((x & ZP) ^ (z & XP)) & mw;
+          const uint64_t f = x ^ ((XP & ZP) | (~XP & z));
+          const uint64_t plus = anti & f, minus = anti & ~f;
           c1 ^= c0 & plus;
           c0 ^= plus;
           c1 ^= ~c0 & minus;
           c0 ^= minus;
-          uint64_t nx = xpj ? (x ^ mw) : x, nz = zpj ? (z ^ mw) : z;
+          uint64_t nx = x ^ (XP & mw), nz = z ^ (ZP & mw);
           if (w == wpn) {
-            nx = xpj ? (nx | bpn) : (nx & ~bpn);
-            nz = zpj ? (nz | bpn) : (nz & ~bpn);
+            nx = (nx & ~bpn) | (XP & bpn);
+            nz = (nz & ~bpn) | (ZP & bpn);
           }
           if (w == wp) {
             nx &= ~bpb;
-            nz = (j0 + c == am) ? (nz | bpb) : (nz & ~bpb);
+            nz = (g + c * G == am) ? (nz | bpb) : (nz & ~bpb);
           }
           xr[k] = nx;
-          if (nz != z) zl[k * 64] = nz;
+          if (ZP || w == wpn || w == wp) zl[k * 64] = nz;
         }
       }
     } else {
@@ -281,8 +242,8 @@ __global__ void __launch_bounds__(1024) k_meas_xz(TabDev t, PersistArgs a) {
       if (data) {
 #pragma unroll
         for (int k = 0; k < CW; ++k) {
+          if (uint32_t(k) >= ns) continue;   // uniform across the wave
           const uint32_t c = cg + uint32_t(k) * NCG;
-          if (c >= C) continue;   // uniform across the wave
           const uint64_t xt = xr[k] & Tm, zt = zl[k * 64] & Tm;
           ycnt += uint32_t(__popcll(xt & zt));
           uint64_t pre = zt << 1;
@@ -304,10 +265,8 @@ __global__ void __launch_bounds__(1024) k_meas_xz(TabDev t, PersistArgs a) {
       if (lane == 0 && data) {
         uint32_t extra = __popcll(pb) & 1u;
         // carry into this tile from the z parities of the tiles before it
-#pragma unroll
-        for (int k = 0; k < CW; ++k) {
-          const uint32_t c = cg + uint32_t(k) * NCG;
-          if (c >= C) continue;
+        for (uint32_t k = 0; k < ns; ++k) {
+          const uint32_t c = cg + k * NCG;
           const uint32_t carry = uint32_t(__popc(s_ztile[c] & ((1u << tile) - 1u))) & 1u;
           extra ^= carry & (s_xtile[c] >> tile) & 1u;
         }
@@ -328,7 +287,7 @@ __global__ void __launch_bounds__(1024) k_meas_xz(TabDev t, PersistArgs a) {
     }
     __syncthreads();
     if (p != kNone) {
-      uint64_t *part = t.ring + (size_t(m % kRing) * G + g) * t.Wp * 2;
+      uint64_t *part = t.ring + (size_t(m) * G + g) * t.Wp * 2;
       for (uint32_t ww = tid; ww < W; ww += blockDim.x) {
         const uint32_t tl = ww / 64, ln = ww % 64;
         uint64_t a0 = 0, a1 = 0;
@@ -338,68 +297,36 @@ __global__ void __launch_bounds__(1024) k_meas_xz(TabDev t, PersistArgs a) {
           a1 ^= b1 ^ (a0 & b0);
           a0 ^= b0;
         }
+        // read by the reduce kernel after this one: write-through, no fence
         st_relaxed64(part + size_t(ww) * 2, a0);
         st_relaxed64(part + size_t(ww) * 2 + 1, a1);
       }
-      if (wave * 64 < W) __atomic_thread_fence(__ATOMIC_RELEASE);   // waves that stored
-    }
-    __syncthreads();
-    if (tid == 0) {
-      atomicAdd(t.wr + (m % kRing), 1u);
-      if (p != kNone) {
+      if (tid == 0) {
+        // algorithmic sweep bytes: per nonzero row word of the measured
+        // column, x and z of every pivot-touching column read and written
         uint32_t sx = 0, sz = 0, sxz = 0;
-        for (uint32_t c = 0; c < C; ++c) {
-          sx += s_xp[c];
-          sz += s_zp[c];
-          sxz += s_xp[c] | s_zp[c];
+        for (uint32_t q = 0; q < NCG; ++q) {
+          const uint32_t xq = s_xpm[q], zq = s_zpm[q];
+          sx += __popc(xq);
+          sz += __popc(zq);
+          sxz += __popc(xq | zq);
         }
         bytes_acc += 8ull * s_nzw * (2ull * sxz + sx + sz);
         ++n_random;
-      } else {
-        ++n_det;
+        s_nzw = 0;
       }
-      s_nzw = 0;
-      // one pending reduction per iteration when its partials are complete
-      s_red = (r_next <= m && ld_relaxed(t.wr + (r_next % kRing)) >= G * (r_next / kRing + 1)) ? 1u : 0u;
-    }
-    __syncthreads();
-    if (s_red) {
-      reduce_slice(t, a, r_next, g, wave, lane);
-      __syncthreads();
-      if (tid == 0) atomicAdd(t.cons + (r_next % kRing), 1u);
-      ++r_next;
+    } else if (tid == 0) {
+      ++n_det;
     }
     __syncthreads();
   }
-  // ---- finish the reductions still owed, then write the columns back
-  uint32_t spins = 0;
-  while (r_next < a.k) {
-    if (tid == 0) {
-      s_red = ld_relaxed(t.wr + (r_next % kRing)) >= G * (r_next / kRing + 1) ? 1u : 0u;
-      s_abort = ld_relaxed(t.abort_flag);
-      if (!s_red && ++spins > kSpinLimit) {
-        atomicOr(t.abort_flag, 1u);
-        s_abort = 1;
-      }
-    }
-    __syncthreads();
-    if (s_abort) return;
-    if (s_red) {
-      reduce_slice(t, a, r_next, g, wave, lane);
-      __syncthreads();
-      if (tid == 0) atomicAdd(t.cons + (r_next % kRing), 1u);
-      ++r_next;
-    } else {
-      __builtin_amdgcn_s_sleep(2);
-    }
-    __syncthreads();
-  }
+  // ---- write the columns back
 #pragma unroll
   for (int k = 0; k < CW; ++k) {
     const uint32_t c = cg + uint32_t(k) * NCG;
-    if (live && c < C) {
-      t.X[size_t(j0 + c) * t.Wp + w] = xr[k];
-      t.Z[size_t(j0 + c) * t.Wp + w] = zl[k * 64];
+    if (live && uint32_t(k) < ns) {
+      t.X[size_t(g + c * G) * t.Wp + w] = xr[k];
+      t.Z[size_t(g + c * G) * t.Wp + w] = zl[k * 64];
     }
   }
   if (tid == 0) {
@@ -412,24 +339,49 @@ __global__ void __launch_bounds__(1024) k_meas_xz(TabDev t, PersistArgs a) {
   }
 }
 
+// --------------------------------------------------------------- reduce ---
+// c1[m][w] from the partials of all workgroups (mod-4 sum), with the check
+// that the low counter plane vanishes on every updated row but p-n.
+__global__ void __launch_bounds__(256) k_meas_reduce(TabDev t, uint32_t k, uint32_t G) {
+  const uint32_t m = blockIdx.x, w = blockIdx.y * blockDim.x + threadIdx.x;
+  if (m >= k || w >= t.W) return;
+  const uint32_t p = t.pivall[m];
+  if (p == kNone) return;
+  const uint64_t *part = t.ring + size_t(m) * G * t.Wp * 2 + size_t(w) * 2;
+  uint64_t c0 = 0, c1 = 0;
+  for (uint32_t q = 0; q < G; ++q) {
+    const uint64_t b0 = part[size_t(q) * t.Wp * 2], b1 = part[size_t(q) * t.Wp * 2 + 1];
+    c1 ^= b1 ^ (c0 & b0);
+    c0 ^= b0;
+  }
+  uint64_t mw = t.SNall[size_t(m) * t.Wp + w];
+  if (w == (p >> 6)) mw &= ~pbit(p);
+  uint64_t bad = c0 & mw;
+  const uint32_t pn = p - t.n;
+  if (w == (pn >> 6)) bad &= ~pbit(pn);   // row p-n anticommutes with the pivot
+  if (bad) atomicAdd(&t.state[ST_ANOMALY], uint32_t(__popcll(bad)));
+  t.C1all[size_t(m) * t.Wp + w] = c1;
+}
+
 // ---------------------------------------------------------------- signs ---
-// One workgroup per shot: walks the measurements in order with the shot's
-// sign column in LDS.
-__global__ void __launch_bounds__(256) k_meas_signs(TabDev t, uint32_t k, uint64_t seed,
+// One workgroup per shot walks the chunk in order with the shot's sign
+// column in LDS.  Measurement m of the chunk has index base + m in the call.
+__global__ void __launch_bounds__(256) k_meas_signs(TabDev t, uint32_t k, uint32_t base, uint64_t seed,
                                                     uint64_t circuit, uint64_t shot0, uint64_t m0) {
   __shared__ uint64_t sR[16 * 64];
-  __shared__ uint32_t s_rt, s_rp;
+  __shared__ uint32_t s_rt;
   const uint32_t s = blockIdx.x, tid = threadIdx.x, W = t.W, S = t.S, n = t.n;
   for (uint32_t w = tid; w < W; w += blockDim.x) sR[w] = t.R[size_t(w) * S + s];
   __syncthreads();
   for (uint32_t m = 0; m < k; ++m) {
     const uint32_t p = t.pivall[m];
     const uint64_t *col = t.SNall + size_t(m) * t.Wp;
+    const size_t slot = size_t(base) + m;
     if (p != kNone) {
       const uint32_t rp = uint32_t(sR[p >> 6] >> (p & 63)) & 1u;
       __syncthreads();
       const uint32_t pn = p - n;
-      const uint32_t o = outcome_bit(seed, circuit, shot0 + s, m0 + m);
+      const uint32_t o = outcome_bit(seed, circuit, shot0 + s, m0 + slot);
       for (uint32_t w = tid; w < W; w += blockDim.x) {
         uint64_t mw = col[w];
         if (w == (p >> 6)) mw &= ~pbit(p);
@@ -440,8 +392,8 @@ __global__ void __launch_bounds__(256) k_meas_signs(TabDev t, uint32_t k, uint64
         sR[w] = rv;
       }
       if (tid == 0) {
-        t.out[size_t(m) * S + s] = uint8_t(o);
-        if (s == 0) t.kind[m] = 1;
+        t.out[slot * S + s] = uint8_t(o);
+        if (s == 0) t.kind[slot] = 1;
       }
     } else {
       if (tid == 0) s_rt = 0;
@@ -453,9 +405,9 @@ __global__ void __launch_bounds__(256) k_meas_signs(TabDev t, uint32_t k, uint64
       __syncthreads();
       if (tid == 0) {
         const uint32_t y = t.detY[m];
-        t.out[size_t(m) * S + s] = uint8_t(s_rt ^ (t.detpar[m] & 1u) ^ ((y >> 1) & 1u));
+        t.out[slot * S + s] = uint8_t(s_rt ^ (t.detpar[m] & 1u) ^ ((y >> 1) & 1u));
         if (s == 0) {
-          t.kind[m] = 0;
+          t.kind[slot] = 0;
           if (y & 1u) atomicAdd(&t.state[ST_ANOMALY], 1u);
         }
       }
@@ -487,41 +439,32 @@ __global__ void __launch_bounds__(1024) k_meas_begin(TabDev t, const uint32_t *q
     t.detpar[i] = 0;
     t.detY[i] = 0;
   }
-  for (uint32_t i = tid; i < kRing; i += blockDim.x) {
-    t.wr[i] = 0;
-    t.cons[i] = 0;
-  }
   if (tid == 0) *t.abort_flag = 0;
   __syncthreads();
   if (tid == 0) {
     t.pivall[0] = s_p;
-    t.flags[0] = 1;
+    t.flags[0] = s_p + 2u;   // pivot row + 2: never zero
   }
 }
 
-// Launch shape of the register-resident path for n qubits (0 = not usable).
+// Launch shape of the register-resident path for n qubits (false = not usable).
 bool persist_shape(uint32_t n, uint32_t num_cus, uint32_t *G, uint32_t *T, uint32_t *NCG, uint32_t *CW) {
+  if (!persist_layout(n)) return false;
   const uint32_t W = (2 * n + 63) / 64;
-  if (W < 64) return false;   // small tableaux: the step kernel is the better fit
   const uint32_t t = (W + 63) / 64;
-  if (t > 16) return false;
   const uint32_t ncg = 16 / t;
   const uint32_t gmax = num_cus < kPersistMaxGroups ? num_cus : kPersistMaxGroups;
   for (uint32_t cw : {4u, 8u, 12u, 14u}) {
-    // fewest workgroups whose columns fit ncg * cw per workgroup
-    const uint32_t per = ncg * cw;
-    const uint32_t g = (n + per - 1) / per;
-    if (g <= gmax) {
-      // use at least a quarter of the machine so the sweep has enough waves
-      uint32_t gg = g < gmax / 4 ? gmax / 4 : g;
-      if (gg < 1) gg = 1;
-      while ((n + gg - 1) / gg > per) ++gg;
-      *G = gg;
-      *T = t;
-      *NCG = ncg;
-      *CW = cw;
-      return true;
-    }
+    const uint32_t per = ncg * cw;              // columns one workgroup can hold
+    uint32_t g = (n + per - 1) / per;
+    if (g > gmax) continue;
+    if (g < gmax / 4) g = gmax / 4;             // enough waves for the sweep
+    if (g < 1) g = 1;
+    *G = g;
+    *T = t;
+    *NCG = ncg;
+    *CW = cw;
+    return true;
   }
   return false;
 }
@@ -531,26 +474,33 @@ hipError_t launch_measure_persist(const TabDev &t, const uint32_t *dev_qubits, u
                                   int num_cus, hipStream_t st, Profiler *prof) {
   uint32_t G, T, NCG, CW;
   if (!persist_shape(t.n, uint32_t(num_cus), &G, &T, &NCG, &CW)) return hipErrorInvalidValue;
-  if (prof) prof->begin(PK_SELECT, st);
-  k_meas_begin<<<1, 1024, 0, st>>>(t, dev_qubits, k);
-  if (prof) prof->end(PK_SELECT, st);
-  hipError_t e = hipGetLastError();
-  if (e != hipSuccess) return e;
-  PersistArgs a{dev_qubits, k, G, T, NCG};
-  TabDev tv = t;
-  void *args[] = {&tv, &a};
+  const uint32_t kc = persist_chunk(t.n);
   const void *fn = CW == 4 ? reinterpret_cast<const void *>(k_meas_xz<4>)
                  : CW == 8 ? reinterpret_cast<const void *>(k_meas_xz<8>)
                  : CW == 12 ? reinterpret_cast<const void *>(k_meas_xz<12>)
                             : reinterpret_cast<const void *>(k_meas_xz<14>);
-  if (prof) prof->begin(PK_SWEEP, st);
-  e = hipLaunchCooperativeKernel(fn, dim3(G), dim3(1024), args, 0, st);
-  if (prof) prof->end(PK_SWEEP, st);
-  if (e != hipSuccess) return e;
-  if (prof) prof->begin(PK_FINAL, st);
-  k_meas_signs<<<t.S, 256, 0, st>>>(t, k, seed, circuit, shot0, m0);
-  if (prof) prof->end(PK_FINAL, st);
-  return hipGetLastError();
+  for (uint32_t base = 0; base < k; base += kc) {
+    const uint32_t cnt = k - base < kc ? k - base : kc;
+    if (prof) prof->begin(PK_SELECT, st);
+    k_meas_begin<<<1, 1024, 0, st>>>(t, dev_qubits + base, cnt);
+    if (prof) prof->end(PK_SELECT, st);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    PersistArgs a{dev_qubits + base, cnt, G, T, NCG};
+    TabDev tv = t;
+    void *args[] = {&tv, &a};
+    if (prof) prof->begin(PK_SWEEP, st);
+    e = hipLaunchCooperativeKernel(fn, dim3(G), dim3(1024), args, 0, st);
+    if (prof) prof->end(PK_SWEEP, st);
+    if (e != hipSuccess) return e;
+    if (prof) prof->begin(PK_FINAL, st);
+    k_meas_reduce<<<dim3(cnt, (t.W + 255) / 256), 256, 0, st>>>(t, cnt, G);
+    k_meas_signs<<<t.S, 256, 0, st>>>(t, cnt, base, seed, circuit, shot0, m0);
+    if (prof) prof->end(PK_FINAL, st);
+    e = hipGetLastError();
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
 }
 
 }  // namespace cliff
