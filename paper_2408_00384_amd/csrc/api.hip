@@ -262,9 +262,7 @@ int cliff_tab_bind(cliff_ctx *ctx, uint32_t n, uint32_t shots, void *dev, size_t
   v.C1all = reinterpret_cast<uint64_t *>(at(t->o.C1all));
   v.ring = reinterpret_cast<uint64_t *>(at(t->o.ring));
   v.pivall = reinterpret_cast<uint32_t *>(at(t->o.pivall));
-  v.flags = reinterpret_cast<uint32_t *>(at(t->o.flags));
-  v.wr = reinterpret_cast<uint32_t *>(at(t->o.wr));
-  v.cons = reinterpret_cast<uint32_t *>(at(t->o.cons));
+  v.pub = reinterpret_cast<uint64_t *>(at(t->o.pub));
   v.abort_flag = reinterpret_cast<uint32_t *>(at(t->o.abort_flag));
   v.n = n;
   v.S = shots;
@@ -541,16 +539,16 @@ static int measure_pass(cliff_tab *t, const uint32_t *qubits, size_t cnt, uint64
     const uint32_t *dq = nullptr;
     int rc = upload_stream(c, nullptr, 0, qubits, cnt, nullptr, &dq);
     if (rc) return rc;
+    uint32_t done = 0;
     hipError_t e = launch_measure_persist(t->dev, dq, uint32_t(cnt), seed, circuit, shot0, m0,
-                                          c->num_cus, st, &c->prof);
-    if (e == hipSuccess) {
-      t->persist_used = true;
-      return CLIFF_OK;
-    }
+                                          c->num_cus, st, &c->prof, &done);
+    if (done) t->persist_used = true;
+    if (e == hipSuccess) return CLIFF_OK;
     (void)hipGetLastError();
-    if (c->measure_mode == CLIFF_MEASURE_PERSISTENT)
-      return fail(CLIFF_EDEVICE, "cooperative launch failed: %s", hipGetErrorString(e));
-    // fall through: the step kernels need no co-residency
+    if (c->measure_mode == CLIFF_MEASURE_PERSISTENT || done)
+      return fail(CLIFF_EDEVICE, "cooperative launch failed after %u measurements: %s", done,
+                  hipGetErrorString(e));
+    // nothing measured yet: fall through, the step kernels need no co-residency
   }
   HIP_TRY(launch_measure_list(t->dev, qubits, uint32_t(cnt), seed, circuit, shot0, m0, st, &c->prof));
   return CLIFF_OK;

@@ -80,7 +80,7 @@ struct Dims {
 struct Offsets {
   size_t X, Z, R, P, M, xp, zp, rp, part, state, out, kind;
   size_t SN, piv, rps, detpar, detY, detr;
-  size_t SNall, pivall, flags, C1all, ring, wr, cons, abort_flag, total;
+  size_t SNall, pivall, pub, C1all, ring, abort_flag, total;
 };
 
 // Device view passed by value to kernels.
@@ -94,17 +94,20 @@ struct TabDev {
   uint64_t *rps;             // 2 x SW: pivot-row signs handed to the next step
   uint32_t *detpar, *detY;   // n: deterministic-outcome accumulators
   uint64_t *detr;            // n x SW
-  // register-resident path (n >= 2048), per chunk of measurements: published
-  // columns, pivots and flags, per-workgroup counter partials, and the
-  // reduced sign corrections
-  uint64_t *SNall, *C1all, *ring;
-  uint32_t *pivall, *flags, *wr, *cons, *abort_flag;
+  // register-resident path (n >= 2048), per chunk of measurements: measured
+  // columns and pivots, the tagged publication slots, per-workgroup counter
+  // partials, and the reduced sign corrections
+  uint64_t *SNall, *C1all, *ring, *pub;
+  uint32_t *pivall, *abort_flag;
   uint32_t n, S, W, Wp, NW, SW;
 };
 
 constexpr uint32_t kPersistMaxGroups = 256;
 constexpr uint32_t kPersistMaxChunk = 1024;   // measurements per chunk (qubit list held in LDS)
-inline bool persist_layout(uint32_t n) { return (2 * n + 63) / 64 >= 64 && (2 * n + 63) / 64 <= 1024; }
+constexpr uint32_t kPersistMaxWp = 960;       // row words: a column spans at most 15 waves
+inline bool persist_layout(uint32_t n) {
+  return (2 * n + 63) / 64 >= 64 && (2 * n + 63) / 64 <= kPersistMaxWp;
+}
 // Measurements per chunk of the register-resident path: bounded by the HBM
 // kept for per-workgroup counter partials (256 MB for n >= 8192, else 64 MB).
 inline uint32_t persist_chunk(uint32_t n) {
@@ -170,11 +173,9 @@ inline Offsets make_offsets(const Dims &d) {
   const size_t kc = pl ? persist_chunk(d.n) : 0;
   o.SNall = take(kc * d.Wp * 8);
   o.pivall = take(kc * 4);
-  o.flags = take(kc * 4);
+  o.pub = take(kc * 2 * d.Wp * 8);   // [m][word][2] tagged 32-bit halves
   o.C1all = take(kc * d.Wp * 8);
   o.ring = take(kc * kPersistMaxGroups * d.Wp * 16);   // partials [m][workgroup][word][2]
-  o.wr = take(0);
-  o.cons = take(0);
   o.abort_flag = take(pl ? 4 : 0);
   o.total = cur;
   return o;
@@ -195,9 +196,10 @@ hipError_t launch_measure_list(const TabDev &t, const uint32_t *qubits, uint32_t
                                Profiler *prof);
 hipError_t launch_clear_state(const TabDev &t, hipStream_t st);
 bool persist_shape(uint32_t n, uint32_t num_cus, uint32_t *G, uint32_t *T, uint32_t *NCG, uint32_t *CW);
+// *done = measurements whose launches were all enqueued (chunks before a failure).
 hipError_t launch_measure_persist(const TabDev &t, const uint32_t *dev_qubits, uint32_t k,
                                   uint64_t seed, uint64_t circuit, uint64_t shot0, uint64_t m0,
-                                  int num_cus, hipStream_t st, Profiler *prof);
+                                  int num_cus, hipStream_t st, Profiler *prof, uint32_t *done);
 hipError_t launch_batch(const void *descs, const uint64_t *ops, const uint32_t *offs, uint8_t *out,
                         const uint32_t *order, uint32_t count, uint64_t seed, uint32_t *work,
                         uint32_t team, uint32_t maxn, int num_cus, hipStream_t st);
