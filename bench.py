@@ -11,8 +11,9 @@ measure all, 1 shot (the rowsum-dominated single-tableau case).
 
 One JSON line is printed with circuits/s, the roofline of the dominant kernel
 (the rowsum sweep: algorithmic bytes from the device-side counters divided by
-the sweep time from HIP events on its stream) and the CPU oracle timed on a
-bounded sample of the same workload.
+the sweep kernels' time from HIP events recorded on their stream around every
+launch of the timed steps) and the CPU oracle timed on a bounded sample of
+the same workload.
 """
 from __future__ import annotations
 
@@ -27,6 +28,29 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0   # MI355X HBM3E peak
+
+# HBM bytes per launch of the dominant kernel from hardware counters
+# (FETCH_SIZE and WRITE_SIZE, each scaled by what it reads for a copy of known
+# size), valid only for the kernel sources they were taken on.
+TRAFFIC = {
+    "k_meas_xz": {
+        "sources": ("paper_2408_00384_amd/csrc/measure_persist.hip", "paper_2408_00384_amd/csrc/internal.h"),
+        "sha256": "e7a0940f72b533fc6e80c8a3dc201d3bb1080dd5fdd2767af6ce8b35d4c6ff9c",
+        "bytes_per_launch": 2.011e9,
+        "summary": "profiles/k_meas_xz_plain_n10000_measure_all.md",
+    },
+}
+
+
+def traffic_for(kernel: str):
+    import hashlib
+    rec = TRAFFIC.get(kernel)
+    if rec is None:
+        return None
+    h = hashlib.sha256()
+    for f in rec["sources"]:
+        h.update(open(os.path.join(ROOT, f), "rb").read())
+    return rec["bytes_per_launch"] if h.hexdigest() == rec["sha256"] else None
 
 WORKLOADS = {
     "small": dict(desc="plain CHP n=64, 64 layers, measure all, 16 shots", steps=20, warmup=3),
@@ -193,6 +217,8 @@ def main():
     ap.add_argument("--cpu-budget", type=float, default=20.0, help="seconds of oracle work")
     ap.add_argument("--no-batch", action="store_true", help="skip the batched-circuits leg")
     ap.add_argument("--no-serving", action="store_true", help="skip the serving leg")
+    ap.add_argument("--no-profile", action="store_true",
+                    help="no per-kernel HIP events (for hardware-counter runs); no roofline")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only copy 1 GiB device-to-device 4 times (known bytes, to scale HBM counters)")
     args = ap.parse_args()
@@ -239,6 +265,10 @@ def main():
         step()
         print("# warmup %d done" % (i + 1), file=sys.stderr, flush=True)
     torch.cuda.synchronize()
+    # per-kernel HIP events on the library's stream for every launch of the
+    # timed steps (a few microseconds per launch of overhead)
+    if not args.no_profile:
+        P.cliff_ctx_profile(ctx.handle, True)
     stream = torch.cuda.current_stream()
     ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     t0 = time.perf_counter()
@@ -259,17 +289,24 @@ def main():
     if gold is not None and c.shots == 1:
         parity = bool(np.array_equal(out[0], gold[: c.n]))
 
-    # profiled step: per-kernel HIP-event times and device-side byte counters
-    P.cliff_tab_reset_counters(tab.handle)
-    P.cliff_ctx_profile(ctx.handle, True)
-    step()
     prof = {k: P.cliff_ctx_profile_read(ctx.handle, k) for k in P.PROF_KINDS}
-    P.cliff_ctx_profile(ctx.handle, False)
+    if not args.no_profile:
+        P.cliff_ctx_profile(ctx.handle, False)
+    # device counters cover the last step (init clears them); steps are identical
     counters = P.cliff_tab_counters(tab.handle)
+    n, W = c.n, (2 * c.n + 63) // 64
+    nr, nd = counters["random"], counters["deterministic"]
+    alg_step = counters["alg_bytes"]
+    # the sweep kernel's share: x/z words of the pivot-touching columns
+    # (random) and the stabilizer halves (deterministic); the update mask,
+    # counter planes and row rewrites belong to the finalize kernels
+    sweep_step = alg_step - (8 * W * 3 + 80 * n) * nr
     sweep_ms, sweep_launches = prof["sweep"]
-    sweep_bytes = counters["sweep_bytes"]
-    achieved = sweep_bytes / (sweep_ms * 1e-3) / 1e9 if sweep_ms > 0 else 0.0
-    print("# kernels: " + ", ".join("%s %.2f ms/%d" % (k, v[0], v[1]) for k, v in prof.items()),
+    persistent = sweep_launches < steps * len(qubits)
+    achieved = steps * sweep_step / (sweep_ms * 1e-3) / 1e9 if sweep_ms > 0 else 0.0
+    meas_ms = sum(prof[k][0] for k in ("select", "sweep", "final"))
+    print("# kernels over %d steps: " % steps
+          + ", ".join("%s %.2f ms/%d" % (k, v[0], v[1]) for k, v in prof.items()),
           file=sys.stderr, flush=True)
 
     result = {
@@ -291,15 +328,26 @@ def main():
                    "generator_seed": {"small": 0, "mid": 1, "large": 2}[args.workload]},
         "parity_vs_stored_oracle": parity,
         "roofline": {
-            "kernel": "rowsum sweep (k_sweep)",
+            "kernel": ("k_meas_xz (register-resident rowsum sweep, one launch per chunk "
+                       "of measurements)" if persistent else
+                       "k_step (rowsum sweep, one launch per measurement)"),
             "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-            "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+            "frac": achieved / HBM_PEAK_GBS,
+            "traffic": traffic_for("k_meas_xz") if persistent and args.workload == "large" else None,
             "launches": sweep_launches, "avg_launch_us": 1e3 * sweep_ms / max(1, sweep_launches),
-            "alg_bytes_per_launch": sweep_bytes / max(1, sweep_launches),
+            "alg_bytes_per_launch": steps * sweep_step / max(1, sweep_launches),
         },
-        "kernel_ms": {k: round(v[0], 3) for k, v in prof.items()},
+        "measure_phase": {
+            "alg_bytes_per_step": alg_step,
+            "ms_per_step": meas_ms / steps,
+            "alg_gbs": alg_step / (meas_ms / steps * 1e-3) / 1e9 if meas_ms > 0 else 0.0,
+        },
+        "kernel_ms_per_step": {k: round(v[0] / steps, 3) for k, v in prof.items()},
         "anomalies": counters["anomalies"],
     }
+    if args.no_profile:
+        result["roofline"] = None
+        result.pop("measure_phase")
     if not args.no_batch:
         print("# batched circuits ...", file=sys.stderr, flush=True)
         result["batched"] = bench_batch(P, torch, np)

@@ -170,9 +170,12 @@ int cliff_tab_anomalies(cliff_tab *tab, uint64_t *count);
 
 /* Counters since init/reset: out4[0] anomalies (as above), out4[1] random
  * measurements, out4[2] deterministic measurements, out4[3] algorithmic bytes
- * of the rowsum sweeps: per random measurement 8 * (update-mask words that
- * are nonzero) * (2 s + s_x + s_z), s = columns where the pivot row is not I,
- * s_x / s_z = columns where it has an X / Z part.  Synchronizes. */
+ * of the measurements: per random measurement 8 W (2 s + s_x + s_z + 3) + 80 n
+ * (x and z words of the s columns where the pivot row is not I read, the s_x
+ * x-words and s_z z-words written, the update mask and two counter planes;
+ * the pivot-row gather and the rewrite of rows p-n and p), per deterministic
+ * one 8 n W (the stabilizer half of every column read); W = ceil(2n / 64).
+ * Synchronizes. */
 int cliff_tab_counters(cliff_tab *tab, uint64_t *out4);
 int cliff_tab_reset_counters(cliff_tab *tab);
 

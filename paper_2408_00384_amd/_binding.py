@@ -277,11 +277,11 @@ def cliff_tab_anomalies(tab) -> int:
 
 
 def cliff_tab_counters(tab):
-    """dict(anomalies, random, deterministic, sweep_bytes)."""
+    """dict(anomalies, random, deterministic, alg_bytes): see cliff_tab_counters."""
     out = np.zeros(4, np.uint64)
     _check(_lib.cliff_tab_counters(tab, _ptr(out, _u64p)), "cliff_tab_counters")
     return dict(anomalies=int(out[0]), random=int(out[1]), deterministic=int(out[2]),
-                sweep_bytes=int(out[3]))
+                alg_bytes=int(out[3]))
 
 
 def cliff_tab_reset_counters(tab):

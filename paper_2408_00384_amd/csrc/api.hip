@@ -742,12 +742,13 @@ extern "C" int cliff_tab_counters(cliff_tab *t, uint64_t *out4) {
   uint32_t st[kStateWords];
   HIP_TRY(hipMemcpyAsync(st, t->dev.state, sizeof st, hipMemcpyDeviceToHost, t->ctx->stream));
   HIP_TRY(hipStreamSynchronize(t->ctx->stream));
-  uint64_t bytes;
-  memcpy(&bytes, st + ST_SWEEP_BYTES, 8);
+  uint64_t support;
+  memcpy(&support, st + ST_SUPPORT, 8);
+  const uint64_t n = t->d.n, W = t->d.W, nr = st[ST_RANDOM_CNT], nd = st[ST_DET_CNT];
   out4[0] = st[ST_ANOMALY];
-  out4[1] = st[ST_RANDOM_CNT];
-  out4[2] = st[ST_DET_CNT];
-  out4[3] = bytes;
+  out4[1] = nr;
+  out4[2] = nd;
+  out4[3] = 8 * W * (support + 3 * nr) + 80 * n * nr + 8 * n * W * nd;
   return CLIFF_OK;
 }
 

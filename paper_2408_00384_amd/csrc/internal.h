@@ -33,7 +33,7 @@ enum : uint32_t {
   ST_ERROR = 4,      // sticky error bits
   ST_RANDOM_CNT = 5, // random measurements since bind
   ST_DET_CNT = 6,    // deterministic measurements since bind
-  ST_SWEEP_BYTES = 8,  // uint64 (words 8..9): algorithmic bytes of the rowsum sweeps
+  ST_SUPPORT = 8,      // uint64 (words 8..9): sum over random measurements of 2 s + s_x + s_z
 };
 
 // Kernel classes timed by the profiler.
@@ -109,10 +109,11 @@ inline bool persist_layout(uint32_t n) {
   return (2 * n + 63) / 64 >= 64 && (2 * n + 63) / 64 <= kPersistMaxWp;
 }
 // Measurements per chunk of the register-resident path: bounded by the HBM
-// kept for per-workgroup counter partials (256 MB for n >= 8192, else 64 MB).
+// kept for per-workgroup counter partials (1 GB for n >= 8192, else 64 MB);
+// fewer chunks mean fewer launches and tableau reloads.
 inline uint32_t persist_chunk(uint32_t n) {
   const uint32_t Wp = (((2 * n + 63) / 64) + 7) & ~7u;
-  const size_t budget = n >= 8192 ? (size_t(256) << 20) : (size_t(64) << 20);
+  const size_t budget = n >= 8192 ? (size_t(1) << 30) : (size_t(64) << 20);
   size_t kc = budget / (size_t(kPersistMaxGroups) * Wp * 16);
   if (kc < 16) kc = 16;
   if (kc > kPersistMaxChunk) kc = kPersistMaxChunk;

@@ -61,6 +61,16 @@ __device__ __forceinline__ void st_relaxed64(uint64_t *p, uint64_t v) {
   __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
+// Workgroup barrier ordering LDS only.  In the x/z and sign kernels the
+// waves of a workgroup share data through LDS alone (global memory is read
+// or written per thread, or exchanged between workgroups with atomics), so
+// global loads and stores may stay in flight across it.
+__device__ __forceinline__ void lds_barrier() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
+  __builtin_amdgcn_s_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
+}
+
 // Destabilizer half of a column shifted up by n rows (word w).
 __device__ __forceinline__ uint64_t det_word(const uint64_t *col, uint32_t n, uint32_t NW, uint32_t W,
                                              uint32_t w) {
@@ -157,7 +167,7 @@ __global__ void __launch_bounds__(1024) k_meas_xz(TabDev t, PersistArgs a) {
   __shared__ uint32_t s_p[2];                           // pivot row of measurement m in s_p[m & 1]
   __shared__ uint32_t s_xpm[2][kDataWaves], s_zpm[2][kDataWaves];   // per column group: bit k = slot k
   __shared__ uint32_t s_ztile[kDataWaves * CW], s_xtile[kDataWaves * CW];   // per column: bit = tile parity
-  __shared__ uint32_t s_abort, s_nzw, s_par, s_y, s_acc[2];
+  __shared__ uint32_t s_abort, s_par, s_y, s_acc[2];
   const uint32_t tid = threadIdx.x, lane = tid & 63;
   const uint32_t wave = __builtin_amdgcn_readfirstlane(tid >> 6);
   const uint32_t g = blockIdx.x, G = a.G, T = a.T, NCG = a.NCG;
@@ -174,7 +184,6 @@ __global__ void __launch_bounds__(1024) k_meas_xz(TabDev t, PersistArgs a) {
   for (uint32_t i = tid; i < a.k; i += blockDim.x) s_q[i] = a.qubits[i];
   if (tid == 0) {
     s_abort = 0;
-    s_nzw = 0;
     s_acc[0] = 0;
     s_acc[1] = 0;
   }
@@ -196,20 +205,20 @@ __global__ void __launch_bounds__(1024) k_meas_xz(TabDev t, PersistArgs a) {
   // loop's own memory operations, keeps waiting for every outstanding store
   // inside the sweep.
   __builtin_amdgcn_s_waitcnt(0);
-  __syncthreads();
+  lds_barrier();
   if (tid < W) {
     uint64_t v;
     if (fetch_published(t, 0, tid, &v)) s_col[0][tid] = v;
     else s_abort = 1;
   }
-  __syncthreads();
+  lds_barrier();
   if (loader) {
     const uint32_t p0 = apply_published(s_col[0], nullptr, kNone, W, n, lane);
     if (lane == 0) s_p[0] = p0;
   }
-  __syncthreads();
+  lds_barrier();
   if (s_abort) return;
-  unsigned long long bytes_acc = 0;   // algorithmic sweep bytes of this workgroup (thread 0)
+  unsigned long long sup_acc = 0;     // this workgroup's share of 2 s + s_x + s_z (thread 0)
   uint32_t n_random = 0, n_det = 0;
   uint64_t pf_lo = 0, pf_hi = 0;      // this thread's entries of slot m + 1, loaded early
 
@@ -260,7 +269,7 @@ __global__ void __launch_bounds__(1024) k_meas_xz(TabDev t, PersistArgs a) {
         s_y = 0;
       }
     }
-    __syncthreads();
+    lds_barrier();
     if (s_abort) return;
     // ---- phase 2: sweep m, then publish a_{m+2}; the loader applies
     // measurement m to the fetched column a_{m+1}
@@ -378,7 +387,7 @@ __global__ void __launch_bounds__(1024) k_meas_xz(TabDev t, PersistArgs a) {
       }
       const uint64_t pb = __ballot(par & 1u);
       for (int off = 32; off > 0; off >>= 1) ycnt += __shfl_xor(ycnt, off);
-      __syncthreads();
+      lds_barrier();
       if (lane == 0 && data) {
         uint32_t extra = __popcll(pb) & 1u;
         // carry into this tile from the z parities of the tiles before it
@@ -390,7 +399,7 @@ __global__ void __launch_bounds__(1024) k_meas_xz(TabDev t, PersistArgs a) {
         if (extra) atomicXor(&s_par, 1u);
         if (ycnt) atomicAdd(&s_y, ycnt);
       }
-      __syncthreads();
+      lds_barrier();
       if (tid == 0) {
         if (s_par) atomicXor(t.detpar + m, 1u);
         if (s_y) atomicAdd(t.detY + m, s_y);
@@ -400,10 +409,8 @@ __global__ void __launch_bounds__(1024) k_meas_xz(TabDev t, PersistArgs a) {
     if (p != kNone && data) {
       s_c0[wave * 64 + lane] = c0;
       s_c1[wave * 64 + lane] = c1;
-      const uint64_t nz = __ballot(live && mw != 0ull);
-      if (cg == 0 && lane == 0 && nz) atomicAdd(&s_nzw, uint32_t(__popcll(nz)));
     }
-    __syncthreads();
+    lds_barrier();
     // ---- phase 3: load this thread's entries of slot m + 2 early (its owner
     // publishes it during iteration m; checked at the next iteration's top),
     // combine the column groups and write the partials
@@ -428,12 +435,9 @@ __global__ void __launch_bounds__(1024) k_meas_xz(TabDev t, PersistArgs a) {
         st_relaxed64(part + size_t(ww) * 2 + 1, a1);
       }
       if (tid == 0) {
-        // algorithmic sweep bytes: per nonzero row word of the measured
-        // column, x and z of every pivot-touching column read and written
-        // (s_acc: 2 |x or z| + |x| + |z| over the pivot-row bits)
-        bytes_acc += 8ull * s_nzw * s_acc[b];
+        // pivot-row support over this workgroup's columns: 2 s + s_x + s_z
+        sup_acc += s_acc[b];
         ++n_random;
-        s_nzw = 0;
         s_acc[b] = 0;
       }
     } else if (tid == 0) {
@@ -450,8 +454,7 @@ __global__ void __launch_bounds__(1024) k_meas_xz(TabDev t, PersistArgs a) {
     }
   }
   if (tid == 0) {
-    if (bytes_acc)
-      atomicAdd(reinterpret_cast<unsigned long long *>(t.state + ST_SWEEP_BYTES), bytes_acc);
+    if (sup_acc) atomicAdd(reinterpret_cast<unsigned long long *>(t.state + ST_SUPPORT), sup_acc);
     if (g == 0) {
       atomicAdd(&t.state[ST_RANDOM_CNT], n_random);
       atomicAdd(&t.state[ST_DET_CNT], n_det);
@@ -484,57 +487,93 @@ __global__ void __launch_bounds__(256) k_meas_reduce(TabDev t, uint32_t k, uint3
 }
 
 // ---------------------------------------------------------------- signs ---
-// One workgroup per shot walks the chunk in order with the shot's sign
-// column in LDS.  Measurement m of the chunk has index base + m in the call.
-__global__ void __launch_bounds__(256) k_meas_signs(TabDev t, uint32_t k, uint32_t base, uint64_t seed,
-                                                    uint64_t circuit, uint64_t shot0, uint64_t m0) {
-  __shared__ uint64_t sR[16 * 64];
-  __shared__ uint32_t s_rt;
+// One workgroup per shot walks the chunk in order; thread w holds row word w
+// of the shot's sign column (W <= 960) in a register.  The measured column
+// and sign-correction words of the next kSignAhead measurements are loaded
+// ahead, so a step costs one LDS broadcast of the pivot row's sign and one
+// barrier.  Measurement m of the chunk has index base + m in the call.
+constexpr uint32_t kSignAhead = 8;
+
+__global__ void __launch_bounds__(1024) k_meas_signs(TabDev t, uint32_t k, uint32_t base, uint64_t seed,
+                                                     uint64_t circuit, uint64_t shot0, uint64_t m0) {
+  __shared__ uint32_t s_piv[kPersistMaxChunk], s_dp[kPersistMaxChunk], s_dy[kPersistMaxChunk];
+  __shared__ uint32_t s_bit[2], s_par[2];
   const uint32_t s = blockIdx.x, tid = threadIdx.x, W = t.W, S = t.S, n = t.n;
-  for (uint32_t w = tid; w < W; w += blockDim.x) sR[w] = t.R[size_t(w) * S + s];
-  __syncthreads();
-  for (uint32_t m = 0; m < k; ++m) {
-    const uint32_t p = t.pivall[m];
-    const uint64_t *col = t.SNall + size_t(m) * t.Wp;
-    const size_t slot = size_t(base) + m;
-    if (p != kNone) {
-      const uint32_t rp = uint32_t(sR[p >> 6] >> (p & 63)) & 1u;
-      __syncthreads();
-      const uint32_t pn = p - n;
-      const uint32_t o = outcome_bit(seed, circuit, shot0 + s, m0 + slot);
-      for (uint32_t w = tid; w < W; w += blockDim.x) {
-        uint64_t mw = col[w];
-        if (w == (p >> 6)) mw &= ~pbit(p);
-        const uint64_t c1 = t.C1all[size_t(m) * t.Wp + w];
-        uint64_t rv = sR[w] ^ (mw & (c1 ^ (rp ? ~0ull : 0ull)));
-        if (w == (pn >> 6)) rv = rp ? (rv | pbit(pn)) : (rv & ~pbit(pn));
-        if (w == (p >> 6)) rv = o ? (rv | pbit(p)) : (rv & ~pbit(p));
-        sR[w] = rv;
-      }
-      if (tid == 0) {
-        t.out[slot * S + s] = uint8_t(o);
-        if (s == 0) t.kind[slot] = 1;
-      }
-    } else {
-      if (tid == 0) s_rt = 0;
-      __syncthreads();
-      uint32_t par = 0;
-      for (uint32_t w = tid; w < W; w += blockDim.x)
-        par ^= uint32_t(__popcll(det_word(col, n, t.NW, W, w) & sR[w])) & 1u;
-      if (par) atomicXor(&s_rt, 1u);
-      __syncthreads();
-      if (tid == 0) {
-        const uint32_t y = t.detY[m];
-        t.out[slot * S + s] = uint8_t(s_rt ^ (t.detpar[m] & 1u) ^ ((y >> 1) & 1u));
-        if (s == 0) {
-          t.kind[slot] = 0;
-          if (y & 1u) atomicAdd(&t.state[ST_ANOMALY], 1u);
+  const uint32_t lane = tid & 63;
+  const bool own = tid < W;
+  for (uint32_t i = tid; i < k; i += blockDim.x) {
+    s_piv[i] = t.pivall[i];
+    s_dp[i] = t.detpar[i];
+    s_dy[i] = t.detY[i];
+  }
+  if (tid < 2) s_par[tid] = 0;
+  uint64_t r = own ? t.R[size_t(tid) * S + s] : 0ull;
+  uint64_t am[kSignAhead], ac[kSignAhead];   // words of measurements m .. m + kSignAhead - 1
+  // Loads are issued unconditionally (from word 0 of measurement 0 where
+  // there is nothing to load) so every path issues the same number and the
+  // compiler's wait counts stay exact.
+#pragma unroll
+  for (uint32_t d = 0; d < kSignAhead; ++d) {
+    const size_t at = (own && d < k) ? size_t(d) * t.Wp + tid : 0;
+    am[d] = t.SNall[at];
+    ac[d] = t.C1all[at];
+  }
+  // wait for these loads here, so the loop's waits track only its own
+  __builtin_amdgcn_s_waitcnt(0);
+  lds_barrier();
+  for (uint32_t mb = 0; mb < k; mb += kSignAhead) {
+#pragma unroll
+    for (uint32_t d = 0; d < kSignAhead; ++d) {
+      const uint32_t m = mb + d;
+      const uint32_t p = m < k ? s_piv[m] : 0u;
+      if (m < k) {   // uniform
+        const size_t slot = size_t(base) + m;
+        const uint32_t b = m & 1u;
+        if (p != kNone) {
+          const uint32_t wp = p >> 6, pn = p - n;
+          uint32_t o = 0;
+          if (tid == wp) {
+            s_bit[b] = uint32_t(r >> (p & 63)) & 1u;
+            o = outcome_bit(seed, circuit, shot0 + s, m0 + slot);
+            t.out[slot * S + s] = uint8_t(o);
+            if (s == 0) t.kind[slot] = 1;
+          }
+          lds_barrier();
+          const uint64_t rp = s_bit[b] ? ~0ull : 0ull;
+          if (own) {
+            uint64_t mw = am[d];
+            if (tid == wp) mw &= ~pbit(p);
+            r ^= mw & (ac[d] ^ rp);
+            if (tid == (pn >> 6)) r = rp ? (r | pbit(pn)) : (r & ~pbit(pn));
+            if (tid == wp) r = o ? (r | pbit(p)) : (r & ~pbit(p));
+          }
+        } else {
+          // deterministic: parity of the product rows' signs, then the x/z
+          // terms the x/z kernel accumulated
+          uint32_t par = 0;
+          if (own) par = uint32_t(__popcll(det_word(t.SNall + size_t(m) * t.Wp, n, t.NW, W, tid) & r)) & 1u;
+          const uint64_t pb = __ballot(par != 0);
+          if (lane == 0 && (__popcll(pb) & 1)) atomicXor(&s_par[b], 1u);
+          lds_barrier();
+          if (tid == 0) {
+            const uint32_t y = s_dy[m];
+            t.out[slot * S + s] = uint8_t(s_par[b] ^ (s_dp[m] & 1u) ^ ((y >> 1) & 1u));
+            if (s == 0) {
+              t.kind[slot] = 0;
+              if (y & 1u) atomicAdd(&t.state[ST_ANOMALY], 1u);
+            }
+            s_par[b] = 0;   // next used at m + 2, after the next barrier
+          }
         }
       }
+      // refill this ring entry with measurement m + kSignAhead
+      const uint32_t mf = m + kSignAhead;
+      const size_t at = (own && mf < k) ? size_t(mf) * t.Wp + tid : 0;
+      am[d] = t.SNall[at];
+      ac[d] = t.C1all[at];
     }
-    __syncthreads();
   }
-  for (uint32_t w = tid; w < W; w += blockDim.x) t.R[size_t(w) * S + s] = sR[w];
+  if (own) t.R[size_t(tid) * S + s] = r;
 }
 
 // ---------------------------------------------------------------- setup ---
@@ -632,7 +671,7 @@ hipError_t launch_measure_persist(const TabDev &t, const uint32_t *dev_qubits, u
     if (e != hipSuccess) return e;
     if (prof) prof->begin(PK_FINAL, st);
     k_meas_reduce<<<dim3(cnt, (t.W + 255) / 256), 256, 0, st>>>(t, cnt, G);
-    k_meas_signs<<<t.S, 256, 0, st>>>(t, cnt, base, seed, circuit, shot0, m0);
+    k_meas_signs<<<t.S, 1024, 0, st>>>(t, cnt, base, seed, circuit, shot0, m0);
     if (prof) prof->end(PK_FINAL, st);
     e = hipGetLastError();
     if (e != hipSuccess) return e;

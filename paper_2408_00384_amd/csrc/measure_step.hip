@@ -153,7 +153,7 @@ __device__ void finish_prev(const TabDev &t, const StepArgs &s, uint32_t G, uint
 __global__ void __launch_bounds__(1024) k_step(TabDev t, StepArgs s) {
   __shared__ uint64_t s_c0[1024], s_c1[1024];
   __shared__ uint64_t s_xp[kMaxOwnCols / 64], s_zp[kMaxOwnCols / 64];
-  __shared__ uint32_t s_pnext, s_nzw;
+  __shared__ uint32_t s_pnext;
   const uint32_t tid = threadIdx.x, lane = tid & 63;
   const uint32_t wave = __builtin_amdgcn_readfirstlane(tid >> 6);
   const uint32_t nw = blockDim.x >> 6;   // >= 2
@@ -164,10 +164,7 @@ __global__ void __launch_bounds__(1024) k_step(TabDev t, StepArgs s) {
     if (wave == 0 && s.has_prev) finish_prev(t, s, G, g, lane);
     return;
   }
-  if (tid == 0) {
-    s_pnext = kNone;
-    s_nzw = 0;
-  }
+  if (tid == 0) s_pnext = kNone;
   const uint32_t rwave = nw - 1;         // finishes the previous measurement
   const uint32_t nsw = nw - 1;           // sweep waves
   const uint32_t p = t.piv[s.slot % 4];
@@ -219,7 +216,6 @@ __global__ void __launch_bounds__(1024) k_step(TabDev t, StepArgs s) {
       const bool live = w < W;
       const uint64_t m = live ? upd_mask(t, s.slot, p, w) : 0ull;
       const bool touch = live && (m != 0 || w == wpn || w == wp);
-      if (cgi == 0 && sub == 0 && m != 0) atomicAdd(&s_nzw, 1u);
       uint64_t c0 = 0, c1 = 0;
       for (uint32_t jb = j0 + cslot; jb < j1; jb += U * cstride) {
         uint64_t xv[U], zv[U];
@@ -341,18 +337,17 @@ __global__ void __launch_bounds__(1024) k_step(TabDev t, StepArgs s) {
   if (tid == 0 && own_next) t.piv[(s.slot + 1) % 4] = s_pnext;
   if (tid == 0) {
     if (p != kNone) {
-      // algorithmic bytes of this workgroup's share of the rowsum sweep:
-      // 8 * (nonzero update-mask words) * (2 s + s_x + s_z) over its columns
+      // this workgroup's columns' share of 2 s + s_x + s_z (pivot-row support)
       uint32_t sx = 0, sz = 0, sxz = 0;
       for (uint32_t k = 0; k < (j1 - j0 + 63) / 64; ++k) {
         sx += uint32_t(__popcll(s_xp[k]));
         sz += uint32_t(__popcll(s_zp[k]));
         sxz += uint32_t(__popcll(s_xp[k] | s_zp[k]));
       }
-      const uint64_t bytes = 8ull * s_nzw * (2ull * sxz + sx + sz);
-      if (bytes)
-        atomicAdd(reinterpret_cast<unsigned long long *>(t.state + ST_SWEEP_BYTES),
-                  (unsigned long long)bytes);
+      const uint64_t sup = 2ull * sxz + sx + sz;
+      if (sup)
+        atomicAdd(reinterpret_cast<unsigned long long *>(t.state + ST_SUPPORT),
+                  (unsigned long long)sup);
     }
     if (g == 0) atomicAdd(&t.state[p != kNone ? ST_RANDOM_CNT : ST_DET_CNT], 1u);
   }

@@ -11,7 +11,7 @@ import numpy as np
 import pytest
 
 import oracle
-from inputs import (layered_circuit, plain_mid, plain_small, random_gate_list)
+from inputs import (layered_circuit, plain_large, plain_mid, plain_small, random_gate_list)
 
 pytestmark = pytest.mark.gpu
 
@@ -296,3 +296,70 @@ def test_persistent_equals_step_measure_all(ctx, n):
     for A, B in zip(a[2], b[2]):
         assert np.array_equal(A, B)
     assert a[3] == 0 and b[3] == 0
+
+
+def _golden_bits(hexstr, n):
+    return np.unpackbits(np.frombuffer(bytes.fromhex(hexstr), np.uint8), bitorder="little")[:n]
+
+
+def _tab_digest(x, z, r):
+    import hashlib
+    h = hashlib.sha256()
+    for arr in (x, z, r):
+        h.update(np.ascontiguousarray(arr, np.uint8).tobytes())
+    return h.hexdigest()
+
+
+@pytest.mark.parametrize("mode", ["auto", "step"])
+def test_plain_large_vs_stored_oracle(ctx, mode):
+    """n = 10,000, 20 layers, measure all, 1 shot, in the launch configuration
+    the benchmark times (op stream resident on the device, one measure-all
+    call) against the oracle's stored run: every outcome, which outcomes were
+    random, and digests of the tableau after the gates and at the end."""
+    import torch
+    from paper_2408_00384_amd import (MEASURE_AUTO, MEASURE_STEP, cliff_apply_encoded,
+                                      cliff_ctx_set_measure_mode, cliff_encode_layers,
+                                      cliff_measure, cliff_tab_init_zero)
+    path = os.path.join(GOLDEN, "plain_large.json")
+    if not os.path.exists(path):
+        pytest.skip("stored oracle run for n = 10,000 not present")
+    rec = json.load(open(path))
+    c = plain_large()
+    assert c.seed == rec["seed"]
+    cliff_ctx_set_measure_mode(ctx.handle, MEASURE_STEP if mode == "step" else MEASURE_AUTO)
+    try:
+        t = _tab(ctx, c.n, 1)
+        ops, offs = cliff_encode_layers(c.n, c.h, c.s, c.ctrl, c.tgt)
+        dev_ops = torch.from_numpy(ops.view(np.int64)).to("cuda:0")
+        cliff_tab_init_zero(t.handle)
+        cliff_apply_encoded(t.handle, dev_ops.data_ptr(), offs)
+        assert _tab_digest(*t.export()) == rec["after_gates_sha256"]
+        out, rnd = cliff_measure(t.handle, c.qubits, c.seed, c.circuit_id, 0, 0)
+    finally:
+        cliff_ctx_set_measure_mode(ctx.handle, MEASURE_AUTO)
+    assert np.array_equal(out[0], _golden_bits(rec["outcomes"], c.n))
+    assert np.array_equal(rnd, _golden_bits(rec["random"], c.n))
+    assert _tab_digest(*t.export()) == rec["final_sha256"]
+    assert t.anomalies() == 0
+
+
+def test_plain_large_prefix_vs_stored_oracle(ctx):
+    """The same circuit measured in three calls (16, 240 and the remaining
+    measurements, the measurement index continuing across calls), with the
+    tableau digest checked against the oracle's after 16 and 256."""
+    path = os.path.join(GOLDEN, "plain_large.json")
+    if not os.path.exists(path):
+        pytest.skip("stored oracle run for n = 10,000 not present")
+    rec = json.load(open(path))
+    c = plain_large()
+    t = _tab(ctx, c.n, 1).apply_circuit_gates(c)
+    outs, rnds = [], []
+    for lo, hi in ((0, 16), (16, 256), (256, c.n)):
+        o, r = t.measure(c.qubits[lo:hi], seed=c.seed, circuit=c.circuit_id, m0=lo)
+        outs.append(o[0])
+        rnds.append(r)
+        if str(hi) in rec["prefix_sha256"]:
+            assert _tab_digest(*t.export()) == rec["prefix_sha256"][str(hi)], "after %d" % hi
+    assert np.array_equal(np.concatenate(outs), _golden_bits(rec["outcomes"], c.n))
+    assert np.array_equal(np.concatenate(rnds), _golden_bits(rec["random"], c.n))
+    assert _tab_digest(*t.export()) == rec["final_sha256"]
