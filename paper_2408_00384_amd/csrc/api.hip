@@ -530,9 +530,8 @@ static int measure_pass(cliff_tab *t, const uint32_t *qubits, size_t cnt, uint64
                         uint64_t circuit, uint64_t shot0, uint64_t m0) {
   cliff_ctx *c = t->ctx;
   hipStream_t st = c->stream;
-  uint32_t G, T, NCG, CW;
-  const bool shape_ok = persist_layout(t->d.n) &&
-                        persist_shape(t->d.n, uint32_t(c->num_cus), &G, &T, &NCG, &CW);
+  uint32_t G, L, CW;
+  const bool shape_ok = persist_layout(t->d.n) && persist_shape(t->d.n, uint32_t(c->num_cus), &G, &L, &CW);
   if (c->measure_mode == CLIFF_MEASURE_PERSISTENT && !shape_ok)
     return fail(CLIFF_EINVAL, "register-resident measurement does not fit n = %u", t->d.n);
   if (c->measure_mode != CLIFF_MEASURE_STEP && shape_ok) {

@@ -104,7 +104,8 @@ struct TabDev {
 
 constexpr uint32_t kPersistMaxGroups = 256;
 constexpr uint32_t kPersistMaxChunk = 1024;   // measurements per chunk (qubit list held in LDS)
-constexpr uint32_t kPersistMaxWp = 960;       // row words: a column spans at most 15 waves
+constexpr uint32_t kPersistMaxWp = 320;       // row words: at most 5 per lane of a wave
+constexpr uint32_t kPersistMaxSlots = 6;      // whole columns per wave
 inline bool persist_layout(uint32_t n) {
   return (2 * n + 63) / 64 >= 64 && (2 * n + 63) / 64 <= kPersistMaxWp;
 }
@@ -196,7 +197,7 @@ hipError_t launch_measure_list(const TabDev &t, const uint32_t *qubits, uint32_t
                                uint64_t circuit, uint64_t shot0, uint64_t m0, hipStream_t st,
                                Profiler *prof);
 hipError_t launch_clear_state(const TabDev &t, hipStream_t st);
-bool persist_shape(uint32_t n, uint32_t num_cus, uint32_t *G, uint32_t *T, uint32_t *NCG, uint32_t *CW);
+bool persist_shape(uint32_t n, uint32_t num_cus, uint32_t *G, uint32_t *L, uint32_t *CW);
 // *done = measurements whose launches were all enqueued (chunks before a failure).
 hipError_t launch_measure_persist(const TabDev &t, const uint32_t *dev_qubits, uint32_t k,
                                   uint64_t seed, uint64_t circuit, uint64_t shot0, uint64_t m0,

@@ -9,25 +9,29 @@
 // the sign of the product of the selected stabilizers).  Only where the data
 // lives and how workgroups meet differs:
 //
-//  * x/z kernel (k_meas_xz): G workgroups of 16 waves; workgroup g owns the
+//  * x/z kernel (k_meas_xz): G workgroups of 8 waves; workgroup g owns the
 //    columns j = g (mod G), so consecutive qubits belong to different
-//    workgroups.  Each of the first 15 waves (data waves) holds, for one
-//    64-row word tile, up to CW of the workgroup's columns: x bits in
-//    registers, z bits in LDS, for the whole chunk, so the rowsum sweep
-//    touches no HBM.  Between workgroups only measured columns travel: right
-//    after its sweep of measurement m, the owner of a_{m+2} publishes that
-//    column as it stands after measurement m, as tagged 64-bit entries (32
-//    data bits and the 32-bit slot tag in one atomic store, so a reader knows
-//    each entry is complete without a separate flag or fence).  One iteration
-//    later every thread of every workgroup fetches one word of it into a
-//    double-buffered LDS slot, and wave 15 (the loader), while the data waves
-//    sweep measurement m + 1, applies measurement m + 1's update to it from
-//    the measured column and pivot the workgroup already holds (x ^= M when
-//    the pivot row has x = 1 there; rows p-n and p rewritten) and finds the
-//    next pivot row.  Only this local step is sequential; the cross-workgroup
-//    latency has a whole iteration of slack.
-//    Each workgroup writes its (c0, c1) counter pair per row word for every
-//    measurement of the chunk to HBM with write-through stores.
+//    workgroups, and wave v of it the workgroup's columns c = v (mod 8).  A
+//    wave holds up to CW whole columns: lane l has row words l, l + 64, ...
+//    (L = ceil(W / 64) of them) of each, x bits in registers and z bits in
+//    LDS, for the whole chunk, so the rowsum sweep touches no HBM and the
+//    per-column decisions (the pivot row's Pauli on it) are taken once per
+//    column rather than once per 64 rows.  Between workgroups only measured
+//    columns travel: right after its sweep of measurement m, the owner of
+//    a_{m+2} publishes that column as it stands after measurement m, as
+//    tagged 64-bit entries (32 data bits and the 32-bit slot tag in one
+//    atomic store, so a reader knows each entry is complete without a
+//    separate flag or fence).  Every workgroup issues the loads of that
+//    column (one word per thread, plus the pivot row's word) at the start of
+//    iteration m + 1 and uses them after its sweep: each thread applies
+//    measurement m + 1's update to its word (x ^= M where the pivot row has
+//    x = 1 on that column; rows p-n and p rewritten) and the workgroup takes
+//    the smallest stabilizer row with x = 1 as the next pivot.  The
+//    cross-workgroup latency is hidden behind a whole sweep; each iteration
+//    costs three LDS-only barriers.  The waves' mod-4 counters are summed in
+//    LDS with atomic XORs (the XOR's old value gives the carry into the high
+//    plane) and each workgroup writes its (c0, c1) pair per row word for
+//    every measurement of the chunk to HBM.
 //  * reduce kernel: c1[m][w] = mod-4 sum of the partials of all workgroups.
 //  * sign kernel: one workgroup per shot walks the chunk in order with that
 //    shot's sign column in LDS: r ^= M & (c1 ^ r_p), rows p-n and p rewritten,
@@ -42,11 +46,11 @@
 namespace cliff {
 
 constexpr uint32_t kSpinLimit = 1u << 20;   // polling rounds before giving up (~seconds)
-constexpr uint32_t kDataWaves = 15;         // wave 15 is the loader
+constexpr uint32_t kWaves = 8;              // waves of an x/z workgroup (256 VGPRs each)
 
 struct PersistArgs {
   const uint32_t *qubits;   // device, this chunk's k entries
-  uint32_t k, G, T, NCG;
+  uint32_t k, G;
 };
 
 __device__ __forceinline__ uint64_t pbit(uint32_t b) { return 1ull << (b & 63); }
@@ -88,140 +92,119 @@ __device__ __forceinline__ uint64_t det_word(const uint64_t *col, uint32_t n, ui
   return v;
 }
 
-// One thread per row word: wait for the tagged entries of word w of
-// published slot j and return the word; false when the wait gave up or
-// another workgroup raised the abort flag.
-__device__ __forceinline__ bool fetch_published(const TabDev &t, uint32_t j, uint32_t w, uint64_t *out) {
-  const uint64_t *src = t.pub + size_t(j) * 2 * t.Wp + 2 * w;
+// Entry pair of word w of published slot j; the data when both carry the
+// slot's tag.
+__device__ __forceinline__ bool tagged_word(uint64_t lo, uint64_t hi, uint32_t j, uint64_t *out) {
   const uint64_t tag = uint64_t(j + 1) << 32, hi_mask = ~0xffffffffull;
-  uint64_t lo = ld_relaxed64(src), hi = ld_relaxed64(src + 1);
+  *out = (lo & 0xffffffffull) | (hi << 32);
+  return (lo & hi_mask) == tag && (hi & hi_mask) == tag;
+}
+
+// Wait for word w of published slot j (pub: the slots, Wp: their stride in
+// words); false when the wait gave up or another workgroup raised the abort
+// flag.
+__device__ __forceinline__ bool wait_published(const uint64_t *pub, uint32_t Wp, uint32_t *abort_flag,
+                                               uint32_t j, uint32_t w, uint64_t *out) {
+  const uint64_t *src = pub + size_t(j) * 2 * Wp + 2 * w;
   uint32_t spins = 0;
-  while ((lo & hi_mask) != tag || (hi & hi_mask) != tag) {
-    if (__hip_atomic_load(t.abort_flag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) return false;
+  while (!tagged_word(ld_relaxed64(src), ld_relaxed64(src + 1), j, out)) {
+    if (ld_relaxed(abort_flag)) return false;
     if (++spins > kSpinLimit) {
-      atomicOr(t.abort_flag, 1u);
+      atomicOr(abort_flag, 1u);
       return false;
     }
     __builtin_amdgcn_s_sleep(1);
-    lo = ld_relaxed64(src);
-    hi = ld_relaxed64(src + 1);
   }
-  *out = (lo & 0xffffffffull) | (hi << 32);
   return true;
 }
 
-// Loader wave: col holds a fetched slot.  When pm != kNone the slot is the
-// column as it stood before the measurement whose measured column is colm
-// and pivot row pm: its update is applied in place (x ^= M if the pivot row
-// has x = 1 on this column, M = colm without row pm; row pm - n takes the
-// pivot row's bit, row pm is cleared).  Returns the pivot row of the result:
-// the smallest stabilizer row with x = 1, or kNone.
-__device__ uint32_t apply_published(uint64_t *col, const uint64_t *colm, uint32_t pm, uint32_t W,
-                                    uint32_t n, uint32_t lane) {
-  constexpr uint32_t kU = 2;   // words per lane in flight
-  uint32_t bit = 0;
-  if (pm != kNone) bit = uint32_t(col[pm >> 6] >> (pm & 63)) & 1u;   // read before any lane writes
-  __builtin_amdgcn_wave_barrier();
-  const uint32_t pn = pm - n;
-  uint32_t best = kNone;   // wave-uniform: words are visited in increasing order
-  for (uint32_t w0 = 0; w0 < W; w0 += 64 * kU) {
-    uint64_t v[kU], mw[kU];
-#pragma unroll
-    for (uint32_t u = 0; u < kU; ++u) {
-      const uint32_t w = w0 + u * 64 + lane;
-      v[u] = w < W ? col[w] : 0ull;
-      mw[u] = (w < W && pm != kNone && bit) ? colm[w] : 0ull;
-    }
-#pragma unroll
-    for (uint32_t u = 0; u < kU; ++u) {
-      const uint32_t w = w0 + u * 64 + lane;
-      uint64_t x = v[u];
-      if (w < W && pm != kNone) {
-        uint64_t m = mw[u];
-        if (w == (pm >> 6)) m &= ~pbit(pm);
-        x ^= m;
-        if (w == (pn >> 6)) x = bit ? (x | pbit(pn)) : (x & ~pbit(pn));
-        if (w == (pm >> 6)) x &= ~pbit(pm);
-        col[w] = x;
-      }
-      uint64_t sv = (w < W && w >= (n >> 6)) ? x : 0ull;
-      if (w == (n >> 6)) sv &= ~0ull << (n & 63);
-      const uint64_t bal = __ballot(sv != 0ull);
-      if (best == kNone && bal) {
-        const uint32_t l = uint32_t(__builtin_ctzll(bal));
-        const uint64_t hv = __shfl(sv, int(l));
-        best = (w0 + u * 64 + l) * 64 + uint32_t(__builtin_ctzll(hv));
-      }
-    }
-  }
-  return best;
+// Smallest stabilizer row with x = 1 in word w (value v) of a column, or kNone.
+__device__ __forceinline__ uint32_t pivot_candidate(uint64_t v, uint32_t w, uint32_t n, uint32_t W) {
+  if (w >= W || w < (n >> 6)) return kNone;
+  if (w == (n >> 6)) v &= ~0ull << (n & 63);
+  return v ? w * 64 + uint32_t(__builtin_ctzll(v)) : kNone;
 }
 
-template <int CW>
-__global__ void __launch_bounds__(1024) k_meas_xz(TabDev t, PersistArgs a) {
-  // x bits of the owned columns live in registers, z bits in LDS
-  __shared__ uint64_t sZ[kDataWaves * CW * 64];
-  __shared__ uint64_t s_c0[kDataWaves * 64], s_c1[kDataWaves * 64];
+// Minimum of a wave's candidates when lane l holds word 64 * wave + l (the
+// first lane with a candidate has the smallest); lane 0 folds it into *dst.
+__device__ __forceinline__ void wave_min_into(uint32_t cand, uint32_t lane, uint32_t *dst) {
+  const uint64_t bal = __ballot(cand != kNone);
+  if (bal) {
+    const uint32_t l = uint32_t(__builtin_ctzll(bal));
+    const uint32_t v = uint32_t(__builtin_amdgcn_readlane(int(cand), int(l)));
+    if (lane == 0) atomicMin(dst, v);
+  }
+}
+
+template <int L, int CW>
+__global__ void __launch_bounds__(kWaves * 64) k_meas_xz(TabDev t, PersistArgs a) {
+  // x bits of the owned columns live in registers, z bits in LDS:
+  // z of slot k, word i of this lane at sZ[((wave * CW + k) * L + i) * 64 + lane]
+  __shared__ uint64_t sZ[kWaves * CW * L * 64];
   __shared__ uint64_t s_col[2][kPersistMaxWp];          // column of measurement m in s_col[m & 1]
+  __shared__ unsigned long long s_s0[kPersistMaxWp], s_s1[kPersistMaxWp];   // workgroup counter sums
   __shared__ uint32_t s_q[kPersistMaxChunk];            // this chunk's measured qubits
   __shared__ uint32_t s_p[2];                           // pivot row of measurement m in s_p[m & 1]
-  __shared__ uint32_t s_xpm[2][kDataWaves], s_zpm[2][kDataWaves];   // per column group: bit k = slot k
-  __shared__ uint32_t s_ztile[kDataWaves * CW], s_xtile[kDataWaves * CW];   // per column: bit = tile parity
+  __shared__ uint32_t s_xpm[2][kWaves], s_zpm[2][kWaves];   // per wave: bit k = slot k
   __shared__ uint32_t s_abort, s_par, s_y, s_acc[2];
   const uint32_t tid = threadIdx.x, lane = tid & 63;
   const uint32_t wave = __builtin_amdgcn_readfirstlane(tid >> 6);
-  const uint32_t g = blockIdx.x, G = a.G, T = a.T, NCG = a.NCG;
+  const uint32_t g = blockIdx.x, G = a.G;
   const uint32_t n = t.n, W = t.W;
   const uint32_t C = g < n ? (n - g + G - 1) / G : 0;   // owned columns g, g+G, g+2G, ...
-  const bool data = wave < T * NCG;
-  const bool loader = wave == kDataWaves;
-  const uint32_t tile = data ? wave % T : 0, cg = data ? wave / T : 0;
-  // slots k < ns of this wave hold columns c = cg + k * NCG < C (wave-uniform)
-  const uint32_t ns = data && C > cg ? (C - cg + NCG - 1) / NCG : 0;
-  const uint32_t w = tile * 64 + lane;
-  const bool live = data && w < W;
+  // slots k < ns of this wave hold columns c = wave + 8 k < C (wave-uniform)
+  const uint32_t ns = C > wave ? (C - wave + kWaves - 1) / kWaves : 0;
+  const bool word = tid < W;   // this thread carries row word tid of the measured columns
+  uint64_t *zw = sZ + size_t(wave) * CW * L * 64 + lane;   // z of slot k, word i at zw[(k * L + i) * 64]
 
   for (uint32_t i = tid; i < a.k; i += blockDim.x) s_q[i] = a.qubits[i];
   if (tid == 0) {
     s_abort = 0;
     s_acc[0] = 0;
     s_acc[1] = 0;
+    s_p[0] = kNone;
+  }
+  if (word) {
+    s_s0[tid] = 0;
+    s_s1[tid] = 0;
   }
   // ---- load the owned columns: x into registers, z into LDS
-  uint64_t xr[CW];
-  uint64_t *zl = sZ + size_t(data ? wave : 0) * CW * 64 + lane;   // z of slot k at zl[k * 64]
+  uint64_t xr[CW][L];
 #pragma unroll
   for (int k = 0; k < CW; ++k) {
-    const uint32_t c = cg + uint32_t(k) * NCG;
-    const bool have = live && uint32_t(k) < ns;
-    // every lane loads (an in-range word when it has no column) so the loads
-    // of all slots are in flight together
-    const size_t at = have ? size_t(g + c * G) * t.Wp + w : 0;
-    const uint64_t xv = t.X[at], zv = t.Z[at];
-    xr[k] = have ? xv : 0ull;
-    if (data) zl[k * 64] = have ? zv : 0ull;
+    const uint32_t c = wave + uint32_t(k) * kWaves;
+#pragma unroll
+    for (int i = 0; i < L; ++i) {
+      const uint32_t w = uint32_t(i) * 64 + lane;
+      const bool have = uint32_t(k) < ns && w < W;
+      // every lane loads (an in-range word when it has nothing) so the loads
+      // of all slots are in flight together
+      const size_t at = have ? size_t(g + c * G) * t.Wp + w : 0;
+      const uint64_t xv = t.X[at], zv = t.Z[at];
+      xr[k][i] = have ? xv : 0ull;
+      zw[(k * L + i) * 64] = have ? zv : 0ull;
+    }
   }
   // Wait for these loads here: otherwise the compiler, merging them with the
   // loop's own memory operations, keeps waiting for every outstanding store
   // inside the sweep.
   __builtin_amdgcn_s_waitcnt(0);
   lds_barrier();
-  if (tid < W) {
-    uint64_t v;
-    if (fetch_published(t, 0, tid, &v)) s_col[0][tid] = v;
-    else s_abort = 1;
-  }
-  lds_barrier();
-  if (loader) {
-    const uint32_t p0 = apply_published(s_col[0], nullptr, kNone, W, n, lane);
-    if (lane == 0) s_p[0] = p0;
+  // ---- the first measured column (published complete by the setup kernel)
+  {
+    uint64_t v = 0;
+    if (word) {
+      if (!wait_published(t.pub, t.Wp, t.abort_flag, 0, tid, &v)) s_abort = 1;
+      s_col[0][tid] = v;
+    }
+    wave_min_into(pivot_candidate(v, tid, n, W), lane, &s_p[0]);
   }
   lds_barrier();
   if (s_abort) return;
   unsigned long long sup_acc = 0;     // this workgroup's share of 2 s + s_x + s_z (thread 0)
   uint32_t n_random = 0, n_det = 0;
-  uint64_t pf_lo = 0, pf_hi = 0;      // this thread's entries of slot m + 1, loaded early
 
+#pragma unroll 1
   for (uint32_t m = 0; m < a.k; ++m) {
     const uint32_t b = m & 1u;
     const uint32_t p = s_p[b];
@@ -229,210 +212,218 @@ __global__ void __launch_bounds__(1024) k_meas_xz(TabDev t, PersistArgs a) {
     const uint32_t am = s_q[m];
     const uint32_t pn = p - n, wpn = pn >> 6, wp = p >> 6;
     const uint64_t bpn = pbit(pn), bpb = pbit(p);
-    // ---- phase 1: fetch slot m + 1 (one word per thread); the row mask M and
-    // the pivot-row bits of the owned columns
-    if (m + 1 < a.k && tid < W) {
-      const uint64_t tag = uint64_t(m + 2) << 32, hi_mask = ~0xffffffffull;
-      uint64_t v;
-      if ((pf_lo & hi_mask) == tag && (pf_hi & hi_mask) == tag)
-        s_col[b ^ 1u][tid] = (pf_lo & 0xffffffffull) | (pf_hi << 32);
-      else if (fetch_published(t, m + 1, tid, &v))
-        s_col[b ^ 1u][tid] = v;
-      else
-        s_abort = 1;
-    }
-    uint64_t mw = 0;
-    if (live) {
-      mw = col[w];
-      if (p != kNone && w == wp) mw &= ~bpb;
-    }
-    if (p != kNone && live && w == wp) {
+    const bool next = m + 1 < a.k;
+    // ---- phase a: loads of slot m + 1 (this thread's word and the pivot
+    // row's word, issued unconditionally so wait counts stay exact); the
+    // pivot-row bits of the owned columns
+    const uint64_t *nsrc = t.pub + size_t(next ? m + 1 : 0) * 2 * t.Wp;
+    const uint32_t fw = word ? tid : 0, gw = p != kNone ? wp : 0;
+    const uint64_t f_lo = ld_relaxed64(nsrc + 2 * fw), f_hi = ld_relaxed64(nsrc + 2 * fw + 1);
+    const uint64_t g_lo = ld_relaxed64(nsrc + 2 * gw), g_hi = ld_relaxed64(nsrc + 2 * gw + 1);
+    if (p != kNone && lane == (wp & 63)) {
+      // the lane holding row p: its bits in the owned columns (every slot
+      // read, no branch, so the LDS reads overlap; slots past ns hold zeros)
+      const uint32_t ip = wp >> 6, sh = p & 63;
       uint32_t xm = 0, zm = 0;
 #pragma unroll
       for (int k = 0; k < CW; ++k) {
-        if (uint32_t(k) < ns) {
-          xm |= uint32_t((xr[k] >> (p & 63)) & 1u) << k;
-          zm |= uint32_t((zl[k * 64] >> (p & 63)) & 1u) << k;
-        }
+        uint64_t xv = 0;
+#pragma unroll
+        for (int i = 0; i < L; ++i) xv = uint32_t(i) == ip ? xr[k][i] : xv;
+        xm |= uint32_t((xv >> sh) & 1u) << k;
+        zm |= uint32_t((zw[(k * L + ip) * 64] >> sh) & 1u) << k;
       }
-      s_xpm[b][cg] = xm;
-      s_zpm[b][cg] = zm;
+      s_xpm[b][wave] = xm;
+      s_zpm[b][wave] = zm;
       atomicAdd(&s_acc[b], uint32_t(2 * __popc(xm | zm) + __popc(xm) + __popc(zm)));
     }
-    if (p == kNone) {
-      if (tid < kDataWaves * CW) {
-        s_ztile[tid] = 0;
-        s_xtile[tid] = 0;
-      }
-      if (tid == 0) {
-        s_par = 0;
-        s_y = 0;
-      }
+    if (tid == 0) {
+      s_p[b ^ 1u] = kNone;
+      s_par = 0;
+      s_y = 0;
     }
     lds_barrier();
-    if (s_abort) return;
-    // ---- phase 2: sweep m, then publish a_{m+2}; the loader applies
-    // measurement m to the fetched column a_{m+1}
-    const uint32_t xm = p != kNone && data ? __builtin_amdgcn_readfirstlane(s_xpm[b][cg]) : 0u;
-    const uint32_t zm = p != kNone && data ? __builtin_amdgcn_readfirstlane(s_zpm[b][cg]) : 0u;
-    uint64_t c0 = 0, c1 = 0;
+    // ---- phase b: sweep m, then publish a_{m+2}
     if (p != kNone) {
-      if (live) {
-        // One wave-uniform branch per slot on the pivot row's Pauli on that
-        // column.  Rows in M that anticommute with it there contribute
-        // g = +1 or -1 (pivot Y: g = z - x; X: g = z(2x - 1); Z: g = x(1 - 2z)),
-        // added to the mod-4 counter (c1, c0) as the two-bit value
-        // (minus, anti): c1 ^= minus ^ (c0 & anti), c0 ^= anti.  Columns where
-        // the pivot row is the identity are untouched.  Rows p-n and p are
-        // rewritten afterwards.
+      const uint32_t xm = __builtin_amdgcn_readfirstlane(s_xpm[b][wave]);
+      const uint32_t zm = __builtin_amdgcn_readfirstlane(s_zpm[b][wave]);
+      uint64_t mw[L], c0[L], c1[L];
 #pragma unroll
-        for (int k = 0; k < CW; ++k) {
-          if (uint32_t(k) >= ns) continue;
-          const uint32_t ty = ((xm >> k) & 1u) | (((zm >> k) & 1u) << 1);   // wave-uniform
-          if (ty == 0) continue;
-          const uint64_t x = xr[k], z = zl[k * 64];
-          if (ty == 1) {                       // pivot X: x ^= M
-            const uint64_t anti = z & mw, minus = anti & ~x;
-            c1 ^= minus ^ (c0 & anti);
-            c0 ^= anti;
-            xr[k] = x ^ mw;
-          } else if (ty == 2) {                // pivot Z: z ^= M
-            const uint64_t anti = x & mw, minus = anti & z;
-            c1 ^= minus ^ (c0 & anti);
-            c0 ^= anti;
-            zl[k * 64] = z ^ mw;
-          } else {                             // pivot Y: x ^= M, z ^= M
-            const uint64_t anti = (x ^ z) & mw, minus = anti & x;
-            c1 ^= minus ^ (c0 & anti);
-            c0 ^= anti;
-            xr[k] = x ^ mw;
-            zl[k * 64] = z ^ mw;
+      for (int i = 0; i < L; ++i) {
+        // the row mask M: rows other than p with x = 1 on the measured column
+        const uint32_t w = uint32_t(i) * 64 + lane;
+        mw[i] = w < W ? (w == wp ? col[w] & ~bpb : col[w]) : 0ull;
+        c0[i] = c1[i] = 0;
+      }
+      // One wave-uniform branch per column on the pivot row's Pauli on it.
+      // Rows in M that anticommute with it there contribute g = +1 or -1
+      // (pivot Y: g = z - x; X: g = z(2x - 1); Z: g = x(1 - 2z)), added to
+      // the mod-4 counter (c1, c0) as the two-bit value (minus, anti):
+      // c1 ^= minus ^ (c0 & anti), c0 ^= anti.  Columns where the pivot row
+      // is the identity are untouched.  Rows p-n and p are rewritten after.
+#pragma unroll
+      for (int k = 0; k < CW; ++k) {
+        if (uint32_t(k) >= ns) continue;
+        const uint32_t ty = ((xm >> k) & 1u) | (((zm >> k) & 1u) << 1);   // wave-uniform
+        if (ty == 0) continue;
+        uint64_t zz[L];
+#pragma unroll
+        for (int i = 0; i < L; ++i) zz[i] = zw[(k * L + i) * 64];
+        if (ty == 1) {                         // pivot X: x ^= M
+#pragma unroll
+          for (int i = 0; i < L; ++i) {
+            const uint64_t anti = zz[i] & mw[i], minus = anti & ~xr[k][i];
+            c1[i] ^= minus ^ (c0[i] & anti);
+            c0[i] ^= anti;
+            xr[k][i] ^= mw[i];
           }
-        }
-        // row p-n becomes the old row p; row p becomes Z on the measured
-        // qubit (only the waves holding those two words): x in the lane
-        // holding the word, branch-free over the slots; z with lane k
-        // rewriting slot k's word of that lane
-        if (tile == (wpn >> 6) || tile == (wp >> 6)) {
-          const uint64_t mpn = w == wpn ? bpn : 0ull, mp = w == wp ? bpb : 0ull;
+        } else if (ty == 2) {                  // pivot Z: z ^= M
 #pragma unroll
-          for (int k = 0; k < CW; ++k)
-            if (uint32_t(k) < ns) xr[k] = (xr[k] & ~(mpn | mp)) | (((xm >> k) & 1u) ? mpn : 0ull);
-          __builtin_amdgcn_wave_barrier();
-          if (lane < ns) {
-            uint64_t *zk = sZ + size_t(wave) * CW * 64 + lane * 64;
-            if (tile == (wpn >> 6)) {
-              uint64_t &zw = zk[wpn & 63];
-              zw = ((zm >> lane) & 1u) ? (zw | bpn) : (zw & ~bpn);
-            }
-            if (tile == (wp >> 6)) {
-              uint64_t &zw = zk[wp & 63];
-              zw = (g + (cg + lane * NCG) * G == am) ? (zw | bpb) : (zw & ~bpb);
-            }
+          for (int i = 0; i < L; ++i) {
+            const uint64_t anti = xr[k][i] & mw[i], minus = anti & zz[i];
+            c1[i] ^= minus ^ (c0[i] & anti);
+            c0[i] ^= anti;
+            zw[(k * L + i) * 64] = zz[i] ^ mw[i];
+          }
+        } else {                               // pivot Y: x ^= M, z ^= M
+#pragma unroll
+          for (int i = 0; i < L; ++i) {
+            const uint64_t anti = (xr[k][i] ^ zz[i]) & mw[i], minus = anti & xr[k][i];
+            c1[i] ^= minus ^ (c0[i] & anti);
+            c0[i] ^= anti;
+            xr[k][i] ^= mw[i];
+            zw[(k * L + i) * 64] = zz[i] ^ mw[i];
           }
         }
       }
+      // the wave's counters into the workgroup sums: mod-4 addition with the
+      // low plane's carry taken from the atomic XOR's old value
+#pragma unroll
+      for (int i = 0; i < L; ++i) {
+        const uint32_t w = uint32_t(i) * 64 + lane;
+        if (w < W && (c0[i] | c1[i])) {
+          const uint64_t old = atomicXor(&s_s0[w], (unsigned long long)c0[i]);
+          const uint64_t hi = c1[i] ^ (old & c0[i]);
+          if (hi) atomicXor(&s_s1[w], (unsigned long long)hi);
+        }
+      }
+      // row p-n becomes the old row p; row p becomes Z on the measured
+      // qubit: x in the lanes holding those words; z with lane k rewriting
+      // slot k's two words
+      const uint32_t ipn = wpn >> 6, ip = wp >> 6;
+#pragma unroll
+      for (int i = 0; i < L; ++i) {
+        if (uint32_t(i) != ipn && uint32_t(i) != ip) continue;   // wave-uniform
+        const uint64_t mpn = (uint32_t(i) == ipn && lane == (wpn & 63)) ? bpn : 0ull;
+        const uint64_t mp = (uint32_t(i) == ip && lane == (wp & 63)) ? bpb : 0ull;
+#pragma unroll
+        for (int k = 0; k < CW; ++k)
+          xr[k][i] = (xr[k][i] & ~(mpn | mp)) | (((xm >> k) & 1u) ? mpn : 0ull);
+      }
+      __builtin_amdgcn_wave_barrier();
+      if (lane < ns) {
+        uint64_t *zk = sZ + size_t(wave) * CW * L * 64 + size_t(lane) * L * 64;   // slot `lane`
+        uint64_t &za = zk[ipn * 64 + (wpn & 63)];
+        za = ((zm >> lane) & 1u) ? (za | bpn) : (za & ~bpn);
+        uint64_t &zb = zk[ip * 64 + (wp & 63)];
+        zb = (g + (wave + lane * kWaves) * G == am) ? (zb | bpb) : (zb & ~bpb);
+      }
     }
-    if (m + 2 < a.k && live) {
+    if (m + 2 < a.k) {
       // the owner publishes column a_{m+2} as it stands after measurement m
       const uint32_t a2 = s_q[m + 2];
       const uint32_t c2 = a2 / G;
-      if (a2 % G == g && c2 % NCG == cg) {
-        const uint32_t k2 = c2 / NCG;
-        uint64_t *dst = t.pub + size_t(m + 2) * 2 * t.Wp + 2 * w;
+      if (a2 % G == g && c2 % kWaves == wave) {
+        const uint32_t k2 = c2 / kWaves;
+        uint64_t *dst = t.pub + size_t(m + 2) * 2 * t.Wp;
         const uint64_t tag = uint64_t(m + 3) << 32;
         // one uniform branch per slot (a select chain over xr would make the
         // compiler index the register array dynamically)
 #pragma unroll
         for (int k = 0; k < CW; ++k) {
           if (uint32_t(k) != k2) continue;
-          st_relaxed64(dst, (xr[k] & 0xffffffffull) | tag);
-          st_relaxed64(dst + 1, (xr[k] >> 32) | tag);
+#pragma unroll
+          for (int i = 0; i < L; ++i) {
+            const uint32_t w = uint32_t(i) * 64 + lane;
+            if (w < W) {
+              st_relaxed64(dst + 2 * w, (xr[k][i] & 0xffffffffull) | tag);
+              st_relaxed64(dst + 2 * w + 1, (xr[k][i] >> 32) | tag);
+            }
+          }
         }
       }
     }
-    if (loader && m + 1 < a.k) {
-      const uint32_t pnext = apply_published(s_col[b ^ 1u], col, p, W, n, lane);
-      if (lane == 0) s_p[b ^ 1u] = pnext;
-      if (g == 0) {
-        // for the reduce and sign kernels after this one
-        for (uint32_t ww = lane; ww < W; ww += 64) t.SNall[size_t(m + 1) * t.Wp + ww] = s_col[b ^ 1u][ww];
-        if (lane == 0) t.pivall[m + 1] = pnext;
-      }
-    }
     if (p == kNone) {
-      // deterministic: pairs s < t of product rows with z_s x_t per column
-      // (prefix inside the tile, carry between tiles through LDS) and Y count
-      const uint64_t Tm = live ? det_word(col, n, t.NW, W, w) : 0ull;
+      // deterministic: per column, pairs s < t of product rows with z_s x_t
+      // (prefix parity inside a word, carry across lanes and words in row
+      // order) and the Y count; summed over the workgroup's columns
+      // (runtime loops, x picked out of the register array by selects: this
+      // branch is rare in dense states and must not cost registers)
       uint32_t ycnt = 0, par = 0;
-      if (data) {
+      const uint64_t below = pbit(lane) - 1;   // lanes before this one
+#pragma unroll 1
+      for (uint32_t k = 0; k < ns; ++k) {
+        uint32_t carry = 0;                    // z parity of the product rows in earlier words
+#pragma unroll 1
+        for (uint32_t i = 0; i < uint32_t(L); ++i) {
+          uint64_t xv = 0;
 #pragma unroll
-        for (int k = 0; k < CW; ++k) {
-          if (uint32_t(k) >= ns) continue;   // uniform across the wave
-          const uint32_t c = cg + uint32_t(k) * NCG;
-          const uint64_t xt = xr[k] & Tm, zt = zl[k * 64] & Tm;
+          for (int kk = 0; kk < CW; ++kk)
+#pragma unroll
+            for (int ii = 0; ii < L; ++ii) xv = (uint32_t(kk) == k && uint32_t(ii) == i) ? xr[kk][ii] : xv;
+          const uint64_t tm = det_word(col, n, t.NW, W, i * 64 + lane);
+          const uint64_t xt = xv & tm, zt = zw[(k * L + i) * 64] & tm;
           ycnt += uint32_t(__popcll(xt & zt));
           uint64_t pre = zt << 1;
           pre ^= pre << 1; pre ^= pre << 2; pre ^= pre << 4;
           pre ^= pre << 8; pre ^= pre << 16; pre ^= pre << 32;
           const uint64_t zb = __ballot(__popcll(zt) & 1);
-          const uint64_t xb = __ballot(__popcll(xt) & 1);
-          const uint32_t cin = uint32_t(__popcll(zb & (pbit(lane) - 1))) & 1u;
+          const uint32_t cin = (carry ^ uint32_t(__popcll(zb & below))) & 1u;
           par ^= (uint32_t(__popcll(xt & pre)) & 1u) ^ (cin & uint32_t(__popcll(xt)) & 1u);
-          if (lane == 0) {
-            if (__popcll(zb) & 1) atomicOr(&s_ztile[c], 1u << tile);
-            if (__popcll(xb) & 1) atomicOr(&s_xtile[c], 1u << tile);
-          }
+          carry ^= uint32_t(__popcll(zb)) & 1u;
         }
       }
       const uint64_t pb = __ballot(par & 1u);
       for (int off = 32; off > 0; off >>= 1) ycnt += __shfl_xor(ycnt, off);
-      lds_barrier();
-      if (lane == 0 && data) {
-        uint32_t extra = __popcll(pb) & 1u;
-        // carry into this tile from the z parities of the tiles before it
-        for (uint32_t k = 0; k < ns; ++k) {
-          const uint32_t c = cg + k * NCG;
-          const uint32_t carry = uint32_t(__popc(s_ztile[c] & ((1u << tile) - 1u))) & 1u;
-          extra ^= carry & (s_xtile[c] >> tile) & 1u;
-        }
-        if (extra) atomicXor(&s_par, 1u);
+      if (lane == 0) {
+        if (__popcll(pb) & 1) atomicXor(&s_par, 1u);
         if (ycnt) atomicAdd(&s_y, ycnt);
       }
-      lds_barrier();
-      if (tid == 0) {
-        if (s_par) atomicXor(t.detpar + m, 1u);
-        if (s_y) atomicAdd(t.detY + m, s_y);
-      }
-    }
-    // ---- this workgroup's partial counters for measurement m
-    if (p != kNone && data) {
-      s_c0[wave * 64 + lane] = c0;
-      s_c1[wave * 64 + lane] = c1;
     }
     lds_barrier();
-    // ---- phase 3: load this thread's entries of slot m + 2 early (its owner
-    // publishes it during iteration m; checked at the next iteration's top),
-    // combine the column groups and write the partials
-    if (m + 2 < a.k && tid < W) {
-      const uint64_t *src = t.pub + size_t(m + 2) * 2 * t.Wp + 2 * tid;
-      pf_lo = ld_relaxed64(src);
-      pf_hi = ld_relaxed64(src + 1);
+    // ---- phase c: column a_{m+1} and its pivot (one word per thread), then
+    // this workgroup's partial counters for measurement m
+    if (next) {
+      uint64_t v = 0, pw = 0;
+      bool ok = true;
+      if (word && !tagged_word(f_lo, f_hi, m + 1, &v))
+        ok = wait_published(t.pub, t.Wp, t.abort_flag, m + 1, tid, &v);
+      if (word && p != kNone && !tagged_word(g_lo, g_hi, m + 1, &pw))
+        ok &= wait_published(t.pub, t.Wp, t.abort_flag, m + 1, wp, &pw);
+      if (!ok) s_abort = 1;
+      if (word && p != kNone) {
+        // measurement m's update of the column: x ^= M where the pivot row
+        // has x = 1 on it; row p-n takes the pivot row's bit, row p is cleared
+        const uint32_t bit = uint32_t(pw >> (p & 63)) & 1u;
+        uint64_t mv = col[tid];
+        if (tid == wp) mv &= ~bpb;
+        if (bit) v ^= mv;
+        if (tid == wpn) v = bit ? (v | bpn) : (v & ~bpn);
+        if (tid == wp) v &= ~bpb;
+      }
+      if (word) {
+        s_col[b ^ 1u][tid] = v;
+        if (g == 0) t.SNall[size_t(m + 1) * t.Wp + tid] = v;   // for the kernels after this one
+      }
+      wave_min_into(pivot_candidate(v, tid, n, W), lane, &s_p[b ^ 1u]);
     }
     if (p != kNone) {
-      uint64_t *part = t.ring + (size_t(m) * G + g) * t.Wp * 2;
-      for (uint32_t ww = tid; ww < W; ww += blockDim.x) {
-        const uint32_t tl = ww / 64, ln = ww % 64;
-        uint64_t a0 = 0, a1 = 0;
-        for (uint32_t gg = 0; gg < NCG; ++gg) {
-          const uint32_t wv = gg * T + tl;
-          const uint64_t b0 = s_c0[wv * 64 + ln], b1 = s_c1[wv * 64 + ln];
-          a1 ^= b1 ^ (a0 & b0);
-          a0 ^= b0;
-        }
-        // read by the reduce kernel after this one: write-through, no fence
-        st_relaxed64(part + size_t(ww) * 2, a0);
-        st_relaxed64(part + size_t(ww) * 2 + 1, a1);
+      if (word) {
+        // read by the reduce kernel after this one: one 16-byte store
+        uint64_t *part = t.ring + (size_t(m) * G + g) * t.Wp * 2;
+        *reinterpret_cast<ulonglong2 *>(part + size_t(tid) * 2) = make_ulonglong2(s_s0[tid], s_s1[tid]);
+        s_s0[tid] = 0;
+        s_s1[tid] = 0;
       }
       if (tid == 0) {
         // pivot-row support over this workgroup's columns: 2 s + s_x + s_z
@@ -441,16 +432,25 @@ __global__ void __launch_bounds__(1024) k_meas_xz(TabDev t, PersistArgs a) {
         s_acc[b] = 0;
       }
     } else if (tid == 0) {
+      if (s_par) atomicXor(t.detpar + m, 1u);
+      if (s_y) atomicAdd(t.detY + m, s_y);
       ++n_det;
     }
+    lds_barrier();
+    if (s_abort) return;
+    if (next && g == 0 && tid == 0) t.pivall[m + 1] = s_p[b ^ 1u];
   }
   // ---- write the columns back
 #pragma unroll
   for (int k = 0; k < CW; ++k) {
-    const uint32_t c = cg + uint32_t(k) * NCG;
-    if (live && uint32_t(k) < ns) {
-      t.X[size_t(g + c * G) * t.Wp + w] = xr[k];
-      t.Z[size_t(g + c * G) * t.Wp + w] = zl[k * 64];
+    const uint32_t c = wave + uint32_t(k) * kWaves;
+#pragma unroll
+    for (int i = 0; i < L; ++i) {
+      const uint32_t w = uint32_t(i) * 64 + lane;
+      if (uint32_t(k) < ns && w < W) {
+        t.X[size_t(g + c * G) * t.Wp + w] = xr[k][i];
+        t.Z[size_t(g + c * G) * t.Wp + w] = zw[(k * L + i) * 64];
+      }
     }
   }
   if (tid == 0) {
@@ -590,7 +590,7 @@ __global__ void __launch_bounds__(1024) k_meas_begin(TabDev t, const uint32_t *q
        i += size_t(gridDim.x) * blockDim.x)
     t.pub[i] = 0;
   if (blockIdx.x == 1 && k > 1) {
-    // slot 1: column a_1 before measurement 0 (the loader applies it)
+    // slot 1: column a_1 before measurement 0 (each workgroup applies it)
     const uint64_t *c1 = t.X + size_t(qubits[1]) * t.Wp;
     for (uint32_t w = tid; w < t.Wp; w += blockDim.x) {
       const uint64_t x = w < t.W ? c1[w] : 0ull;
@@ -621,40 +621,48 @@ __global__ void __launch_bounds__(1024) k_meas_begin(TabDev t, const uint32_t *q
   if (tid == 0) t.pivall[0] = s_p;
 }
 
-// Launch shape of the register-resident path for n qubits (false = not usable).
-bool persist_shape(uint32_t n, uint32_t num_cus, uint32_t *G, uint32_t *T, uint32_t *NCG, uint32_t *CW) {
+// Launch shape of the register-resident path for n qubits (false = not
+// usable): G workgroups, L row words per lane, CW columns per wave.
+bool persist_shape(uint32_t n, uint32_t num_cus, uint32_t *G, uint32_t *L, uint32_t *CW) {
   if (!persist_layout(n)) return false;
   const uint32_t W = (2 * n + 63) / 64;
-  const uint32_t t = (W + 63) / 64;
-  const uint32_t ncg = kDataWaves / t;          // column groups of t data waves
+  const uint32_t l = (W + 63) / 64;
   const uint32_t gmax = num_cus < kPersistMaxGroups ? num_cus : kPersistMaxGroups;
-  for (uint32_t cw : {4u, 8u, 12u, 14u, 16u}) {
-    const uint32_t per = ncg * cw;              // columns one workgroup can hold
+  for (uint32_t cw = 1; cw <= kPersistMaxSlots; ++cw) {
+    const uint32_t per = kWaves * cw;           // columns one workgroup can hold
     uint32_t g = (n + per - 1) / per;
     if (g > gmax) continue;
     if (g < gmax / 4) g = gmax / 4;             // enough waves for the sweep
     if (g < 1) g = 1;
     *G = g;
-    *T = t;
-    *NCG = ncg;
+    *L = l;
     *CW = cw;
     return true;
   }
   return false;
 }
 
+template <int L>
+static const void *xz_kernel(uint32_t cw) {
+  switch (cw) {
+    case 1: return reinterpret_cast<const void *>(k_meas_xz<L, 1>);
+    case 2: return reinterpret_cast<const void *>(k_meas_xz<L, 2>);
+    case 3: return reinterpret_cast<const void *>(k_meas_xz<L, 3>);
+    case 4: return reinterpret_cast<const void *>(k_meas_xz<L, 4>);
+    case 5: return reinterpret_cast<const void *>(k_meas_xz<L, 5>);
+    default: return reinterpret_cast<const void *>(k_meas_xz<L, 6>);
+  }
+}
+
 hipError_t launch_measure_persist(const TabDev &t, const uint32_t *dev_qubits, uint32_t k,
                                   uint64_t seed, uint64_t circuit, uint64_t shot0, uint64_t m0,
                                   int num_cus, hipStream_t st, Profiler *prof, uint32_t *done) {
   *done = 0;
-  uint32_t G, T, NCG, CW;
-  if (!persist_shape(t.n, uint32_t(num_cus), &G, &T, &NCG, &CW)) return hipErrorInvalidValue;
+  uint32_t G, L, CW;
+  if (!persist_shape(t.n, uint32_t(num_cus), &G, &L, &CW)) return hipErrorInvalidValue;
   const uint32_t kc = persist_chunk(t.n);
-  const void *fn = CW == 4 ? reinterpret_cast<const void *>(k_meas_xz<4>)
-                 : CW == 8 ? reinterpret_cast<const void *>(k_meas_xz<8>)
-                 : CW == 12 ? reinterpret_cast<const void *>(k_meas_xz<12>)
-                 : CW == 14 ? reinterpret_cast<const void *>(k_meas_xz<14>)
-                            : reinterpret_cast<const void *>(k_meas_xz<16>);
+  const void *fn = L == 1 ? xz_kernel<1>(CW) : L == 2 ? xz_kernel<2>(CW) : L == 3 ? xz_kernel<3>(CW)
+                 : L == 4 ? xz_kernel<4>(CW) : xz_kernel<5>(CW);
   for (uint32_t base = 0; base < k; base += kc) {
     const uint32_t cnt = k - base < kc ? k - base : kc;
     if (prof) prof->begin(PK_SELECT, st);
@@ -662,11 +670,11 @@ hipError_t launch_measure_persist(const TabDev &t, const uint32_t *dev_qubits, u
     if (prof) prof->end(PK_SELECT, st);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    PersistArgs a{dev_qubits + base, cnt, G, T, NCG};
+    PersistArgs a{dev_qubits + base, cnt, G};
     TabDev tv = t;
     void *args[] = {&tv, &a};
     if (prof) prof->begin(PK_SWEEP, st);
-    e = hipLaunchCooperativeKernel(fn, dim3(G), dim3(1024), args, 0, st);
+    e = hipLaunchCooperativeKernel(fn, dim3(G), dim3(kWaves * 64), args, 0, st);
     if (prof) prof->end(PK_SWEEP, st);
     if (e != hipSuccess) return e;
     if (prof) prof->begin(PK_FINAL, st);
