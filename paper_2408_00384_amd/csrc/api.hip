@@ -122,6 +122,9 @@ struct cliff_ctx {
   size_t pinned_cap = 0;         // words
   hipEvent_t upload_done = nullptr;
   bool upload_pending = false;
+  // register-resident measurement: second stream and its events (lazily made)
+  hipStream_t aux = nullptr;
+  hipEvent_t persist_ev[4] = {nullptr, nullptr, nullptr, nullptr};
   int gate_mode = CLIFF_GATES_AUTO;
   int measure_mode = CLIFF_MEASURE_AUTO;
 };
@@ -187,6 +190,12 @@ int cliff_ctx_destroy(cliff_ctx *c) {
   if (c->dev_ops) (void)hipFree(c->dev_ops);
   if (c->pinned) (void)hipHostFree(c->pinned);
   if (c->upload_done) (void)hipEventDestroy(c->upload_done);
+  if (c->aux) {
+    (void)hipStreamSynchronize(c->aux);
+    (void)hipStreamDestroy(c->aux);
+  }
+  for (hipEvent_t &e : c->persist_ev)
+    if (e) (void)hipEventDestroy(e);
   delete c;
   return CLIFF_OK;
 }
@@ -538,9 +547,14 @@ static int measure_pass(cliff_tab *t, const uint32_t *qubits, size_t cnt, uint64
     const uint32_t *dq = nullptr;
     int rc = upload_stream(c, nullptr, 0, qubits, cnt, nullptr, &dq);
     if (rc) return rc;
+    if (!c->aux) {
+      HIP_TRY(hipStreamCreateWithFlags(&c->aux, hipStreamNonBlocking));
+      for (hipEvent_t &ev : c->persist_ev) HIP_TRY(hipEventCreateWithFlags(&ev, hipEventDisableTiming));
+    }
+    PersistStreams ps{st, c->aux, {c->persist_ev[0], c->persist_ev[1], c->persist_ev[2], c->persist_ev[3]}};
     uint32_t done = 0;
     hipError_t e = launch_measure_persist(t->dev, dq, uint32_t(cnt), seed, circuit, shot0, m0,
-                                          c->num_cus, st, &c->prof, &done);
+                                          c->num_cus, ps, &c->prof, &done);
     if (done) t->persist_used = true;
     if (e == hipSuccess) return CLIFF_OK;
     (void)hipGetLastError();

@@ -172,7 +172,8 @@ inline Offsets make_offsets(const Dims &d) {
   o.detY = take(size_t(d.n) * 4);
   o.detr = take(size_t(d.n) * d.SW * 8);
   const bool pl = persist_layout(d.n);
-  const size_t kc = pl ? persist_chunk(d.n) : 0;
+  // two of each, for chunk c and chunk c + 1 in flight together
+  const size_t kc = pl ? 2 * size_t(persist_chunk(d.n)) : 0;
   o.SNall = take(kc * d.Wp * 8);
   o.pivall = take(kc * 4);
   o.pub = take(kc * 2 * d.Wp * 8);   // [m][word][2] tagged 32-bit halves
@@ -198,10 +199,17 @@ hipError_t launch_measure_list(const TabDev &t, const uint32_t *qubits, uint32_t
                                Profiler *prof);
 hipError_t launch_clear_state(const TabDev &t, hipStream_t st);
 bool persist_shape(uint32_t n, uint32_t num_cus, uint32_t *G, uint32_t *L, uint32_t *CW);
+// Streams and events of the register-resident path: chunk c's x/z kernel
+// runs on `main` while chunk c - 1's reduction and sign walk run on `aux`;
+// ev[0..1] mark x/z done and ev[2..3] finalize done per scratch buffer.
+struct PersistStreams {
+  hipStream_t main, aux;
+  hipEvent_t ev[4];
+};
 // *done = measurements whose launches were all enqueued (chunks before a failure).
 hipError_t launch_measure_persist(const TabDev &t, const uint32_t *dev_qubits, uint32_t k,
                                   uint64_t seed, uint64_t circuit, uint64_t shot0, uint64_t m0,
-                                  int num_cus, hipStream_t st, Profiler *prof, uint32_t *done);
+                                  int num_cus, const PersistStreams &ps, Profiler *prof, uint32_t *done);
 hipError_t launch_batch(const void *descs, const uint64_t *ops, const uint32_t *offs, uint8_t *out,
                         const uint32_t *order, uint32_t count, uint64_t seed, uint32_t *work,
                         uint32_t team, uint32_t maxn, int num_cus, hipStream_t st);

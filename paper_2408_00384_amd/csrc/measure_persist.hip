@@ -487,37 +487,48 @@ __global__ void __launch_bounds__(256) k_meas_reduce(TabDev t, uint32_t k, uint3
 }
 
 // ---------------------------------------------------------------- signs ---
-// One workgroup per shot walks the chunk in order; thread w holds row word w
-// of the shot's sign column (W <= 960) in a register.  The measured column
-// and sign-correction words of the next kSignAhead measurements are loaded
-// ahead, so a step costs one LDS broadcast of the pivot row's sign and one
-// barrier.  Measurement m of the chunk has index base + m in the call.
-constexpr uint32_t kSignAhead = 8;
+// One workgroup of 256 threads per shot walks the chunk in order; thread t
+// holds row words t and t + 256 of the shot's sign column (W <= 512) in
+// registers.  The measured column and sign-correction words of the next
+// kSignAhead measurements are loaded ahead, so a step costs one LDS broadcast
+// of the pivot row's sign and one barrier.  Small enough in registers and LDS
+// to run beside the x/z kernel of the next chunk.  Measurement m of the
+// chunk has index base + m in the call.
+constexpr uint32_t kSignAhead = 4;
+constexpr uint32_t kSignThreads = 256;
+constexpr uint32_t kSignWords = 2;   // words per thread
 
-__global__ void __launch_bounds__(1024) k_meas_signs(TabDev t, uint32_t k, uint32_t base, uint64_t seed,
-                                                     uint64_t circuit, uint64_t shot0, uint64_t m0) {
+__global__ void __launch_bounds__(kSignThreads) k_meas_signs(TabDev t, uint32_t k, uint32_t base, uint64_t seed,
+                                                             uint64_t circuit, uint64_t shot0, uint64_t m0) {
   __shared__ uint32_t s_piv[kPersistMaxChunk], s_dp[kPersistMaxChunk], s_dy[kPersistMaxChunk];
   __shared__ uint32_t s_bit[2], s_par[2];
   const uint32_t s = blockIdx.x, tid = threadIdx.x, W = t.W, S = t.S, n = t.n;
   const uint32_t lane = tid & 63;
-  const bool own = tid < W;
   for (uint32_t i = tid; i < k; i += blockDim.x) {
     s_piv[i] = t.pivall[i];
     s_dp[i] = t.detpar[i];
     s_dy[i] = t.detY[i];
   }
   if (tid < 2) s_par[tid] = 0;
-  uint64_t r = own ? t.R[size_t(tid) * S + s] : 0ull;
-  uint64_t am[kSignAhead], ac[kSignAhead];   // words of measurements m .. m + kSignAhead - 1
+  uint64_t r[kSignWords];
+#pragma unroll
+  for (uint32_t j = 0; j < kSignWords; ++j) {
+    const uint32_t w = tid + j * kSignThreads;
+    r[j] = w < W ? t.R[size_t(w) * S + s] : 0ull;
+  }
   // Loads are issued unconditionally (from word 0 of measurement 0 where
   // there is nothing to load) so every path issues the same number and the
   // compiler's wait counts stay exact.
+  uint64_t am[kSignAhead][kSignWords], ac[kSignAhead][kSignWords];   // words of measurements m .. m + kSignAhead - 1
 #pragma unroll
-  for (uint32_t d = 0; d < kSignAhead; ++d) {
-    const size_t at = (own && d < k) ? size_t(d) * t.Wp + tid : 0;
-    am[d] = t.SNall[at];
-    ac[d] = t.C1all[at];
-  }
+  for (uint32_t d = 0; d < kSignAhead; ++d)
+#pragma unroll
+    for (uint32_t j = 0; j < kSignWords; ++j) {
+      const uint32_t w = tid + j * kSignThreads;
+      const size_t at = (w < W && d < k) ? size_t(d) * t.Wp + w : 0;
+      am[d][j] = t.SNall[at];
+      ac[d][j] = t.C1all[at];
+    }
   // wait for these loads here, so the loop's waits track only its own
   __builtin_amdgcn_s_waitcnt(0);
   lds_barrier();
@@ -530,28 +541,37 @@ __global__ void __launch_bounds__(1024) k_meas_signs(TabDev t, uint32_t k, uint3
         const size_t slot = size_t(base) + m;
         const uint32_t b = m & 1u;
         if (p != kNone) {
-          const uint32_t wp = p >> 6, pn = p - n;
+          const uint32_t wp = p >> 6, pn = p - n, wpn = pn >> 6;
           uint32_t o = 0;
-          if (tid == wp) {
-            s_bit[b] = uint32_t(r >> (p & 63)) & 1u;
+          if (tid == (wp % kSignThreads)) {
+            const uint64_t rw = wp / kSignThreads == 0 ? r[0] : r[1];
+            s_bit[b] = uint32_t(rw >> (p & 63)) & 1u;
             o = outcome_bit(seed, circuit, shot0 + s, m0 + slot);
             t.out[slot * S + s] = uint8_t(o);
             if (s == 0) t.kind[slot] = 1;
           }
           lds_barrier();
           const uint64_t rp = s_bit[b] ? ~0ull : 0ull;
-          if (own) {
-            uint64_t mw = am[d];
-            if (tid == wp) mw &= ~pbit(p);
-            r ^= mw & (ac[d] ^ rp);
-            if (tid == (pn >> 6)) r = rp ? (r | pbit(pn)) : (r & ~pbit(pn));
-            if (tid == wp) r = o ? (r | pbit(p)) : (r & ~pbit(p));
+#pragma unroll
+          for (uint32_t j = 0; j < kSignWords; ++j) {
+            const uint32_t w = tid + j * kSignThreads;
+            if (w >= W) continue;
+            uint64_t mw = am[d][j];
+            if (w == wp) mw &= ~pbit(p);
+            uint64_t rv = r[j] ^ (mw & (ac[d][j] ^ rp));
+            if (w == wpn) rv = rp ? (rv | pbit(pn)) : (rv & ~pbit(pn));
+            if (w == wp) rv = o ? (rv | pbit(p)) : (rv & ~pbit(p));
+            r[j] = rv;
           }
         } else {
           // deterministic: parity of the product rows' signs, then the x/z
           // terms the x/z kernel accumulated
           uint32_t par = 0;
-          if (own) par = uint32_t(__popcll(det_word(t.SNall + size_t(m) * t.Wp, n, t.NW, W, tid) & r)) & 1u;
+#pragma unroll
+          for (uint32_t j = 0; j < kSignWords; ++j) {
+            const uint32_t w = tid + j * kSignThreads;
+            if (w < W) par ^= uint32_t(__popcll(det_word(t.SNall + size_t(m) * t.Wp, n, t.NW, W, w) & r[j])) & 1u;
+          }
           const uint64_t pb = __ballot(par != 0);
           if (lane == 0 && (__popcll(pb) & 1)) atomicXor(&s_par[b], 1u);
           lds_barrier();
@@ -568,12 +588,20 @@ __global__ void __launch_bounds__(1024) k_meas_signs(TabDev t, uint32_t k, uint3
       }
       // refill this ring entry with measurement m + kSignAhead
       const uint32_t mf = m + kSignAhead;
-      const size_t at = (own && mf < k) ? size_t(mf) * t.Wp + tid : 0;
-      am[d] = t.SNall[at];
-      ac[d] = t.C1all[at];
+#pragma unroll
+      for (uint32_t j = 0; j < kSignWords; ++j) {
+        const uint32_t w = tid + j * kSignThreads;
+        const size_t at = (w < W && mf < k) ? size_t(mf) * t.Wp + w : 0;
+        am[d][j] = t.SNall[at];
+        ac[d][j] = t.C1all[at];
+      }
     }
   }
-  if (own) t.R[size_t(tid) * S + s] = r;
+#pragma unroll
+  for (uint32_t j = 0; j < kSignWords; ++j) {
+    const uint32_t w = tid + j * kSignThreads;
+    if (w < W) t.R[size_t(w) * S + s] = r[j];
+  }
 }
 
 // ---------------------------------------------------------------- setup ---
@@ -656,36 +684,61 @@ static const void *xz_kernel(uint32_t cw) {
 
 hipError_t launch_measure_persist(const TabDev &t, const uint32_t *dev_qubits, uint32_t k,
                                   uint64_t seed, uint64_t circuit, uint64_t shot0, uint64_t m0,
-                                  int num_cus, hipStream_t st, Profiler *prof, uint32_t *done) {
+                                  int num_cus, const PersistStreams &ps, Profiler *prof, uint32_t *done) {
   *done = 0;
   uint32_t G, L, CW;
   if (!persist_shape(t.n, uint32_t(num_cus), &G, &L, &CW)) return hipErrorInvalidValue;
   const uint32_t kc = persist_chunk(t.n);
+  // per-chunk scratch, two sets: chunk c uses set c & 1
+  TabDev tb[2] = {t, t};
+  tb[1].SNall += size_t(kc) * t.Wp;
+  tb[1].pivall += kc;
+  tb[1].pub += size_t(kc) * 2 * t.Wp;
+  tb[1].C1all += size_t(kc) * t.Wp;
+  tb[1].ring += size_t(kc) * kPersistMaxGroups * t.Wp * 2;
+  tb[1].detpar += kc;   // n >= 2048 >= 2 kc entries
+  tb[1].detY += kc;
+  const hipStream_t st = ps.main, aux = ps.aux;
   const void *fn = L == 1 ? xz_kernel<1>(CW) : L == 2 ? xz_kernel<2>(CW) : L == 3 ? xz_kernel<3>(CW)
                  : L == 4 ? xz_kernel<4>(CW) : xz_kernel<5>(CW);
-  for (uint32_t base = 0; base < k; base += kc) {
+  uint32_t last = 0;
+  for (uint32_t base = 0, c = 0; base < k; base += kc, ++c) {
     const uint32_t cnt = k - base < kc ? k - base : kc;
+    const uint32_t b = c & 1u;
+    last = b;
+    const TabDev &tv = tb[b];
+    // set b is free once chunk c - 2's finalize is done
+    hipError_t e = hipStreamWaitEvent(st, ps.ev[2 + b], 0);
+    if (e != hipSuccess) return e;
     if (prof) prof->begin(PK_SELECT, st);
-    k_meas_begin<<<64, 1024, 0, st>>>(t, dev_qubits + base, cnt);
+    k_meas_begin<<<64, 1024, 0, st>>>(tv, dev_qubits + base, cnt);
     if (prof) prof->end(PK_SELECT, st);
-    hipError_t e = hipGetLastError();
+    e = hipGetLastError();
     if (e != hipSuccess) return e;
     PersistArgs a{dev_qubits + base, cnt, G};
-    TabDev tv = t;
-    void *args[] = {&tv, &a};
+    TabDev targ = tv;
+    void *args[] = {&targ, &a};
     if (prof) prof->begin(PK_SWEEP, st);
     e = hipLaunchCooperativeKernel(fn, dim3(G), dim3(kWaves * 64), args, 0, st);
     if (prof) prof->end(PK_SWEEP, st);
     if (e != hipSuccess) return e;
-    if (prof) prof->begin(PK_FINAL, st);
-    k_meas_reduce<<<dim3(cnt, (t.W + 255) / 256), 256, 0, st>>>(t, cnt, G);
-    k_meas_signs<<<t.S, 1024, 0, st>>>(t, cnt, base, seed, circuit, shot0, m0);
-    if (prof) prof->end(PK_FINAL, st);
+    e = hipEventRecord(ps.ev[b], st);
+    if (e != hipSuccess) return e;
+    // finalize on the second stream, overlapping the next chunk's x/z kernel
+    e = hipStreamWaitEvent(aux, ps.ev[b], 0);
+    if (e != hipSuccess) return e;
+    if (prof) prof->begin(PK_FINAL, aux);
+    k_meas_reduce<<<dim3(cnt, (t.W + 255) / 256), 256, 0, aux>>>(tv, cnt, G);
+    k_meas_signs<<<t.S, kSignThreads, 0, aux>>>(tv, cnt, base, seed, circuit, shot0, m0);
+    if (prof) prof->end(PK_FINAL, aux);
     e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    e = hipEventRecord(ps.ev[2 + b], aux);
     if (e != hipSuccess) return e;
     *done = base + cnt;
   }
-  return hipSuccess;
+  // the caller's stream sees the outcomes and signs only after the last finalize
+  return k ? hipStreamWaitEvent(st, ps.ev[2 + last], 0) : hipSuccess;
 }
 
 }  // namespace cliff
