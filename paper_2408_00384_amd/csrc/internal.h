@@ -105,7 +105,6 @@ struct TabDev {
 constexpr uint32_t kPersistMaxGroups = 256;
 constexpr uint32_t kPersistMaxChunk = 1024;   // measurements per chunk (qubit list held in LDS)
 constexpr uint32_t kPersistMaxWp = 320;       // row words: at most 5 per lane of a wave
-constexpr uint32_t kPersistMaxSlots = 6;      // whole columns per wave
 inline bool persist_layout(uint32_t n) {
   return (2 * n + 63) / 64 >= 64 && (2 * n + 63) / 64 <= kPersistMaxWp;
 }

@@ -9,34 +9,35 @@
 // the sign of the product of the selected stabilizers).  Only where the data
 // lives and how workgroups meet differs:
 //
-//  * x/z kernel (k_meas_xz): G workgroups of 8 waves; workgroup g owns the
-//    columns j = g (mod G), so consecutive qubits belong to different
-//    workgroups, and wave v of it the workgroup's columns c = v (mod 8).  A
-//    wave holds up to CW whole columns: lane l has row words l, l + 64, ...
-//    (L = ceil(W / 64) of them) of each, x bits in registers and z bits in
-//    LDS, for the whole chunk, so the rowsum sweep touches no HBM and the
-//    per-column decisions (the pivot row's Pauli on it) are taken once per
-//    column rather than once per 64 rows.  Between workgroups only measured
-//    columns travel: right after its sweep of measurement m, the owner of
-//    a_{m+2} publishes that column as it stands after measurement m, as
-//    tagged 64-bit entries (32 data bits and the 32-bit slot tag in one
-//    atomic store, so a reader knows each entry is complete without a
-//    separate flag or fence).  Every workgroup issues the loads of that
-//    column (one word per thread, plus the pivot row's word) at the start of
-//    iteration m + 1 and uses them after its sweep: each thread applies
-//    measurement m + 1's update to its word (x ^= M where the pivot row has
-//    x = 1 on that column; rows p-n and p rewritten) and the workgroup takes
-//    the smallest stabilizer row with x = 1 as the next pivot.  The
-//    cross-workgroup latency is hidden behind a whole sweep; each iteration
-//    costs three LDS-only barriers.  The waves' mod-4 counters are summed in
-//    LDS with atomic XORs (the XOR's old value gives the carry into the high
-//    plane) and each workgroup writes its (c0, c1) pair per row word for
-//    every measurement of the chunk to HBM.
+//  * x/z kernel (k_meas_xz): G workgroups of 8 waves (two per SIMD).
+//    Workgroup g owns the columns j = g (mod G), so consecutive qubits belong
+//    to different workgroups, and wave v of it the workgroup's columns
+//    c = v (mod 8).  A wave holds CW = L whole columns: lane l has row
+//    words l, l + 64, ... (L = ceil(W / 64) <= 5 of them) of each, x bits in
+//    registers and z bits in LDS, for the whole chunk, so the rowsum sweep
+//    touches no HBM and the per-column decisions (the pivot row's Pauli on
+//    the column) are taken once per column rather than once per 64 rows.
+//    Between workgroups only measured columns travel: right after its sweep
+//    of measurement m, the owner of a_{m+2} publishes that column as it
+//    stands after measurement m, as tagged 64-bit entries (32 data bits and
+//    the 32-bit slot tag in one atomic store, so a reader knows each entry is
+//    complete without a separate flag or fence).  Every workgroup issues the
+//    loads of that column (its words spread over the threads, plus the pivot
+//    row's word) at the start of iteration m + 1 and uses them after its
+//    sweep: each thread applies measurement m + 1's update to its words
+//    (x ^= M where the pivot row has x = 1 on that column; rows p-n and p
+//    rewritten) and the workgroup takes the smallest stabilizer row with
+//    x = 1 as the next pivot.  The cross-workgroup latency is hidden behind a
+//    whole sweep; each iteration costs three LDS-only barriers.  The waves'
+//    mod-4 counters are summed in LDS with atomic XORs (the XOR's old value
+//    gives the carry into the high plane) and each workgroup writes its
+//    (c0, c1) pair per row word for every measurement of the chunk to HBM.
 //  * reduce kernel: c1[m][w] = mod-4 sum of the partials of all workgroups.
 //  * sign kernel: one workgroup per shot walks the chunk in order with that
-//    shot's sign column in LDS: r ^= M & (c1 ^ r_p), rows p-n and p rewritten,
-//    outcome = Philox bit; deterministic outcomes from the XOR of the product
-//    rows' signs and the two x/z terms accumulated by the x/z kernel.
+//    shot's sign column in registers: r ^= M & (c1 ^ r_p), rows p-n and p
+//    rewritten, outcome = Philox bit; deterministic outcomes from the XOR of
+//    the product rows' signs and the two x/z terms accumulated by the x/z
+//    kernel.  It runs on a second stream beside the next chunk's x/z kernel.
 //
 // Every wait is bounded; a timeout raises a device-wide abort flag that every
 // wait checks, so all waves leave the kernel and the host reports the error.
@@ -46,7 +47,9 @@
 namespace cliff {
 
 constexpr uint32_t kSpinLimit = 1u << 20;   // polling rounds before giving up (~seconds)
-constexpr uint32_t kWaves = 8;              // waves of an x/z workgroup (256 VGPRs each)
+constexpr uint32_t kWaves = 8;              // waves of an x/z workgroup (two per SIMD, 256 VGPRs each)
+constexpr uint32_t kThreads = kWaves * 64;
+constexpr uint32_t kWordsPerThread = (kPersistMaxWp + kThreads - 1) / kThreads;   // row words t, t + 512, ...
 
 struct PersistArgs {
   const uint32_t *qubits;   // device, this chunk's k entries
@@ -137,7 +140,7 @@ __device__ __forceinline__ void wave_min_into(uint32_t cand, uint32_t lane, uint
 }
 
 template <int L, int CW>
-__global__ void __launch_bounds__(kWaves * 64) k_meas_xz(TabDev t, PersistArgs a) {
+__global__ void __launch_bounds__(kThreads) k_meas_xz(TabDev t, PersistArgs a) {
   // x bits of the owned columns live in registers, z bits in LDS:
   // z of slot k, word i of this lane at sZ[((wave * CW + k) * L + i) * 64 + lane]
   __shared__ uint64_t sZ[kWaves * CW * L * 64];
@@ -154,7 +157,7 @@ __global__ void __launch_bounds__(kWaves * 64) k_meas_xz(TabDev t, PersistArgs a
   const uint32_t C = g < n ? (n - g + G - 1) / G : 0;   // owned columns g, g+G, g+2G, ...
   // slots k < ns of this wave hold columns c = wave + 8 k < C (wave-uniform)
   const uint32_t ns = C > wave ? (C - wave + kWaves - 1) / kWaves : 0;
-  const bool word = tid < W;   // this thread carries row word tid of the measured columns
+  // thread t carries row words t + kThreads j (j < kWordsPerThread) of the measured columns
   uint64_t *zw = sZ + size_t(wave) * CW * L * 64 + lane;   // z of slot k, word i at zw[(k * L + i) * 64]
 
   for (uint32_t i = tid; i < a.k; i += blockDim.x) s_q[i] = a.qubits[i];
@@ -164,9 +167,9 @@ __global__ void __launch_bounds__(kWaves * 64) k_meas_xz(TabDev t, PersistArgs a
     s_acc[1] = 0;
     s_p[0] = kNone;
   }
-  if (word) {
-    s_s0[tid] = 0;
-    s_s1[tid] = 0;
+  for (uint32_t w = tid; w < W; w += kThreads) {
+    s_s0[w] = 0;
+    s_s1[w] = 0;
   }
   // ---- load the owned columns: x into registers, z into LDS
   uint64_t xr[CW][L];
@@ -191,13 +194,15 @@ __global__ void __launch_bounds__(kWaves * 64) k_meas_xz(TabDev t, PersistArgs a
   __builtin_amdgcn_s_waitcnt(0);
   lds_barrier();
   // ---- the first measured column (published complete by the setup kernel)
-  {
+#pragma unroll
+  for (uint32_t j = 0; j < kWordsPerThread; ++j) {
+    const uint32_t w = tid + j * kThreads;
     uint64_t v = 0;
-    if (word) {
-      if (!wait_published(t.pub, t.Wp, t.abort_flag, 0, tid, &v)) s_abort = 1;
-      s_col[0][tid] = v;
+    if (w < W) {
+      if (!wait_published(t.pub, t.Wp, t.abort_flag, 0, w, &v)) s_abort = 1;
+      s_col[0][w] = v;
     }
-    wave_min_into(pivot_candidate(v, tid, n, W), lane, &s_p[0]);
+    wave_min_into(pivot_candidate(v, w, n, W), lane, &s_p[0]);
   }
   lds_barrier();
   if (s_abort) return;
@@ -217,8 +222,14 @@ __global__ void __launch_bounds__(kWaves * 64) k_meas_xz(TabDev t, PersistArgs a
     // row's word, issued unconditionally so wait counts stay exact); the
     // pivot-row bits of the owned columns
     const uint64_t *nsrc = t.pub + size_t(next ? m + 1 : 0) * 2 * t.Wp;
-    const uint32_t fw = word ? tid : 0, gw = p != kNone ? wp : 0;
-    const uint64_t f_lo = ld_relaxed64(nsrc + 2 * fw), f_hi = ld_relaxed64(nsrc + 2 * fw + 1);
+    uint64_t f_lo[kWordsPerThread], f_hi[kWordsPerThread];
+#pragma unroll
+    for (uint32_t j = 0; j < kWordsPerThread; ++j) {
+      const uint32_t w = tid + j * kThreads, fw = w < W ? w : 0;
+      f_lo[j] = ld_relaxed64(nsrc + 2 * fw);
+      f_hi[j] = ld_relaxed64(nsrc + 2 * fw + 1);
+    }
+    const uint32_t gw = p != kNone ? wp : 0;
     const uint64_t g_lo = ld_relaxed64(nsrc + 2 * gw), g_hi = ld_relaxed64(nsrc + 2 * gw + 1);
     if (p != kNone && lane == (wp & 63)) {
       // the lane holding row p: its bits in the owned columns (every slot
@@ -391,39 +402,46 @@ __global__ void __launch_bounds__(kWaves * 64) k_meas_xz(TabDev t, PersistArgs a
       }
     }
     lds_barrier();
-    // ---- phase c: column a_{m+1} and its pivot (one word per thread), then
+    // ---- phase c: column a_{m+1} and its pivot (its words spread over the
+    // threads), then
     // this workgroup's partial counters for measurement m
     if (next) {
-      uint64_t v = 0, pw = 0;
       bool ok = true;
-      if (word && !tagged_word(f_lo, f_hi, m + 1, &v))
-        ok = wait_published(t.pub, t.Wp, t.abort_flag, m + 1, tid, &v);
-      if (word && p != kNone && !tagged_word(g_lo, g_hi, m + 1, &pw))
-        ok &= wait_published(t.pub, t.Wp, t.abort_flag, m + 1, wp, &pw);
+      uint64_t pw = 0;
+      if (tid < W && p != kNone && !tagged_word(g_lo, g_hi, m + 1, &pw))
+        ok = wait_published(t.pub, t.Wp, t.abort_flag, m + 1, wp, &pw);
+      const uint32_t bit = uint32_t(pw >> (p & 63)) & 1u;
+#pragma unroll
+      for (uint32_t j = 0; j < kWordsPerThread; ++j) {
+        const uint32_t w = tid + j * kThreads;
+        uint64_t v = 0;
+        if (w < W) {
+          if (!tagged_word(f_lo[j], f_hi[j], m + 1, &v))
+            ok &= wait_published(t.pub, t.Wp, t.abort_flag, m + 1, w, &v);
+          if (p != kNone) {
+            // measurement m's update of the column: x ^= M where the pivot
+            // row has x = 1 on it; row p-n takes the pivot row's bit, row p
+            // is cleared
+            uint64_t mv = col[w];
+            if (w == wp) mv &= ~bpb;
+            if (bit) v ^= mv;
+            if (w == wpn) v = bit ? (v | bpn) : (v & ~bpn);
+            if (w == wp) v &= ~bpb;
+          }
+          s_col[b ^ 1u][w] = v;
+          if (g == 0) t.SNall[size_t(m + 1) * t.Wp + w] = v;   // for the kernels after this one
+        }
+        wave_min_into(pivot_candidate(v, w, n, W), lane, &s_p[b ^ 1u]);
+      }
       if (!ok) s_abort = 1;
-      if (word && p != kNone) {
-        // measurement m's update of the column: x ^= M where the pivot row
-        // has x = 1 on it; row p-n takes the pivot row's bit, row p is cleared
-        const uint32_t bit = uint32_t(pw >> (p & 63)) & 1u;
-        uint64_t mv = col[tid];
-        if (tid == wp) mv &= ~bpb;
-        if (bit) v ^= mv;
-        if (tid == wpn) v = bit ? (v | bpn) : (v & ~bpn);
-        if (tid == wp) v &= ~bpb;
-      }
-      if (word) {
-        s_col[b ^ 1u][tid] = v;
-        if (g == 0) t.SNall[size_t(m + 1) * t.Wp + tid] = v;   // for the kernels after this one
-      }
-      wave_min_into(pivot_candidate(v, tid, n, W), lane, &s_p[b ^ 1u]);
     }
     if (p != kNone) {
-      if (word) {
-        // read by the reduce kernel after this one: one 16-byte store
-        uint64_t *part = t.ring + (size_t(m) * G + g) * t.Wp * 2;
-        *reinterpret_cast<ulonglong2 *>(part + size_t(tid) * 2) = make_ulonglong2(s_s0[tid], s_s1[tid]);
-        s_s0[tid] = 0;
-        s_s1[tid] = 0;
+      // read by the reduce kernel after this one: one 16-byte store per word
+      uint64_t *part = t.ring + (size_t(m) * G + g) * t.Wp * 2;
+      for (uint32_t w = tid; w < W; w += kThreads) {
+        *reinterpret_cast<ulonglong2 *>(part + size_t(w) * 2) = make_ulonglong2(s_s0[w], s_s1[w]);
+        s_s0[w] = 0;
+        s_s1[w] = 0;
       }
       if (tid == 0) {
         // pivot-row support over this workgroup's columns: 2 s + s_x + s_z
@@ -650,36 +668,21 @@ __global__ void __launch_bounds__(1024) k_meas_begin(TabDev t, const uint32_t *q
 }
 
 // Launch shape of the register-resident path for n qubits (false = not
-// usable): G workgroups, L row words per lane, CW columns per wave.
+// usable): G workgroups, L row words per lane, CW = L columns per wave (8
+// waves x L columns of 64 L words per workgroup: n up to 256 * 8 L >= 64 W).
 bool persist_shape(uint32_t n, uint32_t num_cus, uint32_t *G, uint32_t *L, uint32_t *CW) {
   if (!persist_layout(n)) return false;
   const uint32_t W = (2 * n + 63) / 64;
   const uint32_t l = (W + 63) / 64;
+  const uint32_t cw = l;
   const uint32_t gmax = num_cus < kPersistMaxGroups ? num_cus : kPersistMaxGroups;
-  for (uint32_t cw = 1; cw <= kPersistMaxSlots; ++cw) {
-    const uint32_t per = kWaves * cw;           // columns one workgroup can hold
-    uint32_t g = (n + per - 1) / per;
-    if (g > gmax) continue;
-    if (g < gmax / 4) g = gmax / 4;             // enough waves for the sweep
-    if (g < 1) g = 1;
-    *G = g;
-    *L = l;
-    *CW = cw;
-    return true;
-  }
-  return false;
-}
-
-template <int L>
-static const void *xz_kernel(uint32_t cw) {
-  switch (cw) {
-    case 1: return reinterpret_cast<const void *>(k_meas_xz<L, 1>);
-    case 2: return reinterpret_cast<const void *>(k_meas_xz<L, 2>);
-    case 3: return reinterpret_cast<const void *>(k_meas_xz<L, 3>);
-    case 4: return reinterpret_cast<const void *>(k_meas_xz<L, 4>);
-    case 5: return reinterpret_cast<const void *>(k_meas_xz<L, 5>);
-    default: return reinterpret_cast<const void *>(k_meas_xz<L, 6>);
-  }
+  const uint32_t per = kWaves * cw;   // columns one workgroup holds
+  const uint32_t g = (n + per - 1) / per;
+  if (g > gmax) return false;
+  *G = g;
+  *L = l;
+  *CW = cw;
+  return true;
 }
 
 hipError_t launch_measure_persist(const TabDev &t, const uint32_t *dev_qubits, uint32_t k,
@@ -699,8 +702,12 @@ hipError_t launch_measure_persist(const TabDev &t, const uint32_t *dev_qubits, u
   tb[1].detpar += kc;   // n >= 2048 >= 2 kc entries
   tb[1].detY += kc;
   const hipStream_t st = ps.main, aux = ps.aux;
-  const void *fn = L == 1 ? xz_kernel<1>(CW) : L == 2 ? xz_kernel<2>(CW) : L == 3 ? xz_kernel<3>(CW)
-                 : L == 4 ? xz_kernel<4>(CW) : xz_kernel<5>(CW);
+  const void *fn = L == 1 ? reinterpret_cast<const void *>(k_meas_xz<1, 1>)
+                 : L == 2 ? reinterpret_cast<const void *>(k_meas_xz<2, 2>)
+                 : L == 3 ? reinterpret_cast<const void *>(k_meas_xz<3, 3>)
+                 : L == 4 ? reinterpret_cast<const void *>(k_meas_xz<4, 4>)
+                          : reinterpret_cast<const void *>(k_meas_xz<5, 5>);
+  (void)CW;   // = L, fixed by the instance
   uint32_t last = 0;
   for (uint32_t base = 0, c = 0; base < k; base += kc, ++c) {
     const uint32_t cnt = k - base < kc ? k - base : kc;
@@ -719,7 +726,7 @@ hipError_t launch_measure_persist(const TabDev &t, const uint32_t *dev_qubits, u
     TabDev targ = tv;
     void *args[] = {&targ, &a};
     if (prof) prof->begin(PK_SWEEP, st);
-    e = hipLaunchCooperativeKernel(fn, dim3(G), dim3(kWaves * 64), args, 0, st);
+    e = hipLaunchCooperativeKernel(fn, dim3(G), dim3(kThreads), args, 0, st);
     if (prof) prof->end(PK_SWEEP, st);
     if (e != hipSuccess) return e;
     e = hipEventRecord(ps.ev[b], st);
