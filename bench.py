@@ -35,8 +35,8 @@ HBM_PEAK_GBS = 8000.0   # MI355X HBM3E peak
 TRAFFIC = {
     "k_meas_xz": {
         "sources": ("paper_2408_00384_amd/csrc/measure_persist.hip", "paper_2408_00384_amd/csrc/internal.h"),
-        "sha256": "e7a0940f72b533fc6e80c8a3dc201d3bb1080dd5fdd2767af6ce8b35d4c6ff9c",
-        "bytes_per_launch": 2.011e9,
+        "sha256": "7a436f33ef73021164eae502813de191d9381c705a8e9ba51a8edec3e1d970d9",
+        "bytes_per_launch": 1.122e+09,
         "summary": "profiles/k_meas_xz_plain_n10000_measure_all.md",
     },
 }

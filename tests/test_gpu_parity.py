@@ -276,17 +276,20 @@ def test_large_n_partial_measure_vs_oracle(ctx, measure_mode, n):
     assert t.anomalies() == 0
 
 
-@pytest.mark.parametrize("n", [2048, 4096, 10000])
-def test_persistent_equals_step_measure_all(ctx, n):
+@pytest.mark.parametrize("n,shots", [(2048, 2), (2100, 130), (4096, 2), (6000, 2), (8192, 2), (8200, 1),
+                                     (10000, 2)])
+def test_persistent_equals_step_measure_all(ctx, n, shots):
     """Register-resident and per-measurement-kernel paths agree bit for bit
-    on a full measure-all (tableau and every shot's outcomes)."""
+    on a full measure-all (tableau and every shot's outcomes); n covers each
+    row-word count per lane (1..5, with 8200 leaving the fifth nearly empty)
+    and 130 shots three sign words per row."""
     from paper_2408_00384_amd import (MEASURE_AUTO, MEASURE_PERSISTENT, MEASURE_STEP,
                                       cliff_ctx_set_measure_mode)
-    c = layered_circuit(n, 20 if n > 4096 else 12, 2, gen_seed=[41, n], circuit_id=6)
+    c = layered_circuit(n, 20 if n > 4096 else 12, shots, gen_seed=[41, n], circuit_id=6)
     res = {}
     for mode in (MEASURE_STEP, MEASURE_PERSISTENT):
         cliff_ctx_set_measure_mode(ctx.handle, mode)
-        t = _tab(ctx, n, 2).apply_circuit_gates(c)
+        t = _tab(ctx, n, shots).apply_circuit_gates(c)
         out, rnd = t.measure(c.qubits, seed=c.seed, circuit=6)
         res[mode] = (out, rnd, t.export(), t.anomalies())
         t.close()
@@ -363,3 +366,36 @@ def test_plain_large_prefix_vs_stored_oracle(ctx):
     assert np.array_equal(np.concatenate(outs), _golden_bits(rec["outcomes"], c.n))
     assert np.array_equal(np.concatenate(rnds), _golden_bits(rec["random"], c.n))
     assert _tab_digest(*t.export()) == rec["final_sha256"]
+
+
+def test_persistent_ghz_mostly_deterministic(ctx):
+    """A GHZ state on 4096 qubits: the first measurement is random, the other
+    4095 deterministic (all equal to the first).  Register-resident path
+    against the per-measurement path over all of them, and against the oracle
+    on the first 40."""
+    from paper_2408_00384_amd import (MEASURE_AUTO, MEASURE_PERSISTENT, MEASURE_STEP,
+                                      cliff_ctx_set_measure_mode)
+    n, shots = 4096, 4
+    ops = [0] + [2] * (n - 1)
+    a = [0] + list(range(n - 1))
+    b = [0] + list(range(1, n))
+    res = {}
+    for mode in (MEASURE_STEP, MEASURE_PERSISTENT):
+        cliff_ctx_set_measure_mode(ctx.handle, mode)
+        t = _tab(ctx, n, shots).apply_gates(ops, a, b)
+        out, rnd = t.measure(np.arange(n), seed=17, circuit=2)
+        res[mode] = (out, rnd, t.export(), t.anomalies())
+        t.close()
+    cliff_ctx_set_measure_mode(ctx.handle, MEASURE_AUTO)
+    out, rnd, tab, anom = res[MEASURE_PERSISTENT]
+    assert rnd[0] == 1 and rnd[1:].sum() == 0 and anom == 0
+    assert all(len(set(row.tolist())) == 1 for row in out)
+    so, sr, stab, _ = res[MEASURE_STEP]
+    assert np.array_equal(out, so) and np.array_equal(rnd, sr)
+    for A, B in zip(tab, stab):
+        assert np.array_equal(A, B)
+    ref = oracle.Tableau(n)
+    ref.apply_gates(np.array(ops, np.uint8), np.array(a, np.uint32), np.array(b, np.uint32))
+    for s_ in range(shots):
+        o, k = ref.clone().measure_list(np.arange(40, dtype=np.uint32), seed=17, circuit=2, shot=s_)
+        assert np.array_equal(out[s_, :40], o) and np.array_equal(rnd[:40], k)
