@@ -58,8 +58,12 @@ const char *cliff_last_error(void);
 const char *cliff_strerror(int code);
 
 /* Context: one device and one HIP stream (borrowed; may be NULL for the
- * default stream).  All work of tableaux bound to it is enqueued on that
- * stream.  Owns small staging buffers only. */
+ * default stream).  All work of tableaux bound to it is ordered on that
+ * stream: a call's kernels may also run on a second stream the context owns
+ * (the register-resident measurement overlaps a chunk's finalize with the
+ * next chunk), but the bound stream waits for them before the call's later
+ * work, so everything enqueued afterwards on the bound stream sees the
+ * results.  Owns small staging buffers, that stream and its events. */
 int cliff_ctx_create(int device, void *hip_stream, cliff_ctx **out);
 int cliff_ctx_destroy(cliff_ctx *ctx);
 /* Block until all work enqueued by the context has finished. */
@@ -77,10 +81,11 @@ int cliff_ctx_num_cus(const cliff_ctx *ctx);
 int cliff_ctx_set_gate_mode(cliff_ctx *ctx, int mode);
 
 /* Measurement strategy.  AUTO: the register-resident path when the tableau
- * shape allows it (64 <= ceil(2n/64) <= 1024 and the columns fit the
- * registers of the device's compute units), else one kernel per measurement.
- * STEP: always one kernel per measurement.  PERSISTENT: always the
- * register-resident path (EINVAL if n does not fit).  Results are identical. */
+ * shape allows it (64 <= ceil(2n/64) <= 320, i.e. 2017 <= n <= 10240, and the
+ * columns fit the registers and LDS of at most 256 compute units), else one
+ * kernel per measurement.  STEP: always one kernel per measurement.
+ * PERSISTENT: always the register-resident path (EINVAL if n does not fit).
+ * Results are identical; only speed differs. */
 #define CLIFF_MEASURE_AUTO 0
 #define CLIFF_MEASURE_STEP 1
 #define CLIFF_MEASURE_PERSISTENT 2
