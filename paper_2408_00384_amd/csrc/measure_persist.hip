@@ -237,12 +237,13 @@ __global__ void __launch_bounds__(kThreads) k_meas_xz(TabDev t, PersistArgs a) {
       const uint32_t ip = wp >> 6, sh = p & 63;
       uint32_t xm = 0, zm = 0;
 #pragma unroll
-      for (int k = 0; k < CW; ++k) {
-        uint64_t xv = 0;
+      for (int i = 0; i < L; ++i) {
+        if (uint32_t(i) != ip) continue;   // wave-uniform: one branch picks the word
 #pragma unroll
-        for (int i = 0; i < L; ++i) xv = uint32_t(i) == ip ? xr[k][i] : xv;
-        xm |= uint32_t((xv >> sh) & 1u) << k;
-        zm |= uint32_t((zw[(k * L + ip) * 64] >> sh) & 1u) << k;
+        for (int k = 0; k < CW; ++k) {
+          xm |= uint32_t((xr[k][i] >> sh) & 1u) << k;
+          zm |= uint32_t((zw[(k * L + i) * 64] >> sh) & 1u) << k;
+        }
       }
       s_xpm[b][wave] = xm;
       s_zpm[b][wave] = zm;
@@ -312,10 +313,9 @@ __global__ void __launch_bounds__(kThreads) k_meas_xz(TabDev t, PersistArgs a) {
 #pragma unroll
       for (int i = 0; i < L; ++i) {
         const uint32_t w = uint32_t(i) * 64 + lane;
-        if (w < W && (c0[i] | c1[i])) {
+        if (w < W) {
           const uint64_t old = atomicXor(&s_s0[w], (unsigned long long)c0[i]);
-          const uint64_t hi = c1[i] ^ (old & c0[i]);
-          if (hi) atomicXor(&s_s1[w], (unsigned long long)hi);
+          atomicXor(&s_s1[w], (unsigned long long)(c1[i] ^ (old & c0[i])));
         }
       }
       // row p-n becomes the old row p; row p becomes Z on the measured
