@@ -81,9 +81,9 @@ int cliff_ctx_num_cus(const cliff_ctx *ctx);
 int cliff_ctx_set_gate_mode(cliff_ctx *ctx, int mode);
 
 /* Measurement strategy.  AUTO: the register-resident path when the tableau
- * shape allows it (64 <= ceil(2n/64) <= 320, i.e. 2017 <= n <= 10240, and the
- * columns fit the registers and LDS of at most 256 compute units), else one
- * kernel per measurement.  STEP: always one kernel per measurement.
+ * shape allows it (ceil(2n/64) <= 320, i.e. n <= 10240, and the columns fit
+ * the registers and LDS of at most 256 compute units), else one kernel per
+ * measurement.  STEP: always one kernel per measurement.
  * PERSISTENT: always the register-resident path (EINVAL if n does not fit).
  * Results are identical; only speed differs. */
 #define CLIFF_MEASURE_AUTO 0

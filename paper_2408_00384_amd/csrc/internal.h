@@ -94,7 +94,7 @@ struct TabDev {
   uint64_t *rps;             // 2 x SW: pivot-row signs handed to the next step
   uint32_t *detpar, *detY;   // n: deterministic-outcome accumulators
   uint64_t *detr;            // n x SW
-  // register-resident path (n >= 2048), per chunk of measurements: measured
+  // register-resident path (n <= 10240), per chunk of measurements: measured
   // columns and pivots, the tagged publication slots, per-workgroup counter
   // partials, and the reduced sign corrections
   uint64_t *SNall, *C1all, *ring, *pub;
@@ -106,7 +106,7 @@ constexpr uint32_t kPersistMaxGroups = 256;
 constexpr uint32_t kPersistMaxChunk = 1024;   // measurements per chunk (qubit list held in LDS)
 constexpr uint32_t kPersistMaxWp = 320;       // row words: at most 5 per lane of a wave
 inline bool persist_layout(uint32_t n) {
-  return (2 * n + 63) / 64 >= 64 && (2 * n + 63) / 64 <= kPersistMaxWp;
+  return n >= 1 && (2 * n + 63) / 64 <= kPersistMaxWp;
 }
 // Measurements per chunk of the register-resident path: bounded by the HBM
 // kept for per-workgroup counter partials (1 GB for n >= 8192, else 64 MB);

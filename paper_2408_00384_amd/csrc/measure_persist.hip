@@ -699,7 +699,9 @@ hipError_t launch_measure_persist(const TabDev &t, const uint32_t *dev_qubits, u
   tb[1].pub += size_t(kc) * 2 * t.Wp;
   tb[1].C1all += size_t(kc) * t.Wp;
   tb[1].ring += size_t(kc) * kPersistMaxGroups * t.Wp * 2;
-  tb[1].detpar += kc;   // n >= 2048 >= 2 kc entries
+  // a pass holds at most n measurements: set 1 serves chunks at offset kc of
+  // it, so its entries end by n
+  tb[1].detpar += kc;
   tb[1].detY += kc;
   const hipStream_t st = ps.main, aux = ps.aux;
   const void *fn = L == 1 ? reinterpret_cast<const void *>(k_meas_xz<1, 1>)

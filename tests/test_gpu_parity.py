@@ -26,6 +26,15 @@ def ctx():
     c.close()
 
 
+@pytest.fixture(params=["step", "persistent"])
+def measure_mode(request, ctx):
+    from paper_2408_00384_amd import (MEASURE_AUTO, MEASURE_PERSISTENT, MEASURE_STEP,
+                                      cliff_ctx_set_measure_mode)
+    cliff_ctx_set_measure_mode(ctx.handle, MEASURE_STEP if request.param == "step" else MEASURE_PERSISTENT)
+    yield request.param
+    cliff_ctx_set_measure_mode(ctx.handle, MEASURE_AUTO)
+
+
 def _tab(ctx, n, shots=1):
     from paper_2408_00384_amd import DeviceTableau
     return DeviceTableau(ctx, n, shots)
@@ -106,13 +115,13 @@ def _check_circuit(ctx, c, shots_to_check=None):
 
 
 @pytest.mark.parametrize("n", RAGGED)
-def test_measure_all_matches_oracle(ctx, n):
+def test_measure_all_matches_oracle(ctx, measure_mode, n):
     c = layered_circuit(n, 6, 3, gen_seed=[12, n], circuit_id=n)
     _check_circuit(ctx, c)
 
 
 @pytest.mark.parametrize("n", [2, 9, 40, 70, 140])
-def test_mostly_deterministic_measurements(ctx, n):
+def test_mostly_deterministic_measurements(ctx, measure_mode, n):
     # shallow circuits with few H gates: most outcomes are determined
     c = layered_circuit(n, 2, 4, gen_seed=[13, n], circuit_id=3)
     c.h[:] = 0
@@ -121,7 +130,7 @@ def test_mostly_deterministic_measurements(ctx, n):
     assert rnd.sum() < n
 
 
-def test_ghz_and_zero_state(ctx):
+def test_ghz_and_zero_state(ctx, measure_mode):
     n = 70
     t = _tab(ctx, n, 8)
     ops = [0] + [2] * (n - 1)
@@ -137,7 +146,7 @@ def test_ghz_and_zero_state(ctx):
 
 
 @pytest.mark.parametrize("seed", range(6))
-def test_interleaved_gates_and_measurements(ctx, seed):
+def test_interleaved_gates_and_measurements(ctx, measure_mode, seed):
     rng = np.random.default_rng(500 + seed)
     n = int(rng.integers(2, 150))
     shots = 3
@@ -160,12 +169,12 @@ def test_interleaved_gates_and_measurements(ctx, seed):
     assert t.anomalies() == 0
 
 
-def test_plain_small_all_shots(ctx):
+def test_plain_small_all_shots(ctx, measure_mode):
     """n = 64, 64 layers, measure all, 16 shots."""
     _check_circuit(ctx, plain_small())
 
 
-def test_plain_mid_sampled_shots(ctx):
+def test_plain_mid_sampled_shots(ctx, measure_mode):
     """n = 1,024, 100 layers, measure all, 128 shots (checked on sampled shots)."""
     c = plain_mid()
     path = os.path.join(GOLDEN, "plain_mid.json")
@@ -247,15 +256,6 @@ def test_error_paths(ctx):
     assert out.sum() == 0 and rnd.sum() == 0
 
 
-@pytest.fixture(params=["step", "persistent"])
-def measure_mode(request, ctx):
-    from paper_2408_00384_amd import (MEASURE_AUTO, MEASURE_PERSISTENT, MEASURE_STEP,
-                                      cliff_ctx_set_measure_mode)
-    cliff_ctx_set_measure_mode(ctx.handle, MEASURE_STEP if request.param == "step" else MEASURE_PERSISTENT)
-    yield request.param
-    cliff_ctx_set_measure_mode(ctx.handle, MEASURE_AUTO)
-
-
 @pytest.mark.parametrize("n", [2048, 2111, 3000, 4096, 6000])
 def test_large_n_partial_measure_vs_oracle(ctx, measure_mode, n):
     """Both measurement strategies against the oracle on the first qubits of a
@@ -276,13 +276,14 @@ def test_large_n_partial_measure_vs_oracle(ctx, measure_mode, n):
     assert t.anomalies() == 0
 
 
-@pytest.mark.parametrize("n,shots", [(2048, 2), (2100, 130), (4096, 2), (6000, 2), (8192, 2), (8200, 1),
-                                     (10000, 2)])
+@pytest.mark.parametrize("n,shots", [(1, 1), (33, 65), (700, 3), (1024, 128), (1500, 2), (2048, 2),
+                                     (2100, 130), (4096, 2), (6000, 2), (8192, 2), (8200, 1), (10000, 2)])
 def test_persistent_equals_step_measure_all(ctx, n, shots):
     """Register-resident and per-measurement-kernel paths agree bit for bit
     on a full measure-all (tableau and every shot's outcomes); n covers each
-    row-word count per lane (1..5, with 8200 leaving the fifth nearly empty)
-    and 130 shots three sign words per row."""
+    row-word count per lane (1..5, with 8200 leaving the fifth nearly empty),
+    a single row word (n = 1, 33) and 65 or 130 shots two or three sign words
+    per row."""
     from paper_2408_00384_amd import (MEASURE_AUTO, MEASURE_PERSISTENT, MEASURE_STEP,
                                       cliff_ctx_set_measure_mode)
     c = layered_circuit(n, 20 if n > 4096 else 12, shots, gen_seed=[41, n], circuit_id=6)
