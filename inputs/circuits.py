@@ -156,13 +156,30 @@ def serving_workload(count: int, rate_hz: float, seed: int = 4, **kw):
     return [serving_request(i, arrivals, ns, shots, seed) for i in range(count)]
 
 
-def random_gate_list(rng: np.random.Generator, n: int, count: int, p_cnot: float = 0.4):
-    """Unstructured gate list: op codes 0 = H, 1 = S, 2 = CNOT(a -> b)."""
-    ops = np.where(rng.random(count) < p_cnot, 2, rng.integers(0, 2, size=count)).astype(np.uint8)
+# Gate-list op codes (the library's public numbering).
+OP_H, OP_S, OP_CNOT, OP_SDG, OP_X, OP_Y, OP_Z, OP_CZ, OP_SWAP = range(9)
+TWO_QUBIT_OPS = (OP_CNOT, OP_CZ, OP_SWAP)
+
+
+def random_gate_list(rng: np.random.Generator, n: int, count: int, p_cnot: float = 0.4,
+                     full: bool = False):
+    """Unstructured gate list: op codes 0 = H, 1 = S, 2 = CNOT(a -> b); with
+    ``full`` also 3 = S^dagger, 4..6 = X, Y, Z, 7 = CZ, 8 = SWAP (two-qubit ops
+    with probability p_cnot, spread evenly over CNOT, CZ and SWAP).  b is 0
+    for single-qubit ops."""
+    two = rng.random(count) < p_cnot
+    if full:
+        single = np.array([OP_H, OP_S, OP_SDG, OP_X, OP_Y, OP_Z], np.uint8)
+        ops = np.where(two, np.array(TWO_QUBIT_OPS, np.uint8)[rng.integers(0, 3, size=count)],
+                       single[rng.integers(0, 6, size=count)]).astype(np.uint8)
+    else:
+        ops = np.where(two, OP_CNOT, rng.integers(0, 2, size=count)).astype(np.uint8)
     a = rng.integers(0, n, size=count).astype(np.uint32)
     b = rng.integers(0, n - 1, size=count).astype(np.uint32) if n > 1 else np.zeros(count, np.uint32)
     b = np.where(b >= a, b + 1, b).astype(np.uint32)
+    is_two = np.isin(ops, TWO_QUBIT_OPS)
     if n == 1:
-        ops[:] = np.where(ops == 2, 0, ops)
-    b = np.where(ops == 2, b, 0).astype(np.uint32)
+        ops[:] = np.where(is_two, OP_H, ops)
+        is_two[:] = False
+    b = np.where(is_two, b, 0).astype(np.uint32)
     return ops, a, b

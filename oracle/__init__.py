@@ -7,8 +7,10 @@ The arithmetic lives in ``chp.c`` (plain C, one byte per tableau bit), built
 with gcc into ``oracle/_build/liboracle.so`` by :func:`build`.  This module is
 argument marshalling only.  The algorithm is the phase-space tableau method the
 paper's Clifford backend implements (Sec. 2, citing Aaronson & Gottesman 2004):
-gate rules, rowsum with the phase function g, and Z-measurement with a random
-branch (pivot found) and a deterministic branch (scratch-row product).
+gate rules (H, S, CNOT and the rest of the Clifford gate set: S^dagger, X, Y,
+Z, CZ, SWAP), rowsum with the phase function g, and measurement of Z (or X, Y)
+on one qubit with a random branch (pivot found) and a deterministic branch
+(scratch-row product).
 
 Every function here is pinned by ``tests/test_oracle_*.py`` against brute-force
 statevector simulation, explicit Pauli matrices, closed-form identities,
@@ -62,11 +64,16 @@ def _load():
     lib.orc_anomalies.argtypes = [vp]
     lib.orc_get.argtypes = [vp, _u8p, _u8p, _u8p]
     lib.orc_set.argtypes = [vp, _u8p, _u8p, _u8p]
-    for f in (lib.orc_h, lib.orc_s):
+    for f in (lib.orc_h, lib.orc_s, lib.orc_sdg, lib.orc_x, lib.orc_y, lib.orc_z):
         f.argtypes = [vp, ctypes.c_int]
-    lib.orc_cnot.argtypes = [vp, ctypes.c_int, ctypes.c_int]
+    for f in (lib.orc_cnot, lib.orc_cz, lib.orc_swap):
+        f.argtypes = [vp, ctypes.c_int, ctypes.c_int]
     lib.orc_apply_layers.argtypes = [vp, ctypes.c_int, _u8p, _u8p, _u32p, _u32p, ctypes.c_int]
+    lib.orc_apply_gates.restype = ctypes.c_long
     lib.orc_apply_gates.argtypes = [vp, ctypes.c_long, _u8p, _u32p, _u32p]
+    lib.orc_measure_pauli.argtypes = [vp, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_uint64,
+                                      ctypes.c_uint64, ctypes.c_uint64, ctypes.c_uint64,
+                                      ctypes.POINTER(ctypes.c_int)]
     lib.orc_g.argtypes = [ctypes.c_int] * 4
     lib.orc_rowsum.argtypes = [vp, ctypes.c_int, ctypes.c_int]
     lib.orc_measure.argtypes = [vp, ctypes.c_int, ctypes.c_uint64, ctypes.c_uint64,
@@ -84,6 +91,14 @@ def _load():
 
 def _p(a: np.ndarray, t):
     return a.ctypes.data_as(t)
+
+
+# Gate-list op codes and measurement bases (the same numbering as the library's
+# public header, an interface both consume).
+GATE_CODES = {"h": 0, "s": 1, "cnot": 2, "sdg": 3, "x": 4, "y": 5, "z": 6, "cz": 7, "swap": 8}
+BASIS_Z, BASIS_X, BASIS_Y = 0, 1, 2
+# (x, z) bits of the measured Pauli per basis code
+_BASIS_BITS = {BASIS_Z: (0, 1), BASIS_X: (1, 0), BASIS_Y: (1, 1)}
 
 
 def philox4x64_10(counter, key) -> np.ndarray:
@@ -141,6 +156,30 @@ class Tableau:
         self._lib.orc_cnot(self._h, int(a), int(b))
         return self
 
+    def sdg(self, a: int):
+        self._lib.orc_sdg(self._h, int(a))
+        return self
+
+    def x(self, a: int):
+        self._lib.orc_x(self._h, int(a))
+        return self
+
+    def y(self, a: int):
+        self._lib.orc_y(self._h, int(a))
+        return self
+
+    def z(self, a: int):
+        self._lib.orc_z(self._h, int(a))
+        return self
+
+    def cz(self, a: int, b: int):
+        self._lib.orc_cz(self._h, int(a), int(b))
+        return self
+
+    def swap(self, a: int, b: int):
+        self._lib.orc_swap(self._h, int(a), int(b))
+        return self
+
     def rowsum(self, h: int, i: int) -> int:
         return int(self._lib.orc_rowsum(self._h, int(h), int(i)))
 
@@ -159,10 +198,13 @@ class Tableau:
         return self.apply_layers(c.h, c.s, c.ctrl, c.tgt)
 
     def apply_gates(self, ops, a, b):
+        """Gate list with op codes GATE_CODES (H, S, CNOT, SDG, X, Y, Z, CZ, SWAP)."""
         ops = np.ascontiguousarray(ops, np.uint8)
         a = np.ascontiguousarray(a, np.uint32)
         b = np.ascontiguousarray(b, np.uint32)
-        self._lib.orc_apply_gates(self._h, len(ops), _p(ops, _u8p), _p(a, _u32p), _p(b, _u32p))
+        bad = self._lib.orc_apply_gates(self._h, len(ops), _p(ops, _u8p), _p(a, _u32p), _p(b, _u32p))
+        if bad >= 0:
+            raise ValueError("unknown gate op %d at position %d" % (int(ops[bad]), bad))
         return self
 
     def measure(self, a: int, seed: int = 0, circuit: int = 0, shot: int = 0, m: int = 0):
@@ -170,6 +212,23 @@ class Tableau:
         kind = ctypes.c_int(0)
         out = self._lib.orc_measure(self._h, int(a), seed, circuit, shot, m, ctypes.byref(kind))
         return int(out), bool(kind.value)
+
+    def measure_pauli(self, a: int, basis: int, seed: int = 0, circuit: int = 0, shot: int = 0,
+                      m: int = 0):
+        """Measure X (basis 1), Y (2) or Z (0) on qubit a. Returns (outcome, was_random)."""
+        px, pz = _BASIS_BITS[int(basis)]
+        kind = ctypes.c_int(0)
+        out = self._lib.orc_measure_pauli(self._h, int(a), px, pz, seed, circuit, shot, m,
+                                          ctypes.byref(kind))
+        return int(out), bool(kind.value)
+
+    def measure_bases(self, qubits, bases, seed=0, circuit=0, shot=0, m0=0):
+        """measure_pauli over a list, measurement index m0 + position."""
+        out = np.zeros(len(qubits), np.uint8)
+        kind = np.zeros(len(qubits), np.uint8)
+        for i, (q, b) in enumerate(zip(qubits, bases)):
+            out[i], kind[i] = self.measure_pauli(int(q), int(b), seed, circuit, shot, m0 + i)
+        return out, kind
 
     def measure_list(self, qubits, seed=0, circuit=0, shot=0, m0=0):
         q = np.ascontiguousarray(qubits, np.uint32)

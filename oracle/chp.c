@@ -124,6 +124,16 @@ void orc_set(otab *t, const uint8_t *x, const uint8_t *z, const uint8_t *r) {
  * Conjugation rules, one row at a time (AG): the sign picks up x*z for H and
  * S, and x_a z_b (x_b xor z_a xor 1) for CNOT(a -> b).  Each rule reads and
  * writes only its own row, so a whole circuit may be applied row by row.
+ *
+ * The rest of the Clifford gate set, each from U P U^dagger for the single-
+ * qubit Paulis on its qubits:
+ *   S^dagger = diag(1, -i): X -> -Y, Y -> X, Z -> Z, so z ^= x and the sign
+ *     flips on X (x = 1, z = 0);
+ *   X, Y, Z: the Pauli anticommuting with the gate flips sign -- X flips rows
+ *     with z = 1, Z rows with x = 1, Y rows with x xor z = 1;
+ *   CZ(a, b) = diag(1, 1, 1, -1): X_a -> X_a Z_b, X_b -> Z_a X_b, Z's fixed;
+ *     sign flip x_a x_b (z_a xor z_b) (X_a X_b -> Y_a Y_b, Y_a X_b -> -X_a Y_b);
+ *   SWAP(a, b): exchanges the two columns, no sign.
  */
 static void h_row(otab *t, int i, int a) {
     uint8_t xa = X(t, i, a), za = Z(t, i, a);
@@ -145,9 +155,41 @@ static void cnot_row(otab *t, int i, int a, int b) {
     Z(t, i, a) = (uint8_t)(za ^ zb);
 }
 
+static void sdg_row(otab *t, int i, int a) {
+    uint8_t xa = X(t, i, a), za = Z(t, i, a);
+    t->r[i] ^= (uint8_t)(xa & (za ^ 1));
+    Z(t, i, a) = (uint8_t)(za ^ xa);
+}
+
+static void pauli_row(otab *t, int i, int a, int px, int pz) {
+    /* sign flips when P(x_a, z_a) anticommutes with P(px, pz) */
+    t->r[i] ^= (uint8_t)((X(t, i, a) & pz) ^ (Z(t, i, a) & px));
+}
+
+static void cz_row(otab *t, int i, int a, int b) {
+    uint8_t xa = X(t, i, a), za = Z(t, i, a), xb = X(t, i, b), zb = Z(t, i, b);
+    t->r[i] ^= (uint8_t)(xa & xb & (za ^ zb));
+    Z(t, i, a) = (uint8_t)(za ^ xb);
+    Z(t, i, b) = (uint8_t)(zb ^ xa);
+}
+
+static void swap_row(otab *t, int i, int a, int b) {
+    uint8_t xa = X(t, i, a), za = Z(t, i, a);
+    X(t, i, a) = X(t, i, b);
+    Z(t, i, a) = Z(t, i, b);
+    X(t, i, b) = xa;
+    Z(t, i, b) = za;
+}
+
 void orc_h(otab *t, int a) { for (int i = 0; i < 2 * t->n; ++i) h_row(t, i, a); }
 void orc_s(otab *t, int a) { for (int i = 0; i < 2 * t->n; ++i) s_row(t, i, a); }
 void orc_cnot(otab *t, int a, int b) { for (int i = 0; i < 2 * t->n; ++i) cnot_row(t, i, a, b); }
+void orc_sdg(otab *t, int a) { for (int i = 0; i < 2 * t->n; ++i) sdg_row(t, i, a); }
+void orc_x(otab *t, int a) { for (int i = 0; i < 2 * t->n; ++i) pauli_row(t, i, a, 1, 0); }
+void orc_y(otab *t, int a) { for (int i = 0; i < 2 * t->n; ++i) pauli_row(t, i, a, 1, 1); }
+void orc_z(otab *t, int a) { for (int i = 0; i < 2 * t->n; ++i) pauli_row(t, i, a, 0, 1); }
+void orc_cz(otab *t, int a, int b) { for (int i = 0; i < 2 * t->n; ++i) cz_row(t, i, a, b); }
+void orc_swap(otab *t, int a, int b) { for (int i = 0; i < 2 * t->n; ++i) swap_row(t, i, a, b); }
 
 /* Layered circuit: per qubit H (if h) then S (if s), then every CNOT pair;
  * applied row by row (each row runs through all layers in order).  Gates on
@@ -178,13 +220,26 @@ void orc_apply_layers(otab *t, int depth, const uint8_t *h, const uint8_t *s,
     free(hl); free(sl); free(hc); free(sc);
 }
 
-/* Gate list: op 0 = H(a), 1 = S(a), 2 = CNOT(a -> b). */
-void orc_apply_gates(otab *t, long count, const uint8_t *op, const uint32_t *a, const uint32_t *b) {
+/* Gate list: op 0 = H(a), 1 = S(a), 2 = CNOT(a -> b), 3 = S^dagger(a),
+ * 4 = X(a), 5 = Y(a), 6 = Z(a), 7 = CZ(a, b), 8 = SWAP(a, b).  Returns the
+ * index of the first unknown op code (nothing after it applied), or -1. */
+long orc_apply_gates(otab *t, long count, const uint8_t *op, const uint32_t *a, const uint32_t *b) {
     for (long k = 0; k < count; ++k) {
-        if (op[k] == 0) orc_h(t, (int)a[k]);
-        else if (op[k] == 1) orc_s(t, (int)a[k]);
-        else orc_cnot(t, (int)a[k], (int)b[k]);
+        const int qa = (int)a[k], qb = (int)b[k];
+        switch (op[k]) {
+            case 0: orc_h(t, qa); break;
+            case 1: orc_s(t, qa); break;
+            case 2: orc_cnot(t, qa, qb); break;
+            case 3: orc_sdg(t, qa); break;
+            case 4: orc_x(t, qa); break;
+            case 5: orc_y(t, qa); break;
+            case 6: orc_z(t, qa); break;
+            case 7: orc_cz(t, qa, qb); break;
+            case 8: orc_swap(t, qa, qb); break;
+            default: return k;
+        }
     }
+    return -1;
 }
 
 /* ---------------------------------------------------------- g / rowsum ---
@@ -222,22 +277,30 @@ int orc_rowsum(otab *t, int h, int i) {
 }
 
 /* ----------------------------------------------------------- measurement ---
- * Z-measurement of qubit a (AG).  Returns the outcome bit; *kind is set to 1
- * when the outcome was random, 0 when it was determined by the state.
+ * Measurement of the single-qubit Pauli P_a = P(px, pz) on qubit a (AG's
+ * Z-measurement, px = 0 and pz = 1, with "row i anticommutes with Z_a", x_ia =
+ * 1, read as "row i anticommutes with P_a": x_ia pz xor z_ia px = 1; the
+ * argument of AG carries over unchanged to any Pauli).  Returns the outcome
+ * bit (0 for eigenvalue +1); *kind is set to 1 when the outcome was random, 0
+ * when it was determined by the state.
  */
-int orc_measure(otab *t, int a, uint64_t seed, uint64_t circuit, uint64_t shot,
-                uint64_t m, int *kind) {
+static int anticommutes(const otab *t, int i, int a, int px, int pz) {
+    return (X(t, i, a) & pz) ^ (Z(t, i, a) & px);
+}
+
+int orc_measure_pauli(otab *t, int a, int px, int pz, uint64_t seed, uint64_t circuit,
+                      uint64_t shot, uint64_t m, int *kind) {
     int n = t->n;
     int p = -1;
     for (int i = n; i < 2 * n; ++i)
-        if (X(t, i, a)) { p = i; break; }
+        if (anticommutes(t, i, a, px, pz)) { p = i; break; }
 
     if (p >= 0) {
         /* random: multiply the pivot into every other row that anticommutes
-           with Z_a, move the pivot into its destabilizer slot, and replace it
-           by +-Z_a with a fresh random sign */
+           with P_a, move the pivot into its destabilizer slot, and replace it
+           by +-P_a with a fresh random sign */
         for (int i = 0; i < 2 * n; ++i) {
-            if (i == p || !X(t, i, a)) continue;
+            if (i == p || !anticommutes(t, i, a, px, pz)) continue;
             int e;
             rowsum_raw(t, i, p, &e);
             if ((e & 1) && i != p - n) t->anomalies++;
@@ -247,26 +310,33 @@ int orc_measure(otab *t, int a, uint64_t seed, uint64_t circuit, uint64_t shot,
         t->r[p - n] = t->r[p];
         memset(&X(t, p, 0), 0, (size_t)n);
         memset(&Z(t, p, 0), 0, (size_t)n);
-        Z(t, p, a) = 1;
+        X(t, p, a) = (uint8_t)px;
+        Z(t, p, a) = (uint8_t)pz;
         t->r[p] = (uint8_t)orc_random_bit(seed, circuit, shot, m);
         if (kind) *kind = 1;
         return t->r[p];
     }
 
     /* deterministic: accumulate the product of the stabilizers whose
-       destabilizer partner anticommutes with Z_a in the scratch row */
+       destabilizer partner anticommutes with P_a in the scratch row */
     int sc = 2 * n;
     memset(&X(t, sc, 0), 0, (size_t)n);
     memset(&Z(t, sc, 0), 0, (size_t)n);
     t->r[sc] = 0;
     for (int i = 0; i < n; ++i) {
-        if (!X(t, i, a)) continue;
+        if (!anticommutes(t, i, a, px, pz)) continue;
         int e;
         rowsum_raw(t, sc, i + n, &e);
         if (e & 1) t->anomalies++;
     }
     if (kind) *kind = 0;
     return t->r[sc];
+}
+
+/* Z-measurement of qubit a (AG). */
+int orc_measure(otab *t, int a, uint64_t seed, uint64_t circuit, uint64_t shot,
+                uint64_t m, int *kind) {
+    return orc_measure_pauli(t, a, 0, 1, seed, circuit, shot, m, kind);
 }
 
 /*

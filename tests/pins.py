@@ -72,14 +72,53 @@ class StateVector:
             for c, t in zip(ctrl[l], tgt[l]):
                 self.cnot(int(c), int(t))
 
+    def sdg(self, a):
+        self._apply1(SM.conj(), a)
+
+    def x(self, a):
+        self._apply1(PX, a)
+
+    def y(self, a):
+        self._apply1(PY, a)
+
+    def z(self, a):
+        self._apply1(PZ, a)
+
+    def cz(self, a, b):
+        idx = np.arange(2 ** self.n)
+        both = (((idx >> a) & 1) & ((idx >> b) & 1)) == 1
+        self.psi = np.where(both, -self.psi, self.psi)
+
+    def swap(self, a, b):
+        idx = np.arange(2 ** self.n)
+        src = idx ^ ((((idx >> a) ^ (idx >> b)) & 1) * ((1 << a) | (1 << b)))
+        self.psi = self.psi[src]
+
     def apply_gates(self, ops, a, b):
+        """Op codes: 0 H, 1 S, 2 CNOT(a -> b), 3 S^dagger, 4 X, 5 Y, 6 Z, 7 CZ, 8 SWAP."""
+        one = {0: self.h, 1: self.s, 3: self.sdg, 4: self.x, 5: self.y, 6: self.z}
+        two = {2: self.cnot, 7: self.cz, 8: self.swap}
         for o, x, y in zip(ops, a, b):
-            if o == 0:
-                self.h(int(x))
-            elif o == 1:
-                self.s(int(x))
+            if int(o) in one:
+                one[int(o)](int(x))
             else:
-                self.cnot(int(x), int(y))
+                two[int(o)](int(x), int(y))
+
+    def prob_minus(self, a, pauli) -> float:
+        """Probability of eigenvalue -1 when measuring the 2x2 Pauli on qubit a."""
+        proj = (I2 - pauli) / 2
+        keep = self.psi.copy()
+        self._apply1(proj, a)
+        p = float(np.linalg.norm(self.psi) ** 2)
+        self.psi = keep
+        return p
+
+    def collapse_pauli(self, a, pauli, bit):
+        """Project onto eigenvalue (-1)^bit of the Pauli on qubit a."""
+        self._apply1((I2 + (-1) ** bit * pauli) / 2, a)
+        nrm = np.linalg.norm(self.psi)
+        assert nrm > 1e-9, "collapse onto a zero-probability outcome"
+        self.psi = self.psi / nrm
 
     def prob_one(self, a) -> float:
         idx = np.arange(2 ** self.n)

@@ -7,6 +7,10 @@ term, a swapped operand of g, a wrong pivot row, an off-by-n index) would show:
   * H / S / CNOT row updates vs explicit conjugation U P U^dagger;
   * rowsum vs explicit Pauli-string products with the complex phase tracked;
   * closed-form identities (H^2, S^4, S^2 = Z, CNOT^2, (HS)^3) bit-exactly;
+  * S^dagger, X, Y, Z, CZ, SWAP row updates vs explicit conjugation, and the
+    identities tying them to H / S / CNOT;
+  * X-, Y- and Z-basis measurements vs a dense statevector (probabilities and
+    collapse), and hand-worked eigenstates of each basis;
   * random circuits with interleaved measurements vs a dense statevector;
   * Bell / GHZ correlations; symplectic invariants; log2 |supp psi|.
 """
@@ -111,6 +115,25 @@ def test_s_rule():
     _conj_check(1, lambda t: t.s(0), SM)
 
 
+def test_sdg_and_pauli_rules():
+    _conj_check(1, lambda t: t.sdg(0), SM.conj())
+    _conj_check(1, lambda t: t.x(0), PX)
+    _conj_check(1, lambda t: t.y(0), PY)
+    _conj_check(1, lambda t: t.z(0), PZ)
+
+
+def test_cz_and_swap_rules_both_orientations():
+    CZ = np.diag([1, 1, 1, -1]).astype(complex)
+    SW = np.zeros((4, 4), complex)
+    for i in range(4):
+        SW[((i & 1) << 1) | (i >> 1), i] = 1
+    for a, b in ((0, 1), (1, 0)):
+        _conj_check(2, lambda t: t.cz(a, b), CZ)
+        _conj_check(2, lambda t: t.swap(a, b), SW)
+    # on a third qubit the gate must leave the other column alone
+    _conj_check(3, lambda t: t.cz(2, 0), np.diag([1, 1, 1, 1, 1, -1, 1, -1]).astype(complex))
+
+
 def test_cnot_rule_both_orientations():
     # basis index bit j = qubit j; CNOT(control c, target t)
     def cnot_matrix(c, tq):
@@ -201,6 +224,44 @@ def test_identities_bit_exact(seed):
                     assert np.array_equal(A, B)
 
 
+def _same(u, v):
+    return all(np.array_equal(A, B) for A, B in zip(u.get(), v.get()))
+
+
+@pytest.mark.parametrize("seed", [0, 1])
+def test_full_gate_set_identities_bit_exact(seed):
+    n = 7
+    t = _random_state(n, seed)
+    for a in range(n):
+        assert _same(t.clone().s(a).sdg(a), t)
+        assert _same(t.clone().sdg(a).sdg(a), t.clone().z(a))             # S^dagger^2 = Z
+        assert _same(t.clone().h(a).z(a).h(a), t.clone().x(a))            # HZH = X
+        assert _same(t.clone().x(a).z(a), t.clone().y(a))                 # Y = i X Z
+        for p in ("x", "y", "z"):
+            u = t.clone()
+            getattr(getattr(u, p)(a), p)(a)
+            assert _same(u, t)
+    for a in range(n):
+        for b in range(n):
+            if a == b:
+                continue
+            assert _same(t.clone().cz(a, b), t.clone().cz(b, a))
+            assert _same(t.clone().cz(a, b), t.clone().h(b).cnot(a, b).h(b))
+            assert _same(t.clone().swap(a, b), t.clone().cnot(a, b).cnot(b, a).cnot(a, b))
+            assert _same(t.clone().cz(a, b).cz(a, b), t)
+            assert _same(t.clone().swap(a, b).swap(a, b), t)
+    ops, qa, qb = random_gate_list(np.random.default_rng(seed), n, 40, full=True)
+    u = t.clone().apply_gates(ops, qa, qb)
+    v = t.clone()
+    name = {0: "h", 1: "s", 2: "cnot", 3: "sdg", 4: "x", 5: "y", 6: "z", 7: "cz", 8: "swap"}
+    for o, x, y in zip(ops, qa, qb):
+        f = getattr(v, name[int(o)])
+        f(int(x), int(y)) if int(o) in (2, 7, 8) else f(int(x))
+    assert _same(u, v)
+    with pytest.raises(ValueError):
+        t.clone().apply_gates([9], [0], [0])
+
+
 # ------------------------------------------------------- vs a statevector ---
 
 def _check_stabilizers(t, sv):
@@ -237,6 +298,56 @@ def test_random_circuits_with_measurements_vs_statevector(seed):
             m += 1
             _check_stabilizers(t, sv)
     assert t.anomalies == 0
+
+
+@pytest.mark.parametrize("seed", range(10))
+def test_full_gate_set_and_pauli_measurements_vs_statevector(seed):
+    rng = np.random.default_rng(2000 + seed)
+    n = int(rng.integers(1, 7))
+    t = oracle.Tableau(n)
+    sv = StateVector(n)
+    mats = {oracle.BASIS_Z: PZ, oracle.BASIS_X: PX, oracle.BASIS_Y: PY}
+    m = 0
+    for block in range(6):
+        ops, a, b = random_gate_list(rng, n, int(rng.integers(1, 15)), full=True)
+        t.apply_gates(ops, a, b)
+        sv.apply_gates(ops, a, b)
+        _check_stabilizers(t, sv)
+        for _ in range(int(rng.integers(0, 4))):
+            q = int(rng.integers(0, n))
+            basis = int(rng.integers(0, 3))
+            p1 = sv.prob_minus(q, mats[basis])
+            bit, rnd = t.measure_pauli(q, basis, seed=98, circuit=seed, shot=0, m=m)
+            if rnd:
+                assert np.isclose(p1, 0.5, atol=1e-9)
+                assert bit == oracle.random_bit(98, seed, 0, m)
+            else:
+                assert np.isclose(p1, float(bit), atol=1e-9), (basis, p1, bit)
+            sv.collapse_pauli(q, mats[basis], bit)
+            m += 1
+            _check_stabilizers(t, sv)
+    assert t.anomalies == 0
+
+
+def test_pauli_measurement_eigenstates():
+    """Eigenstates of each basis measure deterministically with the right sign;
+    the other two bases are random on them and leave +-P_a in the stabilizer."""
+    X_, Y_, Z_ = oracle.BASIS_X, oracle.BASIS_Y, oracle.BASIS_Z
+    cases = [  # (preparation, basis, outcome)
+        (lambda t: t, Z_, 0), (lambda t: t.x(0), Z_, 1),
+        (lambda t: t.h(0), X_, 0), (lambda t: t.x(0).h(0), X_, 1),
+        (lambda t: t.h(0).s(0), Y_, 0), (lambda t: t.h(0).sdg(0), Y_, 1),
+    ]
+    for prep, basis, want in cases:
+        assert prep(oracle.Tableau(1)).measure_pauli(0, basis) == (want, False)
+        for other in {X_, Y_, Z_} - {basis}:
+            t = prep(oracle.Tableau(1))
+            bit, rnd = t.measure_pauli(0, other, seed=6, m=1)
+            assert rnd and bit == oracle.random_bit(6, 0, 0, 1)
+            X, Z, R = t.get()
+            px, pz = {X_: (1, 0), Y_: (1, 1), Z_: (0, 1)}[other]
+            assert (X[1, 0], Z[1, 0], R[1]) == (px, pz, bit)
+            assert t.measure_pauli(0, other, m=2) == (bit, False)
 
 
 @pytest.mark.parametrize("n", [3, 6, 10])
