@@ -38,7 +38,7 @@ extern "C" {
 #endif
 
 #define CLIFF_OK 0
-#define CLIFF_EINVAL (-1)   /* bad argument: qubit >= n, CNOT a == b, bad op, NULL, size */
+#define CLIFF_EINVAL (-1)   /* bad argument: qubit >= n, two-qubit gate a == b, bad op, NULL, size */
 #define CLIFF_ENOMEM (-2)   /* buffer too small / host allocation failed / budget exceeded */
 #define CLIFF_EDEVICE (-3)  /* HIP runtime error (message in cliff_last_error) */
 #define CLIFF_EBUSY (-4)    /* resource in use (e.g. admission slots full) */
@@ -48,6 +48,17 @@ extern "C" {
 #define CLIFF_OP_H 0
 #define CLIFF_OP_S 1
 #define CLIFF_OP_CNOT 2
+#define CLIFF_OP_SDG 3    /* S^dagger = diag(1, -i) */
+#define CLIFF_OP_X 4
+#define CLIFF_OP_Y 5
+#define CLIFF_OP_Z 6
+#define CLIFF_OP_CZ 7
+#define CLIFF_OP_SWAP 8
+
+/* Measurement bases of cliff_measure_bases. */
+#define CLIFF_BASIS_Z 0
+#define CLIFF_BASIS_X 1
+#define CLIFF_BASIS_Y 2
 
 typedef struct cliff_ctx cliff_ctx;
 typedef struct cliff_tab cliff_tab;
@@ -107,12 +118,19 @@ int cliff_tab_info(const cliff_tab *tab, uint32_t *n, uint32_t *shots);
  * initial tableau of the phase-space method, Sec. 2 / AG). */
 int cliff_tab_init_zero(cliff_tab *tab);
 
-/* Apply gates in order.  op[k] in {CLIFF_OP_H, CLIFF_OP_S, CLIFF_OP_CNOT};
- * a[k] is the qubit (CNOT control), b[k] the CNOT target (ignored otherwise).
- * Update rules per row (AG, via Sec. 2):
+/* Apply gates in order.  op[k] is a CLIFF_OP_* code; a[k] is the qubit (the
+ * CNOT control), b[k] the second qubit of CNOT (target), CZ and SWAP (ignored
+ * otherwise).  Update rules per row (AG, via Sec. 2; the others from
+ * conjugating each single-qubit Pauli by the gate):
  *   H(a): r ^= x_a z_a, swap x_a and z_a;   S(a): r ^= x_a z_a, z_a ^= x_a;
- *   CNOT(a->b): r ^= x_a z_b (x_b ^ z_a ^ 1), x_b ^= x_a, z_a ^= z_b.
- * Validated on the host before any launch (EINVAL on bad op / qubit / a == b). */
+ *   CNOT(a->b): r ^= x_a z_b (x_b ^ z_a ^ 1), x_b ^= x_a, z_a ^= z_b;
+ *   SDG(a): r ^= x_a (z_a ^ 1), z_a ^= x_a;
+ *   X(a): r ^= z_a;   Y(a): r ^= x_a ^ z_a;   Z(a): r ^= x_a;
+ *   CZ(a,b): r ^= x_a x_b (z_a ^ z_b), z_a ^= x_b, z_b ^= x_a;
+ *   SWAP(a,b): exchange columns a and b.
+ * Runs of single-qubit gates on a qubit are composed into one column update
+ * on the host.  Validated on the host before any launch (EINVAL on bad op /
+ * qubit / a == b for a two-qubit gate). */
 int cliff_apply_gates(cliff_tab *tab, const uint8_t *op, const uint32_t *a, const uint32_t *b,
                       size_t count);
 
@@ -147,6 +165,17 @@ int cliff_apply_encoded(cliff_tab *tab, const uint64_t *dev_ops, const uint32_t 
 int cliff_measure(cliff_tab *tab, const uint32_t *qubits, size_t k, uint64_t seed,
                   uint64_t circuit, uint64_t shot0, uint64_t m0, uint8_t *host_out,
                   uint8_t *host_random);
+
+/* Measure the single-qubit Pauli bases[i] (CLIFF_BASIS_Z, _X or _Y) on
+ * qubits[i], in order, with the conventions of cliff_measure (outcome 0 =
+ * eigenvalue +1, random branch: the measured Pauli with the Philox bit as
+ * sign).  Measuring P_a is measuring Z_a after a Clifford U with U P_a U^dag =
+ * Z_a (X: H; Y: S^dagger then H) and undoing U afterwards; the library does
+ * exactly that, per run of distinct qubits: one gate layer, a Z-measurement
+ * pass, and the inverse layer.  EINVAL on a bad basis or qubit. */
+int cliff_measure_bases(cliff_tab *tab, const uint32_t *qubits, const uint8_t *bases, size_t k,
+                        uint64_t seed, uint64_t circuit, uint64_t shot0, uint64_t m0,
+                        uint8_t *host_out, uint8_t *host_random);
 
 /* Asynchronous form of cliff_measure for k <= n measurements: only enqueues
  * the work on the context stream.  The outcomes stay in the tableau's device

@@ -20,7 +20,8 @@ CLIFF_ENOMEM = -2
 CLIFF_EDEVICE = -3
 CLIFF_EBUSY = -4
 CLIFF_EINTERNAL = -5
-OP_H, OP_S, OP_CNOT = 0, 1, 2
+OP_H, OP_S, OP_CNOT, OP_SDG, OP_X, OP_Y, OP_Z, OP_CZ, OP_SWAP = range(9)
+BASIS_Z, BASIS_X, BASIS_Y = 0, 1, 2
 
 
 class CliffError(RuntimeError):
@@ -71,6 +72,7 @@ _SIGS = {
                                            _u32p, ctypes.POINTER(_sz)]),
     "cliff_apply_encoded": (ctypes.c_int, [_vp, _vp, _u32p, _u32]),
     "cliff_measure": (ctypes.c_int, [_vp, _u32p, _sz, _u64, _u64, _u64, _u64, _u8p, _u8p]),
+    "cliff_measure_bases": (ctypes.c_int, [_vp, _u32p, _u8p, _sz, _u64, _u64, _u64, _u64, _u8p, _u8p]),
     "cliff_sample": (ctypes.c_int, [_vp, _vp, _u32p, _sz, _u64, _u64, _u64, _u8p, _u8p]),
     "cliff_measure_async": (ctypes.c_int, [_vp, _u32p, _sz, _u64, _u64, _u64, _u64]),
     "cliff_tab_read_outcomes": (ctypes.c_int, [_vp, _sz, _u8p, _u8p]),
@@ -227,6 +229,20 @@ def cliff_measure(tab, qubits, seed=0, circuit=0, shot0=0, m0=0, want_out=True):
     return out, rnd
 
 
+def cliff_measure_bases(tab, qubits, bases, seed=0, circuit=0, shot0=0, m0=0, want_out=True):
+    """Like cliff_measure with a basis (BASIS_Z / _X / _Y) per measurement."""
+    _, shots = cliff_tab_info(tab)
+    q = _arr(qubits, np.uint32)
+    b = _arr(bases, np.uint8)
+    if len(b) != len(q):
+        raise ValueError("bases and qubits differ in length")
+    out = np.zeros((shots, len(q)), np.uint8) if want_out else None
+    rnd = np.zeros(len(q), np.uint8)
+    _check(_lib.cliff_measure_bases(tab, _ptr(q, _u32p), _ptr(b, _u8p), len(q), seed, circuit, shot0,
+                                    m0, _ptr(out, _u8p), _ptr(rnd, _u8p)), "cliff_measure_bases")
+    return out, rnd
+
+
 def cliff_measure_async(tab, qubits, seed=0, circuit=0, shot0=0, m0=0):
     q = _arr(qubits, np.uint32)
     _check(_lib.cliff_measure_async(tab, _ptr(q, _u32p), len(q), seed, circuit, shot0, m0),
@@ -347,6 +363,7 @@ def cliff_graph_destroy(graph):
 
 __all__ = [n for n in list(globals()) if n.startswith("cliff_")] + [
     "CLIFF_OK", "CLIFF_EINVAL", "CLIFF_ENOMEM", "CLIFF_EDEVICE", "CLIFF_EBUSY",
-    "CLIFF_EINTERNAL", "OP_H", "OP_S", "OP_CNOT", "CliffError", "LIB_PATH", "exported_symbols",
+    "CLIFF_EINTERNAL", "OP_H", "OP_S", "OP_CNOT", "OP_SDG", "OP_X", "OP_Y", "OP_Z", "OP_CZ",
+    "OP_SWAP", "BASIS_Z", "BASIS_X", "BASIS_Y", "CliffError", "LIB_PATH", "exported_symbols",
     "PROF_KINDS", "BATCH_DESC_DTYPE", "BATCH_CONFIGS", "GATES_AUTO", "GATES_PER_LAYER",
     "GATES_FUSED", "MEASURE_AUTO", "MEASURE_STEP", "MEASURE_PERSISTENT"]

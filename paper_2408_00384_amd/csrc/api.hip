@@ -306,10 +306,6 @@ int cliff_tab_init_zero(cliff_tab *t) {
 
 // ------------------------------------------------------------ gate encoding ---
 
-static inline uint64_t make_op(uint32_t a, uint32_t b, uint64_t flags) {
-  return uint64_t(a) | (uint64_t(b) << kQubitBits) | flags;
-}
-
 static int check_layers(uint32_t n, const uint8_t *h, const uint8_t *s, const uint32_t *ctrl,
                         const uint32_t *tgt, uint32_t npairs, uint32_t depth) {
   if (depth == 0) return CLIFF_OK;
@@ -340,23 +336,17 @@ static size_t encode_layer(uint32_t n, const uint8_t *h, const uint8_t *s, const
     if (ops && cnt < cap) ops[cnt] = v;
     ++cnt;
   };
+  static const uint32_t kHS = sq_compose(SQ_H, SQ_S);
+  auto code = [&](uint32_t q) { return h[q] ? (s[q] ? kHS : SQ_H) : (s[q] ? SQ_S : SQ_I); };
   std::fill(paired.begin(), paired.end(), 0);
   for (uint32_t k = 0; k < npairs; ++k) {
     const uint32_t c = ctrl[k], g = tgt[k];
     paired[c] = paired[g] = 1;
-    uint64_t f = OPF_PAIR;
-    if (h[c]) f |= OPF_HA;
-    if (s[c]) f |= OPF_SA;
-    if (h[g]) f |= OPF_HB;
-    if (s[g]) f |= OPF_SB;
-    emit(make_op(c, g, f));
+    emit(make_op(c, g, code(c), code(g), PAIR_CNOT));
   }
   for (uint32_t q = 0; q < n; ++q) {
     if (paired[q] || !(h[q] | s[q])) continue;
-    uint64_t f = 0;
-    if (h[q]) f |= OPF_HA;
-    if (s[q]) f |= OPF_SA;
-    emit(make_op(q, 0, f));
+    emit(make_op(q, 0, code(q), SQ_I, PAIR_NONE));
   }
   return cnt;
 }
@@ -488,44 +478,92 @@ extern "C" int cliff_apply_encoded(cliff_tab *t, const uint64_t *dev_ops, const 
   return run_encoded(t, dev_ops, offs, doffs, depth);
 }
 
+// Gate list -> encoded layers.  Greedy layering: a gate joins the current
+// layer unless it would have to act after an op of that layer on one of its
+// qubits.  A single-qubit gate on a qubit that only single-qubit gates of the
+// layer touched is composed into that op's code; a two-qubit gate takes over
+// the pending single-qubit codes of its qubits as its "before" parts.  Ops of
+// a layer act on disjoint qubits and commute exactly, and the order of the
+// list is kept on every qubit.
+static int encode_gate_list(uint32_t n, const uint8_t *op, const uint32_t *a, const uint32_t *b,
+                            size_t count, std::vector<uint64_t> &ops, std::vector<uint32_t> &offs) {
+  static const uint32_t kCode[7] = {SQ_H, SQ_S, 0, SQ_SDG, SQ_X, SQ_Y, SQ_Z};
+  for (size_t k = 0; k < count; ++k) {
+    if (op[k] > CLIFF_OP_SWAP) return fail(CLIFF_EINVAL, "gate %zu: bad op %u", k, op[k]);
+    if (a[k] >= n) return fail(CLIFF_EINVAL, "gate %zu: qubit %u >= n = %u", k, a[k], n);
+    const bool two = op[k] == CLIFF_OP_CNOT || op[k] == CLIFF_OP_CZ || op[k] == CLIFF_OP_SWAP;
+    if (two) {
+      if (b[k] >= n) return fail(CLIFF_EINVAL, "gate %zu: second qubit %u >= n = %u", k, b[k], n);
+      if (a[k] == b[k]) return fail(CLIFF_EINVAL, "gate %zu: two-qubit gate on one qubit", k);
+    }
+  }
+  // per qubit: the layer that last touched it, and the slot of its op there
+  // (slot_pair marks a two-qubit op, after which nothing may join the qubit)
+  std::vector<uint32_t> layer_of(n, 0), slot(n, 0);
+  std::vector<uint8_t> slot_pair(n, 0);
+  std::vector<uint64_t> cur;          // ops of the current layer
+  std::vector<uint8_t> gone;          // 1 = taken over by a later two-qubit op
+  uint32_t layer = 1;
+  ops.clear();
+  offs.assign(1, 0);
+  auto flush = [&]() {
+    // single-qubit ops that composed to the identity are dropped here
+    for (size_t i = 0; i < cur.size(); ++i)
+      if (!gone[i] && (op_pair(cur[i]) != PAIR_NONE || op_ca(cur[i]) != SQ_I)) ops.push_back(cur[i]);
+    cur.clear();
+    gone.clear();
+    offs.push_back(uint32_t(ops.size()));
+    ++layer;
+  };
+  for (size_t k = 0; k < count; ++k) {
+    const uint32_t qa = a[k];
+    if (op[k] == CLIFF_OP_CNOT || op[k] == CLIFF_OP_CZ || op[k] == CLIFF_OP_SWAP) {
+      const uint32_t qb = b[k];
+      if ((layer_of[qa] == layer && slot_pair[qa]) || (layer_of[qb] == layer && slot_pair[qb])) flush();
+      uint32_t ca = SQ_I, cb = SQ_I;
+      if (layer_of[qa] == layer) { ca = op_ca(cur[slot[qa]]); gone[slot[qa]] = 1; }
+      if (layer_of[qb] == layer) { cb = op_ca(cur[slot[qb]]); gone[slot[qb]] = 1; }
+      const uint32_t pair = op[k] == CLIFF_OP_CNOT ? PAIR_CNOT : op[k] == CLIFF_OP_CZ ? PAIR_CZ : PAIR_SWAP;
+      layer_of[qa] = layer_of[qb] = layer;
+      slot[qa] = slot[qb] = uint32_t(cur.size());
+      slot_pair[qa] = slot_pair[qb] = 1;
+      cur.push_back(make_op(qa, qb, ca, cb, pair));
+      gone.push_back(0);
+    } else {
+      const uint32_t g = kCode[op[k]];
+      if (layer_of[qa] == layer && slot_pair[qa]) flush();
+      if (layer_of[qa] == layer) {
+        uint64_t &v = cur[slot[qa]];
+        v = make_op(qa, 0, sq_compose(op_ca(v), g), SQ_I, PAIR_NONE);
+      } else {
+        layer_of[qa] = layer;
+        slot[qa] = uint32_t(cur.size());
+        slot_pair[qa] = 0;
+        cur.push_back(make_op(qa, 0, g, SQ_I, PAIR_NONE));
+        gone.push_back(0);
+      }
+    }
+    if (ops.size() + cur.size() > 0xFFFFFFF0ull) return fail(CLIFF_EINVAL, "gate list too long");
+  }
+  if (!cur.empty()) flush();
+  return CLIFF_OK;
+}
+
 extern "C" int cliff_apply_gates(cliff_tab *t, const uint8_t *op, const uint32_t *a,
                                  const uint32_t *b, size_t count) {
   if (!t) return fail(CLIFF_EINVAL, "cliff_apply_gates: NULL tableau");
   if (count == 0) return CLIFF_OK;
   if (!op || !a || !b) return fail(CLIFF_EINVAL, "cliff_apply_gates: NULL array");
   const uint32_t n = t->d.n;
-  for (size_t k = 0; k < count; ++k) {
-    if (op[k] > CLIFF_OP_CNOT) return fail(CLIFF_EINVAL, "gate %zu: bad op %u", k, op[k]);
-    if (a[k] >= n) return fail(CLIFF_EINVAL, "gate %zu: qubit %u >= n = %u", k, a[k], n);
-    if (op[k] == CLIFF_OP_CNOT) {
-      if (b[k] >= n) return fail(CLIFF_EINVAL, "gate %zu: target %u >= n = %u", k, b[k], n);
-      if (a[k] == b[k]) return fail(CLIFF_EINVAL, "gate %zu: CNOT control == target", k);
-    }
-  }
-  // Greedy layering: a gate joins the current layer unless one of its qubits
-  // is already used there.  Gates within a layer act on disjoint qubits and
-  // so commute exactly; layer order preserves the list order per qubit.
   std::vector<uint64_t> ops;
-  std::vector<uint32_t> offs{0};
-  std::vector<uint32_t> used(n, 0);
-  uint32_t layer = 1;
-  ops.reserve(count);
-  for (size_t k = 0; k < count; ++k) {
-    const bool two = op[k] == CLIFF_OP_CNOT;
-    if (used[a[k]] == layer || (two && used[b[k]] == layer)) {
-      offs.push_back(uint32_t(ops.size()));
-      ++layer;
-    }
-    used[a[k]] = layer;
-    if (two) used[b[k]] = layer;
-    uint64_t f = op[k] == CLIFF_OP_H ? OPF_HA : op[k] == CLIFF_OP_S ? OPF_SA : OPF_PAIR;
-    ops.push_back(make_op(a[k], two ? b[k] : 0, f));
-  }
-  offs.push_back(uint32_t(ops.size()));
+  std::vector<uint32_t> offs;
+  int rc = encode_gate_list(n, op, a, b, count, ops, offs);
+  if (rc) return rc;
+  if (ops.empty()) return CLIFF_OK;   // every gate cancelled out
   DeviceGuard g(t->ctx->device);
   const uint64_t *dops = nullptr;
   const uint32_t *doffs = nullptr;
-  int rc = upload_stream(t->ctx, ops.data(), ops.size(), offs.data(), offs.size(), &dops, &doffs);
+  rc = upload_stream(t->ctx, ops.data(), ops.size(), offs.data(), offs.size(), &dops, &doffs);
   if (rc) return rc;
   return run_encoded(t, dops, offs.data(), doffs, uint32_t(offs.size() - 1));
 }
@@ -578,9 +616,10 @@ static int check_abort(cliff_tab *t) {
   return CLIFF_OK;
 }
 
+// Outcome of measurement i of shot s lands at host_out[s * ld + col0 + i].
 static int measure_impl(cliff_tab *t, const uint32_t *qubits, size_t k, uint64_t seed,
                         uint64_t circuit, uint64_t shot0, uint64_t m0, uint8_t *host_out,
-                        uint8_t *host_random) {
+                        uint8_t *host_random, size_t ld, size_t col0) {
   const uint32_t n = t->d.n, S = t->d.S;
   for (size_t i = 0; i < k; ++i)
     if (qubits[i] >= n) return fail(CLIFF_EINVAL, "measure: qubit %u >= n = %u", qubits[i], n);
@@ -604,8 +643,8 @@ static int measure_impl(cliff_tab *t, const uint32_t *qubits, size_t k, uint64_t
       if (arc) return arc;
       if (host_out)
         for (size_t i = 0; i < cnt; ++i)
-          for (uint32_t s = 0; s < S; ++s) host_out[size_t(s) * k + base + i] = out_stage[i * S + s];
-      if (host_random) memcpy(host_random + base, kind_stage.data(), cnt);
+          for (uint32_t s = 0; s < S; ++s) host_out[size_t(s) * ld + col0 + base + i] = out_stage[i * S + s];
+      if (host_random) memcpy(host_random + col0 + base, kind_stage.data(), cnt);
     }
   }
   return CLIFF_OK;
@@ -618,7 +657,58 @@ extern "C" int cliff_measure(cliff_tab *t, const uint32_t *qubits, size_t k, uin
   if (k == 0) return CLIFF_OK;
   if (!qubits) return fail(CLIFF_EINVAL, "cliff_measure: NULL qubits");
   DeviceGuard g(t->ctx->device);
-  return measure_impl(t, qubits, k, seed, circuit, shot0, m0, host_out, host_random);
+  return measure_impl(t, qubits, k, seed, circuit, shot0, m0, host_out, host_random, k, 0);
+}
+
+// One layer of single-qubit ops (distinct qubits), uploaded and applied.
+static int apply_one_layer(cliff_tab *t, const std::vector<uint64_t> &ops) {
+  if (ops.empty()) return CLIFF_OK;
+  const uint32_t offs[2] = {0, uint32_t(ops.size())};
+  const uint64_t *dops = nullptr;
+  const uint32_t *doffs = nullptr;
+  int rc = upload_stream(t->ctx, ops.data(), ops.size(), offs, 2, &dops, &doffs);
+  if (rc) return rc;
+  return run_encoded(t, dops, offs, doffs, 1);
+}
+
+extern "C" int cliff_measure_bases(cliff_tab *t, const uint32_t *qubits, const uint8_t *bases,
+                                   size_t k, uint64_t seed, uint64_t circuit, uint64_t shot0,
+                                   uint64_t m0, uint8_t *host_out, uint8_t *host_random) {
+  if (!t) return fail(CLIFF_EINVAL, "cliff_measure_bases: NULL tableau");
+  if (k == 0) return CLIFF_OK;
+  if (!qubits || !bases) return fail(CLIFF_EINVAL, "cliff_measure_bases: NULL qubits/bases");
+  const uint32_t n = t->d.n;
+  for (size_t i = 0; i < k; ++i) {
+    if (qubits[i] >= n) return fail(CLIFF_EINVAL, "measure: qubit %u >= n = %u", qubits[i], n);
+    if (bases[i] > CLIFF_BASIS_Y) return fail(CLIFF_EINVAL, "measure: bad basis %u at %zu", bases[i], i);
+  }
+  DeviceGuard g(t->ctx->device);
+  // U maps the measured Pauli to Z: X -> H; Y -> S^dagger then H.  U^-1:
+  // H; H then S.
+  static const uint32_t kToZ[3] = {SQ_I, SQ_H, sq_compose(SQ_SDG, SQ_H)};
+  static const uint32_t kBack[3] = {SQ_I, SQ_H, sq_compose(SQ_H, SQ_S)};
+  std::vector<uint32_t> seen(n, 0);
+  std::vector<uint64_t> pre, post;
+  uint32_t run = 0;
+  for (size_t i = 0; i < k;) {
+    ++run;
+    pre.clear();
+    post.clear();
+    size_t j = i;
+    for (; j < k && seen[qubits[j]] != run; ++j) {
+      seen[qubits[j]] = run;
+      if (bases[j] != CLIFF_BASIS_Z) {
+        pre.push_back(make_op(qubits[j], 0, kToZ[bases[j]], SQ_I, PAIR_NONE));
+        post.push_back(make_op(qubits[j], 0, kBack[bases[j]], SQ_I, PAIR_NONE));
+      }
+    }
+    int rc = apply_one_layer(t, pre);
+    if (!rc) rc = measure_impl(t, qubits + i, j - i, seed, circuit, shot0, m0 + i, host_out, host_random, k, i);
+    if (!rc) rc = apply_one_layer(t, post);
+    if (rc) return rc;
+    i = j;
+  }
+  return CLIFF_OK;
 }
 
 extern "C" int cliff_measure_async(cliff_tab *t, const uint32_t *qubits, size_t k, uint64_t seed,
@@ -628,7 +718,7 @@ extern "C" int cliff_measure_async(cliff_tab *t, const uint32_t *qubits, size_t 
   if (!qubits) return fail(CLIFF_EINVAL, "cliff_measure_async: NULL qubits");
   if (k > t->d.n) return fail(CLIFF_EINVAL, "cliff_measure_async: k = %zu > n = %u", k, t->d.n);
   DeviceGuard g(t->ctx->device);
-  return measure_impl(t, qubits, k, seed, circuit, shot0, m0, nullptr, nullptr);
+  return measure_impl(t, qubits, k, seed, circuit, shot0, m0, nullptr, nullptr, k, 0);
 }
 
 extern "C" int cliff_tab_read_outcomes(cliff_tab *t, size_t k, uint8_t *host_out,
@@ -664,7 +754,7 @@ extern "C" int cliff_sample(cliff_tab *t, cliff_tab *work, const uint32_t *qubit
   if (work->ctx->stream != t->ctx->stream) HIP_TRY(hipStreamSynchronize(t->ctx->stream));
   HIP_TRY(launch_copy_tab(work->dev, t->dev, work->ctx->stream));
   if (k == 0) return CLIFF_OK;
-  return measure_impl(work, qubits, k, seed, circuit, shot0, 0, host_out, host_random);
+  return measure_impl(work, qubits, k, seed, circuit, shot0, 0, host_out, host_random, k, 0);
 }
 
 // ------------------------------------------------------------ export/import ---

@@ -79,23 +79,18 @@ __global__ void __launch_bounds__(TEAM) k_batch(const BatchDescDev *__restrict__
         if (w < W) {
           for (uint32_t k = a0 + k0; k < a1; k += kst) {
             const uint64_t op = cops[k];
-            const uint32_t a = uint32_t(op & kQubitMask);
-            const uint32_t bq = uint32_t((op >> kQubitBits) & kQubitMask);
-            if (a >= n || ((op & OPF_PAIR) && (bq >= n || bq == a))) {   // malformed op
+            if (!op_valid(op, n)) {   // malformed op
               atomicAdd(errors, 1u);
               continue;
             }
+            const uint32_t a = op_a(op), pair = op_pair(op);
             uint64_t xa = sX[a * W + w], za = sZ[a * W + w];
-            if (op & OPF_HA) { racc ^= xa & za; const uint64_t t = xa; xa = za; za = t; }
-            if (op & OPF_SA) { racc ^= xa & za; za ^= xa; }
-            if (op & OPF_PAIR) {
-              const uint32_t b = bq;
+            if (op_ca(op)) sq_apply(op_ca(op), xa, za, racc);
+            if (pair != PAIR_NONE) {
+              const uint32_t b = op_b(op);
               uint64_t xb = sX[b * W + w], zb = sZ[b * W + w];
-              if (op & OPF_HB) { racc ^= xb & zb; const uint64_t t = xb; xb = zb; zb = t; }
-              if (op & OPF_SB) { racc ^= xb & zb; zb ^= xb; }
-              racc ^= xa & zb & ~(xb ^ za);
-              xb ^= xa;
-              za ^= zb;
+              if (op_cb(op)) sq_apply(op_cb(op), xb, zb, racc);
+              pair_apply(pair, xa, za, xb, zb, racc);
               sX[b * W + w] = xb;
               sZ[b * W + w] = zb;
             }

@@ -1,10 +1,13 @@
-// Tableau initialisation and gate sweeps (H, S, CNOT column updates).
+// Tableau initialisation and gate sweeps (column updates).
 //
 // Gate rules of the phase-space method (paper Sec. 2, after Aaronson &
 // Gottesman 2004), applied to 64 rows at once with word-wise bit logic:
 //   H(a):        r ^= x_a & z_a;  swap(x_a, z_a)
 //   S(a):        r ^= x_a & z_a;  z_a ^= x_a
 //   CNOT(a->b):  r ^= x_a & z_b & ~(x_b ^ z_a);  x_b ^= x_a;  z_a ^= z_b
+// and the rest of the Clifford gate set (S^dagger, X, Y, Z, CZ, SWAP) in the
+// same form; an op word carries one single-qubit Clifford per qubit and one
+// two-qubit gate (the encoding and rules are in gate_ops.h).
 // Gates on disjoint qubits touch disjoint columns and their sign terms read
 // only their own columns, so every op of a layer can run concurrently; the
 // sign contributions are XOR-accumulated per thread and flushed once.
@@ -62,24 +65,19 @@ __global__ void __launch_bounds__(256) k_gate_layer(TabDev t, const uint64_t *__
   uint64_t racc = 0;
   for (uint32_t o = o0 + wave; o < o1; o += 4) {
     const uint64_t op = ops[o];
-    const uint32_t a = uint32_t(op & kQubitMask);
-    const uint32_t bq = uint32_t((op >> kQubitBits) & kQubitMask);
-    if (a >= t.n || ((op & OPF_PAIR) && (bq >= t.n || bq == a))) continue;   // malformed op
+    if (!op_valid(op, t.n)) continue;   // malformed op
+    const uint32_t a = op_a(op), pair = op_pair(op);
     uint64_t *pxa = t.X + a * Wp + w;
     uint64_t *pza = t.Z + a * Wp + w;
     uint64_t xa = *pxa, za = *pza;
-    if (op & OPF_HA) { racc ^= xa & za; const uint64_t tmp = xa; xa = za; za = tmp; }
-    if (op & OPF_SA) { racc ^= xa & za; za ^= xa; }
-    if (op & OPF_PAIR) {
-      const uint32_t b = bq;
+    if (op_ca(op)) sq_apply(op_ca(op), xa, za, racc);
+    if (pair != PAIR_NONE) {
+      const uint32_t b = op_b(op);
       uint64_t *pxb = t.X + b * Wp + w;
       uint64_t *pzb = t.Z + b * Wp + w;
       uint64_t xb = *pxb, zb = *pzb;
-      if (op & OPF_HB) { racc ^= xb & zb; const uint64_t tmp = xb; xb = zb; zb = tmp; }
-      if (op & OPF_SB) { racc ^= xb & zb; zb ^= xb; }
-      racc ^= xa & zb & ~(xb ^ za);
-      xb ^= xa;
-      za ^= zb;
+      if (op_cb(op)) sq_apply(op_cb(op), xb, zb, racc);
+      pair_apply(pair, xa, za, xb, zb, racc);
       *pxb = xb;
       *pzb = zb;
     }
@@ -117,20 +115,15 @@ __global__ void __launch_bounds__(256) k_gates_fused(TabDev t, const uint64_t *_
     const uint32_t o1 = offs[l + 1];
     for (uint32_t k = offs[l] + tid; k < o1; k += blockDim.x) {
       const uint64_t op = ops[k];
-      const uint32_t a = uint32_t(op & kQubitMask);
-      const uint32_t bq = uint32_t((op >> kQubitBits) & kQubitMask);
-      if (a >= n || ((op & OPF_PAIR) && (bq >= n || bq == a))) continue;   // malformed op
+      if (!op_valid(op, n)) continue;   // malformed op
+      const uint32_t a = op_a(op), pair = op_pair(op);
       uint32_t xa = sx[a], za = sz[a];
-      if (op & OPF_HA) { racc ^= xa & za; const uint32_t tmp = xa; xa = za; za = tmp; }
-      if (op & OPF_SA) { racc ^= xa & za; za ^= xa; }
-      if (op & OPF_PAIR) {
-        const uint32_t b = bq;
+      if (op_ca(op)) sq_apply(op_ca(op), xa, za, racc);
+      if (pair != PAIR_NONE) {
+        const uint32_t b = op_b(op);
         uint32_t xb = sx[b], zb = sz[b];
-        if (op & OPF_HB) { racc ^= xb & zb; const uint32_t tmp = xb; xb = zb; zb = tmp; }
-        if (op & OPF_SB) { racc ^= xb & zb; zb ^= xb; }
-        racc ^= xa & zb & ~(xb ^ za);
-        xb ^= xa;
-        za ^= zb;
+        if (op_cb(op)) sq_apply(op_cb(op), xb, zb, racc);
+        pair_apply(pair, xa, za, xb, zb, racc);
         sx[b] = xb;
         sz[b] = zb;
       }

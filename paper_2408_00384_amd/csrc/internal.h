@@ -18,6 +18,7 @@
 #include <stdint.h>
 
 #include <vector>
+#include "gate_ops.h"
 
 namespace cliff {
 
@@ -60,14 +61,6 @@ struct Profiler {
   ~Profiler();
 };
 
-// Gate op word: a (28 bits) | b (28 bits) << 28 | flags << 56.
-constexpr uint64_t OPF_HA = 1ull << 56;
-constexpr uint64_t OPF_SA = 1ull << 57;
-constexpr uint64_t OPF_HB = 1ull << 58;
-constexpr uint64_t OPF_SB = 1ull << 59;
-constexpr uint64_t OPF_PAIR = 1ull << 60;  // CNOT(a -> b) after the single-qubit gates
-constexpr uint32_t kQubitBits = 28;
-constexpr uint64_t kQubitMask = (1ull << kQubitBits) - 1;
 
 struct Dims {
   uint32_t n, S;   // qubits, shot sign columns

@@ -73,6 +73,9 @@ class DeviceTableau:
     def measure(self, qubits, seed=0, circuit=0, shot0=0, m0=0):
         return B.cliff_measure(self.handle, qubits, seed, circuit, shot0, m0)
 
+    def measure_bases(self, qubits, bases, seed=0, circuit=0, shot0=0, m0=0):
+        return B.cliff_measure_bases(self.handle, qubits, bases, seed, circuit, shot0, m0)
+
     def export(self):
         return B.cliff_tab_export(self.handle)
 

@@ -85,6 +85,77 @@ def test_gate_list_matches_oracle(ctx, gate_mode, n):
     _assert_tab_equal(t.export(), [ref])
 
 
+@pytest.mark.parametrize("n", [1, 2, 3, 17, 64, 65, 130, 1000])
+def test_full_gate_set_list_matches_oracle(ctx, gate_mode, n):
+    """S^dagger, X, Y, Z, CZ and SWAP beside H, S, CNOT; small n make long runs
+    of single-qubit gates on one qubit (composed on the host) and two-qubit
+    gates that take over those runs."""
+    rng = np.random.default_rng([7, n])
+    ops, a, b = random_gate_list(rng, n, 600, full=True)
+    t = _tab(ctx, n, 2).apply_gates(ops, a, b)
+    ref = oracle.Tableau(n).apply_gates(ops, a, b).get()
+    _assert_tab_equal(t.export(), [ref, ref])
+
+
+def test_gate_runs_that_cancel(ctx, gate_mode):
+    """Runs composing to the identity (X X, S S^dagger, H H, Y Z X) leave the
+    state alone, on qubit 0 too, also when followed by a two-qubit gate."""
+    from inputs import OP_CNOT, OP_CZ, OP_H, OP_S, OP_SDG, OP_SWAP, OP_X, OP_Y, OP_Z
+    n = 5
+    base_ops, base_a, base_b = random_gate_list(np.random.default_rng(3), n, 60, full=True)
+    seqs = [
+        ([OP_X, OP_X], [0, 0], [0, 0]),
+        ([OP_S, OP_SDG, OP_H, OP_H], [0, 0, 0, 0], [0] * 4),
+        ([OP_Y, OP_Z, OP_X], [3, 3, 3], [0] * 3),
+        ([OP_X, OP_X, OP_CZ, OP_S, OP_SDG, OP_SWAP], [0, 0, 0, 2, 2, 2], [0, 0, 1, 0, 0, 4]),
+        ([OP_H, OP_CNOT, OP_H, OP_CNOT], [1, 1, 1, 1], [0, 2, 0, 2]),
+    ]
+    for ops, qa, qb in seqs:
+        t = _tab(ctx, n).apply_gates(base_ops, base_a, base_b)
+        t.apply_gates(np.array(ops, np.uint8), np.array(qa, np.uint32), np.array(qb, np.uint32))
+        ref = oracle.Tableau(n).apply_gates(base_ops, base_a, base_b)
+        ref.apply_gates(np.array(ops, np.uint8), np.array(qa, np.uint32), np.array(qb, np.uint32))
+        _assert_tab_equal(t.export(), [ref.get()])
+        t.close()
+
+
+@pytest.mark.parametrize("n", [1, 2, 5, 33, 65, 200, 700, 2100])
+def test_measure_bases_match_oracle(ctx, measure_mode, n):
+    """X-, Y- and Z-basis measurements (with repeated qubits, so several runs
+    of distinct qubits) on a full-gate-set state, three shots: outcomes,
+    random flags and the tableau afterwards."""
+    rng = np.random.default_rng([8, n])
+    ops, a, b = random_gate_list(rng, n, 8 * n + 20, full=True)
+    k = min(3 * n, 60)
+    q = rng.integers(0, n, size=k).astype(np.uint32)
+    bases = rng.integers(0, 3, size=k).astype(np.uint8)
+    t = _tab(ctx, n, 3).apply_gates(ops, a, b)
+    out, rnd = t.measure_bases(q, bases, seed=17, circuit=n, m0=4)
+    gx, gz, gr = t.export()
+    for s in range(3):
+        ref = oracle.Tableau(n).apply_gates(ops, a, b)
+        o, kd = ref.measure_bases(q, bases, seed=17, circuit=n, shot=s, m0=4)
+        assert np.array_equal(out[s], o), "outcomes differ (shot %d)" % s
+        assert np.array_equal(rnd, kd), "random flags differ"
+        x, z, r = ref.get()
+        assert np.array_equal(gx, x) and np.array_equal(gz, z) and np.array_equal(gr[s], r)
+    assert t.anomalies() == 0
+
+
+def test_measure_bases_errors(ctx):
+    from paper_2408_00384_amd import CLIFF_EINVAL, CliffError
+    t = _tab(ctx, 4, 1)
+    with pytest.raises(CliffError) as e:
+        t.measure_bases([0, 1], [1, 3])
+    assert e.value.code == CLIFF_EINVAL
+    with pytest.raises(CliffError) as e:
+        t.measure_bases([4], [0])
+    assert e.value.code == CLIFF_EINVAL
+    # |0000> in X: every outcome random; in Z afterwards: random again
+    out, rnd = t.measure_bases([0, 1, 0], [1, 1, 0])
+    assert rnd.tolist() == [1, 1, 1]
+
+
 def test_encoded_stream_from_device_memory(ctx, gate_mode):
     """Pre-encoded ops resident in HBM (cliff_apply_encoded), both strategies."""
     import torch
@@ -243,7 +314,7 @@ def test_error_paths(ctx):
         t.apply_gates([2], [3], [3])
     assert e.value.code == CLIFF_EINVAL
     with pytest.raises(CliffError) as e:
-        t.apply_gates([7], [1], [2])
+        t.apply_gates([9], [1], [2])
     assert e.value.code == CLIFF_EINVAL
     with pytest.raises(CliffError) as e:
         t.measure([11])
