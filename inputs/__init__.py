@@ -5,3 +5,6 @@ from .circuits import (  # noqa: F401
     random_layers, serving_params, serving_request, serving_workload,
     OP_H, OP_S, OP_CNOT, OP_SDG, OP_X, OP_Y, OP_Z, OP_CZ, OP_SWAP, TWO_QUBIT_OPS,
 )
+from .bm_clifford import (  # noqa: F401,E402
+    CliffordCircuit, clifford_from_choices, clifford_workload, random_clifford,
+)
