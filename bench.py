@@ -163,6 +163,118 @@ def bench_batch(P, torch, np, count=4096, plain_sample=48, reps=5):
     }
 
 
+def _gen_clifford(args):
+    from inputs import random_clifford
+    n, seed, i = args
+    c = random_clifford(n, [seed, n, i], circuit_id=i)
+    return c.ops, c.a, c.b
+
+
+def _tab_digest(x, z, r):
+    h = hashlib.sha256()
+    for a in (x, z, r):
+        h.update(a.tobytes())
+    return h.hexdigest()
+
+
+def bench_clifford(P, torch, np, n=1000, count=100, seed=5, reps=3, oracle_circuits=1):
+    """The paper's Fig. 2a workload: `count` uniformly random Clifford circuits
+    on n qubits, gates only, from |0...0>.  Op streams resident in HBM; one
+    many-tableau launch for all circuits vs one launch per circuit (plain);
+    tableaux compared bit for bit between the two, circuit 0 against the
+    oracle's stored digest; the oracle timed on `oracle_circuits` circuits."""
+    import concurrent.futures as cf
+    import multiprocessing as mp
+    t0 = time.perf_counter()
+    workers = max(1, min(16, os.cpu_count() or 1))
+    # children only draw circuits (numpy); spawn, so none inherits GPU state
+    with cf.ProcessPoolExecutor(workers, mp_context=mp.get_context("spawn")) as ex:
+        lists = list(ex.map(_gen_clifford, [(n, seed, i) for i in range(count)]))
+    gen_s = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    with cf.ThreadPoolExecutor(workers) as ex:   # the encoder runs without the GIL
+        enc = list(ex.map(lambda l: P.cliff_encode_gates(n, *l), lists))
+    enc_s = time.perf_counter() - t0
+    gates = sum(len(l[0]) for l in lists)
+    layers = [len(o) - 1 for _, o in enc]
+    stream = torch.cuda.Stream()
+    ctx = P.Context(0, stream)
+    dev = [torch.from_numpy(w.view(np.int64)).to("cuda:0") for w, _ in enc]
+    offs = [o for _, o in enc]
+    ptrs = [d.data_ptr() for d in dev]
+    torch.cuda.synchronize()
+    tabs = [P.DeviceTableau(ctx, n, 1) for _ in range(count)]
+    handles = [t.handle for t in tabs]
+
+    def batched():
+        for t in tabs:
+            t.init_zero()
+        P.cliff_apply_encoded_many(handles, ptrs, offs)
+
+    def plain():
+        for t, p, o in zip(tabs, ptrs, offs):
+            t.init_zero()
+            P.cliff_apply_encoded(t.handle, p, o)
+
+    res = {}
+    digests = {}
+    with torch.cuda.stream(stream):
+        for name, fn in (("batched", batched), ("plain", plain)):
+            fn()   # warm-up
+            ctx.sync()
+            P.cliff_ctx_profile(ctx.handle, True)
+            ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            t1 = time.perf_counter()
+            ev0.record(stream)
+            for _ in range(reps):
+                fn()
+            ev1.record(stream)
+            ctx.sync()
+            wall = (time.perf_counter() - t1) / reps
+            gate_ms, launches = P.cliff_ctx_profile_read(ctx.handle, "gate")
+            P.cliff_ctx_profile(ctx.handle, False)
+            ms = ev0.elapsed_time(ev1) / reps
+            res[name] = {"circuits_per_s": count / (ms * 1e-3), "ms": ms, "ms_wall": wall * 1e3,
+                         "gate_kernel_ms": gate_ms / reps, "gate_launches": launches // reps}
+            digests[name] = []
+            for t in tabs:
+                x, z, r = t.export()
+                digests[name].append(_tab_digest(x, z, r[0]))
+    for t in tabs:
+        t.close()
+    golden = os.path.join(ROOT, "tests", "golden", "clifford_n%d.json" % n)
+    vs_oracle = None
+    if os.path.exists(golden) and seed == 5:
+        rec = json.load(open(golden))["circuits"]
+        vs_oracle = all(digests["batched"][int(i)] == v["tableau_sha256"] for i, v in rec.items()
+                        if int(i) < count)
+    cpu = None
+    if oracle_circuits:
+        import oracle
+        t2 = time.perf_counter()
+        for i in range(oracle_circuits):
+            oracle.Tableau(n).apply_gates(*lists[i])
+        cpu_s = (time.perf_counter() - t2) / oracle_circuits
+        cpu = {"circuits_per_s": 1.0 / cpu_s, "cores": 1, "kind": "oracle",
+               "sample": "%d of the %d circuits, gates only" % (oracle_circuits, count)}
+    b = res["batched"]
+    return {
+        "workload": "%d uniformly random Clifford circuits (Bravyi-Maslov canonical form), n = %d, "
+                    "gates only, from |0...0>" % (count, n),
+        "circuits_per_s": b["circuits_per_s"],
+        "gates_per_circuit": gates / count,
+        "layers_per_circuit": float(np.mean(layers)),
+        "row_gate_updates_per_s": gates * 2 * n / (b["ms"] * 1e-3),
+        "batched": b,
+        "plain": res["plain"],
+        "batched_vs_plain": b["circuits_per_s"] / res["plain"]["circuits_per_s"],
+        "bit_exact_batched_vs_plain": digests["batched"] == digests["plain"],
+        "bit_exact_vs_oracle_stored": vs_oracle,
+        "cpu_baseline": cpu,
+        "generate_s": gen_s, "encode_s": enc_s,
+    }
+
+
 def bench_serving(P, np, count=96, seed=4, budget=64 << 30, lanes=8):
     """Serving workload: n log-uniform in [16, 4096], depth 2n, shots in
     [1, 1024], admission by tableau bytes against a 64 GB budget.  First a
@@ -217,6 +329,8 @@ def main():
     ap.add_argument("--cpu-budget", type=float, default=20.0, help="seconds of oracle work")
     ap.add_argument("--no-batch", action="store_true", help="skip the batched-circuits leg")
     ap.add_argument("--no-serving", action="store_true", help="skip the serving leg")
+    ap.add_argument("--no-clifford", action="store_true",
+                    help="skip the uniform-random-Clifford (gates only) leg")
     ap.add_argument("--no-profile", action="store_true",
                     help="no per-kernel HIP events (for hardware-counter runs); no roofline")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -354,6 +468,9 @@ def main():
     if not args.no_serving:
         print("# serving ...", file=sys.stderr, flush=True)
         result["serving"] = bench_serving(P, np)
+    if not args.no_clifford:
+        print("# uniform random Cliffords, gates only ...", file=sys.stderr, flush=True)
+        result["random_clifford"] = bench_clifford(P, torch, np)
     if not args.no_cpu_baseline:
         print("# cpu baseline (oracle) ...", file=sys.stderr, flush=True)
         result["cpu_baseline"] = cpu_baseline(c, args.cpu_budget)

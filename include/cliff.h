@@ -152,6 +152,38 @@ int cliff_encode_layers(uint32_t n, const uint8_t *h, const uint8_t *s, const ui
 int cliff_apply_encoded(cliff_tab *tab, const uint64_t *dev_ops, const uint32_t *offs,
                         uint32_t depth);
 
+/* Encode a gate list (op codes and rules of cliff_apply_gates) into the
+ * library's op words and layer boundaries, for device-resident reuse with
+ * cliff_apply_encoded / cliff_apply_encoded_many.  *nops and *depth receive
+ * the sizes; ops (capacity ops_cap words) and offs (offs_cap entries, depth
+ * + 1 needed) may be NULL to query them only.  EINVAL as cliff_apply_gates;
+ * ENOMEM if a non-NULL output is too small (sizes still reported). */
+int cliff_encode_gates(uint32_t n, const uint8_t *op, const uint32_t *a, const uint32_t *b,
+                       size_t count, uint64_t *ops, size_t ops_cap, uint32_t *offs, size_t offs_cap,
+                       size_t *nops, uint32_t *depth);
+
+/* Gates only, on many tableaux in one launch (the paper's Fig. 2a workload:
+ * many random Clifford circuits, no measurement).  Every tableau is split
+ * into groups of rows_per_group rows (32 or 64; 0 = 64 when every n <= 10,176
+ * and the launch has at least 4 groups per compute unit, else 32); one
+ * workgroup holds its group of every column in LDS and runs all layers.
+ * tabs[0..count): distinct tableaux bound to one context, 2 n rows_per_group/8
+ * bytes <= 159 KiB (n <= 20,352 at 32 rows, 10,176 at 64), count <= 65,535.
+ * _encoded_many: tableau i runs the encoded stream at DEVICE pointer
+ * dev_ops[i] (caller-owned, unchanged until the launch has run) with the HOST
+ * array offs[i][0..depths[i]] of layer boundaries.  _gates_many: tableau i
+ * runs the gate list (op[i], a[i], b[i], counts[i]) as cliff_apply_gates
+ * would, encoded on the host.  Only enqueues work (the staged descriptors
+ * and offsets are copied before the call returns).  EINVAL on a NULL array
+ * or tableau, a repeated tableau, tableaux on different contexts, a size
+ * that does not fit, bad ops, or decreasing offsets. */
+int cliff_apply_encoded_many(cliff_tab *const *tabs, const uint64_t *const *dev_ops,
+                             const uint32_t *const *offs, const uint32_t *depths, size_t count,
+                             int rows_per_group);
+int cliff_apply_gates_many(cliff_tab *const *tabs, const uint8_t *const *op, const uint32_t *const *a,
+                           const uint32_t *const *b, const size_t *counts, size_t count,
+                           int rows_per_group);
+
 /* Z-measure qubits[0..k) in order (AG measurement, via Sec. 2).  Measurement
  * i has index m = m0 + i for the random-bit counter.  Random branch: the pivot
  * is the smallest stabilizer row with x_a = 1; every other row with x_a = 1

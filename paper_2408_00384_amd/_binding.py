@@ -49,6 +49,8 @@ _u8p = ctypes.POINTER(ctypes.c_uint8)
 _u32p = ctypes.POINTER(ctypes.c_uint32)
 _u64p = ctypes.POINTER(ctypes.c_uint64)
 _sz = ctypes.c_size_t
+_szp = ctypes.POINTER(ctypes.c_size_t)
+_vpp = ctypes.POINTER(ctypes.c_void_p)
 _u32 = ctypes.c_uint32
 _u64 = ctypes.c_uint64
 
@@ -71,6 +73,10 @@ _SIGS = {
     "cliff_encode_layers": (ctypes.c_int, [_u32, _u8p, _u8p, _u32p, _u32p, _u32, _u32, _u64p, _sz,
                                            _u32p, ctypes.POINTER(_sz)]),
     "cliff_apply_encoded": (ctypes.c_int, [_vp, _vp, _u32p, _u32]),
+    "cliff_encode_gates": (ctypes.c_int, [_u32, _u8p, _u32p, _u32p, _sz, _u64p, _sz, _u32p, _sz,
+                                          ctypes.POINTER(_sz), ctypes.POINTER(_u32)]),
+    "cliff_apply_encoded_many": (ctypes.c_int, [_vpp, _vpp, _vpp, _u32p, _sz, ctypes.c_int]),
+    "cliff_apply_gates_many": (ctypes.c_int, [_vpp, _vpp, _vpp, _vpp, _szp, _sz, ctypes.c_int]),
     "cliff_measure": (ctypes.c_int, [_vp, _u32p, _sz, _u64, _u64, _u64, _u64, _u8p, _u8p]),
     "cliff_measure_bases": (ctypes.c_int, [_vp, _u32p, _u8p, _sz, _u64, _u64, _u64, _u64, _u8p, _u8p]),
     "cliff_sample": (ctypes.c_int, [_vp, _vp, _u32p, _sz, _u64, _u64, _u64, _u8p, _u8p]),
@@ -210,6 +216,50 @@ def cliff_encode_layers(n, h, s, ctrl, tgt):
     _check(_lib.cliff_encode_layers(*args, _ptr(ops, _u64p), ops.size, _ptr(offs, _u32p),
                                     ctypes.byref(nops)), "cliff_encode_layers")
     return ops[: nops.value], offs
+
+
+def cliff_encode_gates(n, ops, a, b):
+    """Gate list -> (op words uint64[nops], layer offsets uint32[depth+1])."""
+    o, a, b = _arr(ops, np.uint8), _arr(a, np.uint32), _arr(b, np.uint32)
+    nops, depth = _sz(), _u32()
+    args = (n, _ptr(o, _u8p), _ptr(a, _u32p), _ptr(b, _u32p), len(o))
+    _check(_lib.cliff_encode_gates(*args, None, 0, None, 0, ctypes.byref(nops), ctypes.byref(depth)),
+           "cliff_encode_gates")
+    words = np.zeros(max(1, nops.value), np.uint64)
+    offs = np.zeros(depth.value + 1, np.uint32)
+    _check(_lib.cliff_encode_gates(*args, _ptr(words, _u64p), words.size, _ptr(offs, _u32p), offs.size,
+                                   ctypes.byref(nops), ctypes.byref(depth)), "cliff_encode_gates")
+    return words[: nops.value], offs
+
+
+def _ptr_array(items):
+    """void* array from handles (c_void_p) or integer addresses."""
+    def addr(v):
+        if isinstance(v, ctypes.c_void_p):
+            return v.value or 0
+        return int(v) if v else 0
+    return (ctypes.c_void_p * max(1, len(items)))(*[ctypes.c_void_p(addr(v)) for v in items])
+
+
+def cliff_apply_encoded_many(tabs, dev_ops_ptrs, offs_list, rows_per_group=0):
+    """Tableau i runs the device-resident stream dev_ops_ptrs[i] with host offsets offs_list[i]."""
+    offs_list = [_arr(o, np.uint32) for o in offs_list]
+    depths = np.array([len(o) - 1 for o in offs_list], np.uint32)
+    _check(_lib.cliff_apply_encoded_many(_ptr_array(tabs), _ptr_array(dev_ops_ptrs),
+                                         _ptr_array([o.ctypes.data for o in offs_list]),
+                                         _ptr(depths, _u32p), len(tabs), rows_per_group),
+           "cliff_apply_encoded_many")
+
+
+def cliff_apply_gates_many(tabs, gate_lists, rows_per_group=0):
+    """gate_lists[i] = (ops, a, b) for tableau i."""
+    lists = [(_arr(o, np.uint8), _arr(a, np.uint32), _arr(b, np.uint32)) for o, a, b in gate_lists]
+    counts = np.array([len(o) for o, _, _ in lists], np.uintp)
+    _check(_lib.cliff_apply_gates_many(_ptr_array(tabs), _ptr_array([l[0].ctypes.data for l in lists]),
+                                       _ptr_array([l[1].ctypes.data for l in lists]),
+                                       _ptr_array([l[2].ctypes.data for l in lists]),
+                                       counts.ctypes.data_as(_szp), len(tabs), rows_per_group),
+           "cliff_apply_gates_many")
 
 
 def cliff_apply_encoded(tab, dev_ops_ptr: int, offs):

@@ -376,13 +376,12 @@ extern "C" int cliff_encode_layers(uint32_t n, const uint8_t *h, const uint8_t *
   return CLIFF_OK;
 }
 
-// Upload [ops | layer offsets] to the context's device buffer (stream-ordered).
-// Returns device pointers to both parts.
-static int upload_stream(cliff_ctx *c, const uint64_t *ops, size_t nops, const uint32_t *offs,
-                         size_t noffs, const uint64_t **dev_ops, const uint32_t **dev_offs) {
-  const size_t offs_words = (noffs + 1) / 2;
-  const size_t words = nops + offs_words;
-  if (words == 0) return CLIFF_OK;
+// Staged uploads into the context's device buffer (stream-ordered): reserve
+// `words` 64-bit words (waits for the previous upload's host copy, grows the
+// pinned and device buffers if needed), fill the returned pinned area, then
+// commit the copy.  The device base address is known before the copy, so the
+// staged words may point into themselves.
+static int upload_reserve(cliff_ctx *c, size_t words, uint64_t **host, uint64_t **dev) {
   if (c->upload_pending) {
     HIP_TRY(hipEventSynchronize(c->upload_done));
     c->upload_pending = false;
@@ -404,16 +403,36 @@ static int upload_stream(cliff_ctx *c, const uint64_t *ops, size_t nops, const u
     HIP_TRY(hipHostMalloc(reinterpret_cast<void **>(&c->pinned), cap * 8, hipHostMallocDefault));
     c->pinned_cap = cap;
   }
-  if (nops) memcpy(c->pinned, ops, nops * 8);
-  if (noffs) {
-    c->pinned[nops + offs_words - 1] = 0;
-    memcpy(c->pinned + nops, offs, noffs * 4);
-  }
+  *host = c->pinned;
+  *dev = c->dev_ops;
+  return CLIFF_OK;
+}
+
+static int upload_commit(cliff_ctx *c, size_t words) {
   HIP_TRY(hipMemcpyAsync(c->dev_ops, c->pinned, words * 8, hipMemcpyHostToDevice, c->stream));
   HIP_TRY(hipEventRecord(c->upload_done, c->stream));
   c->upload_pending = true;
-  if (dev_ops) *dev_ops = c->dev_ops;
-  if (dev_offs) *dev_offs = reinterpret_cast<const uint32_t *>(c->dev_ops + nops);
+  return CLIFF_OK;
+}
+
+// Upload [ops | layer offsets]; returns device pointers to both parts.
+static int upload_stream(cliff_ctx *c, const uint64_t *ops, size_t nops, const uint32_t *offs,
+                         size_t noffs, const uint64_t **dev_ops, const uint32_t **dev_offs) {
+  const size_t offs_words = (noffs + 1) / 2;
+  const size_t words = nops + offs_words;
+  if (words == 0) return CLIFF_OK;
+  uint64_t *host = nullptr, *dev = nullptr;
+  int rc = upload_reserve(c, words, &host, &dev);
+  if (rc) return rc;
+  if (nops) memcpy(host, ops, nops * 8);
+  if (noffs) {
+    host[nops + offs_words - 1] = 0;
+    memcpy(host + nops, offs, noffs * 4);
+  }
+  rc = upload_commit(c, words);
+  if (rc) return rc;
+  if (dev_ops) *dev_ops = dev;
+  if (dev_offs) *dev_offs = reinterpret_cast<const uint32_t *>(dev + nops);
   return CLIFF_OK;
 }
 
@@ -566,6 +585,151 @@ extern "C" int cliff_apply_gates(cliff_tab *t, const uint8_t *op, const uint32_t
   rc = upload_stream(t->ctx, ops.data(), ops.size(), offs.data(), offs.size(), &dops, &doffs);
   if (rc) return rc;
   return run_encoded(t, dops, offs.data(), doffs, uint32_t(offs.size() - 1));
+}
+
+// --------------------------------------------------------- many tableaux ---
+
+extern "C" int cliff_encode_gates(uint32_t n, const uint8_t *op, const uint32_t *a, const uint32_t *b,
+                                  size_t count, uint64_t *ops, size_t ops_cap, uint32_t *offs,
+                                  size_t offs_cap, size_t *nops, uint32_t *depth) {
+  if (!nops || !depth) return fail(CLIFF_EINVAL, "cliff_encode_gates: nops/depth is NULL");
+  if (n == 0) return fail(CLIFF_EINVAL, "cliff_encode_gates: n == 0");
+  if (count && (!op || !a || !b)) return fail(CLIFF_EINVAL, "cliff_encode_gates: NULL array");
+  std::vector<uint64_t> v;
+  std::vector<uint32_t> o;
+  int rc = encode_gate_list(n, op, a, b, count, v, o);
+  if (rc) return rc;
+  *nops = v.size();
+  *depth = uint32_t(o.size() - 1);
+  if (ops && v.size() > ops_cap) return fail(CLIFF_ENOMEM, "cliff_encode_gates: need %zu op words", v.size());
+  if (offs && o.size() > offs_cap) return fail(CLIFF_ENOMEM, "cliff_encode_gates: need %zu offsets", o.size());
+  if (ops) memcpy(ops, v.data(), v.size() * 8);
+  if (offs) memcpy(offs, o.data(), o.size() * 4);
+  return CLIFF_OK;
+}
+
+// One tableau's part of a many-tableau launch: ops staged from the host
+// (host_ops) or already on the device (dev_ops), and host layer offsets.
+struct ManySource {
+  const uint64_t *host_ops = nullptr;
+  size_t nops = 0;
+  const uint64_t *dev_ops = nullptr;
+  const uint32_t *offs = nullptr;
+  uint32_t depth = 0;
+};
+
+// Descriptors, staged ops and every tableau's offsets in one upload; one launch.
+static int run_many(cliff_tab *const *tabs, const std::vector<ManySource> &src, int rows_per_group) {
+  const size_t count = src.size();
+  if (count == 0) return CLIFF_OK;
+  if (count > 65535) return fail(CLIFF_EINVAL, "many-tableau gates: %zu tableaux > 65535", count);
+  if (!tabs) return fail(CLIFF_EINVAL, "many-tableau gates: NULL tableau array");
+  cliff_ctx *c = tabs[0] ? tabs[0]->ctx : nullptr;
+  uint32_t max_n = 0;
+  size_t groups64 = 0;
+  for (size_t i = 0; i < count; ++i) {
+    if (!tabs[i]) return fail(CLIFF_EINVAL, "many-tableau gates: tableau %zu is NULL", i);
+    if (tabs[i]->ctx != c) return fail(CLIFF_EINVAL, "many-tableau gates: tableaux on different contexts");
+    if (src[i].depth && !src[i].offs) return fail(CLIFF_EINVAL, "many-tableau gates: NULL offsets (%zu)", i);
+    for (uint32_t l = 0; l < src[i].depth; ++l)
+      if (src[i].offs[l + 1] < src[i].offs[l])
+        return fail(CLIFF_EINVAL, "tableau %zu: layer offsets decrease at layer %u", i, l);
+    if (src[i].depth && src[i].offs[src[i].depth] && !src[i].host_ops && !src[i].dev_ops)
+      return fail(CLIFF_EINVAL, "many-tableau gates: NULL ops (%zu)", i);
+    max_n = std::max(max_n, tabs[i]->d.n);
+    groups64 += tabs[i]->d.W;
+  }
+  {
+    std::vector<const cliff_tab *> sorted(tabs, tabs + count);
+    std::sort(sorted.begin(), sorted.end());
+    if (std::adjacent_find(sorted.begin(), sorted.end()) != sorted.end())
+      return fail(CLIFF_EINVAL, "many-tableau gates: a tableau appears twice");
+  }
+  uint32_t rows;
+  if (rows_per_group == 0)
+    rows = (many_gates_fit(max_n, 64) && groups64 >= 4 * size_t(c->num_cus)) ? 64 : 32;
+  else if (rows_per_group == 32 || rows_per_group == 64)
+    rows = uint32_t(rows_per_group);
+  else
+    return fail(CLIFF_EINVAL, "rows_per_group must be 0, 32 or 64 (got %d)", rows_per_group);
+  if (!many_gates_fit(max_n, rows))
+    return fail(CLIFF_EINVAL, "many-tableau gates: n = %u does not fit LDS at %u rows per group", max_n, rows);
+  const size_t desc_words = count * (sizeof(ManyDesc) / 8);
+  size_t words = desc_words;
+  for (const ManySource &m : src) words += (m.host_ops ? m.nops : 0) + (size_t(m.depth) + 2) / 2;
+  DeviceGuard g(c->device);
+  uint64_t *host = nullptr, *dev = nullptr;
+  int rc = upload_reserve(c, words, &host, &dev);
+  if (rc) return rc;
+  ManyDesc *hd = reinterpret_cast<ManyDesc *>(host);
+  size_t at = desc_words;
+  for (size_t i = 0; i < count; ++i) {
+    const ManySource &m = src[i];
+    ManyDesc d{};
+    d.X = tabs[i]->dev.X;
+    d.Z = tabs[i]->dev.Z;
+    d.P = tabs[i]->dev.P;
+    d.n = tabs[i]->d.n;
+    d.Wp = tabs[i]->d.Wp;
+    d.depth = m.depth;
+    if (m.host_ops) {
+      if (m.nops) memcpy(host + at, m.host_ops, m.nops * 8);
+      d.ops = dev + at;
+      at += m.nops;
+    } else {
+      d.ops = m.dev_ops;
+    }
+    const size_t ow = (size_t(m.depth) + 2) / 2;
+    host[at + ow - 1] = 0;
+    if (m.depth) memcpy(host + at, m.offs, (size_t(m.depth) + 1) * 4);
+    else reinterpret_cast<uint32_t *>(host + at)[0] = 0;
+    d.offs = reinterpret_cast<const uint32_t *>(dev + at);
+    at += ow;
+    hd[i] = d;
+  }
+  rc = upload_commit(c, words);
+  if (rc) return rc;
+  c->prof.begin(PK_GATE, c->stream);
+  hipError_t e = launch_gates_many(reinterpret_cast<const ManyDesc *>(dev), uint32_t(count), max_n, rows,
+                                   c->stream);
+  c->prof.end(PK_GATE, c->stream);
+  HIP_TRY(e);
+  return CLIFF_OK;
+}
+
+extern "C" int cliff_apply_encoded_many(cliff_tab *const *tabs, const uint64_t *const *dev_ops,
+                                        const uint32_t *const *offs, const uint32_t *depths, size_t count,
+                                        int rows_per_group) {
+  if (count == 0) return CLIFF_OK;
+  if (!dev_ops || !offs || !depths) return fail(CLIFF_EINVAL, "cliff_apply_encoded_many: NULL array");
+  std::vector<ManySource> src(count);
+  for (size_t i = 0; i < count; ++i) {
+    src[i].dev_ops = dev_ops[i];
+    src[i].offs = offs[i];
+    src[i].depth = depths[i];
+  }
+  return run_many(tabs, src, rows_per_group);
+}
+
+extern "C" int cliff_apply_gates_many(cliff_tab *const *tabs, const uint8_t *const *op,
+                                      const uint32_t *const *a, const uint32_t *const *b,
+                                      const size_t *counts, size_t count, int rows_per_group) {
+  if (count == 0) return CLIFF_OK;
+  if (!tabs || !op || !a || !b || !counts) return fail(CLIFF_EINVAL, "cliff_apply_gates_many: NULL array");
+  std::vector<std::vector<uint64_t>> ops(count);
+  std::vector<std::vector<uint32_t>> offs(count);
+  std::vector<ManySource> src(count);
+  for (size_t i = 0; i < count; ++i) {
+    if (!tabs[i]) return fail(CLIFF_EINVAL, "cliff_apply_gates_many: tableau %zu is NULL", i);
+    if (counts[i] && (!op[i] || !a[i] || !b[i])) return fail(CLIFF_EINVAL, "cliff_apply_gates_many: NULL list %zu", i);
+    int rc = encode_gate_list(tabs[i]->d.n, op[i], a[i], b[i], counts[i], ops[i], offs[i]);
+    if (rc) return rc;
+    src[i].host_ops = ops[i].data();
+    src[i].nops = ops[i].size();
+    src[i].offs = offs[i].data();
+    src[i].depth = uint32_t(offs[i].size() - 1);
+  }
+  return run_many(tabs, src, rows_per_group);
 }
 
 // ---------------------------------------------------------------- measure ---

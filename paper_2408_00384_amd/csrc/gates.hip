@@ -87,41 +87,46 @@ __global__ void __launch_bounds__(256) k_gate_layer(TabDev t, const uint64_t *__
   if (racc) atomicXor(reinterpret_cast<unsigned long long *>(t.P + w), (unsigned long long)racc);
 }
 
+__device__ __forceinline__ void lds_xor(uint32_t *p, uint32_t v) { atomicXor(p, v); }
+__device__ __forceinline__ void lds_xor(uint64_t *p, uint64_t v) {
+  atomicXor(reinterpret_cast<unsigned long long *>(p), (unsigned long long)v);
+}
+
 // All layers of a gate stream in one launch.  Gates act row by row, so a
-// workgroup that owns 32 rows (one half of a 64-row word) of every column can
-// apply every layer to them without talking to any other workgroup: it loads
-// its half-words of X and Z into LDS (8n bytes), runs the layers with a
-// workgroup barrier between consecutive layers, and writes them back once.
-// Its sign flips stay in registers and land in its own half of P.
-__global__ void __launch_bounds__(256) k_gates_fused(TabDev t, const uint64_t *__restrict__ ops,
-                                                     const uint32_t *__restrict__ offs, uint32_t depth) {
-  extern __shared__ uint32_t lds_u32[];
-  const uint32_t n = t.n;
-  uint32_t *sx = lds_u32, *sz = lds_u32 + n;
-  __shared__ uint32_t s_r;
-  const uint32_t h = blockIdx.x;                  // half-word index: rows 32h .. 32h+31
+// workgroup that owns a group of rows (32 or 64: the bits of T) of every
+// column can apply every layer to them without talking to any other
+// workgroup: it loads its row group of X and Z into LDS (2 n sizeof(T)
+// bytes), runs the layers with a workgroup barrier between consecutive
+// layers, and writes them back once.  Its sign flips stay in registers and
+// land in its own part of P.
+template <typename T>
+__device__ __forceinline__ void fused_body(uint64_t *X, uint64_t *Z, uint64_t *P, uint32_t n, uint32_t Wp,
+                                           const uint64_t *__restrict__ ops,
+                                           const uint32_t *__restrict__ offs, uint32_t depth,
+                                           uint32_t unit, T *sx, T *sz, T *s_r) {
+  constexpr uint32_t kPer = 8 / sizeof(T);       // T words per 64-bit row word
   const uint32_t tid = threadIdx.x;
-  const size_t hs = size_t(t.Wp) * 2;             // column stride in half-words
-  const uint32_t *X32 = reinterpret_cast<const uint32_t *>(t.X);
-  const uint32_t *Z32 = reinterpret_cast<const uint32_t *>(t.Z);
+  const size_t cs = size_t(Wp) * kPer;           // column stride in T words
+  const T *XT = reinterpret_cast<const T *>(X);
+  const T *ZT = reinterpret_cast<const T *>(Z);
   for (uint32_t j = tid; j < n; j += blockDim.x) {
-    sx[j] = X32[j * hs + h];
-    sz[j] = Z32[j * hs + h];
+    sx[j] = XT[j * cs + unit];
+    sz[j] = ZT[j * cs + unit];
   }
-  if (tid == 0) s_r = 0;
+  if (tid == 0) *s_r = 0;
   __syncthreads();
-  uint32_t racc = 0;
+  T racc = 0;
   for (uint32_t l = 0; l < depth; ++l) {
     const uint32_t o1 = offs[l + 1];
     for (uint32_t k = offs[l] + tid; k < o1; k += blockDim.x) {
       const uint64_t op = ops[k];
       if (!op_valid(op, n)) continue;   // malformed op
       const uint32_t a = op_a(op), pair = op_pair(op);
-      uint32_t xa = sx[a], za = sz[a];
+      T xa = sx[a], za = sz[a];
       if (op_ca(op)) sq_apply(op_ca(op), xa, za, racc);
       if (pair != PAIR_NONE) {
         const uint32_t b = op_b(op);
-        uint32_t xb = sx[b], zb = sz[b];
+        T xb = sx[b], zb = sz[b];
         if (op_cb(op)) sq_apply(op_cb(op), xb, zb, racc);
         pair_apply(pair, xa, za, xb, zb, racc);
         sx[b] = xb;
@@ -132,18 +137,38 @@ __global__ void __launch_bounds__(256) k_gates_fused(TabDev t, const uint64_t *_
     }
     __syncthreads();
   }
-  if (racc) atomicXor(&s_r, racc);
-  uint32_t *X32w = reinterpret_cast<uint32_t *>(t.X);
-  uint32_t *Z32w = reinterpret_cast<uint32_t *>(t.Z);
+  if (racc) lds_xor(s_r, racc);
+  T *XW = reinterpret_cast<T *>(X);
+  T *ZW = reinterpret_cast<T *>(Z);
   for (uint32_t j = tid; j < n; j += blockDim.x) {
-    X32w[j * hs + h] = sx[j];
-    Z32w[j * hs + h] = sz[j];
+    XW[j * cs + unit] = sx[j];
+    ZW[j * cs + unit] = sz[j];
   }
   __syncthreads();
-  if (tid == 0 && s_r) {
-    uint32_t *P32 = reinterpret_cast<uint32_t *>(t.P);
-    P32[h] ^= s_r;   // this half of P belongs to this workgroup alone
-  }
+  if (tid == 0 && *s_r) reinterpret_cast<T *>(P)[unit] ^= *s_r;   // this part of P is ours alone
+}
+
+// One tableau, 32-row groups (twice as many workgroups as 64-row ones: a
+// single tableau is latency-bound, not throughput-bound).
+__global__ void __launch_bounds__(256) k_gates_fused(TabDev t, const uint64_t *__restrict__ ops,
+                                                     const uint32_t *__restrict__ offs, uint32_t depth) {
+  extern __shared__ uint64_t lds_u64[];
+  __shared__ uint32_t s_r;
+  uint32_t *sx = reinterpret_cast<uint32_t *>(lds_u64), *sz = sx + t.n;
+  fused_body<uint32_t>(t.X, t.Z, t.P, t.n, t.Wp, ops, offs, depth, blockIdx.x, sx, sz, &s_r);
+}
+
+// Many tableaux in one launch: blockIdx.y picks the tableau, blockIdx.x its
+// row group (groups past the tableau's 2n rows exit at once).
+template <typename T>
+__global__ void __launch_bounds__(256) k_gates_many(const ManyDesc *__restrict__ descs) {
+  extern __shared__ uint64_t lds_u64[];
+  __shared__ T s_r;
+  const ManyDesc d = descs[blockIdx.y];
+  constexpr uint32_t kBits = 8 * sizeof(T);
+  if (blockIdx.x >= (2 * d.n + kBits - 1) / kBits) return;
+  T *sx = reinterpret_cast<T *>(lds_u64), *sz = sx + d.n;
+  fused_body<T>(d.X, d.Z, d.P, d.n, d.Wp, d.ops, d.offs, d.depth, blockIdx.x, sx, sz, &s_r);
 }
 
 // dst <- src with every sign column of dst set to src's column 0 (+ pending).
@@ -216,6 +241,28 @@ hipError_t launch_gates_fused(const TabDev &t, const uint64_t *ops, const uint32
   }
   const uint32_t halves = (2 * t.n + 31) / 32;
   k_gates_fused<<<halves, 256, lds, st>>>(t, ops, dev_offs, depth);
+  return hipGetLastError();
+}
+
+bool many_gates_fit(uint32_t max_n, uint32_t rows) { return 2 * size_t(max_n) * (rows / 8) <= kFusedGateLds; }
+
+hipError_t launch_gates_many(const ManyDesc *dev_descs, uint32_t count, uint32_t max_n, uint32_t rows,
+                             hipStream_t st) {
+  if (count == 0) return hipSuccess;
+  const void *fn = rows == 64 ? reinterpret_cast<const void *>(k_gates_many<uint64_t>)
+                              : reinterpret_cast<const void *>(k_gates_many<uint32_t>);
+  static bool attr_set[2] = {false, false};
+  if (!attr_set[rows == 64]) {
+    hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, int(kFusedGateLds));
+    if (e != hipSuccess) return e;
+    attr_set[rows == 64] = true;
+  }
+  const size_t lds = 2 * size_t(max_n) * (rows / 8);
+  const dim3 grid((2 * max_n + rows - 1) / rows, count);
+  if (rows == 64)
+    k_gates_many<uint64_t><<<grid, 256, lds, st>>>(dev_descs);
+  else
+    k_gates_many<uint32_t><<<grid, 256, lds, st>>>(dev_descs);
   return hipGetLastError();
 }
 

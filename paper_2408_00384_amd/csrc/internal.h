@@ -184,6 +184,17 @@ hipError_t launch_gate_layer(const TabDev &t, const uint64_t *ops, uint32_t nops
 // LDS budget of the fused all-layers gate kernel (8 bytes per qubit).
 constexpr size_t kFusedGateLds = 160 * 1024 - 1024;
 bool fused_gates_fit(uint32_t n);
+// One tableau of a many-tableau gate launch (device memory).
+struct ManyDesc {
+  uint64_t *X, *Z, *P;
+  const uint64_t *ops;      // encoded ops of this tableau
+  const uint32_t *offs;     // its layer boundaries [depth + 1]
+  uint32_t n, Wp, depth, pad;
+};
+static_assert(sizeof(ManyDesc) == 56, "descriptor layout");
+bool many_gates_fit(uint32_t max_n, uint32_t rows);
+hipError_t launch_gates_many(const ManyDesc *dev_descs, uint32_t count, uint32_t max_n, uint32_t rows,
+                             hipStream_t st);
 hipError_t launch_gates_fused(const TabDev &t, const uint64_t *ops, const uint32_t *dev_offs,
                               uint32_t depth, hipStream_t st);
 hipError_t launch_measure_list(const TabDev &t, const uint32_t *qubits, uint32_t k, uint64_t seed,

@@ -2,6 +2,7 @@
 
     python tests/golden/make_golden.py mid      # n = 1,024: a few shots (~1 min)
     python tests/golden/make_golden.py large    # n = 10,000, 1 shot (hours)
+    python tests/golden/make_golden.py clifford # n = 1,000 uniform random Cliffords (~40 s)
 
 Values are the CPU oracle's results on the seeded circuits of ``inputs``;
 nothing here touches the GPU library.  Tableau digests are SHA-256 over the
@@ -21,7 +22,7 @@ ROOT = os.path.dirname(os.path.dirname(os.path.dirname(os.path.abspath(__file__)
 sys.path.insert(0, ROOT)
 
 import oracle  # noqa: E402
-from inputs import plain_large, plain_mid  # noqa: E402
+from inputs import plain_large, plain_mid, random_clifford  # noqa: E402
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 
@@ -78,11 +79,29 @@ def make_large(checkpoint_every=16):
         json.dump(rec, f, indent=1)
 
 
+def make_clifford(n=1000, count=4, seed=5):
+    """Tableaux after the gates of uniform random Clifford circuits i < count
+    (generator seed [seed, n, i]) applied to |0...0>."""
+    rec = {"workload": "uniform random Clifford circuits, n=%d, gates only (generator seed [%d, n, i])"
+           % (n, seed), "n": n, "circuits": {}}
+    for i in range(count):
+        c = random_clifford(n, [seed, n, i], circuit_id=i)
+        t0 = time.time()
+        t = oracle.Tableau(n).apply_gates(c.ops, c.a, c.b)
+        rec["circuits"][str(i)] = {"gates": c.gate_count(), "tableau_sha256": digest(*t.get()),
+                                   "oracle_seconds": round(time.time() - t0, 2)}
+        print("clifford", i, c.gate_count(), "gates", flush=True)
+    with open(os.path.join(HERE, "clifford_n%d.json" % n), "w") as f:
+        json.dump(rec, f, indent=1)
+
+
 if __name__ == "__main__":
     what = sys.argv[1] if len(sys.argv) > 1 else "mid"
     if what == "mid":
         make_mid()
     elif what == "large":
         make_large()
+    elif what == "clifford":
+        make_clifford()
     else:
-        raise SystemExit("usage: make_golden.py mid|large")
+        raise SystemExit("usage: make_golden.py mid|large|clifford")
