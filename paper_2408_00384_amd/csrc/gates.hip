@@ -87,6 +87,9 @@ __global__ void __launch_bounds__(256) k_gate_layer(TabDev t, const uint64_t *__
   if (racc) atomicXor(reinterpret_cast<unsigned long long *>(t.P + w), (unsigned long long)racc);
 }
 
+typedef __attribute__((address_space(1))) const uint64_t GlobalU64;
+typedef __attribute__((address_space(1))) const uint32_t GlobalU32;
+
 __device__ __forceinline__ void lds_xor(uint32_t *p, uint32_t v) { atomicXor(p, v); }
 __device__ __forceinline__ void lds_xor(uint64_t *p, uint64_t v) {
   atomicXor(reinterpret_cast<unsigned long long *>(p), (unsigned long long)v);
@@ -100,47 +103,75 @@ __device__ __forceinline__ void lds_xor(uint64_t *p, uint64_t v) {
 // layers, and writes them back once.  Its sign flips stay in registers and
 // land in its own part of P.
 template <typename T>
+__device__ __forceinline__ void apply_op_lds(uint64_t op, uint32_t n, T *sx, T *sz, T &racc) {
+  if (!op_valid(op, n)) return;   // malformed op
+  const uint32_t a = op_a(op), pair = op_pair(op);
+  T xa = sx[a], za = sz[a];
+  if (op_ca(op)) sq_apply(op_ca(op), xa, za, racc);
+  if (pair != PAIR_NONE) {
+    const uint32_t b = op_b(op);
+    T xb = sx[b], zb = sz[b];
+    if (op_cb(op)) sq_apply(op_cb(op), xb, zb, racc);
+    pair_apply(pair, xa, za, xb, zb, racc);
+    sx[b] = xb;
+    sz[b] = zb;
+  }
+  sx[a] = xa;
+  sz[a] = za;
+}
+
+template <typename T>
 __device__ __forceinline__ void fused_body(uint64_t *X, uint64_t *Z, uint64_t *P, uint32_t n, uint32_t Wp,
                                            const uint64_t *__restrict__ ops,
                                            const uint32_t *__restrict__ offs, uint32_t depth,
                                            uint32_t unit, T *sx, T *sz, T *s_r) {
   constexpr uint32_t kPer = 8 / sizeof(T);       // T words per 64-bit row word
-  const uint32_t tid = threadIdx.x;
+  const uint32_t tid = threadIdx.x, lane = tid & 63, nthr = blockDim.x;
   const size_t cs = size_t(Wp) * kPer;           // column stride in T words
   const T *XT = reinterpret_cast<const T *>(X);
   const T *ZT = reinterpret_cast<const T *>(Z);
-  for (uint32_t j = tid; j < n; j += blockDim.x) {
+  for (uint32_t j = tid; j < n; j += nthr) {
     sx[j] = XT[j * cs + unit];
     sz[j] = ZT[j * cs + unit];
   }
   if (tid == 0) *s_r = 0;
   __syncthreads();
-  T racc = 0;
-  for (uint32_t l = 0; l < depth; ++l) {
-    const uint32_t o1 = offs[l + 1];
-    for (uint32_t k = offs[l] + tid; k < o1; k += blockDim.x) {
-      const uint64_t op = ops[k];
-      if (!op_valid(op, n)) continue;   // malformed op
-      const uint32_t a = op_a(op), pair = op_pair(op);
-      T xa = sx[a], za = sz[a];
-      if (op_ca(op)) sq_apply(op_ca(op), xa, za, racc);
-      if (pair != PAIR_NONE) {
-        const uint32_t b = op_b(op);
-        T xb = sx[b], zb = sz[b];
-        if (op_cb(op)) sq_apply(op_cb(op), xb, zb, racc);
-        pair_apply(pair, xa, za, xb, zb, racc);
-        sx[b] = xb;
-        sz[b] = zb;
-      }
-      sx[a] = xa;
-      sz[a] = za;
+  // The op stream and the offsets are read through global-address-space
+  // pointers: global (not flat) loads count only in vmcnt, so the LDS waits
+  // of a layer do not wait for them.
+  const GlobalU64 *gops = (const GlobalU64 *)ops;
+  const GlobalU32 *goffs = (const GlobalU32 *)offs;
+  // Layer boundaries: lane i of every wave holds offs[base + i] of the
+  // current block of 64 (one load per 64 layers); a layer reads its two
+  // bounds with readlane.  The first op of the next layer is loaded while
+  // the current layer runs, so its latency hides behind the LDS work.
+  uint32_t base = 0, offv = lane <= depth ? goffs[lane] : 0u;
+  auto bound = [&](uint32_t i) -> uint32_t {   // offs[i], i uniform, i <= depth
+    if ((i & ~63u) != base) {
+      base = i & ~63u;
+      offv = base + lane <= depth ? goffs[base + lane] : 0u;
     }
-    __syncthreads();
+    return uint32_t(__builtin_amdgcn_readlane(int(offv), int(i & 63u)));
+  };
+  T racc = 0;
+  uint32_t lo = bound(0), hi = depth ? bound(1) : lo;
+  uint64_t nxt = lo + tid < hi ? gops[lo + tid] : 0ull;
+  for (uint32_t l = 0; l < depth; ++l) {
+    const uint32_t a0 = lo, a1 = hi;
+    const uint64_t cur = nxt;
+    if (l + 1 < depth) {
+      lo = a1;
+      hi = bound(l + 2);
+      nxt = lo + tid < hi ? gops[lo + tid] : 0ull;
+    }
+    if (a0 + tid < a1) apply_op_lds(cur, n, sx, sz, racc);
+    for (uint32_t k = a0 + tid + nthr; k < a1; k += nthr) apply_op_lds(uint64_t(gops[k]), n, sx, sz, racc);
+    lds_barrier();
   }
   if (racc) lds_xor(s_r, racc);
   T *XW = reinterpret_cast<T *>(X);
   T *ZW = reinterpret_cast<T *>(Z);
-  for (uint32_t j = tid; j < n; j += blockDim.x) {
+  for (uint32_t j = tid; j < n; j += nthr) {
     XW[j * cs + unit] = sx[j];
     ZW[j * cs + unit] = sz[j];
   }

@@ -22,6 +22,16 @@
 
 namespace cliff {
 
+// Workgroup barrier ordering LDS only, for kernels whose waves share data
+// through LDS alone (global memory is read or written per thread, or
+// exchanged between workgroups with atomics): global loads and stores may
+// stay in flight across it.
+__device__ __forceinline__ void lds_barrier() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
+  __builtin_amdgcn_s_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
+}
+
 constexpr uint32_t kNone = 0xFFFFFFFFu;
 constexpr uint32_t kStateWords = 64;   // uint32 words of measurement state
 

@@ -68,15 +68,6 @@ __device__ __forceinline__ void st_relaxed64(uint64_t *p, uint64_t v) {
   __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
-// Workgroup barrier ordering LDS only.  In the x/z and sign kernels the
-// waves of a workgroup share data through LDS alone (global memory is read
-// or written per thread, or exchanged between workgroups with atomics), so
-// global loads and stores may stay in flight across it.
-__device__ __forceinline__ void lds_barrier() {
-  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
-  __builtin_amdgcn_s_barrier();
-  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
-}
 
 // Destabilizer half of a column shifted up by n rows (word w).
 __device__ __forceinline__ uint64_t det_word(const uint64_t *col, uint32_t n, uint32_t NW, uint32_t W,
