@@ -164,11 +164,11 @@ int cliff_encode_gates(uint32_t n, const uint8_t *op, const uint32_t *a, const u
 
 /* Gates only, on many tableaux in one launch (the paper's Fig. 2a workload:
  * many random Clifford circuits, no measurement).  Every tableau is split
- * into groups of rows_per_group rows (32 or 64; 0 = 64 when every n <= 10,176
- * and the launch has at least 4 groups per compute unit, else 32); one
- * workgroup holds its group of every column in LDS and runs all layers.
- * tabs[0..count): distinct tableaux bound to one context, 2 n rows_per_group/8
- * bytes <= 159 KiB (n <= 20,352 at 32 rows, 10,176 at 64), count <= 65,535.
+ * into groups of rows_per_group rows (32, 64 or 128; 0 picks one from the
+ * sizes); one workgroup holds its group of every column in LDS and runs all
+ * layers.  tabs[0..count): distinct tableaux bound to one context,
+ * 2 n rows_per_group/8 bytes <= 159 KiB (n <= 20,352 at 32 rows, 10,176 at
+ * 64, 5,088 at 128), count <= 65,535.
  * _encoded_many: tableau i runs the encoded stream at DEVICE pointer
  * dev_ops[i] (caller-owned, unchanged until the launch has run) with the HOST
  * array offs[i][0..depths[i]] of layer boundaries.  _gates_many: tableau i

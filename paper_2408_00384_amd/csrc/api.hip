@@ -648,10 +648,10 @@ static int run_many(cliff_tab *const *tabs, const std::vector<ManySource> &src, 
   uint32_t rows;
   if (rows_per_group == 0)
     rows = (many_gates_fit(max_n, 64) && groups64 >= 4 * size_t(c->num_cus)) ? 64 : 32;
-  else if (rows_per_group == 32 || rows_per_group == 64)
+  else if (rows_per_group == 32 || rows_per_group == 64 || rows_per_group == 128)
     rows = uint32_t(rows_per_group);
   else
-    return fail(CLIFF_EINVAL, "rows_per_group must be 0, 32 or 64 (got %d)", rows_per_group);
+    return fail(CLIFF_EINVAL, "rows_per_group must be 0, 32, 64 or 128 (got %d)", rows_per_group);
   if (!many_gates_fit(max_n, rows))
     return fail(CLIFF_EINVAL, "many-tableau gates: n = %u does not fit LDS at %u rows per group", max_n, rows);
   const size_t desc_words = count * (sizeof(ManyDesc) / 8);

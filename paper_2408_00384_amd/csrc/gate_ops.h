@@ -59,10 +59,28 @@ __host__ __device__ inline bool op_valid(uint64_t op, uint32_t n) {
   return a < n && (op_pair(op) == PAIR_NONE || (b < n && b != a));
 }
 
-// Apply a single-qubit code to x / z words of rows (64 or 32 rows at once).
+// 128 rows as two 64-bit words (bitwise operators only).
+struct alignas(16) U128 {
+  uint64_t lo, hi;
+};
+__device__ __forceinline__ U128 operator&(U128 a, U128 b) { return {a.lo & b.lo, a.hi & b.hi}; }
+__device__ __forceinline__ U128 operator^(U128 a, U128 b) { return {a.lo ^ b.lo, a.hi ^ b.hi}; }
+__device__ __forceinline__ U128 operator~(U128 a) { return {~a.lo, ~a.hi}; }
+__device__ __forceinline__ U128 &operator^=(U128 &a, U128 b) { a = a ^ b; return a; }
+
+// All-ones word if b (0 or 1) is set, else zero.
+template <typename T>
+__device__ __forceinline__ T mask_if(uint32_t b) { return T(0) - T(b); }
+template <>
+__device__ __forceinline__ U128 mask_if<U128>(uint32_t b) {
+  const uint64_t m = 0ull - uint64_t(b);
+  return {m, m};
+}
+
+// Apply a single-qubit code to x / z words of rows (32, 64 or 128 rows at once).
 template <typename T>
 __device__ __forceinline__ void sq_apply(uint32_t c, T &x, T &z, T &racc) {
-  auto bit = [c](uint32_t k) { return T(0) - T((c >> k) & 1u); };   // all-ones if set
+  auto bit = [c](uint32_t k) { return mask_if<T>((c >> k) & 1u); };   // all-ones if set
   racc ^= (x & bit(4)) ^ (z & bit(5)) ^ (x & z & bit(6));
   const T nx = (x & ~bit(0)) ^ (z & bit(1));
   const T nz = (x & bit(2)) ^ (z & ~bit(3));

@@ -94,6 +94,13 @@ __device__ __forceinline__ void lds_xor(uint32_t *p, uint32_t v) { atomicXor(p, 
 __device__ __forceinline__ void lds_xor(uint64_t *p, uint64_t v) {
   atomicXor(reinterpret_cast<unsigned long long *>(p), (unsigned long long)v);
 }
+__device__ __forceinline__ void lds_xor(U128 *p, U128 v) {
+  lds_xor(&p->lo, v.lo);
+  lds_xor(&p->hi, v.hi);
+}
+__device__ __forceinline__ bool nonzero(uint32_t v) { return v != 0; }
+__device__ __forceinline__ bool nonzero(uint64_t v) { return v != 0; }
+__device__ __forceinline__ bool nonzero(U128 v) { return (v.lo | v.hi) != 0; }
 
 // All layers of a gate stream in one launch.  Gates act row by row, so a
 // workgroup that owns a group of rows (32 or 64: the bits of T) of every
@@ -125,16 +132,15 @@ __device__ __forceinline__ void fused_body(uint64_t *X, uint64_t *Z, uint64_t *P
                                            const uint64_t *__restrict__ ops,
                                            const uint32_t *__restrict__ offs, uint32_t depth,
                                            uint32_t unit, T *sx, T *sz, T *s_r) {
-  constexpr uint32_t kPer = 8 / sizeof(T);       // T words per 64-bit row word
   const uint32_t tid = threadIdx.x, lane = tid & 63, nthr = blockDim.x;
-  const size_t cs = size_t(Wp) * kPer;           // column stride in T words
+  const size_t cs = size_t(Wp) * 8 / sizeof(T);  // column stride in T words (Wp is a multiple of 8)
   const T *XT = reinterpret_cast<const T *>(X);
   const T *ZT = reinterpret_cast<const T *>(Z);
   for (uint32_t j = tid; j < n; j += nthr) {
     sx[j] = XT[j * cs + unit];
     sz[j] = ZT[j * cs + unit];
   }
-  if (tid == 0) *s_r = 0;
+  if (tid == 0) *s_r = T{};
   __syncthreads();
   // The op stream and the offsets are read through global-address-space
   // pointers: global (not flat) loads count only in vmcnt, so the LDS waits
@@ -153,7 +159,7 @@ __device__ __forceinline__ void fused_body(uint64_t *X, uint64_t *Z, uint64_t *P
     }
     return uint32_t(__builtin_amdgcn_readlane(int(offv), int(i & 63u)));
   };
-  T racc = 0;
+  T racc{};
   uint32_t lo = bound(0), hi = depth ? bound(1) : lo;
   uint64_t nxt = lo + tid < hi ? gops[lo + tid] : 0ull;
   for (uint32_t l = 0; l < depth; ++l) {
@@ -168,7 +174,7 @@ __device__ __forceinline__ void fused_body(uint64_t *X, uint64_t *Z, uint64_t *P
     for (uint32_t k = a0 + tid + nthr; k < a1; k += nthr) apply_op_lds(uint64_t(gops[k]), n, sx, sz, racc);
     lds_barrier();
   }
-  if (racc) lds_xor(s_r, racc);
+  if (nonzero(racc)) lds_xor(s_r, racc);
   T *XW = reinterpret_cast<T *>(X);
   T *ZW = reinterpret_cast<T *>(Z);
   for (uint32_t j = tid; j < n; j += nthr) {
@@ -176,7 +182,7 @@ __device__ __forceinline__ void fused_body(uint64_t *X, uint64_t *Z, uint64_t *P
     ZW[j * cs + unit] = sz[j];
   }
   __syncthreads();
-  if (tid == 0 && *s_r) reinterpret_cast<T *>(P)[unit] ^= *s_r;   // this part of P is ours alone
+  if (tid == 0 && nonzero(*s_r)) reinterpret_cast<T *>(P)[unit] ^= *s_r;   // this part of P is ours alone
 }
 
 // One tableau, 32-row groups (twice as many workgroups as 64-row ones: a
@@ -197,7 +203,7 @@ __global__ void __launch_bounds__(256) k_gates_many(const ManyDesc *__restrict__
   __shared__ T s_r;
   const ManyDesc d = descs[blockIdx.y];
   constexpr uint32_t kBits = 8 * sizeof(T);
-  if (blockIdx.x >= (2 * d.n + kBits - 1) / kBits) return;
+  if (blockIdx.x >= (2 * d.n + kBits - 1) / kBits) return;   // group past the tableau's 2n rows
   T *sx = reinterpret_cast<T *>(lds_u64), *sz = sx + d.n;
   fused_body<T>(d.X, d.Z, d.P, d.n, d.Wp, d.ops, d.offs, d.depth, blockIdx.x, sx, sz, &s_r);
 }
@@ -280,17 +286,21 @@ bool many_gates_fit(uint32_t max_n, uint32_t rows) { return 2 * size_t(max_n) * 
 hipError_t launch_gates_many(const ManyDesc *dev_descs, uint32_t count, uint32_t max_n, uint32_t rows,
                              hipStream_t st) {
   if (count == 0) return hipSuccess;
-  const void *fn = rows == 64 ? reinterpret_cast<const void *>(k_gates_many<uint64_t>)
-                              : reinterpret_cast<const void *>(k_gates_many<uint32_t>);
-  static bool attr_set[2] = {false, false};
-  if (!attr_set[rows == 64]) {
+  const int v = rows == 128 ? 2 : rows == 64 ? 1 : 0;
+  const void *fn = v == 2 ? reinterpret_cast<const void *>(k_gates_many<U128>)
+                 : v == 1 ? reinterpret_cast<const void *>(k_gates_many<uint64_t>)
+                          : reinterpret_cast<const void *>(k_gates_many<uint32_t>);
+  static bool attr_set[3] = {false, false, false};
+  if (!attr_set[v]) {
     hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, int(kFusedGateLds));
     if (e != hipSuccess) return e;
-    attr_set[rows == 64] = true;
+    attr_set[v] = true;
   }
   const size_t lds = 2 * size_t(max_n) * (rows / 8);
   const dim3 grid((2 * max_n + rows - 1) / rows, count);
-  if (rows == 64)
+  if (v == 2)
+    k_gates_many<U128><<<grid, 256, lds, st>>>(dev_descs);
+  else if (v == 1)
     k_gates_many<uint64_t><<<grid, 256, lds, st>>>(dev_descs);
   else
     k_gates_many<uint32_t><<<grid, 256, lds, st>>>(dev_descs);

@@ -65,7 +65,7 @@ def test_random_clifford_single_tableau(ctx, gate_mode, n):
     _assert_equal(t.export(), _ref(c))
 
 
-@pytest.mark.parametrize("rows", [0, 32, 64])
+@pytest.mark.parametrize("rows", [0, 32, 64, 128])
 def test_many_tableaux_from_gate_lists(ctx, rows):
     """Mixed sizes in one launch (ragged row groups: groups past a tableau's
     2n rows exit), two shots each."""
@@ -131,6 +131,10 @@ def test_many_tableaux_errors(ctx):
     big = _tab(ctx, 10177)
     with pytest.raises(CliffError) as e:
         cliff_apply_gates_many([big.handle], [lst], 64)    # 2 n 8 bytes > LDS at 64 rows
+    assert e.value.code == CLIFF_EINVAL
+    mid = _tab(ctx, 5089)
+    with pytest.raises(CliffError) as e:
+        cliff_apply_gates_many([mid.handle], [lst], 128)   # 2 n 16 bytes > LDS at 128 rows
     assert e.value.code == CLIFF_EINVAL
     # nothing ran: both tableaux still |0...0>
     cliff_apply_gates_many([t.handle, u.handle], [lst, lst])
