@@ -35,8 +35,8 @@ HBM_PEAK_GBS = 8000.0   # MI355X HBM3E peak
 TRAFFIC = {
     "k_meas_xz": {
         "sources": ("paper_2408_00384_amd/csrc/measure_persist.hip", "paper_2408_00384_amd/csrc/internal.h"),
-        "sha256": "7a436f33ef73021164eae502813de191d9381c705a8e9ba51a8edec3e1d970d9",
-        "bytes_per_launch": 1.122e+09,
+        "sha256": "d2d60e28cf004c87d9275df38522355362d23e219595e0d3f67c7ec7196dc549",
+        "bytes_per_launch": 1.12e+09,
         "summary": "profiles/k_meas_xz_plain_n10000_measure_all.md",
     },
 }
