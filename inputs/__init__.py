@@ -8,3 +8,4 @@ from .circuits import (  # noqa: F401
 from .bm_clifford import (  # noqa: F401,E402
     CliffordCircuit, clifford_from_choices, clifford_workload, random_clifford,
 )
+from .programs import Program, random_program  # noqa: F401,E402

@@ -71,6 +71,8 @@ def _load():
     lib.orc_apply_layers.argtypes = [vp, ctypes.c_int, _u8p, _u8p, _u32p, _u32p, ctypes.c_int]
     lib.orc_apply_gates.restype = ctypes.c_long
     lib.orc_apply_gates.argtypes = [vp, ctypes.c_long, _u8p, _u32p, _u32p]
+    lib.orc_reset.argtypes = [vp, ctypes.c_int, ctypes.c_uint64, ctypes.c_uint64, ctypes.c_uint64,
+                              ctypes.c_uint64, ctypes.POINTER(ctypes.c_int)]
     lib.orc_measure_pauli.argtypes = [vp, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_uint64,
                                       ctypes.c_uint64, ctypes.c_uint64, ctypes.c_uint64,
                                       ctypes.POINTER(ctypes.c_int)]
@@ -222,6 +224,19 @@ class Tableau:
                                           ctypes.byref(kind))
         return int(out), bool(kind.value)
 
+    def reset(self, a: int, seed: int = 0, circuit: int = 0, shot: int = 0, m: int = 0):
+        """Reset qubit a to |0> (Z-measure, then X where the outcome was 1).
+        Returns (outcome, was_random) of the measurement."""
+        kind = ctypes.c_int(0)
+        out = self._lib.orc_reset(self._h, int(a), seed, circuit, shot, m, ctypes.byref(kind))
+        return int(out), bool(kind.value)
+
+    def pauli(self, a: int, p: int):
+        """Apply the Pauli p (1 = X, 2 = Y, 3 = Z; 0 = nothing) to qubit a."""
+        if p:
+            (self.x, self.y, self.z)[int(p) - 1](a)
+        return self
+
     def measure_bases(self, qubits, bases, seed=0, circuit=0, shot=0, m0=0):
         """measure_pauli over a list, measurement index m0 + position."""
         out = np.zeros(len(qubits), np.uint8)
@@ -295,3 +310,30 @@ def run_circuit(c, shots=None):
     shots = range(c.shots) if shots is None else shots
     rows = [run_shot(c, int(s))[0] for s in shots]
     return np.stack(rows) if rows else np.zeros((0, len(c.qubits)), np.uint8)
+
+
+def run_program(prog, shot: int):
+    """Run a program of ``inputs.programs`` (mid-circuit measurement, reset,
+    conditioned Paulis) for one shot from |0...0>.  Returns (record uint8[M],
+    random flags uint8[M], final Tableau)."""
+    t = Tableau(prog.n)
+    M = prog.measurements
+    rec = np.zeros(M, np.uint8)
+    kinds = np.zeros(M, np.uint8)
+    col = 0
+    for st in prog.steps:
+        kind = st[0]
+        if kind == "gates":
+            t.apply_gates(st[1], st[2], st[3])
+        elif kind in ("measure", "reset"):
+            fn = t.measure if kind == "measure" else t.reset
+            for q in st[1]:
+                rec[col], kinds[col] = fn(int(q), seed=prog.seed, circuit=prog.circuit_id, shot=shot, m=col)
+                col += 1
+        elif kind == "cond":
+            for q, p, c in zip(st[1], st[2], st[3]):
+                if rec[int(c)]:
+                    t.pauli(int(q), int(p))
+        else:
+            raise ValueError("unknown program step %r" % (kind,))
+    return rec, kinds, t

@@ -339,6 +339,16 @@ int orc_measure(otab *t, int a, uint64_t seed, uint64_t circuit, uint64_t shot,
     return orc_measure_pauli(t, a, 0, 1, seed, circuit, shot, m, kind);
 }
 
+/* Reset of qubit a to |0>: Z-measure it, and where the outcome is 1 apply X
+ * (which maps the post-measurement eigenstate -Z_a to +Z_a).  Returns the
+ * measured outcome. */
+int orc_reset(otab *t, int a, uint64_t seed, uint64_t circuit, uint64_t shot, uint64_t m,
+              int *kind) {
+    int out = orc_measure(t, a, seed, circuit, shot, m, kind);
+    if (out) orc_x(t, a);
+    return out;
+}
+
 /*
  * Whole circuit for one shot: gates on a fresh |0...0>, then measure
  * qubits[0..k) in order with measurement index m = position.  Outcomes and

@@ -463,3 +463,95 @@ def test_hand_worked_deterministic_sign():
     X, Z, R = u.get()
     assert (X[1, 0], Z[1, 0], R[1]) == (0, 1, 1)        # -Z
     assert u.measure(0) == (1, False)
+
+
+# ------------------------------------ mid-circuit measurement, reset, feedback ---
+
+def _program_vs_statevector(prog, shot):
+    """Replay a program on a dense statevector with the oracle's recorded
+    outcomes: each outcome must be possible (and forced when the oracle calls
+    it deterministic), and the oracle's stabilizers must hold after every step."""
+    from inputs import OP_CNOT, OP_CZ, OP_SWAP  # noqa: F401
+    t = oracle.Tableau(prog.n)
+    sv = StateVector(prog.n)
+    rec = []
+    for st in prog.steps:
+        if st[0] == "gates":
+            t.apply_gates(st[1], st[2], st[3])
+            sv.apply_gates(st[1], st[2], st[3])
+        elif st[0] in ("measure", "reset"):
+            for q in st[1]:
+                q = int(q)
+                p1 = sv.prob_one(q)
+                m = len(rec)
+                fn = t.measure if st[0] == "measure" else t.reset
+                bit, rnd = fn(q, seed=prog.seed, circuit=prog.circuit_id, shot=shot, m=m)
+                if rnd:
+                    assert np.isclose(p1, 0.5, atol=1e-9)
+                else:
+                    assert np.isclose(p1, float(bit), atol=1e-9)
+                sv.collapse(q, bit)
+                if st[0] == "reset" and bit:
+                    sv.x(q)
+                if st[0] == "reset":
+                    assert np.isclose(sv.prob_one(q), 0.0, atol=1e-9)
+                rec.append(bit)
+        else:
+            for q, p, c in zip(st[1], st[2], st[3]):
+                if rec[int(c)]:
+                    (sv.x, sv.y, sv.z)[int(p) - 1](int(q))
+                    t.pauli(int(q), int(p))
+        _check_stabilizers(t, sv)
+    assert t.anomalies == 0
+    want, _, u = oracle.run_program(prog, shot)
+    assert np.array_equal(want, np.array(rec, np.uint8))
+    for A, B in zip(u.get(), t.get()):
+        assert np.array_equal(A, B)
+
+
+@pytest.mark.parametrize("seed", range(8))
+def test_programs_with_reset_and_feedback_vs_statevector(seed):
+    from inputs import random_program
+    n = 1 + seed % 5
+    prog = random_program(n, 8, 2, [30, seed], circuit_id=seed)
+    kinds = {st[0] for st in prog.steps}
+    assert "gates" in kinds
+    for shot in range(2):
+        _program_vs_statevector(prog, shot)
+
+
+def test_reset_returns_zero_state_and_keeps_others():
+    """Reset of one half of a Bell pair: the outcome is random, the reset
+    qubit is |0> afterwards and the other qubit keeps the measured value."""
+    for shot in range(16):
+        t = oracle.Tableau(2).h(0).cnot(0, 1)
+        bit, rnd = t.reset(0, seed=4, shot=shot, m=0)
+        assert rnd and bit == oracle.random_bit(4, 0, shot, 0)
+        assert t.measure(0, m=1) == (0, False)
+        assert t.measure(1, m=2) == (bit, False)
+
+
+def test_teleportation_with_conditioned_paulis():
+    """Teleport each of the six single-qubit stabilizer states: Bell pair on
+    qubits 1, 2; Bell measurement of 0, 1; X on 2 if the outcome of qubit 1
+    is 1, Z on 2 if that of qubit 0 is 1.  Qubit 2 then measures
+    deterministically in the prepared state's basis with its eigenvalue."""
+    from inputs.programs import Program
+    from inputs import OP_CNOT, OP_H, OP_S, OP_SDG, OP_X
+    Z_, X_, Y_ = oracle.BASIS_Z, oracle.BASIS_X, oracle.BASIS_Y
+    preps = [([], Z_, 0), ([OP_X], Z_, 1), ([OP_H], X_, 0), ([OP_X, OP_H], X_, 1),
+             ([OP_H, OP_S], Y_, 0), ([OP_H, OP_SDG], Y_, 1)]
+    seen = set()
+    for ops, basis, want in preps:
+        steps = [("gates", np.array(ops + [OP_H, OP_CNOT, OP_CNOT, OP_H], np.uint8),
+                  np.array([0] * len(ops) + [1, 1, 0, 0], np.uint32),
+                  np.array([0] * len(ops) + [0, 2, 1, 0], np.uint32)),
+                 ("measure", np.array([0, 1], np.uint32)),
+                 ("cond", np.array([2, 2], np.uint32), np.array([1, 3], np.uint8), np.array([1, 0], np.uint32))]
+        prog = Program(n=3, steps=steps, shots=8)
+        for shot in range(8):
+            rec, kinds, t = oracle.run_program(prog, shot)
+            assert kinds.tolist() == [1, 1]
+            seen.add(tuple(rec.tolist()))
+            assert t.measure_pauli(2, basis, m=9) == (want, False)
+    assert len(seen) == 4          # all four Bell outcomes occurred
