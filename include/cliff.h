@@ -209,6 +209,35 @@ int cliff_measure_bases(cliff_tab *tab, const uint32_t *qubits, const uint8_t *b
                         uint64_t seed, uint64_t circuit, uint64_t shot0, uint64_t m0,
                         uint8_t *host_out, uint8_t *host_random);
 
+/* Mid-circuit measurement into a DEVICE record (caller-owned, at least
+ * shots * ld bytes): as cliff_measure, but the outcome of measurement i of
+ * shot s is written to dev_record[s * ld + col0 + i] (0/1) and, if
+ * dev_random is not NULL, the random flag to dev_random[col0 + i] (device).
+ * Only enqueues work; nothing is copied to the host.  EINVAL if
+ * col0 + k > ld or on a bad qubit. */
+int cliff_measure_record(cliff_tab *tab, const uint32_t *qubits, size_t k, uint64_t seed,
+                         uint64_t circuit, uint64_t shot0, uint64_t m0, uint8_t *dev_record,
+                         size_t ld, size_t col0, uint8_t *dev_random);
+
+/* Reset qubits[0..k) to |0>: Z-measure each (recorded exactly as
+ * cliff_measure_record, measurement index m0 + i) and apply X in every shot
+ * whose outcome was 1.  X flips only signs, so all shots keep one set of X/Z
+ * bits.  A repeated qubit is measured again after its earlier reset. */
+int cliff_reset_record(cliff_tab *tab, const uint32_t *qubits, size_t k, uint64_t seed,
+                       uint64_t circuit, uint64_t shot0, uint64_t m0, uint8_t *dev_record,
+                       size_t ld, size_t col0, uint8_t *dev_random);
+
+/* Classically conditioned Paulis: for i < k apply the Pauli paulis[i] (1 X,
+ * 2 Y, 3 Z) to qubits[i] in every shot s whose record byte
+ * dev_record[s * ld + cols[i]] (device memory, e.g. from
+ * cliff_measure_record) is 1.  A Pauli conjugates every row to itself up to
+ * sign (rows anticommuting with it flip: X flips rows with z = 1, Z rows
+ * with x = 1, Y rows with x ^ z = 1), so the shots keep one set of X/Z bits
+ * and only their sign columns differ.  Only enqueues work.  EINVAL on a bad
+ * qubit, Pauli or column (cols[i] >= ld). */
+int cliff_apply_cond_paulis(cliff_tab *tab, const uint32_t *qubits, const uint8_t *paulis,
+                            const uint32_t *cols, size_t k, const uint8_t *dev_record, size_t ld);
+
 /* Asynchronous form of cliff_measure for k <= n measurements: only enqueues
  * the work on the context stream.  The outcomes stay in the tableau's device
  * staging until cliff_tab_read_outcomes (same k, same layout as cliff_measure,

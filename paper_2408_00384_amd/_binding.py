@@ -79,6 +79,9 @@ _SIGS = {
     "cliff_apply_gates_many": (ctypes.c_int, [_vpp, _vpp, _vpp, _vpp, _szp, _sz, ctypes.c_int]),
     "cliff_measure": (ctypes.c_int, [_vp, _u32p, _sz, _u64, _u64, _u64, _u64, _u8p, _u8p]),
     "cliff_measure_bases": (ctypes.c_int, [_vp, _u32p, _u8p, _sz, _u64, _u64, _u64, _u64, _u8p, _u8p]),
+    "cliff_measure_record": (ctypes.c_int, [_vp, _u32p, _sz, _u64, _u64, _u64, _u64, _vp, _sz, _sz, _vp]),
+    "cliff_reset_record": (ctypes.c_int, [_vp, _u32p, _sz, _u64, _u64, _u64, _u64, _vp, _sz, _sz, _vp]),
+    "cliff_apply_cond_paulis": (ctypes.c_int, [_vp, _u32p, _u8p, _u32p, _sz, _vp, _sz]),
     "cliff_sample": (ctypes.c_int, [_vp, _vp, _u32p, _sz, _u64, _u64, _u64, _u8p, _u8p]),
     "cliff_measure_async": (ctypes.c_int, [_vp, _u32p, _sz, _u64, _u64, _u64, _u64]),
     "cliff_tab_read_outcomes": (ctypes.c_int, [_vp, _sz, _u8p, _u8p]),
@@ -291,6 +294,30 @@ def cliff_measure_bases(tab, qubits, bases, seed=0, circuit=0, shot0=0, m0=0, wa
     _check(_lib.cliff_measure_bases(tab, _ptr(q, _u32p), _ptr(b, _u8p), len(q), seed, circuit, shot0,
                                     m0, _ptr(out, _u8p), _ptr(rnd, _u8p)), "cliff_measure_bases")
     return out, rnd
+
+
+def cliff_measure_record(tab, qubits, dev_record_ptr, ld, col0, dev_random_ptr=0, seed=0, circuit=0,
+                         shot0=0, m0=0):
+    """Outcomes into a device record: shot s, measurement i at [s * ld + col0 + i]."""
+    q = _arr(qubits, np.uint32)
+    _check(_lib.cliff_measure_record(tab, _ptr(q, _u32p), len(q), seed, circuit, shot0, m0,
+                                     dev_record_ptr, ld, col0, dev_random_ptr or None),
+           "cliff_measure_record")
+
+
+def cliff_reset_record(tab, qubits, dev_record_ptr, ld, col0, dev_random_ptr=0, seed=0, circuit=0,
+                       shot0=0, m0=0):
+    q = _arr(qubits, np.uint32)
+    _check(_lib.cliff_reset_record(tab, _ptr(q, _u32p), len(q), seed, circuit, shot0, m0,
+                                   dev_record_ptr, ld, col0, dev_random_ptr or None), "cliff_reset_record")
+
+
+def cliff_apply_cond_paulis(tab, qubits, paulis, cols, dev_record_ptr, ld):
+    q, p, c = _arr(qubits, np.uint32), _arr(paulis, np.uint8), _arr(cols, np.uint32)
+    if not (len(q) == len(p) == len(c)):
+        raise ValueError("qubits, paulis and cols differ in length")
+    _check(_lib.cliff_apply_cond_paulis(tab, _ptr(q, _u32p), _ptr(p, _u8p), _ptr(c, _u32p), len(q),
+                                        dev_record_ptr, ld), "cliff_apply_cond_paulis")
 
 
 def cliff_measure_async(tab, qubits, seed=0, circuit=0, shot0=0, m0=0):

@@ -780,10 +780,19 @@ static int check_abort(cliff_tab *t) {
   return CLIFF_OK;
 }
 
+// Where a measurement call's outcomes go besides the device staging: a
+// caller-owned device record, rec[s * ld + col0 + i] (shot s, measurement
+// i), and random flags rnd[col0 + i] (nullable).
+struct DevRecord {
+  uint8_t *rec = nullptr;
+  size_t ld = 0, col0 = 0;
+  uint8_t *rnd = nullptr;
+};
+
 // Outcome of measurement i of shot s lands at host_out[s * ld + col0 + i].
 static int measure_impl(cliff_tab *t, const uint32_t *qubits, size_t k, uint64_t seed,
                         uint64_t circuit, uint64_t shot0, uint64_t m0, uint8_t *host_out,
-                        uint8_t *host_random, size_t ld, size_t col0) {
+                        uint8_t *host_random, size_t ld, size_t col0, const DevRecord *dr = nullptr) {
   const uint32_t n = t->d.n, S = t->d.S;
   for (size_t i = 0; i < k; ++i)
     if (qubits[i] >= n) return fail(CLIFF_EINVAL, "measure: qubit %u >= n = %u", qubits[i], n);
@@ -797,6 +806,12 @@ static int measure_impl(cliff_tab *t, const uint32_t *qubits, size_t k, uint64_t
     const size_t cnt = std::min<size_t>(n, k - base);
     int rc = measure_pass(t, qubits + base, cnt, seed, circuit, shot0, m0 + base);
     if (rc) return rc;
+    if (dr && dr->rec) {
+      t->ctx->prof.begin(PK_OTHER, st);
+      hipError_t e = launch_record(t->dev, uint32_t(cnt), dr->rec, dr->ld, dr->col0 + base, dr->rnd, st);
+      t->ctx->prof.end(PK_OTHER, st);
+      HIP_TRY(e);
+    }
     if (host_out || host_random) {
       out_stage.resize(cnt * S);
       kind_stage.resize(cnt);
@@ -869,6 +884,81 @@ extern "C" int cliff_measure_bases(cliff_tab *t, const uint32_t *qubits, const u
     int rc = apply_one_layer(t, pre);
     if (!rc) rc = measure_impl(t, qubits + i, j - i, seed, circuit, shot0, m0 + i, host_out, host_random, k, i);
     if (!rc) rc = apply_one_layer(t, post);
+    if (rc) return rc;
+    i = j;
+  }
+  return CLIFF_OK;
+}
+
+extern "C" int cliff_measure_record(cliff_tab *t, const uint32_t *qubits, size_t k, uint64_t seed,
+                                    uint64_t circuit, uint64_t shot0, uint64_t m0, uint8_t *dev_record,
+                                    size_t ld, size_t col0, uint8_t *dev_random) {
+  if (!t) return fail(CLIFF_EINVAL, "cliff_measure_record: NULL tableau");
+  if (k == 0) return CLIFF_OK;
+  if (!qubits || !dev_record) return fail(CLIFF_EINVAL, "cliff_measure_record: NULL qubits/record");
+  if (col0 + k > ld) return fail(CLIFF_EINVAL, "cliff_measure_record: columns %zu..%zu beyond ld = %zu", col0, col0 + k, ld);
+  DeviceGuard g(t->ctx->device);
+  DevRecord dr{dev_record, ld, col0, dev_random};
+  return measure_impl(t, qubits, k, seed, circuit, shot0, m0, nullptr, nullptr, k, 0, &dr);
+}
+
+// Conditional Paulis staged as op words (qubit | Pauli << 24 | column << 32).
+static int cond_paulis(cliff_tab *t, const std::vector<uint64_t> &ops, const uint8_t *rec, size_t ld) {
+  if (ops.empty()) return CLIFF_OK;
+  const uint64_t *dops = nullptr;
+  int rc = upload_stream(t->ctx, ops.data(), ops.size(), nullptr, 0, &dops, nullptr);
+  if (rc) return rc;
+  hipStream_t st = t->ctx->stream;
+  t->ctx->prof.begin(PK_GATE, st);
+  hipError_t e = launch_cond_pauli(t->dev, dops, uint32_t(ops.size()), rec, ld, st);
+  t->ctx->prof.end(PK_GATE, st);
+  HIP_TRY(e);
+  return CLIFF_OK;
+}
+
+extern "C" int cliff_apply_cond_paulis(cliff_tab *t, const uint32_t *qubits, const uint8_t *paulis,
+                                       const uint32_t *cols, size_t k, const uint8_t *dev_record, size_t ld) {
+  if (!t) return fail(CLIFF_EINVAL, "cliff_apply_cond_paulis: NULL tableau");
+  if (k == 0) return CLIFF_OK;
+  if (!qubits || !paulis || !cols || !dev_record) return fail(CLIFF_EINVAL, "cliff_apply_cond_paulis: NULL array");
+  if (k > 0xFFFFFFFFull) return fail(CLIFF_EINVAL, "cliff_apply_cond_paulis: too many ops");
+  std::vector<uint64_t> ops(k);
+  for (size_t i = 0; i < k; ++i) {
+    if (qubits[i] >= t->d.n) return fail(CLIFF_EINVAL, "conditional Pauli %zu: qubit %u >= n = %u", i, qubits[i], t->d.n);
+    if (paulis[i] < 1 || paulis[i] > 3) return fail(CLIFF_EINVAL, "conditional Pauli %zu: bad Pauli %u", i, paulis[i]);
+    if (cols[i] >= ld) return fail(CLIFF_EINVAL, "conditional Pauli %zu: column %u >= ld = %zu", i, cols[i], ld);
+    ops[i] = uint64_t(qubits[i]) | (uint64_t(paulis[i]) << 24) | (uint64_t(cols[i]) << 32);
+  }
+  DeviceGuard g(t->ctx->device);
+  return cond_paulis(t, ops, dev_record, ld);
+}
+
+extern "C" int cliff_reset_record(cliff_tab *t, const uint32_t *qubits, size_t k, uint64_t seed,
+                                  uint64_t circuit, uint64_t shot0, uint64_t m0, uint8_t *dev_record,
+                                  size_t ld, size_t col0, uint8_t *dev_random) {
+  if (!t) return fail(CLIFF_EINVAL, "cliff_reset_record: NULL tableau");
+  if (k == 0) return CLIFF_OK;
+  if (!qubits || !dev_record) return fail(CLIFF_EINVAL, "cliff_reset_record: NULL qubits/record");
+  if (col0 + k > ld) return fail(CLIFF_EINVAL, "cliff_reset_record: columns %zu..%zu beyond ld = %zu", col0, col0 + k, ld);
+  const uint32_t n = t->d.n;
+  for (size_t i = 0; i < k; ++i)
+    if (qubits[i] >= n) return fail(CLIFF_EINVAL, "reset: qubit %u >= n = %u", qubits[i], n);
+  DeviceGuard g(t->ctx->device);
+  // per run of distinct qubits: measure them all, then X in the shots whose
+  // outcome was 1 (a repeated qubit must see its earlier reset first)
+  std::vector<uint32_t> seen(n, 0);
+  std::vector<uint64_t> xs;
+  uint32_t run = 0;
+  for (size_t i = 0; i < k;) {
+    ++run;
+    size_t j = i;
+    for (; j < k && seen[qubits[j]] != run; ++j) seen[qubits[j]] = run;
+    DevRecord dr{dev_record, ld, col0 + i, dev_random};
+    int rc = measure_impl(t, qubits + i, j - i, seed, circuit, shot0, m0 + i, nullptr, nullptr, k, 0, &dr);
+    if (rc) return rc;
+    xs.clear();
+    for (size_t q = i; q < j; ++q) xs.push_back(uint64_t(qubits[q]) | (1ull << 24) | (uint64_t(col0 + q) << 32));
+    rc = cond_paulis(t, xs, dev_record, ld);
     if (rc) return rc;
     i = j;
   }

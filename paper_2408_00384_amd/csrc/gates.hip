@@ -224,6 +224,45 @@ __global__ void __launch_bounds__(256) k_copy_tab(TabDev dst, TabDev src) {
   for (size_t i = size_t(blockIdx.x) * blockDim.x + threadIdx.x; i < dst.Wp; i += stride) dst.P[i] = 0;
 }
 
+// Outcomes of the last measurement pass (staging: out[i * S + s], kind[i])
+// into a caller's record: rec[s * ld + col0 + i], random flags rnd[col0 + i].
+__global__ void __launch_bounds__(256) k_record(TabDev t, uint32_t cnt, uint8_t *__restrict__ rec, size_t ld,
+                                                size_t col0, uint8_t *__restrict__ rnd) {
+  const size_t total = size_t(cnt) * t.S;
+  const size_t stride = size_t(gridDim.x) * blockDim.x;
+  for (size_t j = size_t(blockIdx.x) * blockDim.x + threadIdx.x; j < total; j += stride) {
+    const size_t s = j / cnt, i = j % cnt;
+    rec[s * ld + col0 + i] = t.out[i * t.S + s];
+  }
+  if (rnd)
+    for (size_t i = size_t(blockIdx.x) * blockDim.x + threadIdx.x; i < cnt; i += stride) rnd[col0 + i] = t.kind[i];
+}
+
+// Classically conditioned Paulis: op i = qubit (bits 0..23) | Pauli (bits
+// 24..25: 1 X, 2 Y, 3 Z) | record column (bits 32..63).  In shot s, when
+// rec[s * ld + column] is 1, every row that anticommutes with the Pauli
+// flips sign: X flips rows with z_a = 1, Z rows with x_a = 1, Y rows with
+// x_a ^ z_a = 1.  Thread <-> (row word, shot); the ops only XOR into signs,
+// so their order does not matter.
+__global__ void __launch_bounds__(256) k_cond_pauli(TabDev t, const uint64_t *__restrict__ ops, uint32_t k,
+                                                    const uint8_t *__restrict__ rec, size_t ld) {
+  const size_t total = size_t(t.W) * t.S;
+  const size_t stride = size_t(gridDim.x) * blockDim.x;
+  for (size_t j = size_t(blockIdx.x) * blockDim.x + threadIdx.x; j < total; j += stride) {
+    const size_t w = j / t.S, s = j % t.S;
+    uint64_t flip = 0;
+    for (uint32_t i = 0; i < k; ++i) {
+      const uint64_t op = ops[i];
+      const uint32_t a = uint32_t(op & kQubitMask), p = uint32_t(op >> 24) & 3u;
+      if (a >= t.n || !(rec[s * ld + (op >> 32)] & 1u)) continue;
+      const uint64_t x = t.X[size_t(a) * t.Wp + w], z = t.Z[size_t(a) * t.Wp + w];
+      // the Pauli's x part (X, Y) flips rows with z = 1, its z part (Y, Z) rows with x = 1
+      flip ^= (p != 3u ? z : 0ull) ^ (p != 1u ? x : 0ull);
+    }
+    if (flip) t.R[w * t.S + s] ^= flip;
+  }
+}
+
 static inline uint32_t grid_for(size_t items, uint32_t block, uint32_t cap = 4096) {
   size_t g = (items + block - 1) / block;
   if (g < 1) g = 1;
@@ -304,6 +343,20 @@ hipError_t launch_gates_many(const ManyDesc *dev_descs, uint32_t count, uint32_t
     k_gates_many<uint64_t><<<grid, 256, lds, st>>>(dev_descs);
   else
     k_gates_many<uint32_t><<<grid, 256, lds, st>>>(dev_descs);
+  return hipGetLastError();
+}
+
+hipError_t launch_record(const TabDev &t, uint32_t cnt, uint8_t *rec, size_t ld, size_t col0, uint8_t *rnd,
+                         hipStream_t st) {
+  if (cnt == 0) return hipSuccess;
+  k_record<<<grid_for(size_t(cnt) * t.S, 256), 256, 0, st>>>(t, cnt, rec, ld, col0, rnd);
+  return hipGetLastError();
+}
+
+hipError_t launch_cond_pauli(const TabDev &t, const uint64_t *ops, uint32_t k, const uint8_t *rec, size_t ld,
+                             hipStream_t st) {
+  if (k == 0) return hipSuccess;
+  k_cond_pauli<<<grid_for(size_t(t.W) * t.S, 256), 256, 0, st>>>(t, ops, k, rec, ld);
   return hipGetLastError();
 }
 

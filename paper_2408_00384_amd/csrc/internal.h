@@ -203,6 +203,10 @@ struct ManyDesc {
 };
 static_assert(sizeof(ManyDesc) == 56, "descriptor layout");
 bool many_gates_fit(uint32_t max_n, uint32_t rows);
+hipError_t launch_record(const TabDev &t, uint32_t cnt, uint8_t *rec, size_t ld, size_t col0, uint8_t *rnd,
+                         hipStream_t st);
+hipError_t launch_cond_pauli(const TabDev &t, const uint64_t *ops, uint32_t k, const uint8_t *rec, size_t ld,
+                             hipStream_t st);
 hipError_t launch_gates_many(const ManyDesc *dev_descs, uint32_t count, uint32_t max_n, uint32_t rows,
                              hipStream_t st);
 hipError_t launch_gates_fused(const TabDev &t, const uint64_t *ops, const uint32_t *dev_offs,
