@@ -334,6 +334,9 @@ def run_program(prog, shot: int):
             for q, p, c in zip(st[1], st[2], st[3]):
                 if rec[int(c)]:
                     t.pauli(int(q), int(p))
+        elif kind == "cgates":
+            if rec[int(st[1])]:
+                t.apply_gates(st[2], st[3], st[4])
         else:
             raise ValueError("unknown program step %r" % (kind,))
     return rec, kinds, t

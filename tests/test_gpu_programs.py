@@ -106,3 +106,35 @@ def test_conditional_pauli_errors(ctx):
         with pytest.raises(CliffError) as e:
             cliff_apply_cond_paulis(t.handle, q, p, c, rec.data_ptr(), 3)
         assert e.value.code == CLIFF_EINVAL
+
+
+@pytest.mark.parametrize("n", [3, 33, 200])
+def test_conditioned_gate_programs_match_oracle(ctx, n):
+    """Gate lists conditioned on recorded outcomes: every shot on a tableau of
+    its own; outcomes, random flags and each shot's tableau against the
+    oracle."""
+    from paper_2408_00384_amd.program import run_program
+    prog = random_program(n, 12, 5, [33, n], circuit_id=n, conditioned_gates=True)
+    assert any(st[0] == "cgates" for st in prog.steps)
+    rec, rnd, tabs = run_program(ctx, prog)
+    for s in range(prog.shots):
+        want, kinds, t = oracle.run_program(prog, s)
+        assert np.array_equal(rec[s], want), "record differs (shot %d)" % s
+        assert np.array_equal(rnd[s], kinds), "random flags differ (shot %d)" % s
+        gx, gz, gr = tabs[s].export()
+        x, z, r = t.get()
+        assert np.array_equal(gx, x) and np.array_equal(gz, z) and np.array_equal(gr[0], r)
+
+
+def test_per_shot_mode_equals_shared_mode(ctx):
+    """The per-shot runner on a program without conditioned gates gives the
+    shared-tableau runner's outcomes and tableaux."""
+    from paper_2408_00384_amd.program import _run_per_shot, run_program
+    prog = random_program(40, 8, 4, [34], circuit_id=2)
+    rec, rnd, tab = run_program(ctx, prog)
+    rec2, rnd2, tabs = _run_per_shot(ctx, prog)
+    assert np.array_equal(rec, rec2) and all(np.array_equal(rnd, r) for r in rnd2)
+    gx, gz, gr = tab.export()
+    for s, t in enumerate(tabs):
+        x, z, r = t.export()
+        assert np.array_equal(gx, x) and np.array_equal(gz, z) and np.array_equal(gr[s], r[0])

@@ -496,6 +496,10 @@ def _program_vs_statevector(prog, shot):
                 if st[0] == "reset":
                     assert np.isclose(sv.prob_one(q), 0.0, atol=1e-9)
                 rec.append(bit)
+        elif st[0] == "cgates":
+            if rec[int(st[1])]:
+                t.apply_gates(st[2], st[3], st[4])
+                sv.apply_gates(st[2], st[3], st[4])
         else:
             for q, p, c in zip(st[1], st[2], st[3]):
                 if rec[int(c)]:
@@ -517,6 +521,16 @@ def test_programs_with_reset_and_feedback_vs_statevector(seed):
     kinds = {st[0] for st in prog.steps}
     assert "gates" in kinds
     for shot in range(2):
+        _program_vs_statevector(prog, shot)
+
+
+@pytest.mark.parametrize("seed", range(6))
+def test_programs_with_conditioned_gates_vs_statevector(seed):
+    from inputs import random_program
+    n = 2 + seed % 4
+    prog = random_program(n, 12, 3, [32, seed], circuit_id=seed, conditioned_gates=True)
+    assert any(st[0] == "cgates" for st in prog.steps)
+    for shot in range(3):
         _program_vs_statevector(prog, shot)
 
 
