@@ -35,8 +35,8 @@ HBM_PEAK_GBS = 8000.0   # MI355X HBM3E peak
 TRAFFIC = {
     "k_meas_xz": {
         "sources": ("paper_2408_00384_amd/csrc/measure_persist.hip", "paper_2408_00384_amd/csrc/internal.h"),
-        "sha256": "d2d60e28cf004c87d9275df38522355362d23e219595e0d3f67c7ec7196dc549",
-        "bytes_per_launch": 1.12e+09,
+        "sha256": "33566ed6d0d9407192c8e16d9c55ef6d1dbdaf790494269c7d01900dafae7234",
+        "bytes_per_launch": 1.121e+09,
         "summary": "profiles/k_meas_xz_plain_n10000_measure_all.md",
     },
 }
