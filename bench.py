@@ -275,6 +275,60 @@ def bench_clifford(P, torch, np, n=1000, count=100, seed=5, reps=3, oracle_circu
     }
 
 
+def bench_xlarge(P, torch, np, k=256, reps=2):
+    """The HBM-bound path beyond the Infinity Cache: n = 25,000 (a 313 MB
+    tableau; the register-resident path holds at most n = 10,240), gates, then
+    qubits 0..k-1 measured, one per-measurement kernel each.  Reports the
+    sweep kernels' algorithmic HBM bandwidth (device counters over HIP-event
+    kernel time); the first 32 outcomes are compared with the oracle's."""
+    from inputs import plain_xlarge
+    c = plain_xlarge()
+    ctx = P.Context(0)
+    tab = P.DeviceTableau(ctx, c.n, 1, init=False)
+    ops, offs = P.cliff_encode_layers(c.n, c.h, c.s, c.ctrl, c.tgt)
+    dev_ops = torch.from_numpy(ops.view(np.int64)).to("cuda:0")
+    torch.cuda.synchronize()
+    q = np.arange(k, dtype=np.uint32)
+    n, W = c.n, (2 * c.n + 63) // 64
+    best = None
+    for rep in range(reps + 1):
+        P.cliff_tab_init_zero(tab.handle)
+        P.cliff_apply_encoded(tab.handle, dev_ops.data_ptr(), offs)
+        ctx.sync()
+        P.cliff_ctx_profile(ctx.handle, True)
+        t0 = time.perf_counter()
+        out, rnd = P.cliff_measure(tab.handle, q, c.seed, c.circuit_id, 0, 0)
+        wall = time.perf_counter() - t0
+        prof = {kk: P.cliff_ctx_profile_read(ctx.handle, kk) for kk in P.PROF_KINDS}
+        P.cliff_ctx_profile(ctx.handle, False)
+        if rep and (best is None or wall < best[0]):
+            best = (wall, prof, P.cliff_tab_counters(tab.handle), out, rnd)
+    wall, prof, counters, out, rnd = best
+    nr = counters["random"]
+    sweep_bytes = counters["alg_bytes"] - (8 * W * 3 + 80 * n) * nr
+    sweep_ms, launches = prof["sweep"]
+    gbs = sweep_bytes / (sweep_ms * 1e-3) / 1e9 if sweep_ms > 0 else 0.0
+    parity = None
+    gold = os.path.join(ROOT, "tests", "golden", "plain_xlarge_prefix.json")
+    if os.path.exists(gold):
+        rec = json.load(open(gold))
+        kk = rec["k"]
+        def bits(h):
+            return np.unpackbits(np.frombuffer(bytes.fromhex(h), np.uint8), bitorder="little")[:kk]
+        parity = bool(np.array_equal(out[0][:kk], bits(rec["outcomes"])) and
+                      np.array_equal(rnd[:kk], bits(rec["random"])))
+    tab.close()
+    return {
+        "workload": "n = 25,000, 20 layers (generator seed 6), qubits 0..%d measured, 1 shot" % (k - 1),
+        "tableau_bytes": 2 * n * W * 8,
+        "measurements": k, "random": int(nr), "ms_measure": wall * 1e3,
+        "us_per_measurement": wall * 1e6 / k,
+        "sweep": {"kernel": "k_step (one launch per measurement)", "launches": launches,
+                  "ms": sweep_ms, "alg_bytes": sweep_bytes, "alg_gbs": gbs, "frac_of_8000": gbs / HBM_PEAK_GBS},
+        "parity_first_32_vs_stored_oracle": parity,
+    }
+
+
 def bench_serving(P, np, count=96, seed=4, budget=64 << 30, lanes=8):
     """Serving workload: n log-uniform in [16, 4096], depth 2n, shots in
     [1, 1024], admission by tableau bytes against a 64 GB budget.  First a
@@ -331,6 +385,8 @@ def main():
     ap.add_argument("--no-serving", action="store_true", help="skip the serving leg")
     ap.add_argument("--no-clifford", action="store_true",
                     help="skip the uniform-random-Clifford (gates only) leg")
+    ap.add_argument("--no-xlarge", action="store_true",
+                    help="skip the n = 25,000 HBM-bound measurement leg")
     ap.add_argument("--no-profile", action="store_true",
                     help="no per-kernel HIP events (for hardware-counter runs); no roofline")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -471,6 +527,9 @@ def main():
     if not args.no_clifford:
         print("# uniform random Cliffords, gates only ...", file=sys.stderr, flush=True)
         result["random_clifford"] = bench_clifford(P, torch, np)
+    if not args.no_xlarge:
+        print("# n = 25,000, per-measurement kernels ...", file=sys.stderr, flush=True)
+        result["xlarge_hbm"] = bench_xlarge(P, torch, np)
     if not args.no_cpu_baseline:
         print("# cpu baseline (oracle) ...", file=sys.stderr, flush=True)
         result["cpu_baseline"] = cpu_baseline(c, args.cpu_budget)

@@ -98,6 +98,13 @@ def plain_large() -> Circuit:
     return layered_circuit(10_000, 20, 1, gen_seed=2)
 
 
+def plain_xlarge() -> Circuit:
+    """n = 25,000, 20 layers, 1 shot (generator seed 6): a tableau of 313 MB,
+    larger than the 256 MB Infinity Cache, for the HBM-bound measurement path;
+    measured on a prefix of its qubits."""
+    return layered_circuit(25_000, 20, 1, gen_seed=6)
+
+
 def batch_sizes(count: int = 4096, seed: int = 3, n_lo: int = 8, n_hi: int = 256):
     """Sizes of the batched workload: n ~ U{n_lo..n_hi}, depth ~ U{n..4n}."""
     rng = np.random.Generator(np.random.PCG64(seed))

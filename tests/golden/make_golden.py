@@ -3,6 +3,7 @@
     python tests/golden/make_golden.py mid      # n = 1,024: a few shots (~1 min)
     python tests/golden/make_golden.py large    # n = 10,000, 1 shot (hours)
     python tests/golden/make_golden.py clifford # n = 1,000 uniform random Cliffords (~40 s)
+    python tests/golden/make_golden.py xlarge   # n = 25,000: first 32 measurements (~3 min, 2.5 GB)
 
 Values are the CPU oracle's results on the seeded circuits of ``inputs``;
 nothing here touches the GPU library.  Tableau digests are SHA-256 over the
@@ -22,7 +23,7 @@ ROOT = os.path.dirname(os.path.dirname(os.path.dirname(os.path.abspath(__file__)
 sys.path.insert(0, ROOT)
 
 import oracle  # noqa: E402
-from inputs import plain_large, plain_mid, random_clifford  # noqa: E402
+from inputs import plain_large, plain_mid, plain_xlarge, random_clifford  # noqa: E402
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 
@@ -95,6 +96,21 @@ def make_clifford(n=1000, count=4, seed=5):
         json.dump(rec, f, indent=1)
 
 
+def make_xlarge(k=32):
+    """Outcomes and random flags of the first k measurements (qubits 0..k-1,
+    m = position, shot 0) after the gates of the n = 25,000 circuit."""
+    c = plain_xlarge()
+    t0 = time.time()
+    t = oracle.Tableau(c.n).apply_circuit_gates(c)
+    print("gates done in %.1fs" % (time.time() - t0), flush=True)
+    out, kind = t.measure_list(np.arange(k), seed=c.seed, circuit=c.circuit_id, shot=0)
+    rec = {"workload": "n=25000, 20 layers, 1 shot (generator seed 6), qubits 0..%d measured" % (k - 1),
+           "seed": c.seed, "k": k, "outcomes": bits_hex(out), "random": bits_hex(kind),
+           "anomalies": t.anomalies, "oracle_seconds": round(time.time() - t0, 1)}
+    with open(os.path.join(HERE, "plain_xlarge_prefix.json"), "w") as f:
+        json.dump(rec, f, indent=1)
+
+
 if __name__ == "__main__":
     what = sys.argv[1] if len(sys.argv) > 1 else "mid"
     if what == "mid":
@@ -103,5 +119,7 @@ if __name__ == "__main__":
         make_large()
     elif what == "clifford":
         make_clifford()
+    elif what == "xlarge":
+        make_xlarge()
     else:
-        raise SystemExit("usage: make_golden.py mid|large|clifford")
+        raise SystemExit("usage: make_golden.py mid|large|clifford|xlarge")

@@ -11,7 +11,7 @@ import numpy as np
 import pytest
 
 import oracle
-from inputs import (layered_circuit, plain_large, plain_mid, plain_small, random_gate_list)
+from inputs import (layered_circuit, plain_large, plain_mid, plain_small, plain_xlarge, random_gate_list)
 
 pytestmark = pytest.mark.gpu
 
@@ -471,3 +471,19 @@ def test_persistent_ghz_mostly_deterministic(ctx):
     for s_ in range(shots):
         o, k = ref.clone().measure_list(np.arange(40, dtype=np.uint32), seed=17, circuit=2, shot=s_)
         assert np.array_equal(out[s_, :40], o) and np.array_equal(rnd[:40], k)
+
+
+def test_xlarge_per_measurement_path_vs_stored_oracle(ctx):
+    """n = 25,000: above the register-resident limit, so AUTO runs one kernel
+    per measurement, on a 313 MB tableau that exceeds the Infinity Cache.
+    Gates, then qubits 0..31 measured, against the oracle's stored outcomes
+    and random flags."""
+    rec = json.load(open(os.path.join(GOLDEN, "plain_xlarge_prefix.json")))
+    c = plain_xlarge()
+    k = rec["k"]
+    t = _tab(ctx, c.n, 1).apply_circuit_gates(c)
+    out, rnd = t.measure(np.arange(k, dtype=np.uint32), seed=c.seed, circuit=c.circuit_id)
+    assert np.array_equal(out[0], _golden_bits(rec["outcomes"], k))
+    assert np.array_equal(rnd, _golden_bits(rec["random"], k))
+    assert t.anomalies() == 0 and rec["anomalies"] == 0
+    t.close()
