@@ -102,6 +102,22 @@ int cliff_ctx_set_gate_mode(cliff_ctx *ctx, int mode);
 #define CLIFF_MEASURE_PERSISTENT 2
 int cliff_ctx_set_measure_mode(cliff_ctx *ctx, int mode);
 
+/* Failure handling of the register-resident path.  Its workgroups wait for
+ * each other's published columns with bounded waits; a wait that runs out
+ * raises a device-side abort flag, every workgroup leaves, later chunks of the
+ * pass skip their work, and the tableau's contents are undefined (initialize
+ * or import it again).  The flag stays raised until a synchronizing call
+ * reports CLIFF_EINTERNAL: cliff_measure, cliff_tab_read_outcomes,
+ * cliff_sample, cliff_tab_anomalies or cliff_tab_counters; that report
+ * lowers it.
+ * cliff_ctx_inject_abort (a test aid for this path): counting the
+ * measurements the context performs from now on from 0 (in any tableau, by
+ * any measuring call), every workgroup gives up at measurement `at` exactly as
+ * if a wait had run out, provided that measurement runs on the
+ * register-resident path; then the setting is spent.  UINT64_MAX (the
+ * default) injects nothing. */
+int cliff_ctx_inject_abort(cliff_ctx *ctx, uint64_t at);
+
 /* Bytes of device memory a tableau of n qubits with `shots` sign columns needs,
  * scratch included (X, Z, signs, measurement scratch, outcome staging). */
 size_t cliff_tab_bytes(uint32_t n, uint32_t shots);

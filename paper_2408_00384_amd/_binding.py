@@ -63,6 +63,7 @@ _SIGS = {
     "cliff_ctx_num_cus": (ctypes.c_int, [_vp]),
     "cliff_ctx_set_gate_mode": (ctypes.c_int, [_vp, ctypes.c_int]),
     "cliff_ctx_set_measure_mode": (ctypes.c_int, [_vp, ctypes.c_int]),
+    "cliff_ctx_inject_abort": (ctypes.c_int, [_vp, _u64]),
     "cliff_tab_bytes": (_sz, [_u32, _u32]),
     "cliff_tab_bind": (ctypes.c_int, [_vp, _u32, _u32, _vp, _sz, ctypes.POINTER(_vp)]),
     "cliff_tab_unbind": (ctypes.c_int, [_vp]),
@@ -159,6 +160,12 @@ MEASURE_AUTO, MEASURE_STEP, MEASURE_PERSISTENT = 0, 1, 2
 
 def cliff_ctx_set_measure_mode(ctx, mode: int):
     _check(_lib.cliff_ctx_set_measure_mode(ctx, mode), "cliff_ctx_set_measure_mode")
+
+
+def cliff_ctx_inject_abort(ctx, at: int):
+    """The next register-resident pass on ``ctx`` gives up at its measurement
+    ``at`` as if a wait had run out (a test aid; 2**64 - 1 cancels)."""
+    _check(_lib.cliff_ctx_inject_abort(ctx, at), "cliff_ctx_inject_abort")
 
 
 def cliff_ctx_set_gate_mode(ctx, mode: int):

@@ -127,6 +127,7 @@ struct cliff_ctx {
   hipEvent_t persist_ev[4] = {nullptr, nullptr, nullptr, nullptr};
   int gate_mode = CLIFF_GATES_AUTO;
   int measure_mode = CLIFF_MEASURE_AUTO;
+  uint64_t inject_abort_at = UINT64_MAX;   // test aid: see cliff_ctx_inject_abort
 };
 
 struct cliff_tab {
@@ -208,6 +209,12 @@ int cliff_sync(cliff_ctx *c) {
 }
 
 int cliff_ctx_num_cus(const cliff_ctx *c) { return c ? c->num_cus : 0; }
+
+int cliff_ctx_inject_abort(cliff_ctx *c, uint64_t at) {
+  if (!c) return fail(CLIFF_EINVAL, "cliff_ctx_inject_abort: NULL context");
+  c->inject_abort_at = at;
+  return CLIFF_OK;
+}
 
 int cliff_ctx_set_measure_mode(cliff_ctx *c, int mode) {
   if (!c) return fail(CLIFF_EINVAL, "cliff_ctx_set_measure_mode: NULL context");
@@ -737,8 +744,10 @@ extern "C" int cliff_apply_gates_many(cliff_tab *const *tabs, const uint8_t *con
 // One pass of up to n measurements: the register-resident path when the
 // tableau shape allows it (and the device takes the cooperative launch),
 // else one step kernel per measurement.
+// `abort_at` (test aid): the pass's measurement at which its workgroups give
+// up as on a timed-out wait, or UINT64_MAX.
 static int measure_pass(cliff_tab *t, const uint32_t *qubits, size_t cnt, uint64_t seed,
-                        uint64_t circuit, uint64_t shot0, uint64_t m0) {
+                        uint64_t circuit, uint64_t shot0, uint64_t m0, uint64_t abort_at) {
   cliff_ctx *c = t->ctx;
   hipStream_t st = c->stream;
   uint32_t G, L, CW;
@@ -756,7 +765,7 @@ static int measure_pass(cliff_tab *t, const uint32_t *qubits, size_t cnt, uint64
     PersistStreams ps{st, c->aux, {c->persist_ev[0], c->persist_ev[1], c->persist_ev[2], c->persist_ev[3]}};
     uint32_t done = 0;
     hipError_t e = launch_measure_persist(t->dev, dq, uint32_t(cnt), seed, circuit, shot0, m0,
-                                          c->num_cus, ps, &c->prof, &done);
+                                          c->num_cus, ps, &c->prof, &done, abort_at);
     if (done) t->persist_used = true;
     if (e == hipSuccess) return CLIFF_OK;
     (void)hipGetLastError();
@@ -769,14 +778,21 @@ static int measure_pass(cliff_tab *t, const uint32_t *qubits, size_t cnt, uint64
   return CLIFF_OK;
 }
 
-// After a synchronizing readout: a register-resident pass that timed out
-// leaves the abort flag set.
+// A register-resident pass that gave up (a wait timed out) leaves the abort
+// flag raised; it stays raised -- later chunks skip their work -- until a
+// synchronizing call reports it here, which lowers it again.
 static int check_abort(cliff_tab *t) {
   if (!t->persist_used) return CLIFF_OK;
   uint32_t v = 0;
   HIP_TRY(hipMemcpyAsync(&v, t->dev.abort_flag, 4, hipMemcpyDeviceToHost, t->ctx->stream));
   HIP_TRY(hipStreamSynchronize(t->ctx->stream));
-  if (v) return fail(CLIFF_EINTERNAL, "register-resident measurement timed out waiting for a peer");
+  if (v) {
+    const uint32_t zero = 0;
+    HIP_TRY(hipMemcpyAsync(t->dev.abort_flag, &zero, 4, hipMemcpyHostToDevice, t->ctx->stream));
+    HIP_TRY(hipStreamSynchronize(t->ctx->stream));
+    return fail(CLIFF_EINTERNAL, "register-resident measurement gave up waiting for a peer workgroup; "
+                                 "the tableau's contents are undefined");
+  }
   return CLIFF_OK;
 }
 
@@ -802,9 +818,13 @@ static int measure_impl(cliff_tab *t, const uint32_t *qubits, size_t k, uint64_t
   t->ctx->prof.end(PK_OTHER, st);
   HIP_TRY(fe);
   std::vector<uint8_t> out_stage, kind_stage;
+  // a pending injection counts down over the context's measurements
+  const uint64_t inject = t->ctx->inject_abort_at;
+  if (inject != UINT64_MAX) t->ctx->inject_abort_at = inject >= k ? inject - k : UINT64_MAX;
   for (size_t base = 0; base < k; base += n) {
     const size_t cnt = std::min<size_t>(n, k - base);
-    int rc = measure_pass(t, qubits + base, cnt, seed, circuit, shot0, m0 + base);
+    const uint64_t at = (inject != UINT64_MAX && inject >= base && inject - base < cnt) ? inject - base : UINT64_MAX;
+    int rc = measure_pass(t, qubits + base, cnt, seed, circuit, shot0, m0 + base, at);
     if (rc) return rc;
     if (dr && dr->rec) {
       t->ctx->prof.begin(PK_OTHER, st);
@@ -1058,6 +1078,8 @@ extern "C" int cliff_tab_import(cliff_tab *t, const uint8_t *x, const uint8_t *z
   HIP_TRY(hipMemcpyAsync(t->dev.Z, Z.data(), Z.size() * 8, hipMemcpyHostToDevice, st));
   HIP_TRY(hipMemcpyAsync(t->dev.R, R.data(), R.size() * 8, hipMemcpyHostToDevice, st));
   HIP_TRY(hipMemcpyAsync(t->dev.P, P.data(), P.size() * 8, hipMemcpyHostToDevice, st));
+  const uint32_t zero = 0;
+  HIP_TRY(hipMemcpyAsync(t->dev.abort_flag, &zero, 4, hipMemcpyHostToDevice, st));
   HIP_TRY(hipStreamSynchronize(st));
   return CLIFF_OK;
 }
@@ -1065,6 +1087,8 @@ extern "C" int cliff_tab_import(cliff_tab *t, const uint8_t *x, const uint8_t *z
 extern "C" int cliff_tab_anomalies(cliff_tab *t, uint64_t *count) {
   if (!t || !count) return fail(CLIFF_EINVAL, "cliff_tab_anomalies: NULL argument");
   DeviceGuard g(t->ctx->device);
+  int arc = check_abort(t);
+  if (arc) return arc;
   uint32_t v = 0;
   HIP_TRY(hipMemcpyAsync(&v, t->dev.state + ST_ANOMALY, 4, hipMemcpyDeviceToHost, t->ctx->stream));
   HIP_TRY(hipStreamSynchronize(t->ctx->stream));
@@ -1096,6 +1120,8 @@ extern "C" int cliff_ctx_profile_read(cliff_ctx *c, int kind, double *ms, uint64
 extern "C" int cliff_tab_counters(cliff_tab *t, uint64_t *out4) {
   if (!t || !out4) return fail(CLIFF_EINVAL, "cliff_tab_counters: NULL argument");
   DeviceGuard g(t->ctx->device);
+  int arc = check_abort(t);
+  if (arc) return arc;
   uint32_t st[kStateWords];
   HIP_TRY(hipMemcpyAsync(st, t->dev.state, sizeof st, hipMemcpyDeviceToHost, t->ctx->stream));
   HIP_TRY(hipStreamSynchronize(t->ctx->stream));

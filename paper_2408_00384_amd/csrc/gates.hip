@@ -30,6 +30,7 @@ __global__ void __launch_bounds__(256) k_init_zero(TabDev t) {
   const size_t nr = size_t(t.Wp) * t.S;
   for (size_t i = size_t(blockIdx.x) * blockDim.x + threadIdx.x; i < nr; i += stride) t.R[i] = 0;
   for (size_t i = size_t(blockIdx.x) * blockDim.x + threadIdx.x; i < t.Wp; i += stride) t.P[i] = 0;
+  if (blockIdx.x == 0 && threadIdx.x == 0) *t.abort_flag = 0;
 }
 
 // R[w][s] ^= P[w] for every shot (pending gate sign flips become real).
@@ -222,6 +223,7 @@ __global__ void __launch_bounds__(256) k_copy_tab(TabDev dst, TabDev src) {
     dst.R[i] = src.R[w * src.S] ^ src.P[w];
   }
   for (size_t i = size_t(blockIdx.x) * blockDim.x + threadIdx.x; i < dst.Wp; i += stride) dst.P[i] = 0;
+  if (blockIdx.x == 0 && threadIdx.x == 0) *dst.abort_flag = 0;
 }
 
 // Outcomes of the last measurement pass (staging: out[i * S + s], kind[i])

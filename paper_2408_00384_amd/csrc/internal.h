@@ -181,7 +181,7 @@ inline Offsets make_offsets(const Dims &d) {
   o.pub = take(kc * 2 * d.Wp * 8);   // [m][word][2] tagged 32-bit halves
   o.C1all = take(kc * d.Wp * 8);
   o.ring = take(kc * kPersistMaxGroups * d.Wp * 16);   // partials [m][workgroup][word][2]
-  o.abort_flag = take(pl ? 4 : 0);
+  o.abort_flag = take(4);   // every layout: the init and copy kernels clear it
   o.total = cur;
   return o;
 }
@@ -226,7 +226,8 @@ struct PersistStreams {
 // *done = measurements whose launches were all enqueued (chunks before a failure).
 hipError_t launch_measure_persist(const TabDev &t, const uint32_t *dev_qubits, uint32_t k,
                                   uint64_t seed, uint64_t circuit, uint64_t shot0, uint64_t m0,
-                                  int num_cus, const PersistStreams &ps, Profiler *prof, uint32_t *done);
+                                  int num_cus, const PersistStreams &ps, Profiler *prof, uint32_t *done,
+                                  uint64_t abort_at);
 hipError_t launch_batch(const void *descs, const uint64_t *ops, const uint32_t *offs, uint8_t *out,
                         const uint32_t *order, uint32_t count, uint64_t seed, uint32_t *work,
                         uint32_t team, uint32_t maxn, int num_cus, hipStream_t st);

@@ -54,6 +54,8 @@ constexpr uint32_t kWordsPerThread = (kPersistMaxWp + kThreads - 1) / kThreads; 
 struct PersistArgs {
   const uint32_t *qubits;   // device, this chunk's k entries
   uint32_t k, G;
+  uint32_t abort_at;        // measurement of this chunk at which every workgroup stops as if
+                            // a wait had timed out (kNone: never; a test aid for the error path)
 };
 
 __device__ __forceinline__ uint64_t pbit(uint32_t b) { return 1ull << (b & 63); }
@@ -151,6 +153,8 @@ __global__ void __launch_bounds__(kThreads) k_meas_xz(TabDev t, PersistArgs a) {
   // thread t carries row words t + kThreads j (j < kWordsPerThread) of the measured columns
   uint64_t *zw = sZ + size_t(wave) * CW * L * 64 + lane;   // z of slot k, word i at zw[(k * L + i) * 64]
 
+  // an earlier chunk of this pass gave up: the tableau is not to be touched
+  if (ld_relaxed(t.abort_flag)) return;
   for (uint32_t i = tid; i < a.k; i += blockDim.x) s_q[i] = a.qubits[i];
   if (tid == 0) {
     s_abort = 0;
@@ -445,6 +449,10 @@ __global__ void __launch_bounds__(kThreads) k_meas_xz(TabDev t, PersistArgs a) {
       if (s_y) atomicAdd(t.detY + m, s_y);
       ++n_det;
     }
+    if (m == a.abort_at && tid == 0) {   // injected: every workgroup stops at the same iteration
+      atomicOr(t.abort_flag, 1u);
+      s_abort = 1;
+    }
     lds_barrier();
     if (s_abort) return;
     if (next && g == 0 && tid == 0) t.pivall[m + 1] = s_p[b ^ 1u];
@@ -616,9 +624,10 @@ __global__ void __launch_bounds__(kSignThreads) k_meas_signs(TabDev t, uint32_t 
 // ---------------------------------------------------------------- setup ---
 // Publish the first measured column (slot 0, tag 1) and the second one as it
 // stands before measurement 0 (slot 1, tag 2), clear the tags of the chunk's
-// other slots, the deterministic accumulators and the abort flag (kernel
-// stores only, no memset: capture-safe).  Blocks 0 and 1 publish; every
-// block clears a share of the slots.
+// other slots and the deterministic accumulators (kernel stores only, no
+// memset: capture-safe).  Blocks 0 and 1 publish; every block clears a share
+// of the slots.  The abort flag is left alone: it stays raised until the
+// host has reported it, so later chunks of an aborted pass do nothing.
 __global__ void __launch_bounds__(1024) k_meas_begin(TabDev t, const uint32_t *qubits, uint32_t k) {
   __shared__ uint32_t s_p;
   const uint32_t tid = threadIdx.x;
@@ -653,7 +662,6 @@ __global__ void __launch_bounds__(1024) k_meas_begin(TabDev t, const uint32_t *q
     t.detpar[i] = 0;
     t.detY[i] = 0;
   }
-  if (tid == 0) *t.abort_flag = 0;
   __syncthreads();
   if (tid == 0) t.pivall[0] = s_p;
 }
@@ -678,7 +686,8 @@ bool persist_shape(uint32_t n, uint32_t num_cus, uint32_t *G, uint32_t *L, uint3
 
 hipError_t launch_measure_persist(const TabDev &t, const uint32_t *dev_qubits, uint32_t k,
                                   uint64_t seed, uint64_t circuit, uint64_t shot0, uint64_t m0,
-                                  int num_cus, const PersistStreams &ps, Profiler *prof, uint32_t *done) {
+                                  int num_cus, const PersistStreams &ps, Profiler *prof, uint32_t *done,
+                                  uint64_t abort_at) {
   *done = 0;
   uint32_t G, L, CW;
   if (!persist_shape(t.n, uint32_t(num_cus), &G, &L, &CW)) return hipErrorInvalidValue;
@@ -715,7 +724,8 @@ hipError_t launch_measure_persist(const TabDev &t, const uint32_t *dev_qubits, u
     if (prof) prof->end(PK_SELECT, st);
     e = hipGetLastError();
     if (e != hipSuccess) return e;
-    PersistArgs a{dev_qubits + base, cnt, G};
+    const uint32_t ab = (abort_at >= base && abort_at < uint64_t(base) + cnt) ? uint32_t(abort_at - base) : kNone;
+    PersistArgs a{dev_qubits + base, cnt, G, ab};
     TabDev targ = tv;
     void *args[] = {&targ, &a};
     if (prof) prof->begin(PK_SWEEP, st);

@@ -57,6 +57,7 @@ def run_program(ctx: Context, prog, tab: "DeviceTableau | None" = None):
         else:
             raise ValueError("unknown program step %r" % (kind,))
     ctx.sync()
+    tab.anomalies()     # raises if a register-resident measurement gave up
     return rec[:, :M].cpu().numpy(), rnd[:M].cpu().numpy(), tab
 
 
@@ -101,6 +102,8 @@ def _run_per_shot(ctx: Context, prog):
         else:
             raise ValueError("unknown program step %r" % (kind,))
     ctx.sync()
+    for t in tabs:
+        t.anomalies()   # raises if a register-resident measurement gave up
     return rec[:, :M].cpu().numpy(), rnd[:, :M].cpu().numpy(), tabs
 
 
