@@ -35,7 +35,7 @@ HBM_PEAK_GBS = 8000.0   # MI355X HBM3E peak
 TRAFFIC = {
     "k_meas_xz": {
         "sources": ("paper_2408_00384_amd/csrc/measure_persist.hip", "paper_2408_00384_amd/csrc/internal.h"),
-        "sha256": "33566ed6d0d9407192c8e16d9c55ef6d1dbdaf790494269c7d01900dafae7234",
+        "sha256": "42aed41d666719a5fecadcf5c2278747672153053e5a8d02acbc1530a5e900bd",
         "bytes_per_launch": 1.121e+09,
         "summary": "profiles/k_meas_xz_plain_n10000_measure_all.md",
     },
