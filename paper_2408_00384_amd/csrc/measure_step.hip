@@ -149,9 +149,169 @@ __device__ void finish_prev(const TabDev &t, const StepArgs &s, uint32_t G, uint
   }
 }
 
+// Random-branch sweep when a wave works on one column at a time (W > 32):
+// lane l holds row words K l .. K l + K - 1 of a 64 K-word tile (K = 2: one
+// 16-byte access per plane), so the column and the pivot's Pauli on it are
+// wave-uniform and every branch on them is scalar.  Per Pauli the g terms of
+// the update rows reduce to: anti = rows anticommuting with the pivot on this
+// column (pivot X: z; Z: x; Y: x ^ z), where g = +1 if (X: x; Z: ~z; Y: z)
+// and -1 otherwise; adding +-1 to the 2-bit counter flips c1 where c0 equals
+// that +1 condition's complement... written out:
+//   X: c1 ^= anti & ~(c0 ^ x)   Z: c1 ^= anti & (c0 ^ z)   Y: c1 ^= anti & ~(c0 ^ z)
+// and c0 ^= anti in every case.
+template <uint32_t K>
+__device__ __forceinline__ void sweep_uniform(const TabDev &t, const StepArgs &s, uint32_t p, uint32_t j0,
+                                              uint32_t j1, bool own_next, uint64_t *SNn, uint32_t *s_pnext,
+                                              const uint64_t *s_xp, const uint64_t *s_zp, uint64_t *s_c0,
+                                              uint64_t *s_c1, uint32_t wave, uint32_t nsw, uint32_t lane,
+                                              uint32_t G, uint32_t g) {
+  constexpr uint32_t U = 8;   // columns in flight per lane
+  constexpr uint32_t Wl = 64 * K;
+  const uint32_t n = t.n, W = t.W;
+  const uint32_t T = (W + Wl - 1) / Wl;
+  const bool whole_tiles = T >= nsw;
+  const uint32_t ncg = whole_tiles ? 1u : nsw / T;
+  uint32_t cgi, tfirst, tstep;
+  if (whole_tiles) { cgi = 0; tfirst = wave; tstep = nsw; }
+  else { cgi = wave / T; tfirst = cgi < ncg ? wave % T : T; tstep = T; }
+  const uint32_t pn = p - n, wpn = pn >> 6, wp = p >> 6;
+  const uint64_t bpn = bit64(pn), bpb = bit64(p);
+  const uint32_t stride = T * Wl;
+  for (uint32_t tile = tfirst; tile < T; tile += tstep) {
+    const uint32_t w = tile * Wl + lane * K;
+    const bool live = w < W;
+    uint64_t m[K], c0[K], c1[K];
+    bool at_pn[K], at_p[K];
+    bool touch = false;
+#pragma unroll
+    for (uint32_t k = 0; k < K; ++k) {
+      m[k] = live && w + k < W ? upd_mask(t, s.slot, p, w + k) : 0ull;
+      at_pn[k] = w + k == wpn;
+      at_p[k] = w + k == wp;
+      touch |= m[k] != 0 || at_pn[k] || at_p[k];
+      c0[k] = 0;
+      c1[k] = 0;
+    }
+    touch &= live;
+    bool has_pn = false;
+#pragma unroll
+    for (uint32_t k = 0; k < K; ++k) has_pn |= at_pn[k];
+    for (uint32_t jb = j0 + cgi; jb < j1; jb += U * ncg) {
+      uint64_t xv[U][K], zv[U][K];
+      uint32_t ty[U];
+      // issue the loads of U columns first ...
+#pragma unroll
+      for (uint32_t u = 0; u < U; ++u) {
+        const uint32_t j = jb + u * ncg;
+        uint32_t tj = 0;
+        if (j < j1) {
+          const uint32_t c = j - j0;
+          tj = (uint32_t(s_xp[c >> 6] >> (c & 63)) & 1u) | ((uint32_t(s_zp[c >> 6] >> (c & 63)) & 1u) << 1);
+        }
+        tj = __builtin_amdgcn_readfirstlane(tj);
+        ty[u] = tj;
+        const bool nxt = own_next && j == s.a_next;
+        // supported column: every word with rows to update; pivot I here:
+        // only the word of row p-n (it becomes the pivot's zeros)
+        const bool need = j < j1 && live && (nxt || (tj ? touch : has_pn));
+        const size_t at = size_t(j) * t.Wp + w;
+        if constexpr (K == 2) {
+          ulonglong2 vx = make_ulonglong2(0, 0), vz = make_ulonglong2(0, 0);
+          if (need) {
+            vx = *reinterpret_cast<const ulonglong2 *>(t.X + at);
+            vz = *reinterpret_cast<const ulonglong2 *>(t.Z + at);
+          }
+          xv[u][0] = vx.x; xv[u][1] = vx.y;
+          zv[u][0] = vz.x; zv[u][1] = vz.y;
+        } else {
+          xv[u][0] = need ? t.X[at] : 0ull;
+          zv[u][0] = need ? t.Z[at] : 0ull;
+        }
+      }
+      // ... then update them
+#pragma unroll
+      for (uint32_t u = 0; u < U; ++u) {
+        const uint32_t j = jb + u * ncg;
+        if (j >= j1) continue;   // uniform
+        const uint32_t tj = ty[u];
+        const bool nxt = own_next && j == s.a_next;
+        if (!live || !(nxt || (tj ? touch : has_pn))) continue;
+        uint64_t nx[K], nz[K];
+        bool chx = false, chz = false;
+#pragma unroll
+        for (uint32_t k = 0; k < K; ++k) {
+          const uint64_t x = xv[u][k], z = zv[u][k];
+          uint64_t ax = x, az = z;
+          if (tj == 1u) {          // pivot X on this column
+            const uint64_t anti = z & m[k];
+            c1[k] ^= anti & ~(c0[k] ^ x);
+            c0[k] ^= anti;
+            ax = x ^ m[k];
+          } else if (tj == 2u) {   // pivot Z
+            const uint64_t anti = x & m[k];
+            c1[k] ^= anti & (c0[k] ^ z);
+            c0[k] ^= anti;
+            az = z ^ m[k];
+          } else if (tj == 3u) {   // pivot Y
+            const uint64_t anti = (x ^ z) & m[k];
+            c1[k] ^= anti & ~(c0[k] ^ z);
+            c0[k] ^= anti;
+            ax = x ^ m[k];
+            az = z ^ m[k];
+          }
+          if (at_pn[k]) {   // row p-n <- pivot row
+            ax = (tj & 1u) ? (ax | bpn) : (ax & ~bpn);
+            az = (tj & 2u) ? (az | bpn) : (az & ~bpn);
+          }
+          if (at_p[k]) {    // row p <- Z_a
+            ax &= ~bpb;
+            az = (j == s.a) ? (az | bpb) : (az & ~bpb);
+          }
+          nx[k] = ax;
+          nz[k] = az;
+          chx |= ax != x;
+          chz |= az != z;
+        }
+        const size_t at = size_t(j) * t.Wp + w;
+        if constexpr (K == 2) {
+          if (chx) *reinterpret_cast<ulonglong2 *>(t.X + at) = make_ulonglong2(nx[0], nx[1]);
+          if (chz) *reinterpret_cast<ulonglong2 *>(t.Z + at) = make_ulonglong2(nz[0], nz[1]);
+        } else {
+          if (chx) t.X[at] = nx[0];
+          if (chz) t.Z[at] = nz[0];
+        }
+        if (nxt) {
+#pragma unroll
+          for (uint32_t k = 0; k < K; ++k)
+            if (w + k < W) {
+              SNn[w + k] = nx[k];
+              note_pivot(s_pnext, n, w + k, nx[k]);
+            }
+        }
+      }
+    }
+    if (whole_tiles) {
+      if (live) {   // complete over the workgroup's columns: store directly
+        uint64_t *part = t.part + (size_t(s.slot & 1) * G + g) * t.Wp * 2;
+#pragma unroll
+        for (uint32_t k = 0; k < K; ++k) {
+          part[size_t(w + k) * 2] = c0[k];
+          part[size_t(w + k) * 2 + 1] = c1[k];
+        }
+      }
+    } else if (cgi < ncg) {
+#pragma unroll
+      for (uint32_t k = 0; k < K; ++k) {
+        s_c0[cgi * stride + w + k] = c0[k];
+        s_c1[cgi * stride + w + k] = c1[k];
+      }
+    }
+  }
+}
+
 // ------------------------------------------------------------------ step ---
 __global__ void __launch_bounds__(1024) k_step(TabDev t, StepArgs s) {
-  __shared__ uint64_t s_c0[1024], s_c1[1024];
+  __shared__ uint64_t s_c0[2048], s_c1[2048];
   __shared__ uint64_t s_xp[kMaxOwnCols / 64], s_zp[kMaxOwnCols / 64];
   __shared__ uint32_t s_pnext;
   const uint32_t tid = threadIdx.x, lane = tid & 63;
@@ -194,16 +354,23 @@ __global__ void __launch_bounds__(1024) k_step(TabDev t, StepArgs s) {
   }
 
   // lane layout: Wl words per column segment, cpw column segments per wave
-  const uint32_t Wl = W >= 64 ? 64u : (W <= 1 ? 1u : (1u << (32 - __builtin_clz(W - 1))));
-  const uint32_t cpw = 64 / Wl;
+  // (W > 32: one column per wave, K = 2 words per lane from W = 128 on)
+  const bool uniform = W > 32;
+  const uint32_t Wl = W >= 128 ? 128u : W > 32 ? 64u : (W <= 1 ? 1u : (1u << (32 - __builtin_clz(W - 1))));
+  const uint32_t cpw = uniform ? 1u : 64 / Wl;
   const uint32_t T = (W + Wl - 1) / Wl;             // word tiles
   const bool whole_tiles = T >= nsw;                 // each wave owns whole tiles
   const uint32_t ncg = whole_tiles ? 1u : nsw / T;   // column groups per tile
   const uint32_t sub = lane / Wl, wl = lane % Wl;
   const uint32_t stride = T * Wl;                    // LDS row of one column slot
 
-  if (p != kNone && wave != rwave) {
-    // ------------------------------------------------------- random branch
+  if (p != kNone && wave != rwave && uniform) {
+    if (W >= 128)
+      sweep_uniform<2>(t, s, p, j0, j1, own_next, SNn, &s_pnext, s_xp, s_zp, s_c0, s_c1, wave, nsw, lane, G, g);
+    else
+      sweep_uniform<1>(t, s, p, j0, j1, own_next, SNn, &s_pnext, s_xp, s_zp, s_c0, s_c1, wave, nsw, lane, G, g);
+  } else if (p != kNone && wave != rwave) {
+    // ------------------------------------------- random branch, W <= 32
     const uint32_t pn = p - n, wpn = pn >> 6, wp = p >> 6;
     const uint64_t bpn = bit64(pn), bpb = bit64(p);
     uint32_t cgi, tfirst, tstep;

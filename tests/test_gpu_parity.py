@@ -487,3 +487,32 @@ def test_xlarge_per_measurement_path_vs_stored_oracle(ctx):
     assert np.array_equal(rnd, _golden_bits(rec["random"], k))
     assert t.anomalies() == 0 and rec["anomalies"] == 0
     t.close()
+
+
+def test_step_whole_tiles_product_state(ctx):
+    """n = 62,000 (1,938 row words: every sweep wave owns whole 128-word
+    tiles, partial counters stored directly) in a product state whose first
+    64 qubits carry a random circuit and the rest stay |0>: measuring those 64
+    qubits on the per-measurement path gives the 64-qubit oracle's outcomes,
+    and measuring them again gives the same outcomes deterministically."""
+    from paper_2408_00384_amd import MEASURE_AUTO, MEASURE_STEP, cliff_ctx_set_measure_mode
+    k, n = 64, 62_000
+    rng = np.random.Generator(np.random.PCG64(77))
+    ops, a, b = random_gate_list(rng, k, 40 * k, full=True)
+    q = np.arange(k, dtype=np.uint32)
+    cliff_ctx_set_measure_mode(ctx.handle, MEASURE_STEP)
+    try:
+        t = _tab(ctx, n, 2).apply_gates(ops, a, b)
+        out, rnd = t.measure(q, seed=9, circuit=7)
+        again, rnd2 = t.measure(q, seed=9, circuit=7, m0=k)
+        assert t.anomalies() == 0
+        t.close()
+    finally:
+        cliff_ctx_set_measure_mode(ctx.handle, MEASURE_AUTO)
+    ref = oracle.Tableau(k).apply_gates(ops, a, b)
+    for s in range(2):
+        o, kinds = ref.clone().measure_list(q, seed=9, circuit=7, shot=s)
+        assert np.array_equal(out[s], o), "outcomes (shot %d)" % s
+        assert np.array_equal(rnd, kinds)
+    assert rnd.sum() > 0 and rnd2.sum() == 0
+    assert np.array_equal(again, out)
