@@ -397,10 +397,16 @@ def main():
         nbytes = 1 << 30
         src = torch.ones(nbytes, dtype=torch.uint8, device="cuda:0")
         dst = torch.empty_like(src)
-        for _ in range(4):
+        ev = [torch.cuda.Event(enable_timing=True) for _ in range(5)]
+        ev[0].record()
+        for i in range(4):
             dst.copy_(src)
+            ev[i + 1].record()
         torch.cuda.synchronize()
-        print(json.dumps({"copy_bytes_per_launch": nbytes, "launches": 4}))
+        ms = [ev[i].elapsed_time(ev[i + 1]) for i in range(4)]
+        # read + write bytes over the fastest copy's time
+        print(json.dumps({"copy_bytes_per_launch": nbytes, "launches": 4,
+                          "copy_ms": ms, "copy_gbs_read_plus_write": 2 * nbytes / (min(ms) * 1e-3) / 1e9}))
         return
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
