@@ -181,35 +181,48 @@ __global__ void __launch_bounds__(TEAM) k_batch(const BatchDescDev *__restrict__
             sZ[j * W + wl] = nz;
           }
         }
-        sC0[tid] = c0;
-        sC1[tid] = c1;
+        // counters: the cpw column slots of a word sit in lanes sub * Wl + wl
+        // of one wave (same wl): mod-4 sums by a butterfly over them, then
+        // the waves' sums through LDS
+        for (uint32_t off = Wl; off < 64; off <<= 1) {
+          const uint64_t b0 = __shfl_xor(c0, int(off)), b1 = __shfl_xor(c1, int(off));
+          c1 ^= b1 ^ (c0 & b0);
+          c0 ^= b0;
+        }
+        if (lane < Wl) {
+          sC0[wave * Wl + lane] = c0;
+          sC1[wave * Wl + lane] = c1;
+        }
         __syncthreads();
         // reduce counters per word (wave 0), then update the signs of all shots
         if (wave == 0) {
           uint64_t t0 = 0, t1 = 0;
           if (lane < Wl && lane < W) {
-            for (uint32_t sl = 0; sl < slots; ++sl) {
-              const uint32_t th = (sl / cpw) * 64 + (sl % cpw) * Wl + lane;
-              const uint64_t b0 = sC0[th], b1 = sC1[th];
+#pragma unroll
+            for (int wv = 0; wv < NWAVE; ++wv) {
+              const uint64_t b0 = sC0[wv * Wl + lane], b1 = sC1[wv * Wl + lane];
               t1 ^= b1 ^ (t0 & b0);
               t0 ^= b0;
             }
           }
-          // one lane per shot; word values via shuffles
-          for (uint32_t w = 0; w < W; ++w) {
-            const uint64_t mw = __shfl(m, int(w));           // lane w holds word w
-            const uint64_t c1w = __shfl(t1, int(w));
-            if (lane < S) {
-              const uint32_t rpb = uint32_t(rpw >> lane) & 1u;
-              uint64_t rv = sR[w * 64 + lane];
+          // one lane per (word, shot) pair; word values via shuffles (lane w
+          // holds word w)
+          for (uint32_t i0 = 0; i0 < W * S; i0 += 64) {
+            const uint32_t i = i0 + lane, w = i / S, sh = i % S;
+            const int src = int(i < W * S ? w : 0u);
+            const uint64_t mw = __shfl(m, src);
+            const uint64_t c1w = __shfl(t1, src);
+            if (i < W * S) {
+              const uint32_t rpb = uint32_t(rpw >> sh) & 1u;
+              uint64_t rv = sR[w * 64 + sh];
               rv ^= mw & (c1w ^ (rpb ? ~0ull : 0ull));
               if (w == wpn) rv = rpb ? (rv | bpn) : (rv & ~bpn);
               if (w == wp) {
-                const uint32_t o = outcome_bit(seed, d.circuit_id, lane, a);
+                const uint32_t o = outcome_bit(seed, d.circuit_id, sh, a);
                 rv = o ? (rv | bpb) : (rv & ~bpb);
-                cout[size_t(lane) * n + a] = uint8_t(o);
+                cout[size_t(sh) * n + a] = uint8_t(o);
               }
-              sR[w * 64 + lane] = rv;
+              sR[w * 64 + sh] = rv;
             }
           }
           const uint64_t bad = (lane < W) ? (t0 & m & ~(lane == wpn ? bpn : 0ull)) : 0ull;
