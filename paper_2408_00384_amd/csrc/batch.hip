@@ -74,11 +74,20 @@ __global__ void __launch_bounds__(TEAM) k_batch(const BatchDescDev *__restrict__
       const uint32_t *coffs = offs + d.offs_off;
       const uint32_t w = tid % Wl, k0 = tid / Wl, kst = TEAM / Wl;
       uint64_t racc = 0;
-      for (uint32_t l = 0; l < d.depth; ++l) {
-        const uint32_t a0 = coffs[l], a1 = coffs[l + 1];
+      // The next layer's bounds and this thread's first two ops of it are
+      // loaded one layer ahead, so a layer does not start with a chain of
+      // dependent global loads (reads stay inside the circuit's ops).
+      const uint32_t depth = d.depth, end = coffs[depth];
+      auto fetch = [&](uint32_t k) -> uint64_t { return k < end ? cops[k] : 0ull; };
+      uint32_t a0 = coffs[0], a1 = depth ? coffs[1] : a0;
+      uint64_t f0 = fetch(a0 + k0), f1 = fetch(a0 + k0 + kst);
+      for (uint32_t l = 0; l < depth; ++l) {
+        const uint32_t b0 = a1, b1 = l + 2 <= depth ? coffs[l + 2] : a1;
+        const uint64_t g0 = fetch(b0 + k0), g1 = fetch(b0 + k0 + kst);
         if (w < W) {
-          for (uint32_t k = a0 + k0; k < a1; k += kst) {
-            const uint64_t op = cops[k];
+          uint32_t r = 0;
+          for (uint32_t k = a0 + k0; k < a1; k += kst, ++r) {
+            const uint64_t op = r == 0 ? f0 : r == 1 ? f1 : cops[k];
             if (!op_valid(op, n)) {   // malformed op
               atomicAdd(errors, 1u);
               continue;
@@ -99,6 +108,10 @@ __global__ void __launch_bounds__(TEAM) k_batch(const BatchDescDev *__restrict__
           }
         }
         __syncthreads();
+        a0 = b0;
+        a1 = b1;
+        f0 = g0;
+        f1 = g1;
       }
       if (w < W && racc) atomicXor(reinterpret_cast<unsigned long long *>(&sP[w]), (unsigned long long)racc);
       __syncthreads();
