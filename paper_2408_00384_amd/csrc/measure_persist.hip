@@ -153,8 +153,12 @@ __global__ void __launch_bounds__(kThreads) k_meas_xz(TabDev t, PersistArgs a) {
   // thread t carries row words t + kThreads j (j < kWordsPerThread) of the measured columns
   uint64_t *zw = sZ + size_t(wave) * CW * L * 64 + lane;   // z of slot k, word i at zw[(k * L + i) * 64]
 
-  // an earlier chunk of this pass gave up: the tableau is not to be touched
-  if (ld_relaxed(t.abort_flag)) return;
+  // an earlier chunk of this pass gave up: the tableau is not to be touched.
+  // The test is wave-uniform; waves of one workgroup may still disagree when
+  // another workgroup raises the flag meanwhile, which is safe: a barrier
+  // waits only for the waves that have not ended, and every later wait is
+  // bounded and sees the raised flag.
+  if (__builtin_amdgcn_readfirstlane(ld_relaxed(t.abort_flag))) return;
   for (uint32_t i = tid; i < a.k; i += blockDim.x) s_q[i] = a.qubits[i];
   if (tid == 0) {
     s_abort = 0;
@@ -499,7 +503,9 @@ __global__ void __launch_bounds__(256) k_meas_reduce(TabDev t, uint32_t k, uint3
   uint64_t bad = c0 & mw;
   const uint32_t pn = p - t.n;
   if (w == (pn >> 6)) bad &= ~pbit(pn);   // row p-n anticommutes with the pivot
-  if (bad) atomicAdd(&t.state[ST_ANOMALY], uint32_t(__popcll(bad)));
+  // (not counted when an x/z kernel gave up: the partials of the measurements
+  // it did not reach are stale; the flag is read only here, not by every thread)
+  if (bad && !ld_relaxed(t.abort_flag)) atomicAdd(&t.state[ST_ANOMALY], uint32_t(__popcll(bad)));
   t.C1all[size_t(m) * t.Wp + w] = c1;
 }
 
@@ -517,14 +523,19 @@ constexpr uint32_t kSignWords = 2;   // words per thread
 
 __global__ void __launch_bounds__(kSignThreads) k_meas_signs(TabDev t, uint32_t k, uint32_t base, uint64_t seed,
                                                              uint64_t circuit, uint64_t shot0, uint64_t m0) {
-  __shared__ uint32_t s_piv[kPersistMaxChunk], s_dp[kPersistMaxChunk], s_dy[kPersistMaxChunk];
-  __shared__ uint32_t s_bit[2], s_par[2];
+  // pivots, and per deterministic measurement bit 0 = the x/z parity term,
+  // bits 1-2 = the Y count mod 4 (small enough to sit beside the x/z kernel)
+  __shared__ uint32_t s_piv[kPersistMaxChunk];
+  __shared__ uint8_t s_det[kPersistMaxChunk];
+  __shared__ uint32_t s_bit[2], s_par[2], s_stop;
   const uint32_t s = blockIdx.x, tid = threadIdx.x, W = t.W, S = t.S, n = t.n;
   const uint32_t lane = tid & 63;
+  // an x/z kernel gave up: nothing to finish (one read for the workgroup,
+  // tested by every thread after the barrier below)
+  if (tid == 0) s_stop = ld_relaxed(t.abort_flag);
   for (uint32_t i = tid; i < k; i += blockDim.x) {
     s_piv[i] = t.pivall[i];
-    s_dp[i] = t.detpar[i];
-    s_dy[i] = t.detY[i];
+    s_det[i] = uint8_t((t.detpar[i] & 1u) | ((t.detY[i] & 3u) << 1));
   }
   if (tid < 2) s_par[tid] = 0;
   uint64_t r[kSignWords];
@@ -549,6 +560,7 @@ __global__ void __launch_bounds__(kSignThreads) k_meas_signs(TabDev t, uint32_t 
   // wait for these loads here, so the loop's waits track only its own
   __builtin_amdgcn_s_waitcnt(0);
   lds_barrier();
+  if (s_stop) return;
   for (uint32_t mb = 0; mb < k; mb += kSignAhead) {
 #pragma unroll
     for (uint32_t d = 0; d < kSignAhead; ++d) {
@@ -593,11 +605,11 @@ __global__ void __launch_bounds__(kSignThreads) k_meas_signs(TabDev t, uint32_t 
           if (lane == 0 && (__popcll(pb) & 1)) atomicXor(&s_par[b], 1u);
           lds_barrier();
           if (tid == 0) {
-            const uint32_t y = s_dy[m];
-            t.out[slot * S + s] = uint8_t(s_par[b] ^ (s_dp[m] & 1u) ^ ((y >> 1) & 1u));
+            const uint32_t dt = s_det[m];
+            t.out[slot * S + s] = uint8_t(s_par[b] ^ (dt & 1u) ^ ((dt >> 2) & 1u));
             if (s == 0) {
               t.kind[slot] = 0;
-              if (y & 1u) atomicAdd(&t.state[ST_ANOMALY], 1u);
+              if (dt & 2u) atomicAdd(&t.state[ST_ANOMALY], 1u);   // odd Y count
             }
             s_par[b] = 0;   // next used at m + 2, after the next barrier
           }
