@@ -35,7 +35,7 @@ HBM_PEAK_GBS = 8000.0   # MI355X HBM3E peak
 TRAFFIC = {
     "k_meas_xz": {
         "sources": ("paper_2408_00384_amd/csrc/measure_persist.hip", "paper_2408_00384_amd/csrc/internal.h"),
-        "sha256": "42aed41d666719a5fecadcf5c2278747672153053e5a8d02acbc1530a5e900bd",
+        "sha256": "872625f3b0e866cd73c46b213fa8da254155ea7f078a4fd62b7d9fdfd4c5e180",
         "bytes_per_launch": 1.121e+09,
         "summary": "profiles/k_meas_xz_plain_n10000_measure_all.md",
     },
