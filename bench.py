@@ -28,6 +28,7 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0   # MI355X HBM3E peak
+LDS_PEAK_GBS = 256 * 128 * 2.4   # 256 CUs x 128 B/clk x 2.4 GHz = 78,643 GB/s
 
 # HBM bytes per launch of the dominant kernel from hardware counters
 # (FETCH_SIZE and WRITE_SIZE, each scaled by what it reads for a copy of known
@@ -131,6 +132,7 @@ def bench_batch(P, torch, np, count=4096, plain_sample=48, reps=5):
         ev_ms = ev0.elapsed_time(ev1) / reps
         outs = plan.outcomes()
     status = plan.status()
+    lds_bytes = batch_lds_bytes(plan, np)
     # plain path on an evenly spaced sample
     idx = np.linspace(0, count - 1, plain_sample).astype(int)
     pctx = P.Context(0)
@@ -159,8 +161,26 @@ def bench_batch(P, torch, np, count=4096, plain_sample=48, reps=5):
         "bit_exact_vs_plain": parity,
         "device_checks": status,
         "teams": {str(k): v for k, v in load_tuning().items()},
+        "lds": {"alg_bytes_per_batch": lds_bytes, "achieved_gbs": lds_bytes / (ev_ms * 1e-3) / 1e9,
+                "peak_gbs": LDS_PEAK_GBS, "frac": lds_bytes / (ev_ms * 1e-3) / 1e9 / LDS_PEAK_GBS,
+                "note": "tableaux live in LDS; algorithmic LDS bytes of the gate updates and "
+                        "measurement sweeps over the whole batch time"},
         "generate_s": gen_s,
     }
+
+
+def batch_lds_bytes(plan, np):
+    """Algorithmic LDS bytes of a batch: per row word (64 rows, 8 bytes per
+    plane) a two-qubit op reads and writes x and z of two columns (64 B), a
+    single-qubit op of one (32 B); every measurement sweeps all n columns,
+    reading the pivot row's bits and x, z and writing x, z (48 B per column
+    and row word; measurements counted as random, as nearly all are in these
+    dense states)."""
+    n = plan.descs["n"].astype(np.int64)
+    W = (2 * n + 63) // 64
+    gates = (64 * plan.pair_count + 32 * (plan.op_count - plan.pair_count)) * W
+    meas = 48 * n * n * W
+    return int(gates.sum() + meas.sum())
 
 
 def _gen_clifford(args):

@@ -58,6 +58,9 @@ class BatchPlan:
         count = len(circuits)
         descs = np.zeros(count, dtype=B.BATCH_DESC_DTYPE)
         ops_parts, offs_parts = [], []
+        # per circuit: op words and those with a two-qubit gate (for traffic accounting)
+        self.op_count = np.zeros(count, np.int64)
+        self.pair_count = np.zeros(count, np.int64)
         ops_off = offs_off = out_off = 0
         for i, c in enumerate(circuits):
             if c.shots < 1 or c.shots > 64:
@@ -65,6 +68,8 @@ class BatchPlan:
             if len(c.qubits) != c.n or not np.array_equal(c.qubits, np.arange(c.n)):
                 raise ValueError("batched circuits measure qubits 0..n-1 in order")
             ops, offs = B.cliff_encode_layers(c.n, c.h, c.s, c.ctrl, c.tgt)
+            self.op_count[i] = len(ops)
+            self.pair_count[i] = int(np.count_nonzero(ops >> np.uint64(62)))
             descs[i] = (c.n, c.depth, c.shots, 0, ops_off, offs_off, out_off, c.circuit_id)
             ops_parts.append(ops)
             offs_parts.append(offs)

@@ -68,22 +68,52 @@ __device__ __forceinline__ U128 operator^(U128 a, U128 b) { return {a.lo ^ b.lo,
 __device__ __forceinline__ U128 operator~(U128 a) { return {~a.lo, ~a.hi}; }
 __device__ __forceinline__ U128 &operator^=(U128 &a, U128 b) { a = a ^ b; return a; }
 
-// All-ones word if b (0 or 1) is set, else zero.
+// All-ones word if b (0 or 1) is set, else zero (one 32-bit value, repeated).
 template <typename T>
-__device__ __forceinline__ T mask_if(uint32_t b) { return T(0) - T(b); }
+__device__ __forceinline__ T mask_if(uint32_t b);
+template <>
+__device__ __forceinline__ uint32_t mask_if<uint32_t>(uint32_t b) { return 0u - b; }
+template <>
+__device__ __forceinline__ uint64_t mask_if<uint64_t>(uint32_t b) {
+  const uint64_t m = 0u - b;
+  return (m << 32) | m;
+}
 template <>
 __device__ __forceinline__ U128 mask_if<U128>(uint32_t b) {
-  const uint64_t m = 0ull - uint64_t(b);
+  const uint64_t m = mask_if<uint64_t>(b);
   return {m, m};
 }
+
+// Any bitwise function of three words, one v_bitop3 per 32 bits.  LUT is the
+// function's value on the inputs (0xF0, 0xCC, 0xAA): bit (4a + 2b + c) of LUT
+// is f(a, b, c).
+template <uint32_t LUT>
+__device__ __forceinline__ uint32_t bop3(uint32_t a, uint32_t b, uint32_t c) {
+  return __builtin_amdgcn_bitop3_b32(a, b, c, LUT);
+}
+template <uint32_t LUT>
+__device__ __forceinline__ uint64_t bop3(uint64_t a, uint64_t b, uint64_t c) {
+  const uint32_t lo = bop3<LUT>(uint32_t(a), uint32_t(b), uint32_t(c));
+  const uint32_t hi = bop3<LUT>(uint32_t(a >> 32), uint32_t(b >> 32), uint32_t(c >> 32));
+  return (uint64_t(hi) << 32) | lo;
+}
+template <uint32_t LUT>
+__device__ __forceinline__ U128 bop3(U128 a, U128 b, U128 c) {
+  return {bop3<LUT>(a.lo, b.lo, c.lo), bop3<LUT>(a.hi, b.hi, c.hi)};
+}
+constexpr uint32_t LUT_AND3 = 0x80;        // a & b & c
+constexpr uint32_t LUT_AND_XOR = 0x6A;     // (a & b) ^ c
+constexpr uint32_t LUT_ANDN_XOR = 0x9A;    // (a & ~b) ^ c
+constexpr uint32_t LUT_AND_ANDN = 0x40;    // a & b & ~c
 
 // Apply a single-qubit code to x / z words of rows (32, 64 or 128 rows at once).
 template <typename T>
 __device__ __forceinline__ void sq_apply(uint32_t c, T &x, T &z, T &racc) {
   auto bit = [c](uint32_t k) { return mask_if<T>((c >> k) & 1u); };   // all-ones if set
-  racc ^= (x & bit(4)) ^ (z & bit(5)) ^ (x & z & bit(6));
-  const T nx = (x & ~bit(0)) ^ (z & bit(1));
-  const T nz = (x & bit(2)) ^ (z & ~bit(3));
+  // racc ^= (x & p_x) ^ (z & p_z) ^ (x & z & p_xz)
+  racc ^= bop3<LUT_AND_XOR>(z, bit(5), bop3<LUT_AND_XOR>(x, bit(4), bop3<LUT_AND3>(x, z, bit(6))));
+  const T nx = bop3<LUT_ANDN_XOR>(x, bit(0), z & bit(1));   // (x & m00) ^ (z & m01)
+  const T nz = bop3<LUT_ANDN_XOR>(z, bit(3), x & bit(2));   // (x & m10) ^ (z & m11)
   x = nx;
   z = nz;
 }
@@ -91,11 +121,11 @@ __device__ __forceinline__ void sq_apply(uint32_t c, T &x, T &z, T &racc) {
 template <typename T>
 __device__ __forceinline__ void pair_apply(uint32_t kind, T &xa, T &za, T &xb, T &zb, T &racc) {
   if (kind == PAIR_CNOT) {
-    racc ^= xa & zb & ~(xb ^ za);
+    racc ^= bop3<LUT_AND_ANDN>(xa, zb, xb ^ za);   // xa & zb & ~(xb ^ za)
     xb ^= xa;
     za ^= zb;
   } else if (kind == PAIR_CZ) {
-    racc ^= xa & xb & (za ^ zb);
+    racc ^= bop3<LUT_AND3>(xa, xb, za ^ zb);       // xa & xb & (za ^ zb)
     za ^= xb;
     zb ^= xa;
   } else if (kind == PAIR_SWAP) {
