@@ -76,38 +76,52 @@ __global__ void __launch_bounds__(TEAM) k_batch(const BatchDescDev *__restrict__
       uint64_t racc = 0;
       // The next layer's bounds and this thread's first two ops of it are
       // loaded one layer ahead, so a layer does not start with a chain of
-      // dependent global loads (reads stay inside the circuit's ops).
+      // dependent global loads (reads stay inside the circuit's ops).  Layers
+      // and measurement steps meet at LDS-only barriers: they share nothing
+      // else, and a full barrier would also wait for those prefetches and for
+      // the outcome stores.
       const uint32_t depth = d.depth, end = coffs[depth];
-      auto fetch = [&](uint32_t k) -> uint64_t { return k < end ? cops[k] : 0ull; };
+      // every prefetch is an unconditional load from an in-bounds address (the
+      // circuit's last op, or its descriptor when it has none) and the value is
+      // selected after, so the compiler counts the loads in flight exactly
+      const uint64_t *safe = end ? cops + (end - 1) : reinterpret_cast<const uint64_t *>(descs + ci);
+      auto fetch = [&](uint32_t k) -> uint64_t {
+        const uint64_t v = *(k < end ? cops + k : safe);
+        return k < end ? v : 0ull;
+      };
       uint32_t a0 = coffs[0], a1 = depth ? coffs[1] : a0;
       uint64_t f0 = fetch(a0 + k0), f1 = fetch(a0 + k0 + kst);
       for (uint32_t l = 0; l < depth; ++l) {
         const uint32_t b0 = a1, b1 = l + 2 <= depth ? coffs[l + 2] : a1;
         const uint64_t g0 = fetch(b0 + k0), g1 = fetch(b0 + k0 + kst);
-        if (w < W) {
-          uint32_t r = 0;
-          for (uint32_t k = a0 + k0; k < a1; k += kst, ++r) {
-            const uint64_t op = r == 0 ? f0 : r == 1 ? f1 : cops[k];
-            if (!op_valid(op, n)) {   // malformed op
-              atomicAdd(errors, 1u);
-              continue;
-            }
-            const uint32_t a = op_a(op), pair = op_pair(op);
-            uint64_t xa = sX[a * W + w], za = sZ[a * W + w];
-            if (op_ca(op)) sq_apply(op_ca(op), xa, za, racc);
-            if (pair != PAIR_NONE) {
-              const uint32_t b = op_b(op);
-              uint64_t xb = sX[b * W + w], zb = sZ[b * W + w];
-              if (op_cb(op)) sq_apply(op_cb(op), xb, zb, racc);
-              pair_apply(pair, xa, za, xb, zb, racc);
-              sX[b * W + w] = xb;
-              sZ[b * W + w] = zb;
-            }
-            sX[a * W + w] = xa;
-            sZ[a * W + w] = za;
+        // one op on this thread's row word (ops of a layer act on distinct qubits)
+        auto apply = [&](uint64_t op) {
+          if (!op_valid(op, n)) {   // malformed op
+            atomicAdd(errors, 1u);
+            return;
           }
+          const uint32_t a = op_a(op), pair = op_pair(op);
+          uint64_t xa = sX[a * W + w], za = sZ[a * W + w];
+          if (op_ca(op)) sq_apply(op_ca(op), xa, za, racc);
+          if (pair != PAIR_NONE) {
+            const uint32_t b = op_b(op);
+            uint64_t xb = sX[b * W + w], zb = sZ[b * W + w];
+            if (op_cb(op)) sq_apply(op_cb(op), xb, zb, racc);
+            pair_apply(pair, xa, za, xb, zb, racc);
+            sX[b * W + w] = xb;
+            sZ[b * W + w] = zb;
+          }
+          sX[a * W + w] = xa;
+          sZ[a * W + w] = za;
+        };
+        if (w < W) {
+          // the two prefetched ops in straight-line code, so their wait does
+          // not cover the loads just issued for the next layer
+          if (a0 + k0 < a1) apply(f0);
+          if (a0 + k0 + kst < a1) apply(f1);
+          for (uint32_t k = a0 + k0 + 2 * kst; k < a1; k += kst) apply(cops[k]);
         }
-        __syncthreads();
+        lds_barrier();
         a0 = b0;
         a1 = b1;
         f0 = g0;
@@ -163,7 +177,7 @@ __global__ void __launch_bounds__(TEAM) k_batch(const BatchDescDev *__restrict__
         rpw = __ballot(b);
       }
       if (tid == 0) { s_par = 0; s_y = 0; }
-      __syncthreads();   // everyone has column a and r_p before any write
+      lds_barrier();   // everyone has column a and r_p before any write
       if (p != kNone) {
         const uint32_t pn = p - n, wpn = pn >> 6, wp = p >> 6;
         const uint64_t bpn = 1ull << (pn & 63), bpb = 1ull << (p & 63);
@@ -206,7 +220,7 @@ __global__ void __launch_bounds__(TEAM) k_batch(const BatchDescDev *__restrict__
           sC0[wave * Wl + lane] = c0;
           sC1[wave * Wl + lane] = c1;
         }
-        __syncthreads();
+        lds_barrier();
         // reduce counters per word (wave 0), then update the signs of all shots
         if (wave == 0) {
           uint64_t t0 = 0, t1 = 0;
@@ -272,7 +286,7 @@ __global__ void __launch_bounds__(TEAM) k_batch(const BatchDescDev *__restrict__
         }
         if (par & 1u) atomicXor(&s_par, 1u);
         if (ycnt) atomicAdd(&s_y, ycnt);
-        __syncthreads();
+        lds_barrier();
         if (wave == 0) {
           // shuffles with the whole wave active (lane w holds mask word w)
           uint32_t rt = 0;
@@ -284,7 +298,7 @@ __global__ void __launch_bounds__(TEAM) k_batch(const BatchDescDev *__restrict__
         }
         if (wave == 0 && lane == 0 && (s_y & 1u)) atomicAdd(errors + 1, 1u);
       }
-      __syncthreads();
+      lds_barrier();
     }
   }
 }
