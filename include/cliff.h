@@ -310,8 +310,8 @@ int cliff_ctx_profile_read(cliff_ctx *ctx, int kind, double *ms, uint64_t *launc
  * m = qubit, shot index 0..shots-1, circuit index circuit_id for the random
  * bit).  Workgroups take circuits in the order dev_order[0..count) from a
  * device queue.  team (threads per circuit) and maxn select the kernel
- * instance: (64,64) (128,64) (64,128) (128,128) (256,128) (128,256) (256,256)
- * (512,256).  dev_work: cliff_batch_work_bytes() bytes of device scratch,
+ * instance: (64,64) (128,64) (64,128) (128,128) (256,128) (512,128) (128,256)
+ * (256,256) (512,256) (1024,256).  dev_work: cliff_batch_work_bytes() bytes of device scratch,
  * reset by the launch.  All pointers are device pointers; nothing is copied
  * to the host and the call only enqueues work. */
 typedef struct {

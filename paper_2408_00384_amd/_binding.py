@@ -407,8 +407,8 @@ def cliff_ctx_profile_read(ctx, kind):
 BATCH_DESC_DTYPE = np.dtype([("n", np.uint32), ("depth", np.uint32), ("shots", np.uint32),
                              ("reserved", np.uint32), ("ops_off", np.uint64), ("offs_off", np.uint64),
                              ("out_off", np.uint64), ("circuit_id", np.uint64)])
-BATCH_CONFIGS = ((64, 64), (128, 64), (64, 128), (128, 128), (256, 128), (128, 256), (256, 256),
-                 (512, 256))
+BATCH_CONFIGS = ((64, 64), (128, 64), (64, 128), (128, 128), (256, 128), (512, 128), (128, 256),
+                 (256, 256), (512, 256), (1024, 256))
 
 
 def cliff_batch_work_bytes() -> int:

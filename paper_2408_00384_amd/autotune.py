@@ -1,10 +1,11 @@
 """Autotuner for the batched-circuit kernel: team size per size bucket.
 
-    python -m paper_2408_00384_amd.autotune [--circuits 192] [--reps 3]
+    python -m paper_2408_00384_amd.autotune [--batch 4096] [--reps 3]
 
-For every size bucket (max n 64 / 128 / 256) it draws circuits of the batched
-workload's distribution (n uniform in the bucket's range, depth uniform in
-[n, 4n], 4 shots), times every compiled team size on them (HIP events around
+For every size bucket (max n 64 / 128 / 256) it draws that bucket's share of a
+batch of the batched workload's distribution (n uniform in [8, 256], so the
+bucket's share of the n range; depth uniform in [n, 4n], 4 shots), times every
+compiled team size on them (HIP events around
 the persistent launch, median of several runs, after checking that all team
 sizes give identical outcome bytes), and writes the fastest choice per bucket
 to tuning/batch_gfx950.json, which BatchPlan reads.
@@ -48,13 +49,22 @@ def time_plan(plan, reps: int) -> float:
     return float(np.median(times))
 
 
-def autotune(circuits_per_bucket: int = 192, reps: int = 3, out_path: str = TUNING_PATH):
+def bucket_share(maxn: int, batch: int) -> int:
+    """Circuits of a `batch`-circuit workload with n uniform in [8, 256] that
+    fall in the bucket: the choice is a throughput one (many circuits per CU
+    at once), so the bucket is timed at its real size, not on a small sample."""
+    lo = 8 if maxn == BUCKETS[0] else BUCKETS[BUCKETS.index(maxn) - 1] + 1
+    return max(1, round(batch * (maxn - lo + 1) / (BUCKETS[-1] - 8 + 1)))
+
+
+def autotune(batch: int = 4096, reps: int = 3, out_path: str = TUNING_PATH):
     stream = torch.cuda.Stream()
     ctx = Context(0, stream)
     rec = {"device": torch.cuda.get_device_name(0), "created": time.strftime("%Y-%m-%d %H:%M:%S"),
-           "circuits_per_bucket": circuits_per_bucket, "reps": reps, "timings_ms": {}, "best": {}}
+           "batch": batch, "circuits_per_bucket": {}, "reps": reps, "timings_ms": {}, "best": {}}
     for maxn in BUCKETS:
-        circs = bucket_circuits(maxn, circuits_per_bucket)
+        circs = bucket_circuits(maxn, bucket_share(maxn, batch))
+        rec["circuits_per_bucket"][str(maxn)] = len(circs)
         teams = [t for (t, m) in B.BATCH_CONFIGS if m == maxn]
         ref = None
         timings = {}
@@ -86,13 +96,13 @@ def autotune(circuits_per_bucket: int = 192, reps: int = 3, out_path: str = TUNI
 
 def main():
     ap = argparse.ArgumentParser(description=__doc__)
-    ap.add_argument("--circuits", type=int, default=192)
+    ap.add_argument("--batch", type=int, default=4096, help="circuits of the whole batch (split over buckets)")
     ap.add_argument("--reps", type=int, default=3)
     ap.add_argument("--out", default=TUNING_PATH)
     args = ap.parse_args()
     root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
     sys.path.insert(0, root)
-    rec = autotune(args.circuits, args.reps, args.out)
+    rec = autotune(args.batch, args.reps, args.out)
     print(json.dumps(rec["best"]))
 
 

@@ -343,9 +343,11 @@ hipError_t launch_batch(const void *descs, const uint64_t *ops, const uint32_t *
   CLIFF_BATCH_CASE(64, 128)
   CLIFF_BATCH_CASE(128, 128)
   CLIFF_BATCH_CASE(256, 128)
+  CLIFF_BATCH_CASE(512, 128)
   CLIFF_BATCH_CASE(128, 256)
   CLIFF_BATCH_CASE(256, 256)
   CLIFF_BATCH_CASE(512, 256)
+  CLIFF_BATCH_CASE(1024, 256)
 #undef CLIFF_BATCH_CASE
   return hipErrorInvalidValue;
 }

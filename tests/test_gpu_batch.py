@@ -47,8 +47,8 @@ def test_batch_matches_oracle_default_teams(ctx):
     _check(circs, outs)
 
 
-@pytest.mark.parametrize("cfg", [(64, 64), (128, 64), (64, 128), (128, 128), (256, 128),
-                                 (128, 256), (256, 256), (512, 256)])
+@pytest.mark.parametrize("cfg", [(64, 64), (128, 64), (64, 128), (128, 128), (256, 128), (512, 128),
+                                 (128, 256), (256, 256), (512, 256), (1024, 256)])
 def test_every_team_config_is_bit_identical(ctx, cfg):
     from paper_2408_00384_amd.batch import BatchPlan
     team, maxn = cfg
