@@ -138,21 +138,19 @@ __global__ void __launch_bounds__(TEAM) k_batch(const BatchDescDev *__restrict__
     const uint32_t slots = NWAVE * cpw;            // column slots per pass
     const uint32_t slot = wave * cpw + sub;
     uint8_t *cout = out + d.out_off;
-    for (uint32_t a = 0; a < n; ++a) {
-      // pivot: smallest stabilizer row with x_a = 1 (every wave computes it)
-      uint32_t p = kNone;
-      {
-        uint32_t cand = kNone;
-        if (lane < W && lane >= (n >> 6)) {
-          uint64_t v = sX[a * W + lane];
-          if (lane == (n >> 6)) v &= ~0ull << (n & 63);
-          if (v) cand = lane * 64 + uint32_t(__builtin_ctzll(v));
-        }
-        for (int off = 32; off > 0; off >>= 1) cand = min(cand, uint32_t(__shfl_xor(int(cand), off)));
-        p = __builtin_amdgcn_readfirstlane(cand);
+    // Pivot of measurement a (smallest stabilizer row with x_a = 1) and, per
+    // lane word, its update mask (random) or product-row mask T
+    // (deterministic); every wave computes them from column a.
+    auto select = [&](uint32_t a, uint32_t &p, uint64_t &m) {
+      uint32_t cand = kNone;
+      if (lane < W && lane >= (n >> 6)) {
+        uint64_t v = sX[a * W + lane];
+        if (lane == (n >> 6)) v &= ~0ull << (n & 63);
+        if (v) cand = lane * 64 + uint32_t(__builtin_ctzll(v));
       }
-      // update mask (random) or product-row mask T (deterministic), per lane word
-      uint64_t m = 0;
+      for (int off = 32; off > 0; off >>= 1) cand = min(cand, uint32_t(__shfl_xor(int(cand), off)));
+      p = __builtin_amdgcn_readfirstlane(cand);
+      m = 0;
       if (wl < W) {
         if (p != kNone) {
           m = sX[a * W + wl];
@@ -170,14 +168,27 @@ __global__ void __launch_bounds__(TEAM) k_batch(const BatchDescDev *__restrict__
           if (sh) m |= src(i - 1) >> (64 - sh);
         }
       }
-      // pivot signs of every shot, read before any update
+    };
+    // Two barriers per measurement: after the sweep (the columns are final,
+    // so every wave selects measurement a + 1 while wave 0 updates the signs
+    // of a) and after the signs.  The sweep needs none before it: the
+    // selection's reads of column a happened before the last barrier, the
+    // signs it reads are not written by the sweep, and a column's words are
+    // read and written by one wave in program order.
+    uint32_t p;
+    uint64_t m;
+    select(0, p, m);
+    if (tid == 0) { s_par = 0; s_y = 0; }
+    lds_barrier();
+    for (uint32_t a = 0; a < n; ++a) {
+      // pivot signs of every shot, final since the barrier that ended a - 1
       uint64_t rpw = 0;   // bit s = r_p of shot s (wave-uniform)
       if (p != kNone) {
         const uint32_t b = lane < S ? uint32_t(sR[(p >> 6) * 64 + lane] >> (p & 63)) & 1u : 0u;
         rpw = __ballot(b);
       }
-      if (tid == 0) { s_par = 0; s_y = 0; }
-      lds_barrier();   // everyone has column a and r_p before any write
+      uint32_t p_next = kNone;
+      uint64_t m_next = 0;
       if (p != kNone) {
         const uint32_t pn = p - n, wpn = pn >> 6, wp = p >> 6;
         const uint64_t bpn = 1ull << (pn & 63), bpb = 1ull << (p & 63);
@@ -221,6 +232,7 @@ __global__ void __launch_bounds__(TEAM) k_batch(const BatchDescDev *__restrict__
           sC1[wave * Wl + lane] = c1;
         }
         lds_barrier();
+        if (a + 1 < n) select(a + 1, p_next, m_next);
         // reduce counters per word (wave 0), then update the signs of all shots
         if (wave == 0) {
           uint64_t t0 = 0, t1 = 0;
@@ -287,6 +299,7 @@ __global__ void __launch_bounds__(TEAM) k_batch(const BatchDescDev *__restrict__
         if (par & 1u) atomicXor(&s_par, 1u);
         if (ycnt) atomicAdd(&s_y, ycnt);
         lds_barrier();
+        if (a + 1 < n) select(a + 1, p_next, m_next);   // measurement a changed nothing
         if (wave == 0) {
           // shuffles with the whole wave active (lane w holds mask word w)
           uint32_t rt = 0;
@@ -298,7 +311,10 @@ __global__ void __launch_bounds__(TEAM) k_batch(const BatchDescDev *__restrict__
         }
         if (wave == 0 && lane == 0 && (s_y & 1u)) atomicAdd(errors + 1, 1u);
       }
+      if (tid == 0) { s_par = 0; s_y = 0; }   // after this thread's (wave 0's) reads above
       lds_barrier();
+      p = p_next;
+      m = m_next;
     }
   }
 }
