@@ -198,15 +198,16 @@ __global__ void __launch_bounds__(TEAM) k_batch(const BatchDescDev *__restrict__
             const uint32_t xpj = uint32_t(sX[j * W + wp] >> (p & 63)) & 1u;
             const uint32_t zpj = uint32_t(sZ[j * W + wp] >> (p & 63)) & 1u;
             const uint64_t x = sX[j * W + wl], z = sZ[j * W + wl];
-            const uint64_t X1 = xpj ? ~0ull : 0ull, Z1 = zpj ? ~0ull : 0ull;
-            const uint64_t yc = X1 & Z1, xc = X1 & ~Z1, zc = ~X1 & Z1;
-            const uint64_t plus = ((yc & z & ~x) | (xc & z & x) | (zc & x & ~z)) & m;
-            const uint64_t minus = ((yc & x & ~z) | (xc & z & ~x) | (zc & x & z)) & m;
-            c1 ^= c0 & plus;
-            c0 ^= plus;
-            c1 ^= ~c0 & minus;
-            c0 ^= minus;
-            uint64_t nx = x ^ (X1 & m), nz = z ^ (Z1 & m);
+            const uint64_t X1 = mask_if<uint64_t>(xpj), Z1 = mask_if<uint64_t>(zpj);
+            // rows in M anticommuting with the pivot's Pauli on column j (X: z,
+            // Z: x, Y: x ^ z); g = +1 on them where (X: x; Z: ~z; Y: z), else
+            // -1, and adding +-1 to the 2-bit counter flips c1 where c0 equals
+            // that condition: c1 ^= anti & ~(c0 ^ sel), c0 ^= anti
+            const uint64_t anti = bop3<LUT_AND_XOR>(Z1, x, X1 & z) & m;
+            const uint64_t sel = (Z1 & ~(z ^ X1)) | (~Z1 & x);
+            c1 ^= bop3<LUT_AND_XNOR>(anti, c0, sel);
+            c0 ^= anti;
+            uint64_t nx = bop3<LUT_AND_XOR>(X1, m, x), nz = bop3<LUT_AND_XOR>(Z1, m, z);
             if (wl == wpn) {
               nx = xpj ? (nx | bpn) : (nx & ~bpn);
               nz = zpj ? (nz | bpn) : (nz & ~bpn);

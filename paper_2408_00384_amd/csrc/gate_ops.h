@@ -105,6 +105,7 @@ constexpr uint32_t LUT_AND3 = 0x80;        // a & b & c
 constexpr uint32_t LUT_AND_XOR = 0x6A;     // (a & b) ^ c
 constexpr uint32_t LUT_ANDN_XOR = 0x9A;    // (a & ~b) ^ c
 constexpr uint32_t LUT_AND_ANDN = 0x40;    // a & b & ~c
+constexpr uint32_t LUT_AND_XNOR = 0x90;    // a & ~(b ^ c)
 
 // Apply a single-qubit code to x / z words of rows (32, 64 or 128 rows at once).
 template <typename T>
