@@ -165,6 +165,9 @@ __global__ void __launch_bounds__(kThreads) k_meas_xz(TabDev t, PersistArgs a) {
     s_acc[0] = 0;
     s_acc[1] = 0;
     s_p[0] = kNone;
+    s_p[1] = kNone;
+    s_par = 0;
+    s_y = 0;
   }
   for (uint32_t w = tid; w < W; w += kThreads) {
     s_s0[w] = 0;
@@ -248,12 +251,13 @@ __global__ void __launch_bounds__(kThreads) k_meas_xz(TabDev t, PersistArgs a) {
       s_zpm[b][wave] = zm;
       atomicAdd(&s_acc[b], uint32_t(2 * __popc(xm | zm) + __popc(xm) + __popc(zm)));
     }
-    if (tid == 0) {
-      s_p[b ^ 1u] = kNone;
-      s_par = 0;
-      s_y = 0;
-    }
-    lds_barrier();
+    // The pivot-row bits of this wave's columns are read by this wave only, so
+    // phase b needs no workgroup barrier: the values other waves meet on are
+    // reset by thread 0 once their last reader is past a barrier (s_p[b] and
+    // s_par / s_y in phase c, s_acc double-buffered).
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
     // ---- phase b: sweep m, then publish a_{m+2}
     if (p != kNone) {
       const uint32_t xm = __builtin_amdgcn_readfirstlane(s_xpm[b][wave]);
@@ -451,8 +455,13 @@ __global__ void __launch_bounds__(kThreads) k_meas_xz(TabDev t, PersistArgs a) {
     } else if (tid == 0) {
       if (s_par) atomicXor(t.detpar + m, 1u);
       if (s_y) atomicAdd(t.detY + m, s_y);
+      s_par = 0;   // their last reader: cleared for the next deterministic measurement
+      s_y = 0;
       ++n_det;
     }
+    // every thread read s_p[b] (this measurement's pivot) before the barrier
+    // that ended phase b: it becomes the target of measurement m + 2's pivot
+    if (tid == 0) s_p[b] = kNone;
     if (m == a.abort_at && tid == 0) {   // injected: every workgroup stops at the same iteration
       atomicOr(t.abort_flag, 1u);
       s_abort = 1;
