@@ -67,13 +67,17 @@ __global__ void __launch_bounds__(TEAM) k_batch(const BatchDescDev *__restrict__
     for (uint32_t i = tid; i < W * 64; i += TEAM) sR[i] = 0;
     if (tid < MAXW) sP[tid] = 0;
     __syncthreads();
-    // ---- gate layers: thread <-> (op, word); its word is fixed, so the sign
-    // flips it produces accumulate in one register for the whole circuit
+    // ---- gate layers: thread <-> (op, K consecutive row words from w0).  From
+    // W = 5 on K = 2, the two words as one 128-row value: the op's decode and
+    // its single-qubit masks serve both and a layer needs half the passes;
+    // below that the threads per op are few already and K = 1.  A thread's
+    // words are fixed, so the sign flips it produces accumulate in registers
+    // for the whole circuit.  With an odd W the last thread of K = 2 has one
+    // word: its second is never read or written (it would be the next
+    // column's first).
     {
       const uint64_t *cops = ops + d.ops_off;
       const uint32_t *coffs = offs + d.offs_off;
-      const uint32_t w = tid % Wl, k0 = tid / Wl, kst = TEAM / Wl;
-      uint64_t racc = 0;
       // The next layer's bounds and this thread's first two ops of it are
       // loaded one layer ahead, so a layer does not start with a chain of
       // dependent global loads (reads stay inside the circuit's ops).  Layers
@@ -89,45 +93,77 @@ __global__ void __launch_bounds__(TEAM) k_batch(const BatchDescDev *__restrict__
         const uint64_t v = *(k < end ? cops + k : safe);
         return k < end ? v : 0ull;
       };
-      uint32_t a0 = coffs[0], a1 = depth ? coffs[1] : a0;
-      uint64_t f0 = fetch(a0 + k0), f1 = fetch(a0 + k0 + kst);
-      for (uint32_t l = 0; l < depth; ++l) {
-        const uint32_t b0 = a1, b1 = l + 2 <= depth ? coffs[l + 2] : a1;
-        const uint64_t g0 = fetch(b0 + k0), g1 = fetch(b0 + k0 + kst);
-        // one op on this thread's row word (ops of a layer act on distinct qubits)
+      auto gates = [&](auto zero) {
+        using T = decltype(zero);
+        constexpr uint32_t K = sizeof(T) / 8;
+        const uint32_t Wt = (W + K - 1) / K;                                        // threads per op
+        const uint32_t Wq = Wt <= 1 ? 1u : (1u << (32 - __builtin_clz(Wt - 1)));   // pow2 >= Wt
+        const uint32_t t = tid % Wq, k0 = tid / Wq, kst = TEAM / Wq;
+        const uint32_t w0 = K * t;
+        const bool has0 = w0 < W, has1 = K == 2 && w0 + 1 < W;
+        T racc = zero;
+        auto load = [&](const uint64_t *col) -> T {
+          if constexpr (K == 2) return T{col[w0], has1 ? col[w0 + 1] : 0ull};
+          else return col[w0];
+        };
+        auto store = [&](uint64_t *col, T v) {
+          if constexpr (K == 2) {
+            col[w0] = v.lo;
+            if (has1) col[w0 + 1] = v.hi;
+          } else {
+            col[w0] = v;
+          }
+        };
+        // one op on this thread's row words (ops of a layer act on distinct qubits)
         auto apply = [&](uint64_t op) {
           if (!op_valid(op, n)) {   // malformed op
             atomicAdd(errors, 1u);
             return;
           }
           const uint32_t a = op_a(op), pair = op_pair(op);
-          uint64_t xa = sX[a * W + w], za = sZ[a * W + w];
+          T xa = load(sX + a * W), za = load(sZ + a * W);
           if (op_ca(op)) sq_apply(op_ca(op), xa, za, racc);
           if (pair != PAIR_NONE) {
             const uint32_t b = op_b(op);
-            uint64_t xb = sX[b * W + w], zb = sZ[b * W + w];
+            T xb = load(sX + b * W), zb = load(sZ + b * W);
             if (op_cb(op)) sq_apply(op_cb(op), xb, zb, racc);
             pair_apply(pair, xa, za, xb, zb, racc);
-            sX[b * W + w] = xb;
-            sZ[b * W + w] = zb;
+            store(sX + b * W, xb);
+            store(sZ + b * W, zb);
           }
-          sX[a * W + w] = xa;
-          sZ[a * W + w] = za;
+          store(sX + a * W, xa);
+          store(sZ + a * W, za);
         };
-        if (w < W) {
-          // the two prefetched ops in straight-line code, so their wait does
-          // not cover the loads just issued for the next layer
-          if (a0 + k0 < a1) apply(f0);
-          if (a0 + k0 + kst < a1) apply(f1);
-          for (uint32_t k = a0 + k0 + 2 * kst; k < a1; k += kst) apply(cops[k]);
+        uint32_t a0 = coffs[0], a1 = depth ? coffs[1] : a0;
+        uint64_t f0 = fetch(a0 + k0), f1 = fetch(a0 + k0 + kst);
+        for (uint32_t l = 0; l < depth; ++l) {
+          const uint32_t b0 = a1, b1 = l + 2 <= depth ? coffs[l + 2] : a1;
+          const uint64_t g0 = fetch(b0 + k0), g1 = fetch(b0 + k0 + kst);
+          if (has0) {
+            // the two prefetched ops in straight-line code, so their wait does
+            // not cover the loads just issued for the next layer
+            if (a0 + k0 < a1) apply(f0);
+            if (a0 + k0 + kst < a1) apply(f1);
+            for (uint32_t k = a0 + k0 + 2 * kst; k < a1; k += kst) apply(cops[k]);
+          }
+          lds_barrier();
+          a0 = b0;
+          a1 = b1;
+          f0 = g0;
+          f1 = g1;
         }
-        lds_barrier();
-        a0 = b0;
-        a1 = b1;
-        f0 = g0;
-        f1 = g1;
-      }
-      if (w < W && racc) atomicXor(reinterpret_cast<unsigned long long *>(&sP[w]), (unsigned long long)racc);
+        auto flush = [&](uint32_t w, uint64_t v) {
+          if (v) atomicXor(reinterpret_cast<unsigned long long *>(&sP[w]), (unsigned long long)v);
+        };
+        if constexpr (K == 2) {
+          if (has0) flush(w0, racc.lo);
+          if (has1) flush(w0 + 1, racc.hi);
+        } else {
+          if (has0) flush(w0, racc);
+        }
+      };
+      if (W >= 5) gates(U128{0, 0});
+      else gates(uint64_t(0));
       __syncthreads();
       for (uint32_t i = tid; i < W * 64; i += TEAM) sR[i] ^= sP[i / 64];
       __syncthreads();
