@@ -133,6 +133,8 @@ def bench_batch(P, torch, np, count=4096, plain_sample=48, reps=5):
         outs = plan.outcomes()
     status = plan.status()
     lds_bytes = batch_lds_bytes(plan, np)
+    lds_meas = P.cliff_calibrate(ctx.handle, P.CAL_LDS) / 1e9
+    valu_meas = P.cliff_calibrate(ctx.handle, P.CAL_VALU)
     # plain path on an evenly spaced sample
     idx = np.linspace(0, count - 1, plain_sample).astype(int)
     pctx = P.Context(0)
@@ -163,10 +165,42 @@ def bench_batch(P, torch, np, count=4096, plain_sample=48, reps=5):
         "teams": {str(k): v for k, v in load_tuning().items()},
         "lds": {"alg_bytes_per_batch": lds_bytes, "achieved_gbs": lds_bytes / (ev_ms * 1e-3) / 1e9,
                 "peak_gbs": LDS_PEAK_GBS, "frac": lds_bytes / (ev_ms * 1e-3) / 1e9 / LDS_PEAK_GBS,
+                "measured_peak_gbs": lds_meas,
+                "frac_of_measured": lds_bytes / (ev_ms * 1e-3) / 1e9 / lds_meas,
                 "note": "tableaux live in LDS; algorithmic LDS bytes of the gate updates and "
-                        "measurement sweeps over the whole batch time"},
+                        "measurement sweeps over the whole batch time; measured peak: cliff_calibrate "
+                        "(conflict-free 16-byte reads on every CU)"},
+        "valu_measured_lane_ops_per_s": valu_meas,
+        "cpu_baseline": batch_cpu_baseline(circs, np),
         "generate_s": gen_s,
     }
+
+
+def _oracle_circuit(c):
+    import oracle
+    t = oracle.Tableau(c.n).apply_circuit_gates(c)
+    for s in range(c.shots):
+        t.clone().measure_list(c.qubits, seed=c.seed, circuit=c.circuit_id, shot=s)
+
+
+def batch_cpu_baseline(circs, np, sample: int = 512):
+    """The oracle on an evenly spaced sample of the batch, every shot of every
+    circuit (gates once, each shot from the post-gate tableau), one circuit per
+    thread on the host's cores (the oracle's C calls release the GIL)."""
+    import concurrent.futures as cf
+    import oracle
+    oracle.build(force=False)
+    idx = np.linspace(0, len(circs) - 1, min(sample, len(circs))).astype(int)
+    workers = max(1, min(16, os.cpu_count() or 1))
+    t0 = time.perf_counter()
+    with cf.ThreadPoolExecutor(workers) as ex:
+        list(ex.map(lambda i: _oracle_circuit(circs[i]), idx))
+    wall = time.perf_counter() - t0
+    ns = np.array([c.n for c in circs])
+    return {"value": len(idx) / wall, "unit": "circuits/s", "cores": workers, "kind": "oracle",
+            "sample": "%d evenly spaced circuits of the batch (mean n %.0f vs %.0f), all shots, one circuit "
+                      "per thread on %d threads" % (len(idx), ns[idx].mean(), ns.mean(), workers),
+            "seconds": wall, "host": _host_cpu()}
 
 
 def batch_lds_bytes(plan, np):

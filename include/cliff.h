@@ -82,6 +82,16 @@ int cliff_sync(cliff_ctx *ctx);
 /* Number of compute units of the context's device. */
 int cliff_ctx_num_cus(const cliff_ctx *ctx);
 
+/* Roofline calibration (a measurement aid, not part of the simulation):
+ * runs a kernel on every CU of the context's device, on its stream, and writes
+ * the rate it reached to *out.  CLIFF_CAL_LDS: bytes per second of
+ * conflict-free 16-byte LDS reads; CLIFF_CAL_VALU: 32-bit bitwise VALU lane
+ * operations per second (v_xor_b32, independent chains).  Allocates and frees
+ * 4 KB of device memory; synchronizes.  CLIFF_EINVAL for another kind. */
+#define CLIFF_CAL_LDS 0
+#define CLIFF_CAL_VALU 1
+int cliff_calibrate(cliff_ctx *ctx, int kind, double *out);
+
 /* Gate-stream strategy.  AUTO: one launch for all layers when 8n bytes (32
  * rows of every column) fit in LDS, else one launch per layer.  PER_LAYER:
  * always one launch per layer.  FUSED: always one launch (EINVAL if n is too

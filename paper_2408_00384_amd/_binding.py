@@ -61,6 +61,7 @@ _SIGS = {
     "cliff_ctx_destroy": (ctypes.c_int, [_vp]),
     "cliff_sync": (ctypes.c_int, [_vp]),
     "cliff_ctx_num_cus": (ctypes.c_int, [_vp]),
+    "cliff_calibrate": (ctypes.c_int, [_vp, ctypes.c_int, ctypes.POINTER(ctypes.c_double)]),
     "cliff_ctx_set_gate_mode": (ctypes.c_int, [_vp, ctypes.c_int]),
     "cliff_ctx_set_measure_mode": (ctypes.c_int, [_vp, ctypes.c_int]),
     "cliff_ctx_inject_abort": (ctypes.c_int, [_vp, _u64]),
@@ -156,6 +157,16 @@ def cliff_ctx_num_cus(ctx) -> int:
 
 GATES_AUTO, GATES_PER_LAYER, GATES_FUSED = 0, 1, 2
 MEASURE_AUTO, MEASURE_STEP, MEASURE_PERSISTENT = 0, 1, 2
+
+
+CAL_LDS, CAL_VALU = 0, 1
+
+
+def cliff_calibrate(ctx, kind: int) -> float:
+    """Measured LDS read bytes/s (CAL_LDS) or 32-bit VALU lane ops/s (CAL_VALU)."""
+    v = ctypes.c_double()
+    _check(_lib.cliff_calibrate(ctx, kind, ctypes.byref(v)), "cliff_calibrate")
+    return float(v.value)
 
 
 def cliff_ctx_set_measure_mode(ctx, mode: int):
@@ -450,4 +461,4 @@ __all__ = [n for n in list(globals()) if n.startswith("cliff_")] + [
     "CLIFF_EINTERNAL", "OP_H", "OP_S", "OP_CNOT", "OP_SDG", "OP_X", "OP_Y", "OP_Z", "OP_CZ",
     "OP_SWAP", "BASIS_Z", "BASIS_X", "BASIS_Y", "CliffError", "LIB_PATH", "exported_symbols",
     "PROF_KINDS", "BATCH_DESC_DTYPE", "BATCH_CONFIGS", "GATES_AUTO", "GATES_PER_LAYER",
-    "GATES_FUSED", "MEASURE_AUTO", "MEASURE_STEP", "MEASURE_PERSISTENT"]
+    "GATES_FUSED", "MEASURE_AUTO", "MEASURE_STEP", "MEASURE_PERSISTENT", "CAL_LDS", "CAL_VALU"]

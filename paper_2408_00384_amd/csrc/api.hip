@@ -210,6 +210,34 @@ int cliff_sync(cliff_ctx *c) {
 
 int cliff_ctx_num_cus(const cliff_ctx *c) { return c ? c->num_cus : 0; }
 
+int cliff_calibrate(cliff_ctx *c, int kind, double *out) {
+  if (!c || !out) return fail(CLIFF_EINVAL, "cliff_calibrate: NULL argument");
+  if (kind != CLIFF_CAL_LDS && kind != CLIFF_CAL_VALU)
+    return fail(CLIFF_EINVAL, "cliff_calibrate: kind %d (0: LDS bytes/s, 1: VALU lane ops/s)", kind);
+  DeviceGuard g(c->device);
+  uint32_t *sink = nullptr;
+  hipEvent_t ev[2] = {nullptr, nullptr};
+  const uint32_t iters = kind == CLIFF_CAL_LDS ? 4096 : 8192;
+  double work = 0;
+  float ms = 0;
+  hipError_t e = hipMalloc(&sink, 1024 * sizeof(uint32_t));
+  if (e == hipSuccess) e = hipEventCreate(&ev[0]);
+  if (e == hipSuccess) e = hipEventCreate(&ev[1]);
+  if (e == hipSuccess) e = launch_calibrate(kind, c->num_cus, iters, sink, c->stream, &work);   // warm-up
+  if (e == hipSuccess) e = hipEventRecord(ev[0], c->stream);
+  if (e == hipSuccess) e = launch_calibrate(kind, c->num_cus, iters, sink, c->stream, &work);
+  if (e == hipSuccess) e = hipEventRecord(ev[1], c->stream);
+  if (e == hipSuccess) e = hipEventSynchronize(ev[1]);
+  if (e == hipSuccess) e = hipEventElapsedTime(&ms, ev[0], ev[1]);
+  for (hipEvent_t x : ev)
+    if (x) (void)hipEventDestroy(x);
+  if (sink) (void)hipFree(sink);
+  if (e != hipSuccess) return fail(CLIFF_EDEVICE, "cliff_calibrate: %s", hipGetErrorString(e));
+  if (ms <= 0) return fail(CLIFF_EINTERNAL, "cliff_calibrate: no elapsed time");
+  *out = work / (double(ms) * 1e-3);
+  return CLIFF_OK;
+}
+
 int cliff_ctx_inject_abort(cliff_ctx *c, uint64_t at) {
   if (!c) return fail(CLIFF_EINVAL, "cliff_ctx_inject_abort: NULL context");
   c->inject_abort_at = at;
