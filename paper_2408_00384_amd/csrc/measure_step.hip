@@ -165,7 +165,7 @@ __device__ __forceinline__ void sweep_uniform(const TabDev &t, const StepArgs &s
                                               const uint64_t *s_xp, const uint64_t *s_zp, uint64_t *s_c0,
                                               uint64_t *s_c1, uint32_t wave, uint32_t nsw, uint32_t lane,
                                               uint32_t G, uint32_t g) {
-  constexpr uint32_t U = 8;   // columns in flight per lane
+  constexpr uint32_t U = 10;   // columns in flight per lane (128 VGPRs at 1,024 threads; 12 spills)
   constexpr uint32_t Wl = 64 * K;
   const uint32_t n = t.n, W = t.W;
   const uint32_t T = (W + Wl - 1) / Wl;
