@@ -36,7 +36,7 @@ LDS_PEAK_GBS = 256 * 128 * 2.4   # 256 CUs x 128 B/clk x 2.4 GHz = 78,643 GB/s
 TRAFFIC = {
     "k_meas_xz": {
         "sources": ("paper_2408_00384_amd/csrc/measure_persist.hip", "paper_2408_00384_amd/csrc/internal.h"),
-        "sha256": "ddcec300e531bae022e3d1db53255983af46f4f73efb1f4c87eae57f4b8557a8",
+        "sha256": "e28c0bfe9ea07dbadc8e6931e92cd6d18e49da0702fcd6fef24c0e23ea70e526",
         "bytes_per_launch": 1.121e+09,
         "summary": "profiles/k_meas_xz_plain_n10000_measure_all.md",
     },
