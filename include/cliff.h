@@ -285,6 +285,12 @@ int cliff_sample(cliff_tab *tab, cliff_tab *work, const uint32_t *qubits, size_t
 int cliff_tab_export(cliff_tab *tab, uint8_t *x, uint8_t *z, uint8_t *r);
 int cliff_tab_import(cliff_tab *tab, const uint8_t *x, const uint8_t *z, const uint8_t *r);
 
+/* Rows rows[0..k) (each < 2n, any order, repeats allowed) in the same
+ * byte-per-bit form: x, z as uint8 [k][n], r as uint8 [shots][k] (nullable).
+ * Copies only the 64-row words holding them, so rows of tableaux too large to
+ * export whole can be checked.  Synchronizes; CLIFF_EINVAL for a row >= 2n. */
+int cliff_tab_export_rows(cliff_tab *tab, const uint32_t *rows, size_t k, uint8_t *x, uint8_t *z, uint8_t *r);
+
 /* Device-side consistency counters since bind: number of rowsums whose phase
  * came out odd on a row that should commute with the pivot (must stay 0). */
 int cliff_tab_anomalies(cliff_tab *tab, uint64_t *count);

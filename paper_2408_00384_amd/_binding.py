@@ -88,6 +88,7 @@ _SIGS = {
     "cliff_measure_async": (ctypes.c_int, [_vp, _u32p, _sz, _u64, _u64, _u64, _u64]),
     "cliff_tab_read_outcomes": (ctypes.c_int, [_vp, _sz, _u8p, _u8p]),
     "cliff_tab_export": (ctypes.c_int, [_vp, _u8p, _u8p, _u8p]),
+    "cliff_tab_export_rows": (ctypes.c_int, [_vp, _u32p, _sz, _u8p, _u8p, _u8p]),
     "cliff_tab_import": (ctypes.c_int, [_vp, _u8p, _u8p, _u8p]),
     "cliff_tab_anomalies": (ctypes.c_int, [_vp, _u64p]),
     "cliff_tab_counters": (ctypes.c_int, [_vp, _u64p]),
@@ -370,6 +371,19 @@ def cliff_tab_export(tab):
     z = np.zeros((2 * n, n), np.uint8)
     r = np.zeros((shots, 2 * n), np.uint8)
     _check(_lib.cliff_tab_export(tab, _ptr(x, _u8p), _ptr(z, _u8p), _ptr(r, _u8p)), "cliff_tab_export")
+    return x, z, r
+
+
+def cliff_tab_export_rows(tab, rows):
+    """Rows `rows` only: (x uint8[k, n], z uint8[k, n], r uint8[shots, k])."""
+    n, shots = cliff_tab_info(tab)
+    q = _arr(rows, np.uint32)
+    k = len(q)
+    x = np.zeros((k, n), np.uint8)
+    z = np.zeros((k, n), np.uint8)
+    r = np.zeros((shots, k), np.uint8)
+    _check(_lib.cliff_tab_export_rows(tab, _ptr(q, _u32p), k, _ptr(x, _u8p), _ptr(z, _u8p), _ptr(r, _u8p)),
+           "cliff_tab_export_rows")
     return x, z, r
 
 

@@ -9,6 +9,7 @@
 #include <algorithm>
 #include <string>
 #include <vector>
+#include <unordered_map>
 
 #include "../../include/cliff.h"
 #include "internal.h"
@@ -1083,6 +1084,67 @@ extern "C" int cliff_tab_export(cliff_tab *t, uint8_t *x, uint8_t *z, uint8_t *r
   for (uint32_t s = 0; s < d.S; ++s)
     for (uint32_t i = 0; i < rows; ++i)
       r[size_t(s) * rows + i] = uint8_t(((R[size_t(i >> 6) * d.S + s] ^ P[i >> 6]) >> (i & 63)) & 1u);
+  return CLIFF_OK;
+}
+
+namespace cliff {
+// defined beside the other whole-tableau kernels in gates.hip
+hipError_t launch_gather_words(const TabDev &t, const uint32_t *words, uint32_t nw, uint64_t *ox, uint64_t *oz,
+                               hipStream_t st);
+}  // namespace cliff
+
+extern "C" int cliff_tab_export_rows(cliff_tab *t, const uint32_t *rows, size_t k, uint8_t *x, uint8_t *z,
+                                     uint8_t *r) {
+  if (!t) return fail(CLIFF_EINVAL, "cliff_tab_export_rows: NULL tableau");
+  if (k == 0) return CLIFF_OK;
+  if (!rows || !x || !z) return fail(CLIFF_EINVAL, "cliff_tab_export_rows: NULL argument");
+  const Dims &d = t->d;
+  const uint32_t n = d.n, S = d.S;
+  // the 64-row words holding the requested rows, each fetched once
+  std::vector<uint32_t> words, slot(k);
+  std::unordered_map<uint32_t, uint32_t> index;
+  for (size_t i = 0; i < k; ++i) {
+    if (rows[i] >= 2 * n) return fail(CLIFF_EINVAL, "cliff_tab_export_rows: row %u >= 2n = %u", rows[i], 2 * n);
+    const uint32_t w = rows[i] >> 6;
+    auto it = index.find(w);
+    if (it == index.end()) it = index.emplace(w, uint32_t(words.size())).first, words.push_back(w);
+    slot[i] = it->second;
+  }
+  DeviceGuard g(t->ctx->device);
+  hipStream_t st = t->ctx->stream;
+  const size_t nw = words.size();
+  std::vector<uint64_t> cx(nw * n), cz(nw * n), Rw(r ? nw * S : 0), Pw(r ? nw : 0);
+  // word w of every column (n words, a column stride of Wp words apart),
+  // gathered on the device into [word][column] and copied back in one piece
+  const size_t wbytes = align256(nw * 4), cbytes = nw * n * 8;
+  char *buf = nullptr;
+  HIP_TRY(hipMalloc(&buf, wbytes + 2 * cbytes));
+  uint32_t *dw = reinterpret_cast<uint32_t *>(buf);
+  uint64_t *dx = reinterpret_cast<uint64_t *>(buf + wbytes), *dz = dx + nw * n;
+  hipError_t e = hipMemcpyAsync(dw, words.data(), nw * 4, hipMemcpyHostToDevice, st);
+  if (e == hipSuccess) e = launch_gather_words(t->dev, dw, uint32_t(nw), dx, dz, st);
+  if (e == hipSuccess) e = hipMemcpyAsync(cx.data(), dx, cbytes, hipMemcpyDeviceToHost, st);
+  if (e == hipSuccess) e = hipMemcpyAsync(cz.data(), dz, cbytes, hipMemcpyDeviceToHost, st);
+  for (size_t q = 0; r && q < nw && e == hipSuccess; ++q) {
+    const uint32_t w = words[q];
+    e = hipMemcpyAsync(Rw.data() + q * S, t->dev.R + size_t(w) * S, size_t(S) * 8, hipMemcpyDeviceToHost, st);
+    if (e == hipSuccess) e = hipMemcpyAsync(Pw.data() + q, t->dev.P + w, 8, hipMemcpyDeviceToHost, st);
+  }
+  const hipError_t es = hipStreamSynchronize(st);
+  (void)hipFree(buf);
+  HIP_TRY(e);
+  HIP_TRY(es);
+  for (size_t i = 0; i < k; ++i) {
+    const uint32_t sh = rows[i] & 63;
+    const uint64_t *px = cx.data() + size_t(slot[i]) * n, *pz = cz.data() + size_t(slot[i]) * n;
+    for (uint32_t j = 0; j < n; ++j) {
+      x[i * n + j] = uint8_t((px[j] >> sh) & 1u);
+      z[i * n + j] = uint8_t((pz[j] >> sh) & 1u);
+    }
+    if (r)
+      for (uint32_t s = 0; s < S; ++s)
+        r[size_t(s) * k + i] = uint8_t(((Rw[size_t(slot[i]) * S + s] ^ Pw[slot[i]]) >> sh) & 1u);
+  }
   return CLIFF_OK;
 }
 

@@ -226,6 +226,20 @@ __global__ void __launch_bounds__(256) k_copy_tab(TabDev dst, TabDev src) {
   if (blockIdx.x == 0 && threadIdx.x == 0) *dst.abort_flag = 0;
 }
 
+// Word words[q] of every column of X and Z, gathered for a host readout of a
+// few rows: ox[q * n + j] = X[j * Wp + words[q]] (every words[q] < W).
+__global__ void __launch_bounds__(256) k_gather_words(TabDev t, const uint32_t *__restrict__ words, uint32_t nw,
+                                                      uint64_t *__restrict__ ox, uint64_t *__restrict__ oz) {
+  const size_t total = size_t(nw) * t.n;
+  const size_t stride = size_t(gridDim.x) * blockDim.x;
+  for (size_t i = size_t(blockIdx.x) * blockDim.x + threadIdx.x; i < total; i += stride) {
+    const size_t q = i / t.n, j = i % t.n;
+    const size_t at = j * t.Wp + words[q];
+    ox[i] = t.X[at];
+    oz[i] = t.Z[at];
+  }
+}
+
 // Outcomes of the last measurement pass (staging: out[i * S + s], kind[i])
 // into a caller's record: rec[s * ld + col0 + i], random flags rnd[col0 + i].
 __global__ void __launch_bounds__(256) k_record(TabDev t, uint32_t cnt, uint8_t *__restrict__ rec, size_t ld,
@@ -359,6 +373,13 @@ hipError_t launch_cond_pauli(const TabDev &t, const uint64_t *ops, uint32_t k, c
                              hipStream_t st) {
   if (k == 0) return hipSuccess;
   k_cond_pauli<<<grid_for(size_t(t.W) * t.S, 256), 256, 0, st>>>(t, ops, k, rec, ld);
+  return hipGetLastError();
+}
+
+hipError_t launch_gather_words(const TabDev &t, const uint32_t *words, uint32_t nw, uint64_t *ox, uint64_t *oz,
+                               hipStream_t st) {
+  if (nw == 0) return hipSuccess;
+  k_gather_words<<<grid_for(size_t(nw) * t.n, 256), 256, 0, st>>>(t, words, nw, ox, oz);
   return hipGetLastError();
 }
 

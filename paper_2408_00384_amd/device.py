@@ -79,6 +79,9 @@ class DeviceTableau:
     def export(self):
         return B.cliff_tab_export(self.handle)
 
+    def export_rows(self, rows):
+        return B.cliff_tab_export_rows(self.handle, rows)
+
     def import_(self, x, z, r):
         B.cliff_tab_import(self.handle, x, z, r)
         return self

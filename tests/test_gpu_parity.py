@@ -373,6 +373,44 @@ def test_persistent_equals_step_measure_all(ctx, n, shots):
     assert a[3] == 0 and b[3] == 0
 
 
+def _check_symplectic_sample(t, n, seed, k=128, include=()):
+    """Sampled rows of a tableau too large to export whole: destabilizer i
+    and stabilizer n + i anticommute and every other pair of rows commutes
+    (x . z' + z . x' is odd exactly for the pairs (i, n + i)), as in every
+    valid tableau at any n; a wrong row update breaks it for most samples."""
+    rng = np.random.default_rng(seed)
+    extra = np.asarray(include, np.int64)
+    pool = np.setdiff1d(np.arange(n), extra)
+    base = np.concatenate([extra, rng.choice(pool, size=k // 2 - len(extra), replace=False)])
+    rows = np.concatenate([base, base + n]).astype(np.uint32)
+    x, z, _ = t.export_rows(rows)
+    xf, zf = x.astype(np.float32), z.astype(np.float32)   # sums <= n < 2^24: exact
+    g = np.mod(xf @ zf.T + zf @ xf.T, 2).astype(np.uint8)
+    h = len(base)
+    want = np.zeros((2 * h, 2 * h), np.uint8)
+    want[np.arange(h), np.arange(h) + h] = 1
+    want[np.arange(h) + h, np.arange(h)] = 1
+    assert np.array_equal(g, want), "symplectic form of sampled rows"
+
+
+def test_export_rows_matches_export(ctx):
+    """Row subsets (any order, repeats) equal the rows of the full export,
+    signs of every shot included; rows >= 2n are rejected."""
+    from paper_2408_00384_amd import CLIFF_EINVAL, CliffError
+    n = 130
+    c = layered_circuit(n, 9, 3, gen_seed=[50])
+    t = _tab(ctx, n, 3).apply_circuit_gates(c)
+    t.measure(np.arange(0, n, 3), seed=c.seed)
+    x, z, r = t.export()
+    rows = np.array([0, 5, 64, 63, 2 * n - 1, n, 5, 200, 129], np.uint32)
+    xs, zs, rs = t.export_rows(rows)
+    assert np.array_equal(xs, x[rows]) and np.array_equal(zs, z[rows]) and np.array_equal(rs, r[:, rows])
+    _check_symplectic_sample(t, n, seed=3, k=64)
+    with pytest.raises(CliffError) as e:
+        t.export_rows(np.array([2 * n], np.uint32))
+    assert e.value.code == CLIFF_EINVAL
+
+
 def _golden_bits(hexstr, n):
     return np.unpackbits(np.frombuffer(bytes.fromhex(hexstr), np.uint8), bitorder="little")[:n]
 
@@ -485,6 +523,10 @@ def test_xlarge_per_measurement_path_vs_stored_oracle(ctx):
     out, rnd = t.measure(np.arange(k, dtype=np.uint32), seed=c.seed, circuit=c.circuit_id)
     assert np.array_equal(out[0], _golden_bits(rec["outcomes"], k))
     assert np.array_equal(rnd, _golden_bits(rec["random"], k))
+    # on to 256 measured qubits (the benchmark's count), then the tableau's
+    # symplectic form on sampled rows, the measured qubits' rows among them
+    t.measure(np.arange(k, 256, dtype=np.uint32), seed=c.seed, circuit=c.circuit_id, m0=k)
+    _check_symplectic_sample(t, c.n, seed=4, k=192, include=np.arange(0, 256, 8))
     assert t.anomalies() == 0 and rec["anomalies"] == 0
     t.close()
 
@@ -506,6 +548,7 @@ def test_step_whole_tiles_product_state(ctx):
         out, rnd = t.measure(q, seed=9, circuit=7)
         again, rnd2 = t.measure(q, seed=9, circuit=7, m0=k)
         assert t.anomalies() == 0
+        _check_symplectic_sample(t, n, seed=5, k=160, include=np.arange(0, k, 2))
         t.close()
     finally:
         cliff_ctx_set_measure_mode(ctx.handle, MEASURE_AUTO)
