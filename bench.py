@@ -203,6 +203,54 @@ def batch_cpu_baseline(circs, np, sample: int = 512):
             "seconds": wall, "host": _host_cpu()}
 
 
+def _oracle_request_seconds(c, gate_s, meas_s):
+    """One thread's oracle time for one serving request, from a bounded run:
+    gate layers in order until gate_s is spent, the rest scaled by layer count
+    (a layer costs the same in any state: every gate sweeps all 2n rows, one
+    byte per bit); then measurements of shot 0 until meas_s is spent, scaled
+    to all n measurements of every shot (the oracle runs shots one after
+    another from the post-gate tableau).  Returns (seconds, layers, measured)."""
+    import oracle
+    t = oracle.Tableau(c.n)
+    depth = c.h.shape[0]
+    t0 = time.perf_counter()
+    done = 0
+    while done < depth and time.perf_counter() - t0 < gate_s:
+        l1 = min(depth, done + 4)
+        t.apply_layers(c.h[done:l1], c.s[done:l1], c.ctrl[done:l1], c.tgt[done:l1])
+        done = l1
+    gates = (time.perf_counter() - t0) * depth / done
+    t1 = time.perf_counter()
+    k = 0
+    while k < len(c.qubits) and time.perf_counter() - t1 < meas_s:
+        t.measure(int(c.qubits[k]), seed=c.seed, circuit=c.circuit_id, shot=0, m=k)
+        k += 1
+    meas = (time.perf_counter() - t1) / max(1, k) * len(c.qubits) * c.shots
+    return gates + meas, done, k
+
+
+def serving_cpu_baseline(circs, np, gate_s: float = 1.0, meas_s: float = 1.0):
+    """The oracle's rate on the serving requests with one request per thread
+    on the host's cores: every request's single-thread time from a bounded run
+    (`_oracle_request_seconds`), summed and spread evenly over the threads."""
+    import concurrent.futures as cf
+    import oracle
+    oracle.build(force=False)
+    workers = max(1, min(16, os.cpu_count() or 1))
+    t0 = time.perf_counter()
+    with cf.ThreadPoolExecutor(workers) as ex:
+        res = list(ex.map(lambda c: _oracle_request_seconds(c, gate_s, meas_s), circs))
+    wall = time.perf_counter() - t0
+    secs = np.array([r[0] for r in res])
+    full = sum(1 for c, r in zip(circs, res) if r[1] == c.h.shape[0] and r[2] == len(c.qubits))
+    return {"value": float(len(circs) / (secs.sum() / workers)), "unit": "circuits/s", "cores": workers, "kind": "oracle",
+            "sample": "all %d requests, one per thread on %d threads; per request the gate layers of the first "
+                      "%.1f s and the shot-0 measurements of the next %.1f s, scaled to the full depth and to n "
+                      "measurements x shots (gates and shot 0 complete for %d requests); rate = requests / (summed seconds / threads)"
+                      % (len(circs), workers, gate_s, meas_s, full),
+            "oracle_seconds_total": float(secs.sum()), "seconds": wall, "host": _host_cpu()}
+
+
 def batch_lds_bytes(plan, np):
     """Algorithmic LDS bytes of a batch: per row word (64 rows, 8 bytes per
     plane) a two-qubit op reads and writes x and z of two columns (64 B), a
@@ -383,7 +431,7 @@ def bench_xlarge(P, torch, np, k=256, reps=2):
     }
 
 
-def bench_serving(P, np, count=96, seed=4, budget=64 << 30, lanes=8):
+def bench_serving(P, np, count=96, seed=4, budget=64 << 30, lanes=8, cpu=True):
     """Serving workload: n log-uniform in [16, 4096], depth 2n, shots in
     [1, 1024], admission by tableau bytes against a 64 GB budget.  First a
     closed-loop pass (every request admitted at once) gives the saturated
@@ -414,6 +462,7 @@ def bench_serving(P, np, count=96, seed=4, budget=64 << 30, lanes=8):
         "paths": st["paths"], "rejected": st["rejected"],
         "outcomes_same_as_closed_loop": same,
         "max_n": int(max(ns)), "total_shots": int(sum(shots)),
+        "cpu_baseline": serving_cpu_baseline(circs, np) if cpu else None,
     }
 
 
@@ -583,7 +632,7 @@ def main():
         result["batched"] = bench_batch(P, torch, np)
     if not args.no_serving:
         print("# serving ...", file=sys.stderr, flush=True)
-        result["serving"] = bench_serving(P, np)
+        result["serving"] = bench_serving(P, np, cpu=not args.no_cpu_baseline)
     if not args.no_clifford:
         print("# uniform random Cliffords, gates only ...", file=sys.stderr, flush=True)
         result["random_clifford"] = bench_clifford(P, torch, np)
