@@ -559,3 +559,38 @@ def test_step_whole_tiles_product_state(ctx):
         assert np.array_equal(rnd, kinds)
     assert rnd.sum() > 0 and rnd2.sum() == 0
     assert np.array_equal(again, out)
+
+
+@pytest.mark.parametrize("n,persistent", [(10_240, True), (10_241, False)])
+def test_register_resident_size_limit(ctx, n, persistent):
+    """n = 10,240 is the largest tableau the register-resident path holds (320
+    row words: every lane word and column slot of every workgroup full);
+    n = 10,241 is the first that AUTO sends to the per-measurement path.  At
+    both, against the oracle: outcomes and random flags of 32 measurements
+    (the first 16 qubits, 13 spread over the rest, the last, then qubits 0 and
+    n - 1 again, which are deterministic), then sampled tableau rows, the
+    measured qubits' among them, bit for bit."""
+    import paper_2408_00384_amd as P
+    c = layered_circuit(n, 6, 1, gen_seed=[61, n])
+    rng = np.random.default_rng(n)
+    q = np.concatenate([np.arange(16), np.sort(rng.choice(np.arange(16, n - 1), 13, replace=False)),
+                        [n - 1, 0, n - 1]]).astype(np.uint32)
+    t = _tab(ctx, n, 1).apply_circuit_gates(c)
+    P.cliff_ctx_profile(ctx.handle, True)
+    try:
+        out, rnd = t.measure(q, seed=c.seed, circuit=c.circuit_id)
+        launches = P.cliff_ctx_profile_read(ctx.handle, "sweep")[1]
+    finally:
+        P.cliff_ctx_profile(ctx.handle, False)
+    assert (launches < len(q)) == persistent, launches
+    o = oracle.Tableau(n).apply_circuit_gates(c)
+    want = [o.measure(int(a), seed=c.seed, circuit=c.circuit_id, shot=0, m=i) for i, a in enumerate(q)]
+    assert np.array_equal(out[0], [w[0] for w in want])
+    assert np.array_equal(rnd, [w[1] for w in want])
+    assert 0 < int(rnd.sum()) < len(q)            # both branches taken
+    x, z, r = o.get()
+    rows = np.concatenate([q, q + n, rng.choice(2 * n, 64, replace=False)]).astype(np.uint32)
+    gx, gz, gr = t.export_rows(rows)
+    assert np.array_equal(gx, x[rows]) and np.array_equal(gz, z[rows]) and np.array_equal(gr[0], r[rows])
+    assert t.anomalies() == 0
+    t.close()
