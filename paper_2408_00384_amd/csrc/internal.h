@@ -111,13 +111,22 @@ constexpr uint32_t kPersistMaxWp = 320;       // row words: at most 5 per lane o
 inline bool persist_layout(uint32_t n) {
   return n >= 1 && (2 * n + 63) / 64 <= kPersistMaxWp;
 }
-// Measurements per chunk of the register-resident path: bounded by the HBM
-// kept for per-workgroup counter partials (1 GB for n >= 8192, else 64 MB);
-// fewer chunks mean fewer launches and tableau reloads.
+// Measurements per chunk of the register-resident path.  Every chunk costs
+// about 50 us of fixed work (setup kernel, cooperative launch, hand-offs
+// between the two streams), and only the last chunk's finalize (about 1.2 us
+// per measurement) is not hidden behind a later chunk, so below n = 8192 the
+// size follows sqrt(42 n) (the largest power of two up to sqrt(48 n)).  It is
+// bounded by the HBM kept for per-workgroup counter partials: 1 GB for
+// n >= 8192 (where the chunk is as large as that allows), else 256 MB.
 inline uint32_t persist_chunk(uint32_t n) {
   const uint32_t Wp = (((2 * n + 63) / 64) + 7) & ~7u;
-  const size_t budget = n >= 8192 ? (size_t(1) << 30) : (size_t(64) << 20);
+  const size_t budget = n >= 8192 ? (size_t(1) << 30) : (size_t(256) << 20);
   size_t kc = budget / (size_t(kPersistMaxGroups) * Wp * 16);
+  if (n < 8192) {
+    size_t target = 16;
+    while (4 * target * target <= size_t(48) * n) target *= 2;
+    if (kc > target) kc = target;
+  }
   if (kc < 16) kc = 16;
   if (kc > kPersistMaxChunk) kc = kPersistMaxChunk;
   if (kc > n) kc = n;
