@@ -36,8 +36,8 @@ LDS_PEAK_GBS = 256 * 128 * 2.4   # 256 CUs x 128 B/clk x 2.4 GHz = 78,643 GB/s
 TRAFFIC = {
     "k_meas_xz": {
         "sources": ("paper_2408_00384_amd/csrc/measure_persist.hip", "paper_2408_00384_amd/csrc/internal.h"),
-        "sha256": "533382cf58c2d0f51887ab082fa02cef4f2b78bc12de18cb02c2fd9418cbcd29",
-        "bytes_per_launch": 1.122e+09,
+        "sha256": "02882917b882bc270beb0d630402ac2db26ea07aeaecf0c365d1757aec001176",
+        "bytes_per_launch": 1.121e+09,
         "summary": "profiles/k_meas_xz_plain_n10000_measure_all.md",
     },
 }
