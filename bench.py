@@ -215,14 +215,14 @@ def _oracle_request_seconds(c, gate_s, meas_s):
     depth = c.h.shape[0]
     t0 = time.perf_counter()
     done = 0
-    while done < depth and time.perf_counter() - t0 < gate_s:
+    while done < depth and (done == 0 or time.perf_counter() - t0 < gate_s):
         l1 = min(depth, done + 4)
         t.apply_layers(c.h[done:l1], c.s[done:l1], c.ctrl[done:l1], c.tgt[done:l1])
         done = l1
-    gates = (time.perf_counter() - t0) * depth / done
+    gates = (time.perf_counter() - t0) * depth / max(1, done)
     t1 = time.perf_counter()
     k = 0
-    while k < len(c.qubits) and time.perf_counter() - t1 < meas_s:
+    while k < len(c.qubits) and (k == 0 or time.perf_counter() - t1 < meas_s):
         t.measure(int(c.qubits[k]), seed=c.seed, circuit=c.circuit_id, shot=0, m=k)
         k += 1
     meas = (time.perf_counter() - t1) / max(1, k) * len(c.qubits) * c.shots
