@@ -1,6 +1,6 @@
 // C ABI of the tableau library: argument checks, gate encoding, launches and
 // host <-> device marshalling.  Every step of the simulation itself runs in
-// the kernels of gates.hip / measure.hip / batch.hip.
+// the kernels of gates.hip, measure_step.hip, measure_persist.hip and batch.hip.
 #include <stdarg.h>
 #include <stdio.h>
 #include <stdlib.h>
@@ -1054,8 +1054,19 @@ extern "C" int cliff_sample(cliff_tab *t, cliff_tab *work, const uint32_t *qubit
   if (work->base == t->base) return fail(CLIFF_EINVAL, "cliff_sample: work aliases tab");
   if (k && !qubits) return fail(CLIFF_EINVAL, "cliff_sample: NULL qubits");
   DeviceGuard g(t->ctx->device);
-  if (work->ctx->stream != t->ctx->stream) HIP_TRY(hipStreamSynchronize(t->ctx->stream));
+  const bool two = work->ctx->stream != t->ctx->stream;
+  if (two) HIP_TRY(hipStreamSynchronize(t->ctx->stream));
   HIP_TRY(launch_copy_tab(work->dev, t->dev, work->ctx->stream));
+  if (two) {
+    // later work on tab's stream (gates, say) must not overtake the copy
+    hipEvent_t ev;
+    HIP_TRY(hipEventCreateWithFlags(&ev, hipEventDisableTiming));
+    hipError_t e = hipEventRecord(ev, work->ctx->stream);
+    if (e == hipSuccess) e = hipStreamWaitEvent(t->ctx->stream, ev, 0);
+    const hipError_t e2 = hipEventDestroy(ev);
+    HIP_TRY(e);
+    HIP_TRY(e2);
+  }
   if (k == 0) return CLIFF_OK;
   return measure_impl(work, qubits, k, seed, circuit, shot0, 0, host_out, host_random, k, 0);
 }

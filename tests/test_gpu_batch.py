@@ -105,3 +105,53 @@ def test_rejects_oversized_descriptors(ctx):
     got = out[int(d["out_off"]): int(d["out_off"]) + 2 * 20].reshape(2, 20)
     for s in range(2):
         assert np.array_equal(got[s], oracle.run_shot(circs[1], s)[0])
+
+
+def _det_heavy_circuits(maxn, seed, count=6):
+    """Circuits whose measure-all is mostly deterministic after its first
+    random outcome, so the outcomes depend on the batch kernel's sign
+    arithmetic and not only on the Philox bits: half shallow (one layer, H on
+    about a quarter of the qubits, so many CNOT pairs form Bell pairs), half
+    GHZ-like (H on qubit 0 only, then CNOT layers: the state is |0...0> +
+    |v>, whose first measured qubit in supp(v) is random and every other
+    outcome follows from it)."""
+    rng = np.random.default_rng([seed, maxn])
+    lo = {64: 1, 128: 65, 256: 129}[maxn]
+    out = []
+    for i in range(count):
+        n = int(rng.integers(max(lo, 4), maxn + 1))
+        shots = int(rng.choice([1, 17, 64]))
+        if i % 2 == 0:
+            c = layered_circuit(n, 1, shots, gen_seed=[seed, maxn, i], circuit_id=2000 + i)
+            c.h[:] = (rng.random((1, n)) < 0.25).astype(np.uint8)
+        else:
+            c = layered_circuit(n, 6, shots, gen_seed=[seed, maxn, i], circuit_id=2000 + i)
+            c.h[:] = 0
+            c.s[:] = 0
+            c.h[0, 0] = 1
+        out.append(c)
+    return out
+
+
+@pytest.mark.parametrize("cfg", [(64, 64), (128, 64), (64, 128), (128, 128), (256, 128), (512, 128),
+                                 (128, 256), (256, 256), (512, 256), (1024, 256)])
+def test_mostly_deterministic_circuits_every_team_config(ctx, cfg):
+    """Every kernel instance against the oracle, every shot, on circuits
+    where at least 30 % of the outcomes after the first random one are
+    deterministic (each then depends on the signs the kernel tracked)."""
+    from paper_2408_00384_amd.batch import BatchPlan
+    team, maxn = cfg
+    circs = _det_heavy_circuits(maxn, seed=team)
+    with torch.cuda.stream(ctx.stream):
+        plan = BatchPlan(ctx, circs, teams={maxn: team}).run()
+        outs = plan.outcomes()
+    assert plan.status() == dict(rejected=0, anomalies=0)
+    det = after = 0
+    for c, o in zip(circs, outs):
+        for s in range(c.shots):
+            ref, kinds = oracle.run_shot(c, s)
+            assert np.array_equal(o[s], ref), "circuit %d (n=%d) shot %d" % (c.circuit_id, c.n, s)
+        first = int(np.argmax(kinds)) if kinds.any() else len(kinds)
+        det += int((kinds[first + 1:] == 0).sum())
+        after += max(0, len(kinds) - first - 1)
+    assert after > 0 and det >= 0.3 * after, (det, after)

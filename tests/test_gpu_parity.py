@@ -245,31 +245,61 @@ def test_plain_small_all_shots(ctx, measure_mode):
     _check_circuit(ctx, plain_small())
 
 
-def test_plain_mid_sampled_shots(ctx, measure_mode):
-    """n = 1,024, 100 layers, measure all, 128 shots (checked on sampled shots)."""
+def test_plain_mid_all_shots_vs_stored_oracle(ctx, measure_mode):
+    """n = 1,024, 100 layers, measure all, 128 shots: every shot's outcomes,
+    the random flags and every shot's final tableau (x, z and that shot's
+    signs, as a SHA-256 digest) against the oracle's stored run of all 128
+    shots."""
+    import hashlib
     c = plain_mid()
-    path = os.path.join(GOLDEN, "plain_mid.json")
-    if os.path.exists(path):
-        rec = json.load(open(path))
-        import hashlib
-        t = _tab(ctx, c.n, c.shots).apply_circuit_gates(c)
-        out, rnd = t.measure(c.qubits, seed=c.seed, circuit=c.circuit_id)
-        gx, gz, gr = t.export()
-        for s, v in rec["shots"].items():
-            s = int(s)
-            want = np.unpackbits(np.frombuffer(bytes.fromhex(v["outcomes"]), np.uint8),
-                                 bitorder="little")[: c.n]
-            kinds = np.unpackbits(np.frombuffer(bytes.fromhex(v["random"]), np.uint8),
-                                  bitorder="little")[: c.n]
-            assert np.array_equal(out[s], want)
-            assert np.array_equal(rnd, kinds)
-            h = hashlib.sha256()
-            for arr in (gx, gz, gr[s]):
-                h.update(np.ascontiguousarray(arr, np.uint8).tobytes())
-            assert h.hexdigest() == v["tableau_sha256"]
-        assert t.anomalies() == 0
-    else:
-        _check_circuit(ctx, c, shots_to_check=[0, 127])
+    rec = json.load(open(os.path.join(GOLDEN, "plain_mid.json")))
+    assert c.seed == rec["seed"] and len(rec["shots"]) == c.shots
+    t = _tab(ctx, c.n, c.shots).apply_circuit_gates(c)
+    out, rnd = t.measure(c.qubits, seed=c.seed, circuit=c.circuit_id)
+    gx, gz, gr = t.export()
+    for s, v in rec["shots"].items():
+        s = int(s)
+        assert np.array_equal(out[s], _golden_bits(v["outcomes"], c.n)), "outcomes (shot %d)" % s
+        assert np.array_equal(rnd, _golden_bits(v["random"], c.n))
+        h = hashlib.sha256()
+        for arr in (gx, gz, gr[s]):
+            h.update(np.ascontiguousarray(arr, np.uint8).tobytes())
+        assert h.hexdigest() == v["tableau_sha256"], "tableau (shot %d)" % s
+    assert t.anomalies() == 0
+
+
+def _shots1024_sample():
+    # shot 0, one shot in every further 64-shot sign word, and the last
+    return [0] + [64 * j + (37 * j) % 64 for j in range(1, 16)] + [1023]
+
+
+def test_1024_shots_small_vs_oracle(ctx, measure_mode):
+    """1,024 shots (16 sign words per row word) at n = 300: outcomes of a
+    shot in every sign word and of shot 1,023, and those shots' final
+    tableaux, against the oracle run shot by shot."""
+    c = layered_circuit(300, 8, 1024, gen_seed=[71, 300], circuit_id=71)
+    _check_circuit(ctx, c, shots_to_check=_shots1024_sample())
+
+
+def test_1024_shots_n2100_vs_stored_oracle(ctx, measure_mode):
+    """1,024 shots at n = 2,100 (66 row words): 17 sampled shots (one in
+    every sign word, and shot 1,023) against the oracle's stored outcomes,
+    random flags and final-tableau digests."""
+    import sys
+    sys.path.insert(0, GOLDEN)
+    from make_golden import shots1024_circuit, shots1024_sample
+    rec = json.load(open(os.path.join(GOLDEN, "shots1024_n2100.json")))
+    c = shots1024_circuit()
+    assert sorted(int(s) for s in rec["shots"]) == sorted(shots1024_sample())
+    t = _tab(ctx, c.n, c.shots).apply_circuit_gates(c)
+    out, rnd = t.measure(c.qubits, seed=c.seed, circuit=c.circuit_id)
+    gx, gz, gr = t.export()
+    for s, v in rec["shots"].items():
+        s = int(s)
+        assert np.array_equal(out[s], _golden_bits(v["outcomes"], c.n)), "outcomes (shot %d)" % s
+        assert np.array_equal(rnd, _golden_bits(v["random"], c.n))
+        assert _tab_digest(gx, gz, gr[s]) == v["tableau_sha256"], "tableau (shot %d)" % s
+    assert t.anomalies() == 0
 
 
 def test_sample_leaves_state_unchanged(ctx):
@@ -285,6 +315,37 @@ def test_sample_leaves_state_unchanged(ctx):
     for s in range(5):
         o, k = oracle.run_shot(c, s)
         assert np.array_equal(out[s], o) and np.array_equal(rnd, k)
+
+
+def test_sample_on_another_stream_orders_later_gates(ctx):
+    """Sampling into a work tableau of a context on another stream, with no
+    host outputs (nothing synchronizes), then a long gate list on the
+    sampled tableau at once: the copy must see the state before the gates.
+    Work's outcomes (read afterwards) match the oracle on that state, and the
+    sampled tableau ends as the oracle's after the gates."""
+    import torch
+    from paper_2408_00384_amd import Context, DeviceTableau, _binding as B
+    from paper_2408_00384_amd._binding import _lib
+    c = layered_circuit(600, 10, 1, gen_seed=23, circuit_id=4)
+    ctx2 = Context(0, torch.cuda.Stream())
+    t = _tab(ctx, c.n, 1).apply_circuit_gates(c)
+    work = DeviceTableau(ctx2, c.n, 3)
+    q = np.ascontiguousarray(c.qubits[:64], np.uint32)
+    rng = np.random.default_rng(8)
+    ops, a, b = random_gate_list(rng, c.n, 20000)
+    torch.cuda.synchronize()
+    rc = _lib.cliff_sample(t.handle, work.handle, q.ctypes.data_as(B._u32p), len(q), c.seed, 4, 0, None, None)
+    assert rc == 0
+    t.apply_gates(ops, a, b)
+    out, rnd = B.cliff_tab_read_outcomes(work.handle, len(q))
+    ref = oracle.Tableau(c.n).apply_circuit_gates(c)
+    for s in range(3):
+        o, k = ref.clone().measure_list(q, seed=c.seed, circuit=4, shot=s)
+        assert np.array_equal(out[s], o) and np.array_equal(rnd, k), "shot %d" % s
+    ref.apply_gates(ops, a, b)
+    _assert_tab_equal(t.export(), [ref.get()])
+    work.close()
+    ctx2.close()
 
 
 def test_export_import_resume(ctx):
@@ -561,12 +622,13 @@ def test_step_whole_tiles_product_state(ctx):
     assert np.array_equal(again, out)
 
 
-@pytest.mark.parametrize("n,persistent", [(10_240, True), (10_241, False)])
+@pytest.mark.parametrize("n,persistent", [(7_000, True), (8_192, True), (10_240, True), (10_241, False)])
 def test_register_resident_size_limit(ctx, n, persistent):
-    """n = 10,240 is the largest tableau the register-resident path holds (320
-    row words: every lane word and column slot of every workgroup full);
-    n = 10,241 is the first that AUTO sends to the per-measurement path.  At
-    both, against the oracle: outcomes and random flags of 32 measurements
+    """n = 7,000 and 8,192 take the register-resident kernel with four row
+    words per lane (219 and 256 words); n = 10,240 is the largest tableau
+    that path holds (320 row words: every lane word and column slot of every
+    workgroup full); n = 10,241 is the first that AUTO sends to the
+    per-measurement path.  At each, against the oracle: outcomes and random flags of 32 measurements
     (the first 16 qubits, 13 spread over the rest, the last, then qubits 0 and
     n - 1 again, which are deterministic), then sampled tableau rows, the
     measured qubits' among them, bit for bit."""

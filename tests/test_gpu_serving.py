@@ -57,3 +57,37 @@ def test_admission_respects_budget_and_rejects_oversized():
     assert res[3].error is not None
     assert all(res[i].error is None and res[i].outcomes is not None for i in range(3))
     srv.close()
+
+
+def test_large_requests_in_a_mix_vs_stored_oracle():
+    """Three requests of the 96-request serving workload with n between 1,000
+    and 1,800 (depth 2n, 377 to 754 shots), served in a mix with small
+    requests: the first 48 outcomes of shot 0, of a middle shot and of the
+    last shot, and the random flags, against the oracle's stored prefixes."""
+    import json
+    import os
+    import sys
+    from inputs import serving_params, serving_request
+    from paper_2408_00384_amd.serving import Server
+    golden = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
+    sys.path.insert(0, golden)
+    from make_golden import SERVING_COUNT
+    rec = json.load(open(os.path.join(golden, "serving_prefix.json")))
+    k = rec["prefix"]
+    arrivals, ns, shots = serving_params(SERVING_COUNT, 1.0, seed=4)
+    big = [serving_request(int(i), arrivals, ns, shots, seed=4).circuit for i in rec["requests"]]
+    small, small_arr = _workload(count=8, rate=800.0, n_hi=200, shots_hi=60, seed=11)
+    circs = big + small
+    arr = [0.0, 0.001, 0.002] + [0.0005 * (j + 1) for j in range(len(small))]
+    srv = Server(budget_bytes=4 << 30, lanes=4)
+    res = srv.run(circs, arr, realtime=True)
+    srv.close()
+    for j, (i, v) in enumerate(rec["requests"].items()):
+        c, r = big[j], res[j]
+        assert r.error is None and r.path == "hbm"
+        assert (c.n, c.shots) == (v["n"], v["shots"])
+        want_kinds = np.unpackbits(np.frombuffer(bytes.fromhex(v["random"]), np.uint8), bitorder="little")[:k]
+        assert np.array_equal(r.random[:k], want_kinds), "request %s random flags" % i
+        for s, hx in v["outcomes"].items():
+            want = np.unpackbits(np.frombuffer(bytes.fromhex(hx), np.uint8), bitorder="little")[:k]
+            assert np.array_equal(r.outcomes[int(s), :k], want), "request %s shot %s" % (i, s)

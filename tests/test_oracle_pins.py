@@ -412,6 +412,43 @@ def test_symplectic_invariants_after_measurements():
     assert t.anomalies == 0
 
 
+@pytest.mark.parametrize("n", [7, 200, 201])
+def test_layer_routine_equals_gate_by_gate(n):
+    """The oracle's layer routine (every rule applied row by row, all gates of
+    a layer per row) against its gate-by-gate routine on the same circuit
+    written out as a gate list (per layer: H then S on each qubit, then the
+    layer's CNOTs): identical tableaux, signs included, after many layers.
+    Gates of one layer act on distinct qubits, and each rule touches only its
+    own row, so the two orders must agree bit for bit."""
+    from inputs import OP_CNOT, OP_H, OP_S
+    c = layered_circuit(n, 30, 1, gen_seed=[90, n])
+    ops, qa, qb = [], [], []
+    for layer in range(c.depth):
+        for q in range(n):
+            if c.h[layer, q]:
+                ops.append(OP_H); qa.append(q); qb.append(0)
+            if c.s[layer, q]:
+                ops.append(OP_S); qa.append(q); qb.append(0)
+        for a_, b_ in zip(c.ctrl[layer], c.tgt[layer]):
+            ops.append(OP_CNOT); qa.append(int(a_)); qb.append(int(b_))
+    by_layers = oracle.Tableau(n).apply_circuit_gates(c).get()
+    by_gates = oracle.Tableau(n).apply_gates(np.array(ops, np.uint8), np.array(qa, np.uint32),
+                                             np.array(qb, np.uint32)).get()
+    for A, B in zip(by_layers, by_gates):
+        assert np.array_equal(A, B)
+    # a planted mistake fails the comparison: S before H on one qubit of the
+    # first layer that has both
+    both = np.flatnonzero(c.h[0] & c.s[0])
+    assert len(both)
+    j = ops.index(OP_H, 0)
+    while qa[j] != both[0] or ops[j] != OP_H:
+        j += 1
+    ops[j], ops[j + 1] = ops[j + 1], ops[j]
+    planted = oracle.Tableau(n).apply_gates(np.array(ops, np.uint8), np.array(qa, np.uint32),
+                                            np.array(qb, np.uint32)).get()
+    assert any(not np.array_equal(A, B) for A, B in zip(by_layers, planted))
+
+
 def test_run_shot_matches_stepwise():
     c = layered_circuit(20, 10, 3, gen_seed=5, circuit_id=4)
     for shot in range(3):
