@@ -15,7 +15,11 @@
  *    most recent failure on the calling thread.
  *  - Device memory belongs to the caller.  A tableau is a view bound onto one
  *    caller-owned device buffer of cliff_tab_bytes(n, shots) bytes; the library
- *    never frees it.  The context owns only its own staging buffers.
+ *    never frees it.  The context owns only its own staging buffers and the
+ *    register-resident measurement's chunk scratch (allocated at the first
+ *    such measurement, grown to the largest tableau shape the context has
+ *    measured: about 270 MB at n = 4,096, 2.2 GB at n = 10,000; freed by
+ *    cliff_ctx_destroy).
  *  - Host pointers are read (inputs) or written (outputs) before the call
  *    returns.  Calls that return host data synchronize the context stream;
  *    the others only enqueue work on it.
@@ -74,7 +78,9 @@ const char *cliff_strerror(int code);
  * (the register-resident measurement overlaps a chunk's finalize with the
  * next chunk), but the bound stream waits for them before the call's later
  * work, so everything enqueued afterwards on the bound stream sees the
- * results.  Owns small staging buffers, that stream and its events. */
+ * results.  Owns small staging buffers, that stream and its events (created
+ * here) and the measurement chunk scratch (see above).  Destroy synchronizes
+ * both streams before it releases them. */
 int cliff_ctx_create(int device, void *hip_stream, cliff_ctx **out);
 int cliff_ctx_destroy(cliff_ctx *ctx);
 /* Block until all work enqueued by the context has finished. */
@@ -133,8 +139,9 @@ int cliff_ctx_set_measure_mode(cliff_ctx *ctx, int mode);
  * default) injects nothing. */
 int cliff_ctx_inject_abort(cliff_ctx *ctx, uint64_t at);
 
-/* Bytes of device memory a tableau of n qubits with `shots` sign columns needs,
- * scratch included (X, Z, signs, measurement scratch, outcome staging). */
+/* Bytes of device memory a tableau of n qubits with `shots` sign columns needs:
+ * X, Z, signs, the per-measurement path's scratch and the outcome staging
+ * (the register-resident path's chunk scratch belongs to the context). */
 size_t cliff_tab_bytes(uint32_t n, uint32_t shots);
 
 /* Bind a tableau view onto caller-owned device memory `dev` of `bytes` bytes

@@ -123,9 +123,12 @@ struct cliff_ctx {
   size_t pinned_cap = 0;         // words
   hipEvent_t upload_done = nullptr;
   bool upload_pending = false;
-  // register-resident measurement: second stream and its events (lazily made)
+  // register-resident measurement: second stream and its events, and the
+  // chunk scratch (grown on demand to the largest shape measured)
   hipStream_t aux = nullptr;
   hipEvent_t persist_ev[4] = {nullptr, nullptr, nullptr, nullptr};
+  uint8_t *pscratch = nullptr;
+  size_t pscratch_bytes = 0;
   int gate_mode = CLIFF_GATES_AUTO;
   int measure_mode = CLIFF_MEASURE_AUTO;
   uint64_t inject_abort_at = UINT64_MAX;   // test aid: see cliff_ctx_inject_abort
@@ -177,9 +180,12 @@ int cliff_ctx_create(int device, void *hip_stream, cliff_ctx **out) {
   }
   c->num_cus = prop.multiProcessorCount;
   e = hipEventCreateWithFlags(&c->upload_done, hipEventDisableTiming);
+  if (e == hipSuccess) e = hipStreamCreateWithFlags(&c->aux, hipStreamNonBlocking);
+  for (hipEvent_t &ev : c->persist_ev)
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&ev, hipEventDisableTiming);
   if (e != hipSuccess) {
-    delete c;
-    return fail(CLIFF_EDEVICE, "hipEventCreate: %s", hipGetErrorString(e));
+    cliff_ctx_destroy(c);
+    return fail(CLIFF_EDEVICE, "cliff_ctx_create: %s", hipGetErrorString(e));
   }
   *out = c;
   return CLIFF_OK;
@@ -189,7 +195,9 @@ int cliff_ctx_destroy(cliff_ctx *c) {
   if (!c) return CLIFF_OK;
   DeviceGuard g(c->device);
   (void)hipStreamSynchronize(c->stream);
+  if (c->aux) (void)hipStreamSynchronize(c->aux);
   if (c->dev_ops) (void)hipFree(c->dev_ops);
+  if (c->pscratch) (void)hipFree(c->pscratch);
   if (c->pinned) (void)hipHostFree(c->pinned);
   if (c->upload_done) (void)hipEventDestroy(c->upload_done);
   if (c->aux) {
@@ -303,11 +311,8 @@ int cliff_tab_bind(cliff_ctx *ctx, uint32_t n, uint32_t shots, void *dev, size_t
   v.detpar = reinterpret_cast<uint32_t *>(at(t->o.detpar));
   v.detY = reinterpret_cast<uint32_t *>(at(t->o.detY));
   v.detr = reinterpret_cast<uint64_t *>(at(t->o.detr));
-  v.SNall = reinterpret_cast<uint64_t *>(at(t->o.SNall));
-  v.C1all = reinterpret_cast<uint64_t *>(at(t->o.C1all));
-  v.ring = reinterpret_cast<uint64_t *>(at(t->o.ring));
-  v.pivall = reinterpret_cast<uint32_t *>(at(t->o.pivall));
-  v.pub = reinterpret_cast<uint64_t *>(at(t->o.pub));
+  v.SNall = v.C1all = v.ring = v.pub = nullptr;   // chunk scratch: bound per pass
+  v.pivall = nullptr;
   v.abort_flag = reinterpret_cast<uint32_t *>(at(t->o.abort_flag));
   v.n = n;
   v.S = shots;
@@ -775,6 +780,27 @@ extern "C" int cliff_apply_gates_many(cliff_tab *const *tabs, const uint8_t *con
 // else one step kernel per measurement.
 // `abort_at` (test aid): the pass's measurement at which its workgroups give
 // up as on a timed-out wait, or UINT64_MAX.
+// The context's chunk scratch for chunks of kc measurements of t's shape,
+// grown (after both streams drain) when a larger shape comes along.
+static int ctx_persist_scratch(cliff_ctx *c, const Dims &d, uint32_t kc, uint8_t **base) {
+  const size_t need = persist_scratch_layout(d, kc).total;
+  if (c->pscratch_bytes < need) {
+    HIP_TRY(hipStreamSynchronize(c->stream));
+    HIP_TRY(hipStreamSynchronize(c->aux));
+    if (c->pscratch) HIP_TRY(hipFree(c->pscratch));
+    c->pscratch = nullptr;
+    c->pscratch_bytes = 0;
+    hipError_t e = hipMalloc(reinterpret_cast<void **>(&c->pscratch), need);
+    if (e != hipSuccess) {
+      (void)hipGetLastError();
+      return fail(CLIFF_ENOMEM, "measurement scratch of %zu bytes: %s", need, hipGetErrorString(e));
+    }
+    c->pscratch_bytes = need;
+  }
+  *base = c->pscratch;
+  return CLIFF_OK;
+}
+
 static int measure_pass(cliff_tab *t, const uint32_t *qubits, size_t cnt, uint64_t seed,
                         uint64_t circuit, uint64_t shot0, uint64_t m0, uint64_t abort_at) {
   cliff_ctx *c = t->ctx;
@@ -785,15 +811,16 @@ static int measure_pass(cliff_tab *t, const uint32_t *qubits, size_t cnt, uint64
     return fail(CLIFF_EINVAL, "register-resident measurement does not fit n = %u", t->d.n);
   if (c->measure_mode != CLIFF_MEASURE_STEP && shape_ok) {
     const uint32_t *dq = nullptr;
+    uint8_t *base = nullptr;
+    const uint32_t kc = persist_chunk(t->d.n);
     int rc = upload_stream(c, nullptr, 0, qubits, cnt, nullptr, &dq);
+    if (!rc) rc = ctx_persist_scratch(c, t->d, kc, &base);
     if (rc) return rc;
-    if (!c->aux) {
-      HIP_TRY(hipStreamCreateWithFlags(&c->aux, hipStreamNonBlocking));
-      for (hipEvent_t &ev : c->persist_ev) HIP_TRY(hipEventCreateWithFlags(&ev, hipEventDisableTiming));
-    }
+    TabDev dv = t->dev;
+    persist_scratch_bind(dv, t->d, kc, base);
     PersistStreams ps{st, c->aux, {c->persist_ev[0], c->persist_ev[1], c->persist_ev[2], c->persist_ev[3]}};
     uint32_t done = 0;
-    hipError_t e = launch_measure_persist(t->dev, dq, uint32_t(cnt), seed, circuit, shot0, m0,
+    hipError_t e = launch_measure_persist(dv, kc, dq, uint32_t(cnt), seed, circuit, shot0, m0,
                                           c->num_cus, ps, &c->prof, &done, abort_at);
     if (done) t->persist_used = true;
     if (e == hipSuccess) return CLIFF_OK;

@@ -11,6 +11,8 @@
 //   scratch: snapshots of measured columns, pivot ring, pivot signs, per-
 //            workgroup counter partials of two consecutive measurements,
 //            deterministic-outcome accumulators, state words, outcome staging.
+// The register-resident measurement's chunk scratch (persist_scratch_layout)
+// is not part of a tableau: it belongs to the context that runs the pass.
 // Padding rows 2n..64W-1 and padding words W..Wp-1 are always zero.
 #pragma once
 #include <hip/hip_runtime.h>
@@ -83,7 +85,7 @@ struct Dims {
 struct Offsets {
   size_t X, Z, R, P, M, xp, zp, rp, part, state, out, kind;
   size_t SN, piv, rps, detpar, detY, detr;
-  size_t SNall, pivall, pub, C1all, ring, abort_flag, total;
+  size_t abort_flag, total;
 };
 
 // Device view passed by value to kernels.
@@ -99,7 +101,8 @@ struct TabDev {
   uint64_t *detr;            // n x SW
   // register-resident path (n <= 10240), per chunk of measurements: measured
   // columns and pivots, the tagged publication slots, per-workgroup counter
-  // partials, and the reduced sign corrections
+  // partials, and the reduced sign corrections (the chunk scratch, set for
+  // each pass from persist_scratch_layout; null otherwise)
   uint64_t *SNall, *C1all, *ring, *pub;
   uint32_t *pivall, *abort_flag;
   uint32_t n, S, W, Wp, NW, SW;
@@ -182,17 +185,38 @@ inline Offsets make_offsets(const Dims &d) {
   o.detpar = take(size_t(d.n) * 4);
   o.detY = take(size_t(d.n) * 4);
   o.detr = take(size_t(d.n) * d.SW * 8);
-  const bool pl = persist_layout(d.n);
-  // two of each, for chunk c and chunk c + 1 in flight together
-  const size_t kc = pl ? 2 * size_t(persist_chunk(d.n)) : 0;
-  o.SNall = take(kc * d.Wp * 8);
-  o.pivall = take(kc * 4);
-  o.pub = take(kc * 2 * d.Wp * 8);   // [m][word][2] tagged 32-bit halves
-  o.C1all = take(kc * d.Wp * 8);
-  o.ring = take(kc * kPersistMaxGroups * d.Wp * 16);   // partials [m][workgroup][word][2]
   o.abort_flag = take(4);   // every layout: the init and copy kernels clear it
   o.total = cur;
   return o;
+}
+
+// Chunk scratch of the register-resident measurement for a tableau shape and
+// kc measurements per chunk, two sets (chunk c and chunk c + 1 in flight
+// together), offsets from a 256-byte aligned base.
+struct PersistScratchLayout {
+  size_t SNall, pivall, pub, C1all, ring, total;
+};
+inline PersistScratchLayout persist_scratch_layout(const Dims &d, uint32_t kc) {
+  PersistScratchLayout o;
+  size_t cur = 0;
+  auto take = [&](size_t bytes) { size_t at = cur; cur = align256(cur + bytes); return at; };
+  const size_t k2 = 2 * size_t(kc);
+  o.SNall = take(k2 * d.Wp * 8);
+  o.pivall = take(k2 * 4);
+  o.pub = take(k2 * 2 * d.Wp * 8);   // [m][word][2] tagged 32-bit halves
+  o.C1all = take(k2 * d.Wp * 8);
+  o.ring = take(k2 * kPersistMaxGroups * d.Wp * 16);   // partials [m][workgroup][word][2]
+  o.total = cur;
+  return o;
+}
+// Point a tableau view's chunk-scratch fields into `base` (layout above).
+inline void persist_scratch_bind(TabDev &t, const Dims &d, uint32_t kc, uint8_t *base) {
+  const PersistScratchLayout o = persist_scratch_layout(d, kc);
+  t.SNall = reinterpret_cast<uint64_t *>(base + o.SNall);
+  t.pivall = reinterpret_cast<uint32_t *>(base + o.pivall);
+  t.pub = reinterpret_cast<uint64_t *>(base + o.pub);
+  t.C1all = reinterpret_cast<uint64_t *>(base + o.C1all);
+  t.ring = reinterpret_cast<uint64_t *>(base + o.ring);
 }
 
 
@@ -233,7 +257,8 @@ struct PersistStreams {
   hipEvent_t ev[4];
 };
 // *done = measurements whose launches were all enqueued (chunks before a failure).
-hipError_t launch_measure_persist(const TabDev &t, const uint32_t *dev_qubits, uint32_t k,
+// t carries the chunk scratch for chunks of kc measurements (persist_scratch_bind).
+hipError_t launch_measure_persist(const TabDev &t, uint32_t kc, const uint32_t *dev_qubits, uint32_t k,
                                   uint64_t seed, uint64_t circuit, uint64_t shot0, uint64_t m0,
                                   int num_cus, const PersistStreams &ps, Profiler *prof, uint32_t *done,
                                   uint64_t abort_at);

@@ -705,14 +705,14 @@ bool persist_shape(uint32_t n, uint32_t num_cus, uint32_t *G, uint32_t *L, uint3
   return true;
 }
 
-hipError_t launch_measure_persist(const TabDev &t, const uint32_t *dev_qubits, uint32_t k,
+hipError_t launch_measure_persist(const TabDev &t, uint32_t kc, const uint32_t *dev_qubits, uint32_t k,
                                   uint64_t seed, uint64_t circuit, uint64_t shot0, uint64_t m0,
                                   int num_cus, const PersistStreams &ps, Profiler *prof, uint32_t *done,
                                   uint64_t abort_at) {
   *done = 0;
   uint32_t G, L, CW;
   if (!persist_shape(t.n, uint32_t(num_cus), &G, &L, &CW)) return hipErrorInvalidValue;
-  const uint32_t kc = persist_chunk(t.n);
+  if (kc == 0 || kc > kPersistMaxChunk || !t.SNall) return hipErrorInvalidValue;
   // per-chunk scratch, two sets: chunk c uses set c & 1
   TabDev tb[2] = {t, t};
   tb[1].SNall += size_t(kc) * t.Wp;

@@ -5,10 +5,15 @@ arrive over time.  The server admits them first come, first served as device
 memory and execution lanes free up, so work of requests that arrive while
 others run is enqueued right away and overlaps on the device:
 
-  * memory: every admitted request holds the bytes of its tableau
-    (cliff_tab_bytes(n, shots)) in one device arena of a fixed budget; a
-    request waits until its bytes fit; one larger than the whole budget is
-    rejected;
+  * memory: every admitted request holds its device bytes in one arena of a
+    fixed budget: on an HBM lane its tableau (cliff_tab_bytes(n, shots)); on
+    the batch lane, whose tableaux live in LDS, what the batched launch keeps
+    for it in device memory (its op stream, layer offsets, descriptor and
+    outcome bytes, request_bytes below).  A request waits until its bytes
+    fit; one larger than the whole budget is rejected.  Each HBM lane's
+    context also keeps the register-resident measurement's chunk scratch,
+    sized once by the largest tableau shape the lane has measured (about
+    270 MB at n = 4,096); it is not charged per request;
   * HBM lanes: requests that do not fit the batched kernel (n > 256 or more
     than 64 shots) run on one of several streams, each with its own context:
     tableau bound inside the arena, |0...0>, all gate layers, then all
@@ -90,6 +95,18 @@ class Result:
         return self.done - self.arrival
 
 
+def batch_request_bytes(c) -> int:
+    """Device bytes the batched launch keeps for circuit c: op words (at most
+    one per gate; runs of single-qubit gates are composed), layer offsets,
+    a descriptor, and the outcome bytes, rounded up as the arena rounds."""
+    raw = 8 * c.gate_count() + 4 * (c.depth + 1) + 48 + c.shots * c.n
+    return (raw + ALIGN - 1) // ALIGN * ALIGN
+
+
+def request_bytes(c, batch: bool) -> int:
+    return batch_request_bytes(c) if batch else B.cliff_tab_bytes(c.n, c.shots)
+
+
 class _Lane:
     def __init__(self, device: int):
         self.stream = torch.cuda.Stream(device)
@@ -148,12 +165,13 @@ class Server:
             if not self._small(c):
                 rest.append(rid)
                 continue
-            if B.cliff_tab_bytes(c.n, c.shots) > self.alloc.size:
+            need = request_bytes(c, batch=True)
+            if need > self.alloc.size:
                 res = self.results[rid]
-                res.error = "tableau of %d bytes exceeds the budget" % B.cliff_tab_bytes(c.n, c.shots)
+                res.error = "request of %d bytes exceeds the budget" % need
                 res.done = self.now()
                 continue
-            got = self.alloc.alloc(B.cliff_tab_bytes(c.n, c.shots))
+            got = self.alloc.alloc(need)
             if got is None:
                 rest.append(rid)
                 break

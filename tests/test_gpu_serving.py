@@ -41,9 +41,11 @@ def test_mix_equals_alone_and_oracle():
 
 def test_admission_respects_budget_and_rejects_oversized():
     from paper_2408_00384_amd import cliff_tab_bytes
-    from paper_2408_00384_amd.serving import Server
+    from paper_2408_00384_amd.serving import Server, batch_request_bytes
     circs, arr = _workload(count=12, rate=1e6, n_hi=300, shots_hi=150, seed=9)
-    biggest = max(cliff_tab_bytes(c.n, c.shots) for c in circs)
+    # what a request holds: its tableau on an HBM lane, its op stream and
+    # outcomes on the batch lane
+    biggest = max(max(cliff_tab_bytes(c.n, c.shots), batch_request_bytes(c)) for c in circs)
     budget = 2 * biggest + 4096
     srv = Server(budget_bytes=budget, lanes=6)
     res = srv.run(circs, arr, realtime=False)
@@ -52,7 +54,8 @@ def test_admission_respects_budget_and_rejects_oversized():
     assert srv.alloc.used == 0
     # a request larger than the whole budget is rejected, the rest still served
     from inputs import layered_circuit
-    big = layered_circuit(2048, 2, 512, gen_seed=1)
+    big = layered_circuit(4096, 2, 1024, gen_seed=1)
+    assert cliff_tab_bytes(big.n, big.shots) > budget
     res = srv.run(circs[:3] + [big], arr[:3] + [0.0], realtime=False)
     assert res[3].error is not None
     assert all(res[i].error is None and res[i].outcomes is not None for i in range(3))
