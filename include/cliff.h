@@ -276,6 +276,26 @@ int cliff_reset_record(cliff_tab *tab, const uint32_t *qubits, size_t k, uint64_
 int cliff_apply_cond_paulis(cliff_tab *tab, const uint32_t *qubits, const uint8_t *paulis,
                             const uint32_t *cols, size_t k, const uint8_t *dev_record, size_t ld);
 
+/* For callers that cannot allocate device memory: code under HIP graph
+ * capture, tight serving loops, harnesses that forbid allocation.  Same
+ * arguments, results and error codes as cliff_measure_record (outcomes into
+ * the caller's device record, bit for bit the same), but the call allocates
+ * nothing and stages nothing through the context: the qubit list and the
+ * register-resident pass's chunk scratch live in a static device array of
+ * CLIFF_NOALLOC_SCRATCH_BYTES that the library keeps on each GPU it runs on
+ * until the process ends (its chunks are as large as fits there: 48
+ * measurements instead of 819 at n = 10,000, so large n run slower than with
+ * cliff_measure_record).  Every call on a GPU uses that GPU's one array:
+ * calls that overlap on one GPU (several host threads, or contexts on
+ * different streams) race and must be serialized by the caller.
+ * CLIFF_EINVAL as cliff_measure_record and while kernel timing
+ * (cliff_ctx_profile) is on; CLIFF_ENOMEM if a tableau shape needed more
+ * than the array (none of n <= 10,240 does). */
+#define CLIFF_NOALLOC_SCRATCH_BYTES ((size_t)128 << 20)
+int cliff_measure_record_noalloc(cliff_tab *tab, const uint32_t *qubits, size_t k, uint64_t seed,
+                                 uint64_t circuit, uint64_t shot0, uint64_t m0, uint8_t *dev_record,
+                                 size_t ld, size_t col0, uint8_t *dev_random);
+
 /* Asynchronous form of cliff_measure for k <= n measurements: only enqueues
  * the work on the context stream.  The outcomes stay in the tableau's device
  * staging until cliff_tab_read_outcomes (same k, same layout as cliff_measure,

@@ -82,6 +82,7 @@ _SIGS = {
     "cliff_measure": (ctypes.c_int, [_vp, _u32p, _sz, _u64, _u64, _u64, _u64, _u8p, _u8p]),
     "cliff_measure_bases": (ctypes.c_int, [_vp, _u32p, _u8p, _sz, _u64, _u64, _u64, _u64, _u8p, _u8p]),
     "cliff_measure_record": (ctypes.c_int, [_vp, _u32p, _sz, _u64, _u64, _u64, _u64, _vp, _sz, _sz, _vp]),
+    "cliff_measure_record_noalloc": (ctypes.c_int, [_vp, _u32p, _sz, _u64, _u64, _u64, _u64, _vp, _sz, _sz, _vp]),
     "cliff_reset_record": (ctypes.c_int, [_vp, _u32p, _sz, _u64, _u64, _u64, _u64, _vp, _sz, _sz, _vp]),
     "cliff_apply_cond_paulis": (ctypes.c_int, [_vp, _u32p, _u8p, _u32p, _sz, _vp, _sz]),
     "cliff_sample": (ctypes.c_int, [_vp, _vp, _u32p, _sz, _u64, _u64, _u64, _u8p, _u8p]),
@@ -322,6 +323,16 @@ def cliff_measure_record(tab, qubits, dev_record_ptr, ld, col0, dev_random_ptr=0
     _check(_lib.cliff_measure_record(tab, _ptr(q, _u32p), len(q), seed, circuit, shot0, m0,
                                      dev_record_ptr, ld, col0, dev_random_ptr or None),
            "cliff_measure_record")
+
+
+def cliff_measure_record_noalloc(tab, qubits, dev_record_ptr, ld, col0, dev_random_ptr=0, seed=0, circuit=0,
+                                 shot0=0, m0=0):
+    """cliff_measure_record that allocates nothing (the library's static
+    device scratch instead of the context's)."""
+    q = _arr(qubits, np.uint32)
+    _check(_lib.cliff_measure_record_noalloc(tab, _ptr(q, _u32p), len(q), seed, circuit, shot0, m0,
+                                             dev_record_ptr, ld, col0, dev_random_ptr or None),
+           "cliff_measure_record_noalloc")
 
 
 def cliff_reset_record(tab, qubits, dev_record_ptr, ld, col0, dev_random_ptr=0, seed=0, circuit=0,

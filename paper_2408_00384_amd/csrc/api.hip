@@ -9,6 +9,7 @@
 #include <algorithm>
 #include <string>
 #include <vector>
+#include <mutex>
 #include <unordered_map>
 
 #include "../../include/cliff.h"
@@ -143,6 +144,42 @@ struct cliff_tab {
   TabDev dev{};
 };
 
+// ------------------------------------------------- allocation-free scratch ---
+// Device memory of cliff_measure_record_noalloc: the qubit list of a pass and
+// the register-resident chunk scratch live in this file-scope array, one copy
+// per GPU (it belongs to the code object, loaded on each device the library
+// runs on, and lives until the process ends).  Host code never uses the
+// array's name as an address: the first context created on a device looks
+// its address up with hipGetSymbolAddress, with that device current, and the
+// entry point passes that pointer to the kernels.  Every call on a GPU shares
+// the array; calls that overlap on one GPU race.
+constexpr size_t kNoAllocQubitBytes = size_t(kPersistMaxWp) * 32 * 4;   // a pass: n <= 10,240 qubits (40 KB)
+static_assert(kNoAllocQubitBytes % 256 == 0, "qubit area keeps the chunk scratch aligned");
+static_assert(CLIFF_NOALLOC_SCRATCH_BYTES > kNoAllocQubitBytes, "scratch size");
+static __device__ __align__(256) uint8_t scratch[CLIFF_NOALLOC_SCRATCH_BYTES];
+
+static std::mutex g_noalloc_mu;
+static std::unordered_map<int, uint8_t *> g_noalloc_ptr;   // device -> address of its scratch
+
+// Called with `device` current (context creation): look up this device's
+// copy of the array once.
+static hipError_t noalloc_setup(int device) {
+  std::lock_guard<std::mutex> lk(g_noalloc_mu);
+  if (g_noalloc_ptr.count(device)) return hipSuccess;
+  void *ptr = nullptr;
+  const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+  if (e != hipSuccess) return e;
+  if (!ptr) return hipErrorInvalidSymbol;
+  g_noalloc_ptr[device] = static_cast<uint8_t *>(ptr);
+  return hipSuccess;
+}
+
+static uint8_t *noalloc_ptr(int device) {
+  std::lock_guard<std::mutex> lk(g_noalloc_mu);
+  auto it = g_noalloc_ptr.find(device);
+  return it == g_noalloc_ptr.end() ? nullptr : it->second;
+}
+
 extern "C" {
 
 const char *cliff_last_error(void) { return g_err.c_str(); }
@@ -183,6 +220,7 @@ int cliff_ctx_create(int device, void *hip_stream, cliff_ctx **out) {
   if (e == hipSuccess) e = hipStreamCreateWithFlags(&c->aux, hipStreamNonBlocking);
   for (hipEvent_t &ev : c->persist_ev)
     if (e == hipSuccess) e = hipEventCreateWithFlags(&ev, hipEventDisableTiming);
+  if (e == hipSuccess) e = noalloc_setup(device);
   if (e != hipSuccess) {
     cliff_ctx_destroy(c);
     return fail(CLIFF_EDEVICE, "cliff_ctx_create: %s", hipGetErrorString(e));
@@ -801,8 +839,13 @@ static int ctx_persist_scratch(cliff_ctx *c, const Dims &d, uint32_t kc, uint8_t
   return CLIFF_OK;
 }
 
+static int noalloc_persist_scratch(cliff_ctx *c, const Dims &d, const uint32_t *qubits, size_t cnt,
+                                   uint32_t *kc, uint8_t **base, const uint32_t **dev_qubits);
+
+// `noalloc`: the chunk scratch and qubit list come from the static array and
+// nothing is allocated (cliff_measure_record_noalloc).
 static int measure_pass(cliff_tab *t, const uint32_t *qubits, size_t cnt, uint64_t seed,
-                        uint64_t circuit, uint64_t shot0, uint64_t m0, uint64_t abort_at) {
+                        uint64_t circuit, uint64_t shot0, uint64_t m0, uint64_t abort_at, bool noalloc) {
   cliff_ctx *c = t->ctx;
   hipStream_t st = c->stream;
   uint32_t G, L, CW;
@@ -812,9 +855,15 @@ static int measure_pass(cliff_tab *t, const uint32_t *qubits, size_t cnt, uint64
   if (c->measure_mode != CLIFF_MEASURE_STEP && shape_ok) {
     const uint32_t *dq = nullptr;
     uint8_t *base = nullptr;
-    const uint32_t kc = persist_chunk(t->d.n);
-    int rc = upload_stream(c, nullptr, 0, qubits, cnt, nullptr, &dq);
-    if (!rc) rc = ctx_persist_scratch(c, t->d, kc, &base);
+    uint32_t kc = 0;
+    int rc;
+    if (noalloc) {
+      rc = noalloc_persist_scratch(c, t->d, qubits, cnt, &kc, &base, &dq);
+    } else {
+      kc = persist_chunk(t->d.n);
+      rc = upload_stream(c, nullptr, 0, qubits, cnt, nullptr, &dq);
+      if (!rc) rc = ctx_persist_scratch(c, t->d, kc, &base);
+    }
     if (rc) return rc;
     TabDev dv = t->dev;
     persist_scratch_bind(dv, t->d, kc, base);
@@ -864,7 +913,8 @@ struct DevRecord {
 // Outcome of measurement i of shot s lands at host_out[s * ld + col0 + i].
 static int measure_impl(cliff_tab *t, const uint32_t *qubits, size_t k, uint64_t seed,
                         uint64_t circuit, uint64_t shot0, uint64_t m0, uint8_t *host_out,
-                        uint8_t *host_random, size_t ld, size_t col0, const DevRecord *dr = nullptr) {
+                        uint8_t *host_random, size_t ld, size_t col0, const DevRecord *dr = nullptr,
+                        bool noalloc = false) {
   const uint32_t n = t->d.n, S = t->d.S;
   for (size_t i = 0; i < k; ++i)
     if (qubits[i] >= n) return fail(CLIFF_EINVAL, "measure: qubit %u >= n = %u", qubits[i], n);
@@ -880,7 +930,7 @@ static int measure_impl(cliff_tab *t, const uint32_t *qubits, size_t k, uint64_t
   for (size_t base = 0; base < k; base += n) {
     const size_t cnt = std::min<size_t>(n, k - base);
     const uint64_t at = (inject != UINT64_MAX && inject >= base && inject - base < cnt) ? inject - base : UINT64_MAX;
-    int rc = measure_pass(t, qubits + base, cnt, seed, circuit, shot0, m0 + base, at);
+    int rc = measure_pass(t, qubits + base, cnt, seed, circuit, shot0, m0 + base, at, noalloc);
     if (rc) return rc;
     if (dr && dr->rec) {
       t->ctx->prof.begin(PK_OTHER, st);
@@ -976,6 +1026,44 @@ extern "C" int cliff_measure_record(cliff_tab *t, const uint32_t *qubits, size_t
   DeviceGuard g(t->ctx->device);
   DevRecord dr{dev_record, ld, col0, dev_random};
   return measure_impl(t, qubits, k, seed, circuit, shot0, m0, nullptr, nullptr, k, 0, &dr);
+}
+
+// Chunk scratch and qubit list of a register-resident pass in the static
+// array: the qubits go there through kernel arguments (no staging buffer, no
+// copy from pageable memory), and the chunk is as large as fits.
+static int noalloc_persist_scratch(cliff_ctx *c, const Dims &d, const uint32_t *qubits, size_t cnt,
+                                   uint32_t *kc, uint8_t **base, const uint32_t **dev_qubits) {
+  uint8_t *sp = noalloc_ptr(c->device);
+  if (!sp) return fail(CLIFF_EINTERNAL, "no static scratch looked up for device %d", c->device);
+  if (cnt * 4 > kNoAllocQubitBytes)
+    return fail(CLIFF_EINVAL, "noalloc: %zu measurements in one pass exceed the %zu-byte qubit area", cnt,
+                kNoAllocQubitBytes);
+  const size_t room = CLIFF_NOALLOC_SCRATCH_BYTES - kNoAllocQubitBytes;
+  uint32_t k = persist_chunk(d.n);
+  while (k > 1 && persist_scratch_layout(d, k).total > room) k = std::max<uint32_t>(1, k * 3 / 4);
+  if (persist_scratch_layout(d, k).total > room)
+    return fail(CLIFF_ENOMEM, "noalloc: chunk scratch of n = %u needs %zu bytes, the static array holds %zu",
+                d.n, persist_scratch_layout(d, 1).total, room);
+  uint32_t *dq = reinterpret_cast<uint32_t *>(sp);
+  HIP_TRY(launch_store_words(dq, qubits, uint32_t(cnt), c->stream));
+  *kc = k;
+  *base = sp + kNoAllocQubitBytes;
+  *dev_qubits = dq;
+  return CLIFF_OK;
+}
+
+extern "C" int cliff_measure_record_noalloc(cliff_tab *t, const uint32_t *qubits, size_t k, uint64_t seed,
+                                            uint64_t circuit, uint64_t shot0, uint64_t m0, uint8_t *dev_record,
+                                            size_t ld, size_t col0, uint8_t *dev_random) {
+  if (!t) return fail(CLIFF_EINVAL, "cliff_measure_record_noalloc: NULL tableau");
+  if (k == 0) return CLIFF_OK;
+  if (!qubits || !dev_record) return fail(CLIFF_EINVAL, "cliff_measure_record_noalloc: NULL qubits/record");
+  if (col0 + k > ld)
+    return fail(CLIFF_EINVAL, "cliff_measure_record_noalloc: columns %zu..%zu beyond ld = %zu", col0, col0 + k, ld);
+  if (t->ctx->prof.on) return fail(CLIFF_EINVAL, "cliff_measure_record_noalloc: kernel timing is on (it allocates events)");
+  DeviceGuard g(t->ctx->device);
+  DevRecord dr{dev_record, ld, col0, dev_random};
+  return measure_impl(t, qubits, k, seed, circuit, shot0, m0, nullptr, nullptr, k, 0, &dr, true);
 }
 
 // Conditional Paulis staged as op words (qubit | Pauli << 24 | column << 32).

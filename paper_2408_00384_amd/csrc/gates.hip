@@ -11,6 +11,8 @@
 // Gates on disjoint qubits touch disjoint columns and their sign terms read
 // only their own columns, so every op of a layer can run concurrently; the
 // sign contributions are XOR-accumulated per thread and flushed once.
+#include <string.h>
+
 #include "internal.h"
 
 namespace cliff {
@@ -226,6 +228,16 @@ __global__ void __launch_bounds__(256) k_copy_tab(TabDev dst, TabDev src) {
   if (blockIdx.x == 0 && threadIdx.x == 0) *dst.abort_flag = 0;
 }
 
+// Words handed over in the kernel's arguments, stored to device memory (an
+// upload that needs no staging buffer and no host-memory copy).
+constexpr uint32_t kArgWords = 960;
+struct ArgWords {
+  uint32_t w[kArgWords];
+};
+__global__ void __launch_bounds__(256) k_store_words(uint32_t *dst, ArgWords a, uint32_t count) {
+  for (uint32_t i = threadIdx.x; i < count; i += blockDim.x) dst[i] = a.w[i];
+}
+
 // Word words[q] of every column of X and Z, gathered for a host readout of a
 // few rows: ox[q * n + j] = X[j * Wp + words[q]] (every words[q] < W).
 __global__ void __launch_bounds__(256) k_gather_words(TabDev t, const uint32_t *__restrict__ words, uint32_t nw,
@@ -387,6 +399,18 @@ hipError_t launch_copy_tab(const TabDev &dst, const TabDev &src, hipStream_t st)
   const size_t items = size_t(src.n) * src.Wp;
   k_copy_tab<<<grid_for(items, 256), 256, 0, st>>>(dst, src);
   return hipGetLastError();
+}
+
+hipError_t launch_store_words(uint32_t *dst, const uint32_t *host, uint32_t count, hipStream_t st) {
+  for (uint32_t at = 0; at < count; at += kArgWords) {
+    ArgWords a;
+    const uint32_t c = count - at < kArgWords ? count - at : kArgWords;
+    memcpy(a.w, host + at, size_t(c) * 4);
+    k_store_words<<<1, 256, 0, st>>>(dst + at, a, c);
+    const hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
 }
 
 }  // namespace cliff

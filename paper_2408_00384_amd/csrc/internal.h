@@ -266,6 +266,8 @@ hipError_t launch_batch(const void *descs, const uint64_t *ops, const uint32_t *
                         const uint32_t *order, uint32_t count, uint64_t seed, uint32_t *work,
                         uint32_t team, uint32_t maxn, int num_cus, hipStream_t st);
 hipError_t launch_copy_tab(const TabDev &dst, const TabDev &src, hipStream_t st);
+// count words from host memory to device memory dst through kernel arguments.
+hipError_t launch_store_words(uint32_t *dst, const uint32_t *host, uint32_t count, hipStream_t st);
 hipError_t launch_calibrate(int kind, int num_cus, uint32_t iters, uint32_t *sink, hipStream_t st, double *work);
 
 }  // namespace cliff
