@@ -10,10 +10,19 @@ Default workload: n = 10,000 qubits, 20 layers of random H/S/CNOT-matching,
 measure all, 1 shot (the rowsum-dominated single-tableau case).
 
 One JSON line is printed with circuits/s, the roofline of the dominant kernel
-(the rowsum sweep: algorithmic bytes from the device-side counters divided by
-the sweep kernels' time from HIP events recorded on their stream around every
-launch of the timed steps) and the CPU oracle timed on a bounded sample of
-the same workload.
+and the CPU oracle timed on a bounded sample of the same workload.  The
+dominant kernel is the register-resident rowsum kernel k_meas_xz, which keeps
+the tableau in registers and LDS, so its bound is the ALU: its algorithmic
+32-bit lane operations (from the device-side support counters) over its time
+(HIP events recorded on its stream around every launch of the timed steps),
+against the MI355X's vector rate.  The HBM-equivalent rate of the same sweep
+is kept as effective_alg_gbs.  On the per-measurement path (n > 10,240) the
+sweep streams the tableau through HBM and is reported against HBM.
+
+Further legs on the same line: the n = 64 and n = 1,024 workloads, the
+batched 4,096-circuit workload (batched vs one circuit per launch, wall and
+kernel-only), the serving workload, the paper's Fig. 2a sweep of uniformly
+random Cliffords over n, and the n = 25,000 HBM-bound sweep.
 """
 from __future__ import annotations
 
@@ -29,6 +38,9 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0   # MI355X HBM3E peak
 LDS_PEAK_GBS = 256 * 128 * 2.4   # 256 CUs x 128 B/clk x 2.4 GHz = 78,643 GB/s
+# MI355X vector ALU: 157.3 TFLOP/s fp32 counts a fused multiply-add as two
+# operations, so the chip retires 78.6e12 32-bit lane operations per second
+VALU_PEAK_TOPS = 157.3 / 2
 
 # HBM bytes per launch of the dominant kernel from hardware counters
 # (FETCH_SIZE and WRITE_SIZE, each scaled by what it reads for a copy of known
@@ -36,8 +48,8 @@ LDS_PEAK_GBS = 256 * 128 * 2.4   # 256 CUs x 128 B/clk x 2.4 GHz = 78,643 GB/s
 TRAFFIC = {
     "k_meas_xz": {
         "sources": ("paper_2408_00384_amd/csrc/measure_persist.hip", "paper_2408_00384_amd/csrc/internal.h"),
-        "sha256": "02882917b882bc270beb0d630402ac2db26ea07aeaecf0c365d1757aec001176",
-        "bytes_per_launch": 1.121e+09,
+        "sha256": "12b2e3a34d4a3d5cf753ee2261711d3ac66cf81453b6bb501f34d97c2fddb354",
+        "bytes_per_launch": 1.1217e+09,
         "summary": "profiles/k_meas_xz_plain_n10000_measure_all.md",
     },
 }
@@ -58,6 +70,42 @@ WORKLOADS = {
     "mid": dict(desc="plain CHP n=1024, 100 layers, measure all, 128 shots", steps=5, warmup=1),
     "large": dict(desc="plain CHP n=10000, 20 layers, measure all, 1 shot", steps=3, warmup=1),
 }
+
+
+def alu_roofline(counters, n, steps, sweep_ms, launches, traffic):
+    """Roofline of the register-resident rowsum kernel (k_meas_xz).
+
+    Per random measurement with pivot-row support s (columns where the pivot
+    row is not I), s_x (with an X part) and s_z (with a Z part), the sweep
+    does per 64-bit row word of a supported column: the anticommuting rows
+    (1 op, 2 for Y), the -1 rows (1), the mod-4 counter (3) and the updates of
+    the planes the pivot row touches (1 each): 4 s + 2 (s_x + s_z) word
+    operations, i.e. 8 s + 4 (s_x + s_z) = 4 (2 s + s_x + s_z) 32-bit lane
+    operations per row word.  The device counters give sum(2 s + s_x + s_z)
+    through the algorithmic bytes (8 W (2 s + s_x + s_z + 3) + 80 n per random
+    measurement, 8 n W per deterministic one)."""
+    W = (2 * n + 63) // 64
+    nr, nd = counters["random"], counters["deterministic"]
+    sup = (counters["alg_bytes"] - nr * (24 * W + 80 * n) - nd * 8 * n * W) // (8 * W)
+    ops_step = 4 * W * sup
+    ops_launch = steps * ops_step / max(1, launches)
+    avg_s = sweep_ms * 1e-3 / max(1, launches)
+    achieved = ops_launch / avg_s / 1e12 if avg_s > 0 else 0.0
+    sweep_bytes = counters["alg_bytes"] - (8 * W * 3 + 80 * n) * nr
+    return {
+        "kernel": "k_meas_xz (register-resident rowsum sweep, one launch per chunk of measurements)",
+        "bound": "alu", "achieved": achieved, "peak": VALU_PEAK_TOPS, "unit": "TOP/s",
+        "frac": achieved / VALU_PEAK_TOPS,
+        "traffic": traffic,
+        "launches": launches, "avg_launch_us": avg_s * 1e6,
+        "alg_lane_ops_per_launch": ops_launch,
+        "support_sum_per_step": int(sup),
+        "effective_alg_gbs": steps * sweep_bytes / (sweep_ms * 1e-3) / 1e9 if sweep_ms > 0 else 0.0,
+        "note": "32-bit lane operations 4 W sum(2 s + s_x + s_z) per launch over the launch time; peak "
+                "157.3 TFLOP/s fp32 / 2 = 78.6e12 lane ops/s (65.8e12 measured for v_xor_b32 by "
+                "cliff_calibrate); effective_alg_gbs = the sweep's HBM-streaming bytes over the same time "
+                "(the tableau stays on chip, so this exceeds HBM and is not a roofline)",
+    }
 
 
 def make_circuit(name):
@@ -106,10 +154,56 @@ def cpu_baseline(c, budget_s: float):
     }
 
 
+def bench_plain(P, torch, np, name, steps, warmup, cpu_budget):
+    """One of the plain single-circuit workloads (n = 64 or n = 1,024): the
+    step of the headline leg (init, encoded layers already in HBM, measure all
+    shots, outcomes to the host), circuits/s over `steps` steps, outcomes of
+    every shot against the oracle (run live for n = 64, stored for all 128
+    shots of n = 1,024), and the oracle's own rate on a bounded sample."""
+    c = make_circuit(name)
+    ctx = P.Context(0)
+    tab = P.DeviceTableau(ctx, c.n, c.shots, init=False)
+    ops, offs = P.cliff_encode_layers(c.n, c.h, c.s, c.ctrl, c.tgt)
+    dev_ops = torch.from_numpy(ops.view(np.int64)).to("cuda:0")
+    torch.cuda.synchronize()
+
+    def step():
+        P.cliff_tab_init_zero(tab.handle)
+        P.cliff_apply_encoded(tab.handle, dev_ops.data_ptr(), offs)
+        return P.cliff_measure(tab.handle, c.qubits, c.seed, c.circuit_id, 0, 0)
+
+    for _ in range(warmup):
+        step()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        out, rnd = step()
+    wall = (time.perf_counter() - t0) / steps
+    parity = None
+    if name == "small":
+        import oracle
+        parity = all(bool(np.array_equal(out[s], oracle.run_shot(c, s)[0])) for s in range(c.shots))
+    else:
+        rec = json.load(open(os.path.join(ROOT, "tests", "golden", "plain_mid.json")))
+        parity = all(bool(np.array_equal(out[int(s)], np.unpackbits(np.frombuffer(bytes.fromhex(v["outcomes"]),
+                                                                                  np.uint8), bitorder="little")[:c.n]))
+                     for s, v in rec["shots"].items())
+    tab.close()
+    ctx.close()
+    return {"workload": WORKLOADS[name]["desc"], "circuits_per_s": 1.0 / wall, "us_per_circuit": wall * 1e6,
+            "steps": steps, "random_measurements": int(rnd.sum()),
+            "parity_all_shots_vs_oracle": parity,
+            "cpu_baseline": cpu_baseline(c, cpu_budget) if cpu_budget else None}
+
+
 def bench_batch(P, torch, np, count=4096, plain_sample=48, reps=5):
     """Batched workload: all circuits in one graph-captured sequence of
     persistent launches vs the plain path (one circuit at a time through the
-    HBM kernels) on a sample of the same circuits; outcomes compared bit-exact."""
+    HBM kernels) on a sample of the same circuits; outcomes compared bit-exact.
+    The plain path is timed twice: on the wall clock with a tableau
+    allocation, host encoding and upload per circuit, and kernel-only (op
+    streams pre-encoded and resident, tableaux pre-bound, every circuit
+    enqueued on one stream and timed with HIP events on it)."""
     from inputs import batch_workload
     from paper_2408_00384_amd.batch import BatchPlan, load_tuning
     t0 = time.perf_counter()
@@ -149,17 +243,56 @@ def bench_batch(P, torch, np, count=4096, plain_sample=48, reps=5):
         tab.close()
     torch.cuda.synchronize()
     plain_s = (time.perf_counter() - t2) / len(idx)
+    # kernel-only plain path: everything resident, one stream, events around it
+    kstream = torch.cuda.Stream()
+    kctx = P.Context(0, kstream)
+    ktabs, kops = [], []
+    for i in idx:
+        c = circs[i]
+        ops, offs = P.cliff_encode_layers(c.n, c.h, c.s, c.ctrl, c.tgt)
+        kops.append((torch.from_numpy(ops.view(np.int64)).to("cuda:0"), offs))
+        ktabs.append(P.DeviceTableau(kctx, c.n, c.shots, init=False))
+    torch.cuda.synchronize()
+
+    def plain_kernels():
+        for i, t, (d, offs) in zip(idx, ktabs, kops):
+            c = circs[i]
+            P.cliff_tab_init_zero(t.handle)
+            P.cliff_apply_encoded(t.handle, d.data_ptr(), offs)
+            P.cliff_measure_async(t.handle, c.qubits, c.seed, c.circuit_id, 0, 0)
+
+    with torch.cuda.stream(kstream):
+        plain_kernels()   # warm-up
+        kctx.sync()
+        k0, k1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        k0.record(kstream)
+        plain_kernels()
+        k1.record(kstream)
+        kctx.sync()
+    plain_kernel_s = k0.elapsed_time(k1) * 1e-3 / len(idx)
+    for i, t in zip(idx, ktabs):
+        o, _ = P.cliff_tab_read_outcomes(t.handle, len(circs[i].qubits))
+        parity &= bool(np.array_equal(o, outs[i]))
+        t.close()
+    kctx.close()
+    pctx.close()
     # the plain path's time depends on n: weight the sample to the whole batch
     ns = np.array([c.n for c in circs])
     plan.close()
+    ctx.close()
     return {
         "workload": "%d circuits, n ~ U{8..256}, depth ~ U{n..4n}, measure all, 4 shots" % count,
         "circuits_per_s": count / (ev_ms * 1e-3),
         "ms_per_batch": ev_ms, "ms_per_batch_wall": wall * 1e3,
         "plain_circuits_per_s": 1.0 / plain_s,
+        "plain_kernel_circuits_per_s": 1.0 / plain_kernel_s,
         "plain_sample": "%d evenly spaced circuits (mean n %.0f vs %.0f in the batch), one at a time"
                         % (len(idx), ns[idx].mean(), ns.mean()),
         "batched_vs_plain": (count / (ev_ms * 1e-3)) * plain_s,
+        "batched_vs_plain_kernel": (count / (ev_ms * 1e-3)) * plain_kernel_s,
+        "plain_timing": "batched_vs_plain: plain path on the wall clock, a tableau allocated, gates encoded on "
+                        "the host and uploaded per circuit; batched_vs_plain_kernel: op streams pre-encoded in "
+                        "HBM, tableaux pre-bound, all circuits enqueued on one stream, HIP events around them",
         "bit_exact_vs_plain": parity,
         "device_checks": status,
         "teams": {str(k): v for k, v in load_tuning().items()},
@@ -279,20 +412,33 @@ def _tab_digest(x, z, r):
     return h.hexdigest()
 
 
-def bench_clifford(P, torch, np, n=1000, count=100, seed=5, reps=3, oracle_circuits=1):
-    """The paper's Fig. 2a workload: `count` uniformly random Clifford circuits
-    on n qubits, gates only, from |0...0>.  Op streams resident in HBM; one
-    many-tableau launch for all circuits vs one launch per circuit (plain);
-    tableaux compared bit for bit between the two, circuit 0 against the
-    oracle's stored digest; the oracle timed on `oracle_circuits` circuits."""
+FIG2A_NS = tuple(range(100, 1001, 100))
+
+
+def gen_cliffords(ns, count=100, seed=5):
+    """Circuit i of size n: generator seed [seed, n, i].  Drawn in worker
+    processes forked before this process touches the GPU (so no child
+    inherits GPU state, and the pool leaves no helper process behind)."""
     import concurrent.futures as cf
     import multiprocessing as mp
-    t0 = time.perf_counter()
     workers = max(1, min(16, os.cpu_count() or 1))
-    # children only draw circuits (numpy); spawn, so none inherits GPU state
-    with cf.ProcessPoolExecutor(workers, mp_context=mp.get_context("spawn")) as ex:
-        lists = list(ex.map(_gen_clifford, [(n, seed, i) for i in range(count)]))
-    gen_s = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    with cf.ProcessPoolExecutor(workers, mp_context=mp.get_context("fork")) as ex:
+        lists = list(ex.map(_gen_clifford, [(n, seed, i) for n in ns for i in range(count)]))
+    out = {n: lists[k * count:(k + 1) * count] for k, n in enumerate(ns)}
+    return out, time.perf_counter() - t0
+
+
+def bench_clifford(P, torch, np, n, lists, seed=5, reps=3, oracle_circuits=1):
+    """The paper's Fig. 2a workload at one n: uniformly random Clifford
+    circuits on n qubits, gates only, from |0...0>.  Op streams resident in
+    HBM; one many-tableau launch for all circuits vs one launch per circuit
+    (plain); tableaux compared bit for bit between the two, and against the
+    oracle's stored digests where they exist; the oracle timed on
+    `oracle_circuits` circuits."""
+    import concurrent.futures as cf
+    count = len(lists)
+    workers = max(1, min(16, os.cpu_count() or 1))
     t0 = time.perf_counter()
     with cf.ThreadPoolExecutor(workers) as ex:   # the encoder runs without the GIL
         enc = list(ex.map(lambda l: P.cliff_encode_gates(n, *l), lists))
@@ -344,6 +490,7 @@ def bench_clifford(P, torch, np, n=1000, count=100, seed=5, reps=3, oracle_circu
                 digests[name].append(_tab_digest(x, z, r[0]))
     for t in tabs:
         t.close()
+    ctx.close()
     golden = os.path.join(ROOT, "tests", "golden", "clifford_n%d.json" % n)
     vs_oracle = None
     if os.path.exists(golden) and seed == 5:
@@ -361,8 +508,7 @@ def bench_clifford(P, torch, np, n=1000, count=100, seed=5, reps=3, oracle_circu
                "sample": "%d of the %d circuits, gates only" % (oracle_circuits, count)}
     b = res["batched"]
     return {
-        "workload": "%d uniformly random Clifford circuits (Bravyi-Maslov canonical form), n = %d, "
-                    "gates only, from |0...0>" % (count, n),
+        "n": n, "circuits": count,
         "circuits_per_s": b["circuits_per_s"],
         "gates_per_circuit": gates / count,
         "layers_per_circuit": float(np.mean(layers)),
@@ -373,8 +519,19 @@ def bench_clifford(P, torch, np, n=1000, count=100, seed=5, reps=3, oracle_circu
         "bit_exact_batched_vs_plain": digests["batched"] == digests["plain"],
         "bit_exact_vs_oracle_stored": vs_oracle,
         "cpu_baseline": cpu,
-        "generate_s": gen_s, "encode_s": enc_s,
+        "encode_s": enc_s,
     }
+
+
+def bench_fig2a(P, torch, np, lists_by_n, gen_s):
+    """Fig. 2a's curve: 100 uniformly random Cliffords per n, n = 100..1000."""
+    rows = []
+    for n in sorted(lists_by_n):
+        print("#   n = %d" % n, file=sys.stderr, flush=True)
+        rows.append(bench_clifford(P, torch, np, n, lists_by_n[n]))
+    return {"workload": "100 uniformly random Clifford circuits (Bravyi-Maslov canonical form) per n, gates "
+                        "only, from |0...0>; circuit i of size n from generator seed [5, n, i]",
+            "generate_s": gen_s, "per_n": rows}
 
 
 def bench_xlarge(P, torch, np, k=256, reps=2):
@@ -420,6 +577,7 @@ def bench_xlarge(P, torch, np, k=256, reps=2):
         parity = bool(np.array_equal(out[0][:kk], bits(rec["outcomes"])) and
                       np.array_equal(rnd[:kk], bits(rec["random"])))
     tab.close()
+    ctx.close()
     return {
         "workload": "n = 25,000, 20 layers (generator seed 6), qubits 0..%d measured, 1 shot" % (k - 1),
         "tableau_bytes": 2 * n * W * 8,
@@ -431,38 +589,48 @@ def bench_xlarge(P, torch, np, k=256, reps=2):
     }
 
 
-def bench_serving(P, np, count=96, seed=4, budget=64 << 30, lanes=8, cpu=True):
+def bench_serving(P, np, count=1000, sat_count=200, cpu_count=96, seed=4, budget=64 << 30, lanes=8,
+                  cpu=True):
     """Serving workload: n log-uniform in [16, 4096], depth 2n, shots in
-    [1, 1024], admission by tableau bytes against a 64 GB budget.  First a
-    closed-loop pass (every request admitted at once) gives the saturated
-    throughput; then Poisson arrivals at 70% of it give the latencies."""
+    [1, 1024], admission against a 64 GB budget.  A closed-loop pass over the
+    first `sat_count` requests (every one admitted at once) gives the
+    saturated throughput; then all `count` requests arrive as a Poisson
+    stream at 70% of it, for the latencies; the requests served in both
+    passes must give the same outcomes.  The oracle is timed on the first
+    `cpu_count` requests."""
     from inputs import serving_params, serving_request
     from paper_2408_00384_amd.serving import Server, summarize
     arrivals, ns, shots = serving_params(count, 1.0, seed=seed)
     circs = [serving_request(i, arrivals, ns, shots, seed=seed).circuit for i in range(count)]
     srv = Server(budget_bytes=budget, lanes=lanes)
     t0 = time.perf_counter()
-    sat = srv.run(circs, np.zeros(count), realtime=False)
+    sat = srv.run(circs[:sat_count], np.zeros(sat_count), realtime=False)
     sat_s = time.perf_counter() - t0
-    sat_rate = count / sat_s
+    sat_rate = sat_count / sat_s
     rate = 0.7 * sat_rate
-    arrivals, _, _ = serving_params(count, rate, seed=seed)
+    print("#   saturated %.1f requests/s; Poisson at %.1f/s over %d requests" % (sat_rate, rate, count),
+          file=sys.stderr, flush=True)
+    arrivals = np.asarray(arrivals) / rate   # the same unit-rate draws, scaled to `rate`
     mix = srv.run(circs, arrivals, realtime=True)
-    same = all(np.array_equal(sat[i].outcomes, mix[i].outcomes) for i in range(count)
+    same = all(np.array_equal(sat[i].outcomes, mix[i].outcomes) for i in range(sat_count)
                if sat[i].error is None)
     st = summarize(mix)
+    peak = srv.alloc.peak
     srv.close()
     return {
         "workload": "%d requests, n log-uniform [16, 4096], depth 2n, shots U{1..1024}, "
                     "64 GB admission budget, %d HBM lanes + 1 batch lane" % (count, lanes),
         "saturated_circuits_per_s": sat_rate,
+        "saturated_sample": "closed loop over the first %d requests" % sat_count,
         "poisson_rate_hz": rate,
+        "latency_samples": st["completed"],
         "p50_ms": st["p50_ms"], "p99_ms": st["p99_ms"], "mean_ms": st["mean_ms"],
         "circuits_per_s": st["circuits_per_s"],
         "paths": st["paths"], "rejected": st["rejected"],
+        "arena_peak_bytes": peak,
         "outcomes_same_as_closed_loop": same,
         "max_n": int(max(ns)), "total_shots": int(sum(shots)),
-        "cpu_baseline": serving_cpu_baseline(circs, np) if cpu else None,
+        "cpu_baseline": serving_cpu_baseline(circs[:cpu_count], np) if cpu else None,
     }
 
 
@@ -487,7 +655,11 @@ def main():
     ap.add_argument("--no-batch", action="store_true", help="skip the batched-circuits leg")
     ap.add_argument("--no-serving", action="store_true", help="skip the serving leg")
     ap.add_argument("--no-clifford", action="store_true",
-                    help="skip the uniform-random-Clifford (gates only) leg")
+                    help="skip the uniform-random-Clifford (gates only) sweep over n")
+    ap.add_argument("--no-plain-legs", action="store_true",
+                    help="skip the n = 64 and n = 1,024 workloads")
+    ap.add_argument("--serving-only", action="store_true",
+                    help="run only the serving leg (for a kernel trace of it); prints its JSON")
     ap.add_argument("--no-xlarge", action="store_true",
                     help="skip the n = 25,000 HBM-bound measurement leg")
     ap.add_argument("--no-profile", action="store_true",
@@ -518,9 +690,20 @@ def main():
               "single-GPU); run with --gpus 1", file=sys.stderr)
         sys.exit(2)
 
+    # circuits of the Fig. 2a sweep, drawn before anything touches the GPU
+    fig2a_lists, fig2a_gen_s = None, 0.0
+    if not (args.no_clifford or args.serving_only):
+        print("# drawing uniformly random Cliffords for n = %s ..." % (FIG2A_NS,), file=sys.stderr, flush=True)
+        fig2a_lists, fig2a_gen_s = gen_cliffords(FIG2A_NS)
+
     import numpy as np
     import torch
     import paper_2408_00384_amd as P
+
+    if args.serving_only:
+        print(json.dumps({"serving": bench_serving(P, np, cpu=False)}), flush=True)
+        torch.cuda.synchronize()
+        return
 
     wl = WORKLOADS[args.workload]
     steps = args.steps if args.steps is not None else wl["steps"]
@@ -582,8 +765,19 @@ def main():
     sweep_step = alg_step - (8 * W * 3 + 80 * n) * nr
     sweep_ms, sweep_launches = prof["sweep"]
     persistent = sweep_launches < steps * len(qubits)
-    achieved = steps * sweep_step / (sweep_ms * 1e-3) / 1e9 if sweep_ms > 0 else 0.0
     meas_ms = sum(prof[k][0] for k in ("select", "sweep", "final"))
+    if persistent:
+        roofline = alu_roofline(counters, n, steps, sweep_ms, sweep_launches,
+                                traffic_for("k_meas_xz") if args.workload == "large" else None)
+    else:
+        achieved = steps * sweep_step / (sweep_ms * 1e-3) / 1e9 if sweep_ms > 0 else 0.0
+        roofline = {"kernel": "k_step (rowsum sweep, one launch per measurement)",
+                    "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                    "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                    "launches": sweep_launches, "avg_launch_us": 1e3 * sweep_ms / max(1, sweep_launches),
+                    "alg_bytes_per_launch": steps * sweep_step / max(1, sweep_launches)}
+    tab.close()
+    ctx.close()
     print("# kernels over %d steps: " % steps
           + ", ".join("%s %.2f ms/%d" % (k, v[0], v[1]) for k, v in prof.items()),
           file=sys.stderr, flush=True)
@@ -606,16 +800,7 @@ def main():
                    "measurements": int(len(c.qubits)), "random_measurements": int(rnd.sum()),
                    "generator_seed": {"small": 0, "mid": 1, "large": 2}[args.workload]},
         "parity_vs_stored_oracle": parity,
-        "roofline": {
-            "kernel": ("k_meas_xz (register-resident rowsum sweep, one launch per chunk "
-                       "of measurements)" if persistent else
-                       "k_step (rowsum sweep, one launch per measurement)"),
-            "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-            "frac": achieved / HBM_PEAK_GBS,
-            "traffic": traffic_for("k_meas_xz") if persistent and args.workload == "large" else None,
-            "launches": sweep_launches, "avg_launch_us": 1e3 * sweep_ms / max(1, sweep_launches),
-            "alg_bytes_per_launch": steps * sweep_step / max(1, sweep_launches),
-        },
+        "roofline": roofline,
         "measure_phase": {
             "alg_bytes_per_step": alg_step,
             "ms_per_step": meas_ms / steps,
@@ -627,6 +812,14 @@ def main():
     if args.no_profile:
         result["roofline"] = None
         result.pop("measure_phase")
+    if not args.no_plain_legs:
+        budget = 0.0 if args.no_cpu_baseline else 10.0
+        for name in ("small", "mid"):
+            if name == args.workload:
+                continue
+            print("# plain %s ..." % name, file=sys.stderr, flush=True)
+            result["plain_" + name] = bench_plain(P, torch, np, name, WORKLOADS[name]["steps"],
+                                                  WORKLOADS[name]["warmup"], budget)
     if not args.no_batch:
         print("# batched circuits ...", file=sys.stderr, flush=True)
         result["batched"] = bench_batch(P, torch, np)
@@ -634,14 +827,16 @@ def main():
         print("# serving ...", file=sys.stderr, flush=True)
         result["serving"] = bench_serving(P, np, cpu=not args.no_cpu_baseline)
     if not args.no_clifford:
-        print("# uniform random Cliffords, gates only ...", file=sys.stderr, flush=True)
-        result["random_clifford"] = bench_clifford(P, torch, np)
+        print("# uniform random Cliffords, gates only, n = 100..1000 ...", file=sys.stderr, flush=True)
+        result["fig2a"] = bench_fig2a(P, torch, np, fig2a_lists, fig2a_gen_s)
+        result["random_clifford"] = result["fig2a"]["per_n"][-1]   # n = 1000
     if not args.no_xlarge:
         print("# n = 25,000, per-measurement kernels ...", file=sys.stderr, flush=True)
         result["xlarge_hbm"] = bench_xlarge(P, torch, np)
     if not args.no_cpu_baseline:
         print("# cpu baseline (oracle) ...", file=sys.stderr, flush=True)
         result["cpu_baseline"] = cpu_baseline(c, args.cpu_budget)
+    torch.cuda.synchronize()   # every context and tableau above is closed; nothing is left in flight
     print(json.dumps(result), flush=True)
 
 

@@ -4,7 +4,7 @@
     python tests/golden/make_golden.py shots1024 # n = 2,100, 1,024 shots: 18 sampled shots (~5 min)
     python tests/golden/make_golden.py serving  # three n >= 1,000 serving requests: prefixes (~2 min)
     python tests/golden/make_golden.py large    # n = 10,000, 1 shot (hours)
-    python tests/golden/make_golden.py clifford # n = 1,000 uniform random Cliffords (~40 s)
+    python tests/golden/make_golden.py clifford [n ...] # uniform random Cliffords (n = 1,000: ~40 s)
     python tests/golden/make_golden.py xlarge   # n = 25,000: first 32 measurements (~3 min, 2.5 GB)
 
 Values are the CPU oracle's results on the seeded circuits of ``inputs``;
@@ -197,7 +197,8 @@ if __name__ == "__main__":
     elif what == "large":
         make_large()
     elif what == "clifford":
-        make_clifford()
+        for n in (sys.argv[2:] or ["1000"]):
+            make_clifford(n=int(n))
     elif what == "xlarge":
         make_xlarge()
     else:

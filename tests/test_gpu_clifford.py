@@ -95,12 +95,14 @@ def test_many_tableaux_device_resident_streams_twice(ctx):
         _assert_equal(t.export(), ref)
 
 
-def test_n1000_vs_stored_oracle(ctx):
-    """Four n = 1,000 circuits (about 10^6 gates each) in one many-tableau
-    launch, and circuit 0 through the single-tableau path, against the
-    oracle's stored tableau digests."""
+@pytest.mark.parametrize("n", [200, 500, 1000])
+def test_vs_stored_oracle(ctx, n):
+    """Four uniformly random Clifford circuits of n = 200, 500 or 1,000 qubits
+    (about 10^6 gates each at n = 1,000) in one many-tableau launch, and
+    circuit 0 through the single-tableau path, against the oracle's stored
+    tableau digests."""
     from paper_2408_00384_amd import cliff_apply_gates_many
-    rec = json.load(open(os.path.join(GOLDEN, "clifford_n1000.json")))
+    rec = json.load(open(os.path.join(GOLDEN, "clifford_n%d.json" % n)))
     n = rec["n"]
     cs = [random_clifford(n, [5, n, int(i)]) for i in sorted(rec["circuits"], key=int)]
     for c, (i, v) in zip(cs, sorted(rec["circuits"].items(), key=lambda kv: int(kv[0]))):
