@@ -213,6 +213,11 @@ __global__ void __launch_bounds__(kThreads) k_meas_xz(TabDev t, PersistArgs a) {
 
 #pragma unroll 1
   for (uint32_t m = 0; m < a.k; ++m) {
+    // the lane index through an empty asm statement: values derived from it
+    // are recomputed here each iteration instead of being hoisted out of the
+    // loop and held in registers for its whole length
+    uint32_t ln = lane;
+    asm volatile("" : "+v"(ln));
     const uint32_t b = m & 1u;
     const uint32_t p = s_p[b];
     const uint64_t *col = s_col[b];
@@ -233,7 +238,7 @@ __global__ void __launch_bounds__(kThreads) k_meas_xz(TabDev t, PersistArgs a) {
     }
     const uint32_t gw = p != kNone ? wp : 0;
     const uint64_t g_lo = ld_relaxed64(nsrc + 2 * gw), g_hi = ld_relaxed64(nsrc + 2 * gw + 1);
-    if (p != kNone && lane == (wp & 63)) {
+    if (p != kNone && ln == (wp & 63)) {
       // the lane holding row p: its bits in the owned columns (every slot
       // read, no branch, so the LDS reads overlap; slots past ns hold zeros)
       const uint32_t ip = wp >> 6, sh = p & 63;
@@ -266,7 +271,7 @@ __global__ void __launch_bounds__(kThreads) k_meas_xz(TabDev t, PersistArgs a) {
 #pragma unroll
       for (int i = 0; i < L; ++i) {
         // the row mask M: rows other than p with x = 1 on the measured column
-        const uint32_t w = uint32_t(i) * 64 + lane;
+        const uint32_t w = uint32_t(i) * 64 + ln;
         mw[i] = w < W ? (w == wp ? col[w] & ~bpb : col[w]) : 0ull;
         c0[i] = c1[i] = 0;
       }
@@ -315,7 +320,7 @@ __global__ void __launch_bounds__(kThreads) k_meas_xz(TabDev t, PersistArgs a) {
       // low plane's carry taken from the atomic XOR's old value
 #pragma unroll
       for (int i = 0; i < L; ++i) {
-        const uint32_t w = uint32_t(i) * 64 + lane;
+        const uint32_t w = uint32_t(i) * 64 + ln;
         if (w < W) {
           const uint64_t old = atomicXor(&s_s0[w], (unsigned long long)c0[i]);
           atomicXor(&s_s1[w], (unsigned long long)(c1[i] ^ (old & c0[i])));
@@ -328,19 +333,19 @@ __global__ void __launch_bounds__(kThreads) k_meas_xz(TabDev t, PersistArgs a) {
 #pragma unroll
       for (int i = 0; i < L; ++i) {
         if (uint32_t(i) != ipn && uint32_t(i) != ip) continue;   // wave-uniform
-        const uint64_t mpn = (uint32_t(i) == ipn && lane == (wpn & 63)) ? bpn : 0ull;
-        const uint64_t mp = (uint32_t(i) == ip && lane == (wp & 63)) ? bpb : 0ull;
+        const uint64_t mpn = (uint32_t(i) == ipn && ln == (wpn & 63)) ? bpn : 0ull;
+        const uint64_t mp = (uint32_t(i) == ip && ln == (wp & 63)) ? bpb : 0ull;
 #pragma unroll
         for (int k = 0; k < CW; ++k)
           xr[k][i] = (xr[k][i] & ~(mpn | mp)) | (((xm >> k) & 1u) ? mpn : 0ull);
       }
       __builtin_amdgcn_wave_barrier();
-      if (lane < ns) {
-        uint64_t *zk = sZ + size_t(wave) * CW * L * 64 + size_t(lane) * L * 64;   // slot `lane`
+      if (ln < ns) {
+        uint64_t *zk = sZ + size_t(wave) * CW * L * 64 + size_t(ln) * L * 64;   // this lane's slot
         uint64_t &za = zk[ipn * 64 + (wpn & 63)];
-        za = ((zm >> lane) & 1u) ? (za | bpn) : (za & ~bpn);
+        za = ((zm >> ln) & 1u) ? (za | bpn) : (za & ~bpn);
         uint64_t &zb = zk[ip * 64 + (wp & 63)];
-        zb = (g + (wave + lane * kWaves) * G == am) ? (zb | bpb) : (zb & ~bpb);
+        zb = (g + (wave + ln * kWaves) * G == am) ? (zb | bpb) : (zb & ~bpb);
       }
     }
     if (m + 2 < a.k) {
@@ -358,7 +363,7 @@ __global__ void __launch_bounds__(kThreads) k_meas_xz(TabDev t, PersistArgs a) {
           if (uint32_t(k) != k2) continue;
 #pragma unroll
           for (int i = 0; i < L; ++i) {
-            const uint32_t w = uint32_t(i) * 64 + lane;
+            const uint32_t w = uint32_t(i) * 64 + ln;
             if (w < W) {
               st_relaxed64(dst + 2 * w, (xr[k][i] & 0xffffffffull) | tag);
               st_relaxed64(dst + 2 * w + 1, (xr[k][i] >> 32) | tag);
@@ -367,26 +372,22 @@ __global__ void __launch_bounds__(kThreads) k_meas_xz(TabDev t, PersistArgs a) {
         }
       }
     }
-    if (p == kNone) {
+    if (__builtin_expect(p == kNone, 0)) {
       // deterministic: per column, pairs s < t of product rows with z_s x_t
       // (prefix parity inside a word, carry across lanes and words in row
       // order) and the Y count; summed over the workgroup's columns
-      // (runtime loops, x picked out of the register array by selects: this
-      // branch is rare in dense states and must not cost registers)
+      uint64_t tm[L];
+#pragma unroll
+      for (int i = 0; i < L; ++i) tm[i] = det_word(col, n, t.NW, W, uint32_t(i) * 64 + ln);
       uint32_t ycnt = 0, par = 0;
-      const uint64_t below = pbit(lane) - 1;   // lanes before this one
-#pragma unroll 1
-      for (uint32_t k = 0; k < ns; ++k) {
+      const uint64_t below = pbit(ln) - 1;   // lanes before this one
+#pragma unroll
+      for (int k = 0; k < CW; ++k) {
+        if (uint32_t(k) >= ns) continue;       // wave-uniform
         uint32_t carry = 0;                    // z parity of the product rows in earlier words
-#pragma unroll 1
-        for (uint32_t i = 0; i < uint32_t(L); ++i) {
-          uint64_t xv = 0;
 #pragma unroll
-          for (int kk = 0; kk < CW; ++kk)
-#pragma unroll
-            for (int ii = 0; ii < L; ++ii) xv = (uint32_t(kk) == k && uint32_t(ii) == i) ? xr[kk][ii] : xv;
-          const uint64_t tm = det_word(col, n, t.NW, W, i * 64 + lane);
-          const uint64_t xt = xv & tm, zt = zw[(k * L + i) * 64] & tm;
+        for (int i = 0; i < L; ++i) {
+          const uint64_t xt = xr[k][i] & tm[i], zt = zw[(k * L + i) * 64] & tm[i];
           ycnt += uint32_t(__popcll(xt & zt));
           uint64_t pre = zt << 1;
           pre ^= pre << 1; pre ^= pre << 2; pre ^= pre << 4;
@@ -399,7 +400,7 @@ __global__ void __launch_bounds__(kThreads) k_meas_xz(TabDev t, PersistArgs a) {
       }
       const uint64_t pb = __ballot(par & 1u);
       for (int off = 32; off > 0; off >>= 1) ycnt += __shfl_xor(ycnt, off);
-      if (lane == 0) {
+      if (ln == 0) {
         if (__popcll(pb) & 1) atomicXor(&s_par, 1u);
         if (ycnt) atomicAdd(&s_y, ycnt);
       }
@@ -434,7 +435,7 @@ __global__ void __launch_bounds__(kThreads) k_meas_xz(TabDev t, PersistArgs a) {
           s_col[b ^ 1u][w] = v;
           if (g == 0) t.SNall[size_t(m + 1) * t.Wp + w] = v;   // for the kernels after this one
         }
-        wave_min_into(pivot_candidate(v, w, n, W), lane, &s_p[b ^ 1u]);
+        wave_min_into(pivot_candidate(v, w, n, W), ln, &s_p[b ^ 1u]);
       }
       if (!ok) s_abort = 1;
     }
