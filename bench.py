@@ -205,7 +205,7 @@ def bench_batch(P, torch, np, count=4096, plain_sample=48, reps=5):
     streams pre-encoded and resident, tableaux pre-bound, every circuit
     enqueued on one stream and timed with HIP events on it)."""
     from inputs import batch_workload
-    from paper_2408_00384_amd.batch import BatchPlan, load_tuning
+    from paper_2408_00384_amd.batch import BatchPlan
     t0 = time.perf_counter()
     circs = batch_workload(count)
     gen_s = time.perf_counter() - t0
@@ -226,6 +226,7 @@ def bench_batch(P, torch, np, count=4096, plain_sample=48, reps=5):
         ev_ms = ev0.elapsed_time(ev1) / reps
         outs = plan.outcomes()
     status = plan.status()
+    buckets = [{k: b[k] for k in ("edge", "team", "maxn", "max_shots", "count")} for b in plan.buckets]
     lds_bytes = batch_lds_bytes(plan, np)
     lds_meas = P.cliff_calibrate(ctx.handle, P.CAL_LDS) / 1e9
     valu_meas = P.cliff_calibrate(ctx.handle, P.CAL_VALU)
@@ -295,7 +296,7 @@ def bench_batch(P, torch, np, count=4096, plain_sample=48, reps=5):
                         "HBM, tableaux pre-bound, all circuits enqueued on one stream, HIP events around them",
         "bit_exact_vs_plain": parity,
         "device_checks": status,
-        "teams": {str(k): v for k, v in load_tuning().items()},
+        "buckets": buckets,
         "lds": {"alg_bytes_per_batch": lds_bytes, "achieved_gbs": lds_bytes / (ev_ms * 1e-3) / 1e9,
                 "peak_gbs": LDS_PEAK_GBS, "frac": lds_bytes / (ev_ms * 1e-3) / 1e9 / LDS_PEAK_GBS,
                 "measured_peak_gbs": lds_meas,

@@ -350,16 +350,21 @@ int cliff_ctx_profile_read(cliff_ctx *ctx, int kind, double *ms, uint64_t *launc
  * LDS of one workgroup).  Circuit i is described by descs[i]: n qubits
  * (1 <= n <= maxn of the launch), `depth` layers whose encoded ops (see
  * cliff_encode_layers) start at word ops_off of dev_ops, with the layer
- * boundaries offs[offs_off .. offs_off+depth] (relative to ops_off), `shots`
+ * boundaries offs[offs_off .. offs_off+depth] (relative to ops_off; the ops
+ * of one layer act on distinct qubits, as cliff_encode_layers emits them), `shots`
  * sign columns (1..64), and outcomes written as uint8 [shots][n] at byte
  * out_off of dev_out after measuring qubits 0..n-1 in order (measurement index
  * m = qubit, shot index 0..shots-1, circuit index circuit_id for the random
  * bit).  Workgroups take circuits in the order dev_order[0..count) from a
- * device queue.  team (threads per circuit) and maxn select the kernel
- * instance: (64,64) (128,64) (64,128) (128,128) (256,128) (512,128) (128,256)
- * (256,256) (512,256) (1024,256).  dev_work: cliff_batch_work_bytes() bytes of device scratch,
+ * device queue.  team: threads per circuit, 64, 128, 256, 512 or 1024.
+ * maxn (1..256) and max_shots (1..64) size each workgroup's LDS, about
+ * 16 maxn ceil(2 maxn / 64) + 8 ceil(2 maxn / 64) max_shots bytes: a
+ * descriptor with n > maxn or shots > max_shots is skipped and counted as
+ * rejected, and the smaller the bounds, the more circuits run side by side on
+ * a compute unit.  dev_work: cliff_batch_work_bytes() bytes of device scratch,
  * reset by the launch.  All pointers are device pointers; nothing is copied
- * to the host and the call only enqueues work. */
+ * to the host and the call only enqueues work.  CLIFF_EINVAL for a team,
+ * maxn or max_shots out of range. */
 typedef struct {
     uint32_t n, depth, shots, reserved;
     uint64_t ops_off, offs_off, out_off, circuit_id;
@@ -368,7 +373,8 @@ typedef struct {
 size_t cliff_batch_work_bytes(void);
 int cliff_batch_run(cliff_ctx *ctx, const cliff_batch_desc *dev_descs, const uint64_t *dev_ops,
                     const uint32_t *dev_offs, uint8_t *dev_out, const uint32_t *dev_order,
-                    uint32_t count, uint64_t seed, void *dev_work, uint32_t team, uint32_t maxn);
+                    uint32_t count, uint64_t seed, void *dev_work, uint32_t team, uint32_t maxn,
+                    uint32_t max_shots);
 /* out2[0] = descriptors rejected (n or shots out of range), out2[1] = device
  * consistency-check failures, of the last launch using dev_work.  Synchronizes. */
 int cliff_batch_status(cliff_ctx *ctx, const void *dev_work, uint64_t *out2);

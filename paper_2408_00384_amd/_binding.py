@@ -97,7 +97,7 @@ _SIGS = {
     "cliff_ctx_profile": (ctypes.c_int, [_vp, ctypes.c_int]),
     "cliff_ctx_profile_read": (ctypes.c_int, [_vp, ctypes.c_int, ctypes.POINTER(ctypes.c_double), _u64p]),
     "cliff_batch_work_bytes": (_sz, []),
-    "cliff_batch_run": (ctypes.c_int, [_vp, _vp, _vp, _vp, _vp, _vp, _u32, _u64, _vp, _u32, _u32]),
+    "cliff_batch_run": (ctypes.c_int, [_vp, _vp, _vp, _vp, _vp, _vp, _u32, _u64, _vp, _u32, _u32, _u32]),
     "cliff_batch_status": (ctypes.c_int, [_vp, _vp, _u64p]),
     "cliff_graph_begin": (ctypes.c_int, [_vp]),
     "cliff_graph_end": (ctypes.c_int, [_vp, ctypes.POINTER(_vp)]),
@@ -443,8 +443,8 @@ def cliff_ctx_profile_read(ctx, kind):
 BATCH_DESC_DTYPE = np.dtype([("n", np.uint32), ("depth", np.uint32), ("shots", np.uint32),
                              ("reserved", np.uint32), ("ops_off", np.uint64), ("offs_off", np.uint64),
                              ("out_off", np.uint64), ("circuit_id", np.uint64)])
-BATCH_CONFIGS = ((64, 64), (128, 64), (64, 128), (128, 128), (256, 128), (512, 128), (128, 256),
-                 (256, 256), (512, 256), (1024, 256))
+BATCH_TEAMS = (64, 128, 256, 512, 1024)   # threads per circuit of the batch kernel
+BATCH_MAXN = 256                           # largest batched circuit
 
 
 def cliff_batch_work_bytes() -> int:
@@ -452,9 +452,9 @@ def cliff_batch_work_bytes() -> int:
 
 
 def cliff_batch_run(ctx, descs_ptr, ops_ptr, offs_ptr, out_ptr, order_ptr, count, seed, work_ptr,
-                    team, maxn):
+                    team, maxn, max_shots=64):
     _check(_lib.cliff_batch_run(ctx, descs_ptr, ops_ptr, offs_ptr, out_ptr, order_ptr, count, seed,
-                                work_ptr, team, maxn), "cliff_batch_run")
+                                work_ptr, team, maxn, max_shots), "cliff_batch_run")
 
 
 def cliff_batch_status(ctx, work_ptr):
@@ -485,5 +485,5 @@ __all__ = [n for n in list(globals()) if n.startswith("cliff_")] + [
     "CLIFF_OK", "CLIFF_EINVAL", "CLIFF_ENOMEM", "CLIFF_EDEVICE", "CLIFF_EBUSY",
     "CLIFF_EINTERNAL", "OP_H", "OP_S", "OP_CNOT", "OP_SDG", "OP_X", "OP_Y", "OP_Z", "OP_CZ",
     "OP_SWAP", "BASIS_Z", "BASIS_X", "BASIS_Y", "CliffError", "LIB_PATH", "exported_symbols",
-    "PROF_KINDS", "BATCH_DESC_DTYPE", "BATCH_CONFIGS", "GATES_AUTO", "GATES_PER_LAYER",
+    "PROF_KINDS", "BATCH_DESC_DTYPE", "BATCH_TEAMS", "BATCH_MAXN", "GATES_AUTO", "GATES_PER_LAYER",
     "GATES_FUSED", "MEASURE_AUTO", "MEASURE_STEP", "MEASURE_PERSISTENT", "CAL_LDS", "CAL_VALU"]

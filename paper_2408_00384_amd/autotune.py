@@ -1,14 +1,19 @@
-"""Autotuner for the batched-circuit kernel: team size per size bucket.
+"""Autotuner for the batched-circuit kernel: bucket edges and team sizes.
 
     python -m paper_2408_00384_amd.autotune [--batch 4096] [--reps 3]
 
-For every size bucket (max n 64 / 128 / 256) it draws that bucket's share of a
-batch of the batched workload's distribution (n uniform in [8, 256], so the
-bucket's share of the n range; depth uniform in [n, 4n], 4 shots), times every
-compiled team size on them (HIP events around
-the persistent launch, median of several runs, after checking that all team
-sizes give identical outcome bytes), and writes the fastest choice per bucket
-to tuning/batch_gfx950.json, which BatchPlan reads.
+The batch is split into buckets by n, each run as one persistent launch whose
+LDS is sized for its largest circuit: finer buckets let small circuits run
+more teams per compute unit, coarser ones pay fewer launch tails.  Candidate
+edges are the row-word classes n in (32 (k - 1), 32 k], k = 1..8 (a circuit
+of class k has k 64-bit row words per column).  For every contiguous range of
+classes and every team size the tuner times one launch over those circuits of
+a batch drawn from the batched workload's distribution (n uniform in [8, 256],
+depth uniform in [n, 4n], 4 shots; its own generator seed, not the benchmark's
+batch), checks that all team sizes give identical outcome bytes, and picks the
+partition and teams with the least total time by dynamic programming (the
+launches of a plan run back to back, so their times add).  The result goes to
+tuning/batch_gfx950.json, which BatchPlan reads.
 """
 from __future__ import annotations
 
@@ -22,17 +27,16 @@ import numpy as np
 import torch
 
 from . import _binding as B
-from .batch import BUCKETS, TUNING_PATH, BatchPlan
+from .batch import DEFAULT_TEAMS, TUNING_PATH, BatchPlan
 from .device import Context
 
+CLASSES = 8   # row-word classes: n in (32 (k - 1), 32 k]
 
-def bucket_circuits(maxn: int, count: int, seed: int = 17):
-    from inputs import batch_circuit
-    lo = 8 if maxn == BUCKETS[0] else BUCKETS[BUCKETS.index(maxn) - 1] + 1
-    rng = np.random.Generator(np.random.PCG64([seed, maxn]))
-    ns = rng.integers(lo, maxn + 1, size=count)
-    depths = rng.integers(ns, 4 * ns + 1)
-    return [batch_circuit(i, ns, depths, seed=seed + maxn, shots=4) for i in range(count)]
+
+def tuning_batch(count: int, seed: int = 17):
+    from inputs import batch_circuit, batch_sizes
+    ns, depths = batch_sizes(count, seed=seed)
+    return [batch_circuit(i, ns, depths, seed=seed, shots=4) for i in range(count)]
 
 
 def time_plan(plan, reps: int) -> float:
@@ -49,44 +53,85 @@ def time_plan(plan, reps: int) -> float:
     return float(np.median(times))
 
 
-def bucket_share(maxn: int, batch: int) -> int:
-    """Circuits of a `batch`-circuit workload with n uniform in [8, 256] that
-    fall in the bucket: the choice is a throughput one (many circuits per CU
-    at once), so the bucket is timed at its real size, not on a small sample."""
-    lo = 8 if maxn == BUCKETS[0] else BUCKETS[BUCKETS.index(maxn) - 1] + 1
-    return max(1, round(batch * (maxn - lo + 1) / (BUCKETS[-1] - 8 + 1)))
+def word_class(n: int) -> int:
+    return (n + 31) // 32
+
+
+def best_partition(cost):
+    """cost[(i, j)] = (ms, team) of classes i..j (1-based, inclusive), or None
+    for a range without circuits.  Returns (total ms, [(edge, team, ms)])."""
+    best = {0: (0.0, [])}
+    for j in range(1, CLASSES + 1):
+        cands = []
+        for i in range(1, j + 1):
+            ms_team = cost[(i, j)]
+            prev_ms, prev_parts = best[i - 1]
+            if ms_team is None:
+                cands.append((prev_ms, prev_parts))
+            else:
+                ms, team = ms_team
+                cands.append((prev_ms + ms, prev_parts + [(32 * j, team, ms)]))
+        best[j] = min(cands, key=lambda c: c[0])
+    return best[CLASSES]
 
 
 def autotune(batch: int = 4096, reps: int = 3, out_path: str = TUNING_PATH):
     stream = torch.cuda.Stream()
     ctx = Context(0, stream)
+    circs = tuning_batch(batch)
+    encoded = [B.cliff_encode_layers(c.n, c.h, c.s, c.ctrl, c.tgt) for c in circs]
+    cls = np.array([word_class(c.n) for c in circs])
     rec = {"device": torch.cuda.get_device_name(0), "created": time.strftime("%Y-%m-%d %H:%M:%S"),
-           "batch": batch, "circuits_per_bucket": {}, "reps": reps, "timings_ms": {}, "best": {}}
-    for maxn in BUCKETS:
-        circs = bucket_circuits(maxn, bucket_share(maxn, batch))
-        rec["circuits_per_bucket"][str(maxn)] = len(circs)
-        teams = [t for (t, m) in B.BATCH_CONFIGS if m == maxn]
-        ref = None
-        timings = {}
-        for team in teams:
+           "batch": batch, "reps": reps, "circuits_per_class": {str(k): int((cls == k).sum())
+                                                                 for k in range(1, CLASSES + 1)},
+           "timings_ms": {}, "best": {}}
+    cost = {}
+    for i in range(1, CLASSES + 1):
+        for j in range(i, CLASSES + 1):
+            idx = np.nonzero((cls >= i) & (cls <= j))[0]
+            if len(idx) == 0:
+                cost[(i, j)] = None
+                continue
+            sub = [circs[k] for k in idx]
+            enc = [encoded[k] for k in idx]
+            edge = 32 * j
+            ref, timings = None, {}
             with torch.cuda.stream(stream):
-                plan = BatchPlan(ctx, circs, teams={maxn: team})
-                ms = time_plan(plan, reps)
-                outs = plan.outcomes()
-            st = plan.status()
-            if st["rejected"] or st["anomalies"]:
-                raise RuntimeError("batch kernel reported %s (team %d, maxn %d)" % (st, team, maxn))
-            if ref is None:
-                ref = outs
-            elif not all(np.array_equal(a, b) for a, b in zip(ref, outs)):
-                raise RuntimeError("team sizes disagree for maxn %d" % maxn)
-            timings[str(team)] = ms
+                plan = BatchPlan(ctx, sub, teams={edge: B.BATCH_TEAMS[0]}, encoded=enc)
+            for team in B.BATCH_TEAMS:
+                plan.buckets[0]["team"] = team   # one bucket: the same upload serves every team
+                with torch.cuda.stream(stream):
+                    plan.d_out.zero_()
+                    ms = time_plan(plan, reps)
+                    outs = plan.outcomes()
+                st = plan.status()
+                if st["rejected"] or st["anomalies"]:
+                    raise RuntimeError("batch kernel reported %s (team %d, classes %d..%d)" % (st, team, i, j))
+                if ref is None:
+                    ref = outs
+                elif not all(np.array_equal(a, b) for a, b in zip(ref, outs)):
+                    raise RuntimeError("team sizes disagree on classes %d..%d" % (i, j))
+                timings[str(team)] = ms
             plan.close()
-            print("maxn %3d team %3d: %.3f ms (%d circuits)" % (maxn, team, ms, len(circs)),
+            del plan
+            best = min(timings, key=timings.get)
+            cost[(i, j)] = (timings[best], int(best))
+            rec["timings_ms"]["%d-%d" % (32 * (i - 1) + 1, edge)] = timings
+            print("n %3d..%3d (%4d circuits): %s -> team %s" %
+                  (32 * (i - 1) + 1, edge, len(idx), " ".join("%s:%.3f" % kv for kv in timings.items()), best),
                   file=sys.stderr, flush=True)
-        best = min(timings, key=timings.get)
-        rec["timings_ms"][str(maxn)] = timings
-        rec["best"][str(maxn)] = {"team": int(best), "ms": timings[best]}
+    total, parts = best_partition(cost)
+    # the last bucket takes every n up to the largest batched circuit
+    parts[-1] = (B.BATCH_MAXN, parts[-1][1], parts[-1][2])
+    rec["best"] = {str(edge): {"team": team, "ms": ms} for edge, team, ms in parts}
+    rec["best_total_ms"] = total
+    # the fixed 64 / 128 / 256 buckets with their default teams, for reference
+    fixed = 0.0
+    for lo, (edge, team) in zip((0, 64, 128), DEFAULT_TEAMS.items()):
+        i, j = word_class(lo + 1), word_class(edge)
+        if cost[(i, j)] is not None:
+            fixed += rec["timings_ms"]["%d-%d" % (32 * (i - 1) + 1, 32 * j)][str(team)]
+    rec["fixed_buckets_ms"] = fixed
     os.makedirs(os.path.dirname(out_path), exist_ok=True)
     with open(out_path, "w") as f:
         json.dump(rec, f, indent=1)
@@ -96,14 +141,15 @@ def autotune(batch: int = 4096, reps: int = 3, out_path: str = TUNING_PATH):
 
 def main():
     ap = argparse.ArgumentParser(description=__doc__)
-    ap.add_argument("--batch", type=int, default=4096, help="circuits of the whole batch (split over buckets)")
+    ap.add_argument("--batch", type=int, default=4096, help="circuits of the tuning batch")
     ap.add_argument("--reps", type=int, default=3)
     ap.add_argument("--out", default=TUNING_PATH)
     args = ap.parse_args()
     root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
     sys.path.insert(0, root)
     rec = autotune(args.batch, args.reps, args.out)
-    print(json.dumps(rec["best"]))
+    print(json.dumps({"best": rec["best"], "best_total_ms": rec["best_total_ms"],
+                      "fixed_buckets_ms": rec["fixed_buckets_ms"]}))
 
 
 if __name__ == "__main__":

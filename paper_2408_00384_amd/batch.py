@@ -1,11 +1,12 @@
 """Batched execution of many small circuits (device plumbing around cliff_batch_run).
 
 A ``BatchPlan`` packs circuits into one device-resident op stream with one
-descriptor per circuit, splits them into size buckets (max n 64 / 128 / 256),
-orders each bucket by estimated cost (largest first, so the device work queue
-ends with short circuits), and runs every bucket as one persistent launch with
-the team size the autotuner chose for it.  The whole sequence can be captured
-once into a HIP graph and replayed.  All simulation work runs in the
+descriptor per circuit, splits them into size buckets by n (bucket edges and
+the team size of each bucket from the autotuner's table), orders each bucket by
+estimated cost (largest first, so the device work queue ends with short
+circuits), and runs every bucket as one persistent launch whose LDS is sized
+for the bucket's largest circuit and most shots.  The whole sequence can be
+captured once into a HIP graph and replayed.  All simulation work runs in the
 library's batch kernel; this module only marshals arrays.
 """
 from __future__ import annotations
@@ -20,26 +21,26 @@ from . import _binding as B
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 TUNING_PATH = os.path.join(HERE, "tuning", "batch_gfx950.json")
-BUCKETS = (64, 128, 256)
-DEFAULT_TEAM = {64: 64, 128: 128, 256: 256}
+DEFAULT_TEAMS = {64: 128, 128: 256, 256: 256}   # bucket edge (largest n) -> team
 
 
 def load_tuning(path: str = TUNING_PATH) -> dict:
-    """{maxn: team} from the autotuner's table, or the defaults."""
-    table = dict(DEFAULT_TEAM)
+    """{bucket edge: team} from the autotuner's table, or the defaults.  The
+    edges are the largest n of each bucket, ascending; the last is 256."""
     if os.path.exists(path):
         with open(path) as f:
             rec = json.load(f)
-        for k, v in rec.get("best", {}).items():
-            table[int(k)] = int(v["team"])
-    return table
+        best = rec.get("best", {})
+        if best:
+            return check_teams({int(k): int(v["team"]) for k, v in best.items()})
+    return dict(DEFAULT_TEAMS)
 
 
-def bucket_of(n: int) -> int:
-    for b in BUCKETS:
-        if n <= b:
-            return b
-    raise ValueError("batched circuits need n <= %d (got %d)" % (BUCKETS[-1], n))
+def check_teams(teams: dict) -> dict:
+    for edge, team in teams.items():
+        if not 1 <= edge <= B.BATCH_MAXN or team not in B.BATCH_TEAMS:
+            raise ValueError("bad bucket %d -> team %d" % (edge, team))
+    return dict(sorted(teams.items()))
 
 
 def circuit_cost(n: int, depth: int) -> float:
@@ -48,13 +49,17 @@ def circuit_cost(n: int, depth: int) -> float:
 
 
 class BatchPlan:
-    def __init__(self, ctx, circuits, seed=None, teams=None, device="cuda:0"):
+    def __init__(self, ctx, circuits, seed=None, teams=None, device="cuda:0", encoded=None):
+        """teams: {bucket edge: team}, edges ascending (circuit n <= edge
+        goes to the first such bucket), default the autotuner's table.
+        encoded: optional list of (ops, offs) from cliff_encode_layers, one
+        per circuit, to skip re-encoding."""
         if not circuits:
             raise ValueError("empty batch")
         self.ctx = ctx
         self.circuits = circuits
         self.seed = int(circuits[0].seed if seed is None else seed)
-        self.teams = dict(load_tuning() if teams is None else teams)
+        self.teams = check_teams(load_tuning() if teams is None else teams)
         count = len(circuits)
         descs = np.zeros(count, dtype=B.BATCH_DESC_DTYPE)
         ops_parts, offs_parts = [], []
@@ -67,7 +72,8 @@ class BatchPlan:
                 raise ValueError("batched circuits need 1..64 shots")
             if len(c.qubits) != c.n or not np.array_equal(c.qubits, np.arange(c.n)):
                 raise ValueError("batched circuits measure qubits 0..n-1 in order")
-            ops, offs = B.cliff_encode_layers(c.n, c.h, c.s, c.ctrl, c.tgt)
+            ops, offs = (B.cliff_encode_layers(c.n, c.h, c.s, c.ctrl, c.tgt) if encoded is None
+                         else encoded[i])
             self.op_count[i] = len(ops)
             self.pair_count[i] = int(np.count_nonzero(ops >> np.uint64(62)))
             descs[i] = (c.n, c.depth, c.shots, 0, ops_off, offs_off, out_off, c.circuit_id)
@@ -84,19 +90,25 @@ class BatchPlan:
         self.d_offs = torch.from_numpy(offs_all.view(np.int32).copy()).to(device)
         self.d_out = torch.zeros(max(1, out_off), dtype=torch.uint8, device=device)
         self.descs = descs
-        # buckets, each ordered by decreasing cost
+        # buckets, each ordered by decreasing cost, with the LDS bounds of its
+        # contents (largest n, most shots)
         self.buckets = []
         ns = descs["n"].astype(np.int64)
         depths = descs["depth"].astype(np.int64)
-        for b in BUCKETS:
-            lo = 0 if b == BUCKETS[0] else BUCKETS[BUCKETS.index(b) - 1]
-            idx = np.nonzero((ns > lo) & (ns <= b))[0]
+        shots = descs["shots"].astype(np.int64)
+        if ns.max() > max(self.teams):
+            raise ValueError("circuit with n = %d above the largest bucket (%d)" % (ns.max(), max(self.teams)))
+        lo = 0
+        for edge, team in self.teams.items():
+            idx = np.nonzero((ns > lo) & (ns <= edge))[0]
+            lo = edge
             if len(idx) == 0:
                 continue
             cost = np.array([circuit_cost(ns[i], depths[i]) for i in idx])
             idx = idx[np.argsort(-cost, kind="stable")].astype(np.uint32)
             order = torch.from_numpy(idx.view(np.int32).copy()).to(device)
-            self.buckets.append((b, len(idx), order))
+            self.buckets.append(dict(edge=edge, team=team, count=len(idx), order=order,
+                                     maxn=int(ns[idx].max()), max_shots=int(shots[idx].max())))
         # one device scratch slot (queue head, error counters) per bucket launch
         self.work_stride = B.cliff_batch_work_bytes()
         self.d_work = torch.zeros(self.work_stride * max(1, len(self.buckets)), dtype=torch.uint8,
@@ -110,11 +122,11 @@ class BatchPlan:
 
     def launch(self):
         """Enqueue every bucket on the context stream (no host sync)."""
-        for k, (maxn, cnt, order) in enumerate(self.buckets):
+        for k, b in enumerate(self.buckets):
             B.cliff_batch_run(self.ctx.handle, self.d_descs.data_ptr(), self.d_ops.data_ptr(),
-                              self.d_offs.data_ptr(), self.d_out.data_ptr(), order.data_ptr(), cnt,
-                              self.seed, self.d_work.data_ptr() + k * self.work_stride,
-                              self.teams[maxn], maxn)
+                              self.d_offs.data_ptr(), self.d_out.data_ptr(), b["order"].data_ptr(),
+                              b["count"], self.seed, self.d_work.data_ptr() + k * self.work_stride,
+                              b["team"], b["maxn"], b["max_shots"])
 
     def capture(self):
         """Capture the launches into a HIP graph (context must use a side stream)."""

@@ -1367,17 +1367,19 @@ extern "C" size_t cliff_batch_work_bytes(void) { return 256; }
 extern "C" int cliff_batch_run(cliff_ctx *c, const cliff_batch_desc *dev_descs,
                                const uint64_t *dev_ops, const uint32_t *dev_offs, uint8_t *dev_out,
                                const uint32_t *dev_order, uint32_t count, uint64_t seed,
-                               void *dev_work, uint32_t team, uint32_t maxn) {
+                               void *dev_work, uint32_t team, uint32_t maxn, uint32_t max_shots) {
   if (!c || !dev_work || (count && (!dev_descs || !dev_ops || !dev_offs || !dev_out || !dev_order)))
     return fail(CLIFF_EINVAL, "cliff_batch_run: NULL argument");
   if (count == 0) return CLIFF_OK;
   DeviceGuard g(c->device);
   c->prof.begin(PK_BATCH, c->stream);
   hipError_t e = launch_batch(dev_descs, dev_ops, dev_offs, dev_out, dev_order, count, seed,
-                              reinterpret_cast<uint32_t *>(dev_work), team, maxn, c->num_cus, c->stream);
+                              reinterpret_cast<uint32_t *>(dev_work), team, maxn, max_shots, c->num_cus,
+                              c->stream);
   c->prof.end(PK_BATCH, c->stream);
   if (e == hipErrorInvalidValue)
-    return fail(CLIFF_EINVAL, "cliff_batch_run: no kernel for team=%u maxn=%u", team, maxn);
+    return fail(CLIFF_EINVAL, "cliff_batch_run: team=%u maxn=%u max_shots=%u out of range", team, maxn,
+                max_shots);
   HIP_TRY(e);
   return CLIFF_OK;
 }

@@ -12,8 +12,12 @@
 //
 // Work distribution: workgroups pull circuit indices from a device counter in
 // the order given by the host (largest first), until the list is exhausted.
-// LDS layout per team: X[j][w], Z[j][w] (column-major, W <= MAXN/32 words per
-// column), signs R[w][s] (s < 64), pending gate signs, measurement scratch.
+// LDS per team, sized at launch for the largest circuit of the launch (maxn
+// qubits, MW = ceil(2 maxn / 64) row words, SS = most shots): X[j][w] and
+// Z[j][w] (column-major, maxn * MW words each), signs R[w][s] (MW * SS),
+// pending gate signs (MW), and the waves' counter slots (2 * waves * MWl, MWl
+// the power of two >= MW).  Occupancy follows from that size, so a launch of
+// small circuits keeps more teams per compute unit.
 #include "internal.h"
 #include "philox.h"
 
@@ -24,19 +28,35 @@ struct BatchDescDev {
   uint64_t ops_off, offs_off, out_off, circuit_id;
 };
 
-template <int TEAM, int MAXN>
+// LDS words of a launch (the kernel carves its dynamic LDS the same way).
+struct BatchLds {
+  uint32_t mw, mwl, ss, words;
+  __host__ __device__ BatchLds(uint32_t maxn, uint32_t max_shots, uint32_t nwave) {
+    mw = (2 * maxn + 63) / 64;
+    mwl = mw <= 1 ? 1u : (1u << (32 - __builtin_clz(mw - 1)));
+    ss = max_shots;
+    words = 2 * maxn * mw + mw * ss + mw + 2 * nwave * mwl;
+  }
+};
+
+template <int TEAM>
 __global__ void __launch_bounds__(TEAM) k_batch(const BatchDescDev *__restrict__ descs,
                                                const uint64_t *__restrict__ ops,
                                                const uint32_t *__restrict__ offs,
                                                uint8_t *__restrict__ out,
                                                const uint32_t *__restrict__ order, uint32_t count,
-                                               uint64_t seed, uint32_t *queue, uint32_t *errors) {
-  constexpr int MAXW = (2 * MAXN + 63) / 64;
+                                               uint64_t seed, uint32_t *queue, uint32_t *errors,
+                                               uint32_t maxn, uint32_t max_shots) {
   constexpr int NWAVE = TEAM / 64;
-  __shared__ uint64_t sX[MAXN * MAXW], sZ[MAXN * MAXW];
-  __shared__ uint64_t sR[MAXW * 64];        // signs, stride 64 shots
-  __shared__ uint64_t sP[MAXW];             // gate sign flips (same for every shot)
-  __shared__ uint64_t sC0[TEAM], sC1[TEAM]; // counter slots
+  extern __shared__ uint64_t s_dyn[];
+  const BatchLds lay(maxn, max_shots, NWAVE);
+  const uint32_t SS = lay.ss;                    // sign stride (shots)
+  uint64_t *const sX = s_dyn;
+  uint64_t *const sZ = sX + maxn * lay.mw;
+  uint64_t *const sR = sZ + maxn * lay.mw;       // signs, stride SS
+  uint64_t *const sP = sR + lay.mw * SS;         // gate sign flips (same for every shot)
+  uint64_t *const sC0 = sP + lay.mw;             // counter slots
+  uint64_t *const sC1 = sC0 + NWAVE * lay.mwl;
   __shared__ uint32_t s_circ, s_par, s_y;
   const uint32_t tid = threadIdx.x, lane = tid & 63;
   const uint32_t wave = __builtin_amdgcn_readfirstlane(tid >> 6);
@@ -51,7 +71,7 @@ __global__ void __launch_bounds__(TEAM) k_batch(const BatchDescDev *__restrict__
     if (ci == kNone) return;
     const BatchDescDev d = descs[ci];
     const uint32_t n = d.n, S = d.shots;
-    if (n == 0 || n > uint32_t(MAXN) || S == 0 || S > 64) {
+    if (n == 0 || n > maxn || S == 0 || S > SS) {
       if (tid == 0) atomicAdd(errors, 1u);
       __syncthreads();
       continue;
@@ -64,8 +84,8 @@ __global__ void __launch_bounds__(TEAM) k_batch(const BatchDescDev *__restrict__
       sX[i] = (w == (j >> 6)) ? (1ull << (j & 63)) : 0ull;
       sZ[i] = (w == (zr >> 6)) ? (1ull << (zr & 63)) : 0ull;
     }
-    for (uint32_t i = tid; i < W * 64; i += TEAM) sR[i] = 0;
-    if (tid < MAXW) sP[tid] = 0;
+    for (uint32_t i = tid; i < W * SS; i += TEAM) sR[i] = 0;
+    if (tid < lay.mw) sP[tid] = 0;
     __syncthreads();
     // ---- gate layers: thread <-> (op, K consecutive row words from w0).  From
     // W = 5 on K = 2, the two words as one 128-row value: the op's decode and
@@ -114,25 +134,52 @@ __global__ void __launch_bounds__(TEAM) k_batch(const BatchDescDev *__restrict__
             col[w0] = v;
           }
         };
-        // one op on this thread's row words (ops of a layer act on distinct qubits)
-        auto apply = [&](uint64_t op) {
-          if (!op_valid(op, n)) {   // malformed op
-            atomicAdd(errors, 1u);
-            return;
+        // Two ops on this thread's row words (ops of a layer act on distinct
+        // qubits, so their columns are distinct): all loads of both first, so
+        // the second op's reads do not wait behind the first op's writes.  An
+        // absent or malformed op reads column 0 and writes nothing.
+        auto apply2 = [&](uint64_t op0, bool has_op0, uint64_t op1, bool has_op1) {
+          uint32_t a[2], b[2], pr[2], ca[2], cb[2];
+          bool go[2];
+#pragma unroll
+          for (int u = 0; u < 2; ++u) {
+            const uint64_t op = u ? op1 : op0;
+            const bool has = u ? has_op1 : has_op0;
+            go[u] = has && op_valid(op, n);
+            if (has && !go[u]) atomicAdd(errors, 1u);   // malformed op
+            a[u] = go[u] ? op_a(op) : 0u;
+            pr[u] = go[u] ? op_pair(op) : uint32_t(PAIR_NONE);
+            b[u] = pr[u] != PAIR_NONE ? op_b(op) : a[u];
+            ca[u] = go[u] ? op_ca(op) : 0u;
+            cb[u] = pr[u] != PAIR_NONE ? op_cb(op) : 0u;
           }
-          const uint32_t a = op_a(op), pair = op_pair(op);
-          T xa = load(sX + a * W), za = load(sZ + a * W);
-          if (op_ca(op)) sq_apply(op_ca(op), xa, za, racc);
-          if (pair != PAIR_NONE) {
-            const uint32_t b = op_b(op);
-            T xb = load(sX + b * W), zb = load(sZ + b * W);
-            if (op_cb(op)) sq_apply(op_cb(op), xb, zb, racc);
-            pair_apply(pair, xa, za, xb, zb, racc);
-            store(sX + b * W, xb);
-            store(sZ + b * W, zb);
+          T xa[2], za[2], xb[2], zb[2];
+#pragma unroll
+          for (int u = 0; u < 2; ++u) {
+            xa[u] = load(sX + a[u] * W);
+            za[u] = load(sZ + a[u] * W);
+            xb[u] = load(sX + b[u] * W);
+            zb[u] = load(sZ + b[u] * W);
           }
-          store(sX + a * W, xa);
-          store(sZ + a * W, za);
+#pragma unroll
+          for (int u = 0; u < 2; ++u) {
+            if (ca[u]) sq_apply(ca[u], xa[u], za[u], racc);
+            if (pr[u] != PAIR_NONE) {
+              if (cb[u]) sq_apply(cb[u], xb[u], zb[u], racc);
+              pair_apply(pr[u], xa[u], za[u], xb[u], zb[u], racc);
+            }
+          }
+#pragma unroll
+          for (int u = 0; u < 2; ++u) {
+            if (pr[u] != PAIR_NONE) {
+              store(sX + b[u] * W, xb[u]);
+              store(sZ + b[u] * W, zb[u]);
+            }
+            if (go[u]) {
+              store(sX + a[u] * W, xa[u]);
+              store(sZ + a[u] * W, za[u]);
+            }
+          }
         };
         uint32_t a0 = coffs[0], a1 = depth ? coffs[1] : a0;
         uint64_t f0 = fetch(a0 + k0), f1 = fetch(a0 + k0 + kst);
@@ -142,9 +189,11 @@ __global__ void __launch_bounds__(TEAM) k_batch(const BatchDescDev *__restrict__
           if (has0) {
             // the two prefetched ops in straight-line code, so their wait does
             // not cover the loads just issued for the next layer
-            if (a0 + k0 < a1) apply(f0);
-            if (a0 + k0 + kst < a1) apply(f1);
-            for (uint32_t k = a0 + k0 + 2 * kst; k < a1; k += kst) apply(cops[k]);
+            if (a0 + k0 < a1) apply2(f0, true, f1, a0 + k0 + kst < a1);
+            for (uint32_t k = a0 + k0 + 2 * kst; k < a1; k += 2 * kst) {
+              const bool two = k + kst < a1;
+              apply2(cops[k], true, cops[two ? k + kst : k], two);
+            }
           }
           lds_barrier();
           a0 = b0;
@@ -165,7 +214,7 @@ __global__ void __launch_bounds__(TEAM) k_batch(const BatchDescDev *__restrict__
       if (W >= 5) gates(U128{0, 0});
       else gates(uint64_t(0));
       __syncthreads();
-      for (uint32_t i = tid; i < W * 64; i += TEAM) sR[i] ^= sP[i / 64];
+      for (uint32_t i = tid; i < W * SS; i += TEAM) sR[i] ^= sP[i / SS];
       __syncthreads();
     }
     // ---- measure every qubit
@@ -220,7 +269,7 @@ __global__ void __launch_bounds__(TEAM) k_batch(const BatchDescDev *__restrict__
       // pivot signs of every shot, final since the barrier that ended a - 1
       uint64_t rpw = 0;   // bit s = r_p of shot s (wave-uniform)
       if (p != kNone) {
-        const uint32_t b = lane < S ? uint32_t(sR[(p >> 6) * 64 + lane] >> (p & 63)) & 1u : 0u;
+        const uint32_t b = lane < S ? uint32_t(sR[(p >> 6) * SS + lane] >> (p & 63)) & 1u : 0u;
         rpw = __ballot(b);
       }
       uint32_t p_next = kNone;
@@ -230,30 +279,48 @@ __global__ void __launch_bounds__(TEAM) k_batch(const BatchDescDev *__restrict__
         const uint64_t bpn = 1ull << (pn & 63), bpb = 1ull << (p & 63);
         uint64_t c0 = 0, c1 = 0;
         if (wl < W) {
-          for (uint32_t j = slot; j < n; j += slots) {
-            const uint32_t xpj = uint32_t(sX[j * W + wp] >> (p & 63)) & 1u;
-            const uint32_t zpj = uint32_t(sZ[j * W + wp] >> (p & 63)) & 1u;
-            const uint64_t x = sX[j * W + wl], z = sZ[j * W + wl];
-            const uint64_t X1 = mask_if<uint64_t>(xpj), Z1 = mask_if<uint64_t>(zpj);
-            // rows in M anticommuting with the pivot's Pauli on column j (X: z,
-            // Z: x, Y: x ^ z); g = +1 on them where (X: x; Z: ~z; Y: z), else
-            // -1, and adding +-1 to the 2-bit counter flips c1 where c0 equals
-            // that condition: c1 ^= anti & ~(c0 ^ sel), c0 ^= anti
-            const uint64_t anti = bop3<LUT_AND_XOR>(Z1, x, X1 & z) & m;
-            const uint64_t sel = (Z1 & ~(z ^ X1)) | (~Z1 & x);
-            c1 ^= bop3<LUT_AND_XNOR>(anti, c0, sel);
-            c0 ^= anti;
-            uint64_t nx = bop3<LUT_AND_XOR>(X1, m, x), nz = bop3<LUT_AND_XOR>(Z1, m, z);
-            if (wl == wpn) {
-              nx = xpj ? (nx | bpn) : (nx & ~bpn);
-              nz = zpj ? (nz | bpn) : (nz & ~bpn);
+          // two columns per pass, all loads first (distinct columns: the
+          // second's reads need not wait for the first's writes)
+          for (uint32_t j0 = slot; j0 < n; j0 += 2 * slots) {
+            const uint32_t j1 = j0 + slots < n ? j0 + slots : j0;
+            const bool two = j0 + slots < n;
+            uint64_t xp[2], zp[2], xv[2], zv[2];
+#pragma unroll
+            for (int u = 0; u < 2; ++u) {
+              const uint32_t j = u ? j1 : j0;
+              xp[u] = sX[j * W + wp];
+              zp[u] = sZ[j * W + wp];
+              xv[u] = sX[j * W + wl];
+              zv[u] = sZ[j * W + wl];
             }
-            if (wl == wp) {
-              nx &= ~bpb;
-              nz = (j == a) ? (nz | bpb) : (nz & ~bpb);
+#pragma unroll
+            for (int u = 0; u < 2; ++u) {
+              const uint32_t j = u ? j1 : j0;
+              if (u && !two) break;
+              const uint32_t xpj = uint32_t(xp[u] >> (p & 63)) & 1u;
+              const uint32_t zpj = uint32_t(zp[u] >> (p & 63)) & 1u;
+              const uint64_t x = xv[u], z = zv[u];
+              const uint64_t X1 = mask_if<uint64_t>(xpj), Z1 = mask_if<uint64_t>(zpj);
+              // rows in M anticommuting with the pivot's Pauli on column j (X:
+              // z, Z: x, Y: x ^ z); g = +1 on them where (X: x; Z: ~z; Y: z),
+              // else -1, and adding +-1 to the 2-bit counter flips c1 where c0
+              // equals that condition: c1 ^= anti & ~(c0 ^ sel), c0 ^= anti
+              const uint64_t anti = bop3<LUT_AND_XOR>(Z1, x, X1 & z) & m;
+              const uint64_t sel = (Z1 & ~(z ^ X1)) | (~Z1 & x);
+              c1 ^= bop3<LUT_AND_XNOR>(anti, c0, sel);
+              c0 ^= anti;
+              uint64_t nx = bop3<LUT_AND_XOR>(X1, m, x), nz = bop3<LUT_AND_XOR>(Z1, m, z);
+              if (wl == wpn) {
+                nx = xpj ? (nx | bpn) : (nx & ~bpn);
+                nz = zpj ? (nz | bpn) : (nz & ~bpn);
+              }
+              if (wl == wp) {
+                nx &= ~bpb;
+                nz = (j == a) ? (nz | bpb) : (nz & ~bpb);
+              }
+              sX[j * W + wl] = nx;
+              sZ[j * W + wl] = nz;
             }
-            sX[j * W + wl] = nx;
-            sZ[j * W + wl] = nz;
           }
         }
         // counters: the cpw column slots of a word sit in lanes sub * Wl + wl
@@ -290,7 +357,7 @@ __global__ void __launch_bounds__(TEAM) k_batch(const BatchDescDev *__restrict__
             const uint64_t c1w = __shfl(t1, src);
             if (i < W * S) {
               const uint32_t rpb = uint32_t(rpw >> sh) & 1u;
-              uint64_t rv = sR[w * 64 + sh];
+              uint64_t rv = sR[w * SS + sh];
               rv ^= mw & (c1w ^ (rpb ? ~0ull : 0ull));
               if (w == wpn) rv = rpb ? (rv | bpn) : (rv & ~bpn);
               if (w == wp) {
@@ -298,7 +365,7 @@ __global__ void __launch_bounds__(TEAM) k_batch(const BatchDescDev *__restrict__
                 rv = o ? (rv | bpb) : (rv & ~bpb);
                 cout[size_t(sh) * n + a] = uint8_t(o);
               }
-              sR[w * 64 + sh] = rv;
+              sR[w * SS + sh] = rv;
             }
           }
           const uint64_t bad = (lane < W) ? (t0 & m & ~(lane == wpn ? bpn : 0ull)) : 0ull;
@@ -342,7 +409,7 @@ __global__ void __launch_bounds__(TEAM) k_batch(const BatchDescDev *__restrict__
           uint32_t rt = 0;
           for (uint32_t w = 0; w < W; ++w) {
             const uint64_t Tw = __shfl(m, int(w));
-            if (lane < S) rt ^= uint32_t(__popcll(Tw & sR[w * 64 + lane])) & 1u;
+            if (lane < S) rt ^= uint32_t(__popcll(Tw & sR[w * SS + lane])) & 1u;
           }
           if (lane < S) cout[size_t(lane) * n + a] = uint8_t(rt ^ (s_par & 1u) ^ ((s_y >> 1) & 1u));
         }
@@ -356,11 +423,24 @@ __global__ void __launch_bounds__(TEAM) k_batch(const BatchDescDev *__restrict__
   }
 }
 
-template <int TEAM, int MAXN>
+// Teams per compute unit for a launch's LDS size.
+template <int TEAM>
+static uint32_t batch_grid(size_t lds_bytes, int num_cus) {
+  int per = 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k_batch<TEAM>, TEAM, lds_bytes) != hipSuccess ||
+      per < 1)
+    per = 1;
+  return uint32_t(per) * uint32_t(num_cus);
+}
+
+template <int TEAM>
 static hipError_t launch_batch_t(const BatchDescDev *descs, const uint64_t *ops, const uint32_t *offs,
                                  uint8_t *out, const uint32_t *order, uint32_t count, uint64_t seed,
-                                 uint32_t *queue, uint32_t *errors, uint32_t grid, hipStream_t st) {
-  k_batch<TEAM, MAXN><<<grid, TEAM, 0, st>>>(descs, ops, offs, out, order, count, seed, queue, errors);
+                                 uint32_t *queue, uint32_t *errors, uint32_t maxn, uint32_t max_shots,
+                                 int num_cus, hipStream_t st) {
+  const size_t lds = size_t(BatchLds(maxn, max_shots, TEAM / 64).words) * 8;
+  k_batch<TEAM><<<batch_grid<TEAM>(lds, num_cus), TEAM, lds, st>>>(descs, ops, offs, out, order, count, seed,
+                                                                   queue, errors, maxn, max_shots);
   return hipGetLastError();
 }
 
@@ -369,40 +449,23 @@ __global__ void k_reset_queue(uint32_t *work) {
   if (threadIdx.x < 4) work[threadIdx.x] = 0;
 }
 
-// Occupancy-limited grid for a team configuration.
-template <int TEAM, int MAXN>
-static uint32_t batch_grid(int num_cus) {
-  int per = 0;
-  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k_batch<TEAM, MAXN>, TEAM, 0) != hipSuccess ||
-      per < 1)
-    per = 1;
-  return uint32_t(per) * uint32_t(num_cus);
-}
-
 hipError_t launch_batch(const void *descs, const uint64_t *ops, const uint32_t *offs, uint8_t *out,
                         const uint32_t *order, uint32_t count, uint64_t seed, uint32_t *work,
-                        uint32_t team, uint32_t maxn, int num_cus, hipStream_t st) {
+                        uint32_t team, uint32_t maxn, uint32_t max_shots, int num_cus, hipStream_t st) {
+  if (maxn < 1 || maxn > kBatchMaxN || max_shots < 1 || max_shots > 64) return hipErrorInvalidValue;
+  if (team != 64 && team != 128 && team != 256 && team != 512 && team != 1024) return hipErrorInvalidValue;
   const BatchDescDev *d = reinterpret_cast<const BatchDescDev *>(descs);
   k_reset_queue<<<1, 64, 0, st>>>(work);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   uint32_t *q = work, *err = work + 1;
-#define CLIFF_BATCH_CASE(T_, N_)                                                              \
-  if (team == T_ && maxn == N_)                                                               \
-    return launch_batch_t<T_, N_>(d, ops, offs, out, order, count, seed, q, err,              \
-                                  batch_grid<T_, N_>(num_cus), st);
-  CLIFF_BATCH_CASE(64, 64)
-  CLIFF_BATCH_CASE(128, 64)
-  CLIFF_BATCH_CASE(64, 128)
-  CLIFF_BATCH_CASE(128, 128)
-  CLIFF_BATCH_CASE(256, 128)
-  CLIFF_BATCH_CASE(512, 128)
-  CLIFF_BATCH_CASE(128, 256)
-  CLIFF_BATCH_CASE(256, 256)
-  CLIFF_BATCH_CASE(512, 256)
-  CLIFF_BATCH_CASE(1024, 256)
-#undef CLIFF_BATCH_CASE
-  return hipErrorInvalidValue;
+  switch (team) {
+    case 64: return launch_batch_t<64>(d, ops, offs, out, order, count, seed, q, err, maxn, max_shots, num_cus, st);
+    case 128: return launch_batch_t<128>(d, ops, offs, out, order, count, seed, q, err, maxn, max_shots, num_cus, st);
+    case 256: return launch_batch_t<256>(d, ops, offs, out, order, count, seed, q, err, maxn, max_shots, num_cus, st);
+    case 512: return launch_batch_t<512>(d, ops, offs, out, order, count, seed, q, err, maxn, max_shots, num_cus, st);
+    default: return launch_batch_t<1024>(d, ops, offs, out, order, count, seed, q, err, maxn, max_shots, num_cus, st);
+  }
 }
 
 }  // namespace cliff

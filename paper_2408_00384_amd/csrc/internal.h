@@ -262,9 +262,12 @@ hipError_t launch_measure_persist(const TabDev &t, uint32_t kc, const uint32_t *
                                   uint64_t seed, uint64_t circuit, uint64_t shot0, uint64_t m0,
                                   int num_cus, const PersistStreams &ps, Profiler *prof, uint32_t *done,
                                   uint64_t abort_at);
+// Batched circuits: team in {64, 128, 256, 512, 1024}, 1 <= maxn <= kBatchMaxN,
+// 1 <= max_shots <= 64 (hipErrorInvalidValue otherwise).
+constexpr uint32_t kBatchMaxN = 256;
 hipError_t launch_batch(const void *descs, const uint64_t *ops, const uint32_t *offs, uint8_t *out,
                         const uint32_t *order, uint32_t count, uint64_t seed, uint32_t *work,
-                        uint32_t team, uint32_t maxn, int num_cus, hipStream_t st);
+                        uint32_t team, uint32_t maxn, uint32_t max_shots, int num_cus, hipStream_t st);
 hipError_t launch_copy_tab(const TabDev &dst, const TabDev &src, hipStream_t st);
 // count words from host memory to device memory dst through kernel arguments.
 hipError_t launch_store_words(uint32_t *dst, const uint32_t *host, uint32_t count, hipStream_t st);

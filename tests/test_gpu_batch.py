@@ -47,11 +47,13 @@ def test_batch_matches_oracle_default_teams(ctx):
     _check(circs, outs)
 
 
-@pytest.mark.parametrize("cfg", [(64, 64), (128, 64), (64, 128), (128, 128), (256, 128), (512, 128),
-                                 (128, 256), (256, 256), (512, 256), (1024, 256)])
-def test_every_team_config_is_bit_identical(ctx, cfg):
+TEAMS = (64, 128, 256, 512, 1024)
+
+
+@pytest.mark.parametrize("team", TEAMS)
+@pytest.mark.parametrize("maxn", (64, 128, 256))
+def test_every_team_config_is_bit_identical(ctx, team, maxn):
     from paper_2408_00384_amd.batch import BatchPlan
-    team, maxn = cfg
     rng = np.random.default_rng(maxn)
     lo = {64: 1, 128: 65, 256: 129}[maxn]
     circs = [layered_circuit(int(n), int(rng.integers(1, 8)), 4, gen_seed=[3, maxn, i], circuit_id=i)
@@ -97,7 +99,7 @@ def test_rejects_oversized_descriptors(ctx):
         torch.cuda.synchronize()
         B.cliff_batch_run(ctx.handle, plan.d_descs.data_ptr(), plan.d_ops.data_ptr(),
                           plan.d_offs.data_ptr(), plan.d_out.data_ptr(), order.data_ptr(), 2,
-                          plan.seed, plan.d_work.data_ptr(), 64, 64)
+                          plan.seed, plan.d_work.data_ptr(), 64, 64, 2)
         st = B.cliff_batch_status(ctx.handle, plan.d_work.data_ptr())
     assert st["rejected"] == 1
     out = plan.d_out.cpu().numpy()
@@ -133,14 +135,13 @@ def _det_heavy_circuits(maxn, seed, count=6):
     return out
 
 
-@pytest.mark.parametrize("cfg", [(64, 64), (128, 64), (64, 128), (128, 128), (256, 128), (512, 128),
-                                 (128, 256), (256, 256), (512, 256), (1024, 256)])
-def test_mostly_deterministic_circuits_every_team_config(ctx, cfg):
+@pytest.mark.parametrize("team", TEAMS)
+@pytest.mark.parametrize("maxn", (64, 128, 256))
+def test_mostly_deterministic_circuits_every_team_config(ctx, team, maxn):
     """Every kernel instance against the oracle, every shot, on circuits
     where at least 30 % of the outcomes after the first random one are
     deterministic (each then depends on the signs the kernel tracked)."""
     from paper_2408_00384_amd.batch import BatchPlan
-    team, maxn = cfg
     circs = _det_heavy_circuits(maxn, seed=team)
     with torch.cuda.stream(ctx.stream):
         plan = BatchPlan(ctx, circs, teams={maxn: team}).run()
@@ -155,3 +156,67 @@ def test_mostly_deterministic_circuits_every_team_config(ctx, cfg):
         det += int((kinds[first + 1:] == 0).sum())
         after += max(0, len(kinds) - first - 1)
     assert after > 0 and det >= 0.3 * after, (det, after)
+
+
+def test_rejects_shots_above_the_launch_bound(ctx):
+    """LDS holds max_shots sign columns: a circuit with more shots is skipped
+    and counted, the others run (outcomes against the oracle)."""
+    from paper_2408_00384_amd import _binding as B
+    from paper_2408_00384_amd.batch import BatchPlan
+    circs = [layered_circuit(40, 3, 5, gen_seed=4, circuit_id=0),
+             layered_circuit(40, 3, 3, gen_seed=5, circuit_id=1)]
+    with torch.cuda.stream(ctx.stream):
+        plan = BatchPlan(ctx, circs)
+        order = torch.tensor([0, 1], dtype=torch.int32, device="cuda:0")
+        torch.cuda.synchronize()
+        B.cliff_batch_run(ctx.handle, plan.d_descs.data_ptr(), plan.d_ops.data_ptr(),
+                          plan.d_offs.data_ptr(), plan.d_out.data_ptr(), order.data_ptr(), 2,
+                          plan.seed, plan.d_work.data_ptr(), 128, 40, 4)
+        st = B.cliff_batch_status(ctx.handle, plan.d_work.data_ptr())
+    assert st == dict(rejected=1, anomalies=0)
+    out = plan.d_out.cpu().numpy()
+    d = plan.descs[1]
+    got = out[int(d["out_off"]): int(d["out_off"]) + 3 * 40].reshape(3, 40)
+    for s_ in range(3):
+        assert np.array_equal(got[s_], oracle.run_shot(circs[1], s_)[0])
+
+
+@pytest.mark.parametrize("team,maxn,shots", [(96, 64, 4), (2048, 64, 4), (64, 0, 4), (64, 257, 4),
+                                             (64, 64, 0), (64, 64, 65)])
+def test_launch_bounds_out_of_range(ctx, team, maxn, shots):
+    from paper_2408_00384_amd import _binding as B
+    from paper_2408_00384_amd.batch import BatchPlan
+    circs = [layered_circuit(10, 2, 2, gen_seed=1, circuit_id=0)]
+    with torch.cuda.stream(ctx.stream):
+        plan = BatchPlan(ctx, circs)
+        order = torch.tensor([0], dtype=torch.int32, device="cuda:0")
+        torch.cuda.synchronize()
+        with pytest.raises(B.CliffError):
+            B.cliff_batch_run(ctx.handle, plan.d_descs.data_ptr(), plan.d_ops.data_ptr(),
+                              plan.d_offs.data_ptr(), plan.d_out.data_ptr(), order.data_ptr(), 1,
+                              plan.seed, plan.d_work.data_ptr(), team, maxn, shots)
+
+
+def test_tuned_choices_are_bit_identical(ctx):
+    """The autotuner's table (bucket edges and a team per bucket) against the
+    fixed 64 / 128 / 256 buckets with their default teams and against one
+    bucket of every circuit: identical outcome bytes on circuits of the
+    batched workload spread over every row-word class, and the oracle on a
+    sample of them (every shot)."""
+    from inputs import batch_circuit, batch_sizes
+    from paper_2408_00384_amd.batch import DEFAULT_TEAMS, BatchPlan, load_tuning
+    tuned = load_tuning()
+    assert max(tuned) == 256
+    ns, depths = batch_sizes()
+    order = np.argsort(ns, kind="stable")
+    idx = [int(order[k]) for k in np.linspace(0, len(order) - 1, 48).astype(int)]
+    circs = [batch_circuit(i, ns, depths) for i in idx]
+    outs = {}
+    for name, teams in (("tuned", tuned), ("fixed", DEFAULT_TEAMS), ("one", {256: 256})):
+        with torch.cuda.stream(ctx.stream):
+            plan = BatchPlan(ctx, circs, teams=teams).run()
+            outs[name] = plan.outcomes()
+        assert plan.status() == dict(rejected=0, anomalies=0), name
+    for name in ("fixed", "one"):
+        assert all(np.array_equal(a, b) for a, b in zip(outs["tuned"], outs[name])), name
+    _check(circs[::6], outs["tuned"][::6])
