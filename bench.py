@@ -228,6 +228,18 @@ def bench_batch(P, torch, np, count=4096, plain_sample=48, reps=5):
     status = plan.status()
     buckets = [{k: b[k] for k in ("edge", "team", "maxn", "max_shots", "count")} for b in plan.buckets]
     lds_bytes = batch_lds_bytes(plan, np)
+    head = {
+        "workload": "%d circuits, n ~ U{8..256}, depth ~ U{n..4n}, measure all, 4 shots" % count,
+        "circuits_per_s": count / (ev_ms * 1e-3),
+        "ms_per_batch": ev_ms, "ms_per_batch_wall": wall * 1e3,
+        "device_checks": status,
+        "buckets": buckets,
+    }
+    if plain_sample == 0:
+        plan.close()
+        ctx.close()
+        head["lds_alg_bytes_per_batch"] = lds_bytes
+        return head
     lds_meas = P.cliff_calibrate(ctx.handle, P.CAL_LDS) / 1e9
     valu_meas = P.cliff_calibrate(ctx.handle, P.CAL_VALU)
     # plain path on an evenly spaced sample
@@ -282,9 +294,7 @@ def bench_batch(P, torch, np, count=4096, plain_sample=48, reps=5):
     plan.close()
     ctx.close()
     return {
-        "workload": "%d circuits, n ~ U{8..256}, depth ~ U{n..4n}, measure all, 4 shots" % count,
-        "circuits_per_s": count / (ev_ms * 1e-3),
-        "ms_per_batch": ev_ms, "ms_per_batch_wall": wall * 1e3,
+        **head,
         "plain_circuits_per_s": 1.0 / plain_s,
         "plain_kernel_circuits_per_s": 1.0 / plain_kernel_s,
         "plain_sample": "%d evenly spaced circuits (mean n %.0f vs %.0f in the batch), one at a time"
@@ -295,8 +305,6 @@ def bench_batch(P, torch, np, count=4096, plain_sample=48, reps=5):
                         "the host and uploaded per circuit; batched_vs_plain_kernel: op streams pre-encoded in "
                         "HBM, tableaux pre-bound, all circuits enqueued on one stream, HIP events around them",
         "bit_exact_vs_plain": parity,
-        "device_checks": status,
-        "buckets": buckets,
         "lds": {"alg_bytes_per_batch": lds_bytes, "achieved_gbs": lds_bytes / (ev_ms * 1e-3) / 1e9,
                 "peak_gbs": LDS_PEAK_GBS, "frac": lds_bytes / (ev_ms * 1e-3) / 1e9 / LDS_PEAK_GBS,
                 "measured_peak_gbs": lds_meas,
@@ -661,6 +669,9 @@ def main():
                     help="skip the n = 64 and n = 1,024 workloads")
     ap.add_argument("--serving-only", action="store_true",
                     help="run only the serving leg (for a kernel trace of it); prints its JSON")
+    ap.add_argument("--batch-only", action="store_true",
+                    help="run only the batched leg, without its plain-path comparisons and oracle "
+                         "baseline (for kernel traces and counters of the batch kernel); prints its JSON")
     ap.add_argument("--no-xlarge", action="store_true",
                     help="skip the n = 25,000 HBM-bound measurement leg")
     ap.add_argument("--no-profile", action="store_true",
@@ -693,7 +704,7 @@ def main():
 
     # circuits of the Fig. 2a sweep, drawn before anything touches the GPU
     fig2a_lists, fig2a_gen_s = None, 0.0
-    if not (args.no_clifford or args.serving_only):
+    if not (args.no_clifford or args.serving_only or args.batch_only):
         print("# drawing uniformly random Cliffords for n = %s ..." % (FIG2A_NS,), file=sys.stderr, flush=True)
         fig2a_lists, fig2a_gen_s = gen_cliffords(FIG2A_NS)
 
@@ -703,6 +714,10 @@ def main():
 
     if args.serving_only:
         print(json.dumps({"serving": bench_serving(P, np, cpu=False)}), flush=True)
+        torch.cuda.synchronize()
+        return
+    if args.batch_only:
+        print(json.dumps({"batched": bench_batch(P, torch, np, plain_sample=0)}), flush=True)
         torch.cuda.synchronize()
         return
 

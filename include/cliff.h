@@ -375,6 +375,15 @@ int cliff_batch_run(cliff_ctx *ctx, const cliff_batch_desc *dev_descs, const uin
                     const uint32_t *dev_offs, uint8_t *dev_out, const uint32_t *dev_order,
                     uint32_t count, uint64_t seed, void *dev_work, uint32_t team, uint32_t maxn,
                     uint32_t max_shots);
+/* Reorders, in place in host memory, the ops of every layer of one circuit's
+ * encoded stream (ops as from cliff_encode_layers, layer l = ops[offs[l] ..
+ * offs[l+1]), depth layers, n qubits, 1 <= n <= 256) for the batch kernel's
+ * LDS banks: the ops of a layer act on distinct qubits and commute, so any
+ * order gives the same state, outcomes and signs; this one spreads the column
+ * accesses that the kernel issues together over distinct LDS banks.
+ * Deterministic.  CLIFF_EINVAL on n out of range, NULL pointers (ops may be
+ * NULL for an empty stream) or decreasing offsets. */
+int cliff_batch_order_ops(uint32_t n, uint64_t *ops, const uint32_t *offs, uint32_t depth);
 /* out2[0] = descriptors rejected (n or shots out of range), out2[1] = device
  * consistency-check failures, of the last launch using dev_work.  Synchronizes. */
 int cliff_batch_status(cliff_ctx *ctx, const void *dev_work, uint64_t *out2);

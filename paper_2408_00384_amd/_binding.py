@@ -99,6 +99,7 @@ _SIGS = {
     "cliff_batch_work_bytes": (_sz, []),
     "cliff_batch_run": (ctypes.c_int, [_vp, _vp, _vp, _vp, _vp, _vp, _u32, _u64, _vp, _u32, _u32, _u32]),
     "cliff_batch_status": (ctypes.c_int, [_vp, _vp, _u64p]),
+    "cliff_batch_order_ops": (ctypes.c_int, [_u32, _u64p, _u32p, _u32]),
     "cliff_graph_begin": (ctypes.c_int, [_vp]),
     "cliff_graph_end": (ctypes.c_int, [_vp, ctypes.POINTER(_vp)]),
     "cliff_graph_launch": (ctypes.c_int, [_vp]),
@@ -455,6 +456,19 @@ def cliff_batch_run(ctx, descs_ptr, ops_ptr, offs_ptr, out_ptr, order_ptr, count
                     team, maxn, max_shots=64):
     _check(_lib.cliff_batch_run(ctx, descs_ptr, ops_ptr, offs_ptr, out_ptr, order_ptr, count, seed,
                                 work_ptr, team, maxn, max_shots), "cliff_batch_run")
+
+
+def cliff_batch_order_ops(n, ops, offs):
+    """Reorders each layer of an encoded stream (uint64 ops, in place) for the
+    batch kernel's LDS banks; returns ops."""
+    if ops.dtype != np.uint64 or not ops.flags.c_contiguous or not ops.flags.writeable:
+        raise ValueError("ops must be a writable contiguous uint64 array")
+    offs = _arr(offs, np.uint32)
+    if len(offs) < 1 or int(offs[-1]) > len(ops):
+        raise ValueError("layer offsets past the op stream")
+    _check(_lib.cliff_batch_order_ops(n, _ptr(ops, _u64p), _ptr(offs, _u32p), len(offs) - 1),
+           "cliff_batch_order_ops")
+    return ops
 
 
 def cliff_batch_status(ctx, work_ptr):

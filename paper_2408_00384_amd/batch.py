@@ -11,6 +11,7 @@ library's batch kernel; this module only marshals arrays.
 """
 from __future__ import annotations
 
+import concurrent.futures as cf
 import json
 import os
 
@@ -85,6 +86,20 @@ class BatchPlan:
         self.out_bytes = out_off
         ops_all = np.concatenate(ops_parts) if ops_off else np.zeros(1, np.uint64)
         offs_all = np.concatenate(offs_parts)
+        # each circuit's layers in the order that spreads the kernel's LDS
+        # accesses over distinct banks (same results in any order); circuits
+        # on host threads (the library call releases the interpreter lock)
+        def order(d):
+            o, f, depth = int(d["ops_off"]), int(d["offs_off"]), int(d["depth"])
+            if int(offs_all[f + depth]):
+                B.cliff_batch_order_ops(int(d["n"]), ops_all[o: o + int(offs_all[f + depth])],
+                                        offs_all[f: f + depth + 1])
+        if count >= 64:
+            with cf.ThreadPoolExecutor(max_workers=min(16, os.cpu_count() or 1)) as ex:
+                list(ex.map(order, descs))
+        else:
+            for d in descs:
+                order(d)
         self.d_descs = torch.from_numpy(descs.view(np.uint8).copy()).to(device)
         self.d_ops = torch.from_numpy(np.ascontiguousarray(ops_all).view(np.int64)).to(device)
         self.d_offs = torch.from_numpy(offs_all.view(np.int32).copy()).to(device)

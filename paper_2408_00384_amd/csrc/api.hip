@@ -1384,6 +1384,12 @@ extern "C" int cliff_batch_run(cliff_ctx *c, const cliff_batch_desc *dev_descs,
   return CLIFF_OK;
 }
 
+extern "C" int cliff_batch_order_ops(uint32_t n, uint64_t *ops, const uint32_t *offs, uint32_t depth) {
+  if (batch_order_ops(n, ops, offs, depth) != 0)
+    return fail(CLIFF_EINVAL, "cliff_batch_order_ops: n=%u outside 1..256, or NULL or decreasing offsets", n);
+  return CLIFF_OK;
+}
+
 extern "C" int cliff_batch_status(cliff_ctx *c, const void *dev_work, uint64_t *out2) {
   if (!c || !dev_work || !out2) return fail(CLIFF_EINVAL, "cliff_batch_status: NULL argument");
   DeviceGuard g(c->device);

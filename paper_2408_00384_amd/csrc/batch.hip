@@ -13,11 +13,22 @@
 // Work distribution: workgroups pull circuit indices from a device counter in
 // the order given by the host (largest first), until the list is exhausted.
 // LDS per team, sized at launch for the largest circuit of the launch (maxn
-// qubits, MW = ceil(2 maxn / 64) row words, SS = most shots): X[j][w] and
-// Z[j][w] (column-major, maxn * MW words each), signs R[w][s] (MW * SS),
-// pending gate signs (MW), and the waves' counter slots (2 * waves * MWl, MWl
-// the power of two >= MW).  Occupancy follows from that size, so a launch of
-// small circuits keeps more teams per compute unit.
+// qubits, MW = ceil(2 maxn / 64) row words, MWl the power of two >= MW, SS =
+// most shots): X[j][w] and Z[j][w] (column-major, column stride Wl = the power
+// of two >= the circuit's W, maxn * MWl words each), signs R[w][s] (MW * SS),
+// pending gate signs (MW), and the waves' counter slots (2 * waves * MWl).
+// Occupancy follows from that size, so a launch of small circuits keeps more
+// teams per compute unit.
+//
+// LDS banks (64 of 4 bytes): with the power-of-two column stride, column j
+// starts at bank 2 Wl j mod 64, so a gate op's accesses fall in one of 32 / Wl
+// bank ranges set by its qubit (mod 32 / Wl; for W >= 5, two half-ranges
+// picked by the op's slot parity).  The ops of a layer commute, and
+// cliff_batch_order_ops arranges them so the ops sharing a 32-lane access
+// group use distinct ranges.
+#include <algorithm>
+#include <vector>
+
 #include "internal.h"
 #include "philox.h"
 
@@ -35,7 +46,7 @@ struct BatchLds {
     mw = (2 * maxn + 63) / 64;
     mwl = mw <= 1 ? 1u : (1u << (32 - __builtin_clz(mw - 1)));
     ss = max_shots;
-    words = 2 * maxn * mw + mw * ss + mw + 2 * nwave * mwl;
+    words = 2 * maxn * mwl + mw * ss + mw + 2 * nwave * mwl;
   }
 };
 
@@ -52,8 +63,8 @@ __global__ void __launch_bounds__(TEAM) k_batch(const BatchDescDev *__restrict__
   const BatchLds lay(maxn, max_shots, NWAVE);
   const uint32_t SS = lay.ss;                    // sign stride (shots)
   uint64_t *const sX = s_dyn;
-  uint64_t *const sZ = sX + maxn * lay.mw;
-  uint64_t *const sR = sZ + maxn * lay.mw;       // signs, stride SS
+  uint64_t *const sZ = sX + maxn * lay.mwl;
+  uint64_t *const sR = sZ + maxn * lay.mwl;      // signs, stride SS
   uint64_t *const sP = sR + lay.mw * SS;         // gate sign flips (same for every shot)
   uint64_t *const sC0 = sP + lay.mw;             // counter slots
   uint64_t *const sC1 = sC0 + NWAVE * lay.mwl;
@@ -77,24 +88,25 @@ __global__ void __launch_bounds__(TEAM) k_batch(const BatchDescDev *__restrict__
       continue;
     }
     const uint32_t W = (2 * n + 63) / 64;
-    const uint32_t Wl = W <= 1 ? 1u : (1u << (32 - __builtin_clz(W - 1)));   // pow2 >= W
-    // ---- |0...0>
-    for (uint32_t i = tid; i < n * W; i += TEAM) {
-      const uint32_t j = i / W, w = i % W, zr = n + j;
+    const uint32_t Wl = W <= 1 ? 1u : (1u << (32 - __builtin_clz(W - 1)));   // pow2 >= W: column stride
+    // ---- |0...0> (the padding words past W are never read)
+    for (uint32_t i = tid; i < n * Wl; i += TEAM) {
+      const uint32_t j = i / Wl, w = i % Wl, zr = n + j;
       sX[i] = (w == (j >> 6)) ? (1ull << (j & 63)) : 0ull;
       sZ[i] = (w == (zr >> 6)) ? (1ull << (zr & 63)) : 0ull;
     }
     for (uint32_t i = tid; i < W * SS; i += TEAM) sR[i] = 0;
     if (tid < lay.mw) sP[tid] = 0;
     __syncthreads();
-    // ---- gate layers: thread <-> (op, K consecutive row words from w0).  From
-    // W = 5 on K = 2, the two words as one 128-row value: the op's decode and
-    // its single-qubit masks serve both and a layer needs half the passes;
-    // below that the threads per op are few already and K = 1.  A thread's
+    // ---- gate layers: thread <-> (op, K row words).  From W = 5 on K = 2, the
+    // two words as one 128-row value: the op's decode and its single-qubit
+    // masks serve both and a layer needs half the passes; below that the
+    // threads per op are few already and K = 1.  With K = 2 the four threads
+    // of an op hold words t and t + 4 (t = 0..3), the first of the two
+    // accesses reading word t in even op slots and word t + 4 in odd ones, so
+    // the two halves of a column's banks serve two ops at once.  A thread's
     // words are fixed, so the sign flips it produces accumulate in registers
-    // for the whole circuit.  With an odd W the last thread of K = 2 has one
-    // word: its second is never read or written (it would be the next
-    // column's first).
+    // for the whole circuit.
     {
       const uint64_t *cops = ops + d.ops_off;
       const uint32_t *coffs = offs + d.offs_off;
@@ -119,25 +131,30 @@ __global__ void __launch_bounds__(TEAM) k_batch(const BatchDescDev *__restrict__
         const uint32_t Wt = (W + K - 1) / K;                                        // threads per op
         const uint32_t Wq = Wt <= 1 ? 1u : (1u << (32 - __builtin_clz(Wt - 1)));   // pow2 >= Wt
         const uint32_t t = tid % Wq, k0 = tid / Wq, kst = TEAM / Wq;
-        const uint32_t w0 = K * t;
-        const bool has0 = w0 < W, has1 = K == 2 && w0 + 1 < W;
+        // Words past W up to the column stride Wl are padding: the threads
+        // holding them load, update and store them like the others (no
+        // branches), and nothing else reads them.  K = 2: Wq = 4, W in 5..8,
+        // Wl = 8.
+        const uint32_t w0 = K == 2 ? t + 4 * (k0 & 1u) : t, w1 = t + 4 * ((k0 & 1u) ^ 1u);
+        const bool hl = w0 < W, hh = K == 2 && w1 < W;
         T racc = zero;
         auto load = [&](const uint64_t *col) -> T {
-          if constexpr (K == 2) return T{col[w0], has1 ? col[w0 + 1] : 0ull};
+          if constexpr (K == 2) return T{col[w0], col[w1]};
           else return col[w0];
         };
         auto store = [&](uint64_t *col, T v) {
           if constexpr (K == 2) {
             col[w0] = v.lo;
-            if (has1) col[w0 + 1] = v.hi;
+            col[w1] = v.hi;
           } else {
             col[w0] = v;
           }
         };
         // Two ops on this thread's row words (ops of a layer act on distinct
         // qubits, so their columns are distinct): all loads of both first, so
-        // the second op's reads do not wait behind the first op's writes.  An
-        // absent or malformed op reads column 0 and writes nothing.
+        // the second op's reads do not wait behind the first op's writes.
+        // Loads are unconditional (an absent or malformed op reads column 0, a
+        // single-qubit op its own column twice); stores only for present ops.
         auto apply2 = [&](uint64_t op0, bool has_op0, uint64_t op1, bool has_op1) {
           uint32_t a[2], b[2], pr[2], ca[2], cb[2];
           bool go[2];
@@ -156,28 +173,30 @@ __global__ void __launch_bounds__(TEAM) k_batch(const BatchDescDev *__restrict__
           T xa[2], za[2], xb[2], zb[2];
 #pragma unroll
           for (int u = 0; u < 2; ++u) {
-            xa[u] = load(sX + a[u] * W);
-            za[u] = load(sZ + a[u] * W);
-            xb[u] = load(sX + b[u] * W);
-            zb[u] = load(sZ + b[u] * W);
+            xa[u] = load(sX + a[u] * Wl);
+            za[u] = load(sZ + a[u] * Wl);
+            xb[u] = load(sX + b[u] * Wl);
+            zb[u] = load(sZ + b[u] * Wl);
           }
+          // code 0 is the identity, so the single-qubit updates run without a
+          // branch (nearly every op has one)
 #pragma unroll
           for (int u = 0; u < 2; ++u) {
-            if (ca[u]) sq_apply(ca[u], xa[u], za[u], racc);
+            sq_apply(ca[u], xa[u], za[u], racc);
             if (pr[u] != PAIR_NONE) {
-              if (cb[u]) sq_apply(cb[u], xb[u], zb[u], racc);
+              sq_apply(cb[u], xb[u], zb[u], racc);
               pair_apply(pr[u], xa[u], za[u], xb[u], zb[u], racc);
             }
           }
 #pragma unroll
           for (int u = 0; u < 2; ++u) {
             if (pr[u] != PAIR_NONE) {
-              store(sX + b[u] * W, xb[u]);
-              store(sZ + b[u] * W, zb[u]);
+              store(sX + b[u] * Wl, xb[u]);
+              store(sZ + b[u] * Wl, zb[u]);
             }
             if (go[u]) {
-              store(sX + a[u] * W, xa[u]);
-              store(sZ + a[u] * W, za[u]);
+              store(sX + a[u] * Wl, xa[u]);
+              store(sZ + a[u] * Wl, za[u]);
             }
           }
         };
@@ -186,7 +205,7 @@ __global__ void __launch_bounds__(TEAM) k_batch(const BatchDescDev *__restrict__
         for (uint32_t l = 0; l < depth; ++l) {
           const uint32_t b0 = a1, b1 = l + 2 <= depth ? coffs[l + 2] : a1;
           const uint64_t g0 = fetch(b0 + k0), g1 = fetch(b0 + k0 + kst);
-          if (has0) {
+          {
             // the two prefetched ops in straight-line code, so their wait does
             // not cover the loads just issued for the next layer
             if (a0 + k0 < a1) apply2(f0, true, f1, a0 + k0 + kst < a1);
@@ -205,10 +224,10 @@ __global__ void __launch_bounds__(TEAM) k_batch(const BatchDescDev *__restrict__
           if (v) atomicXor(reinterpret_cast<unsigned long long *>(&sP[w]), (unsigned long long)v);
         };
         if constexpr (K == 2) {
-          if (has0) flush(w0, racc.lo);
-          if (has1) flush(w0 + 1, racc.hi);
+          if (hl) flush(w0, racc.lo);
+          if (hh) flush(w1, racc.hi);
         } else {
-          if (has0) flush(w0, racc);
+          if (hl) flush(w0, racc);
         }
       };
       if (W >= 5) gates(U128{0, 0});
@@ -229,7 +248,7 @@ __global__ void __launch_bounds__(TEAM) k_batch(const BatchDescDev *__restrict__
     auto select = [&](uint32_t a, uint32_t &p, uint64_t &m) {
       uint32_t cand = kNone;
       if (lane < W && lane >= (n >> 6)) {
-        uint64_t v = sX[a * W + lane];
+        uint64_t v = sX[a * Wl + lane];
         if (lane == (n >> 6)) v &= ~0ull << (n & 63);
         if (v) cand = lane * 64 + uint32_t(__builtin_ctzll(v));
       }
@@ -238,13 +257,13 @@ __global__ void __launch_bounds__(TEAM) k_batch(const BatchDescDev *__restrict__
       m = 0;
       if (wl < W) {
         if (p != kNone) {
-          m = sX[a * W + wl];
+          m = sX[a * Wl + wl];
           if (wl == (p >> 6)) m &= ~(1ull << (p & 63));
         } else {
           const uint32_t q = n >> 6, sh = n & 63;
           auto src = [&](int32_t i) -> uint64_t {
             if (i < 0 || i >= int32_t((n + 63) / 64)) return 0ull;
-            uint64_t v = sX[a * W + i];
+            uint64_t v = sX[a * Wl + i];
             if (uint32_t(i) == q && sh) v &= (1ull << sh) - 1;
             return v;
           };
@@ -288,10 +307,10 @@ __global__ void __launch_bounds__(TEAM) k_batch(const BatchDescDev *__restrict__
 #pragma unroll
             for (int u = 0; u < 2; ++u) {
               const uint32_t j = u ? j1 : j0;
-              xp[u] = sX[j * W + wp];
-              zp[u] = sZ[j * W + wp];
-              xv[u] = sX[j * W + wl];
-              zv[u] = sZ[j * W + wl];
+              xp[u] = sX[j * Wl + wp];
+              zp[u] = sZ[j * Wl + wp];
+              xv[u] = sX[j * Wl + wl];
+              zv[u] = sZ[j * Wl + wl];
             }
 #pragma unroll
             for (int u = 0; u < 2; ++u) {
@@ -318,8 +337,8 @@ __global__ void __launch_bounds__(TEAM) k_batch(const BatchDescDev *__restrict__
                 nx &= ~bpb;
                 nz = (j == a) ? (nz | bpb) : (nz & ~bpb);
               }
-              sX[j * W + wl] = nx;
-              sZ[j * W + wl] = nz;
+              sX[j * Wl + wl] = nx;
+              sZ[j * Wl + wl] = nz;
             }
           }
         }
@@ -384,14 +403,14 @@ __global__ void __launch_bounds__(TEAM) k_batch(const BatchDescDev *__restrict__
               const int32_t i = int32_t(w) - int32_t(q);
               auto src = [&](int32_t ii) -> uint64_t {
                 if (ii < 0 || ii >= int32_t((n + 63) / 64)) return 0ull;
-                uint64_t v = sX[a * W + ii];
+                uint64_t v = sX[a * Wl + ii];
                 if (uint32_t(ii) == q && sh) v &= (1ull << sh) - 1;
                 return v;
               };
               Tw = src(i) << sh;
               if (sh) Tw |= src(i - 1) >> (64 - sh);
             }
-            const uint64_t xt = sX[j * W + w] & Tw, zt = sZ[j * W + w] & Tw;
+            const uint64_t xt = sX[j * Wl + w] & Tw, zt = sZ[j * Wl + w] & Tw;
             ycnt += uint32_t(__popcll(xt & zt));
             uint64_t pre = zt << 1;
             pre ^= pre << 1; pre ^= pre << 2; pre ^= pre << 4;
@@ -421,6 +440,166 @@ __global__ void __launch_bounds__(TEAM) k_batch(const BatchDescDev *__restrict__
       m = m_next;
     }
   }
+}
+
+// ---- host: op order within a layer for the batch kernel's LDS banks -------
+//
+// For a circuit with W row words, the kernel's 32-lane access groups hold P
+// consecutive ops of a layer (P = 32 / Wq, Wq = threads per op), and an op's
+// column accesses fall in bank range (qubit mod P): P = 8, 16, 32 for W = 3..4,
+// 2, 1.  For W >= 5 a group holds 8 ops, its even and odd slots using the two
+// halves of a column's banks, so each half needs distinct (qubit mod 4).  A
+// group (half) is free of bank conflicts when its ops' first qubits are in
+// distinct classes, and so are their second qubits (a single-qubit op's
+// second access reads its own column again): a bipartite matching between
+// first-qubit and second-qubit classes.  Each group takes a
+// maximum matching, found by augmenting paths that try the class pairs with
+// the most ops left first (which keeps the classes balanced for the groups
+// after it); its free slots take ops from the fullest class pairs.
+namespace {
+
+struct LayerOrder {
+  static constexpr uint32_t kMaxP = 32;
+  uint32_t P = 0, nb = 0;
+  // ops grouped by class pair (a, b), key a * (P + 1) + b: pool[head[k] .. tail[k])
+  std::vector<uint64_t> pool;
+  std::vector<uint32_t> head, tail;
+  uint32_t leftA[kMaxP];
+  int matchA[kMaxP], matchB[kMaxP];
+  char seen[kMaxP];
+
+  uint32_t size(uint32_t ca, uint32_t cb) const {
+    const uint32_t k = ca * (P + 1) + cb;
+    return tail[k] - head[k];
+  }
+  uint64_t pop(uint32_t k) {
+    leftA[k / (P + 1)]--;
+    return pool[--tail[k]];
+  }
+
+  // augmenting path from first-qubit class ca (second classes with the most
+  // ops left tried first); matchA[ca] = its second class
+  bool augment(uint32_t ca) {
+    uint32_t cand[kMaxP + 1], nc = 0;
+    for (uint32_t cb = 0; cb <= P; ++cb)
+      if (size(ca, cb)) {
+        uint32_t at = nc++;   // insertion by size, most first (stable)
+        while (at > 0 && size(ca, cand[at - 1]) < size(ca, cb)) {
+          cand[at] = cand[at - 1];
+          --at;
+        }
+        cand[at] = cb;
+      }
+    for (uint32_t k = 0; k < nc; ++k) {
+      const uint32_t cb = cand[k];
+      if (cb == P) {
+        matchA[ca] = int(P);
+        return true;
+      }
+      if (seen[cb]) continue;
+      seen[cb] = 1;
+      if (matchB[cb] < 0 || augment(uint32_t(matchB[cb]))) {
+        matchA[ca] = int(cb);
+        matchB[cb] = int(ca);
+        return true;
+      }
+    }
+    return false;
+  }
+
+  // up to `slots` ops for one conflict-free group (half), appended to out
+  void take_group(uint32_t slots, std::vector<uint64_t> &out) {
+    uint32_t order[kMaxP];
+    for (uint32_t ca = 0; ca < P; ++ca) {   // first-qubit classes with the most ops left first
+      matchA[ca] = matchB[ca] = -1;
+      uint32_t at = ca;
+      while (at > 0 && leftA[order[at - 1]] < leftA[ca]) {
+        order[at] = order[at - 1];
+        --at;
+      }
+      order[at] = ca;
+    }
+    uint32_t got = 0;
+    for (uint32_t r = 0; r < P && got < slots; ++r) {
+      const uint32_t ca = order[r];
+      if (!leftA[ca]) break;
+      for (uint32_t k = 0; k < P; ++k) seen[k] = 0;
+      if (augment(ca)) ++got;
+    }
+    for (uint32_t ca = 0; ca < P; ++ca)
+      if (matchA[ca] >= 0) out.push_back(pop(ca * (P + 1) + uint32_t(matchA[ca])));
+    for (; got < slots; ++got) {   // no conflict-free op left: the fullest class pair
+      uint32_t best = 0, bi = nb;
+      for (uint32_t k = 0; k < nb; ++k)
+        if (tail[k] - head[k] > best) {
+          best = tail[k] - head[k];
+          bi = k;
+        }
+      if (bi == nb) break;
+      out.push_back(pop(bi));
+    }
+  }
+
+  void run(uint64_t *ops, uint32_t cnt, uint32_t W, std::vector<uint64_t> &tmp) {
+    if (cnt <= 1) return;
+    const bool halves = W >= 5;
+    if (halves) {
+      P = 4;
+    } else {
+      const uint32_t wq = W <= 1 ? 1u : (1u << (32 - __builtin_clz(W - 1)));
+      P = 32 / wq;
+    }
+    nb = P * (P + 1);
+    // the kernel's second access of a single-qubit op reads its own column again
+    auto key = [&](uint64_t op) {
+      return (op_a(op) % P) * (P + 1) + (op_pair(op) != PAIR_NONE ? op_b(op) : op_a(op)) % P;
+    };
+    head.assign(nb + 1, 0);
+    for (uint32_t k = 0; k < cnt; ++k) head[key(ops[k]) + 1]++;
+    for (uint32_t k = 0; k < nb; ++k) head[k + 1] += head[k];
+    tail.assign(head.begin(), head.end() - 1);
+    pool.resize(cnt);
+    for (uint32_t k = cnt; k-- > 0;) pool[tail[key(ops[k])]++] = ops[k];   // reversed: pops give stream order
+    for (uint32_t ca = 0; ca < P; ++ca) leftA[ca] = head[(ca + 1) * (P + 1)] - head[ca * (P + 1)];
+    tmp.clear();
+    while (tmp.size() < cnt) {
+      const uint32_t rest = cnt - uint32_t(tmp.size());
+      if (!halves) {
+        take_group(std::min(P, rest), tmp);
+      } else {
+        uint64_t ev[8], od[8];
+        std::vector<uint64_t> &buf = tmp;   // the two halves, interleaved slot by slot
+        const size_t at = buf.size();
+        take_group(std::min(4u, (rest + 1) / 2), buf);
+        const uint32_t ne = uint32_t(buf.size() - at);
+        for (uint32_t k = 0; k < ne; ++k) ev[k] = buf[at + k];
+        buf.resize(at);
+        take_group(std::min(4u, rest - ne), buf);
+        const uint32_t no = uint32_t(buf.size() - at);
+        for (uint32_t k = 0; k < no; ++k) od[k] = buf[at + k];
+        buf.resize(at);
+        for (uint32_t k = 0; k < 4; ++k) {
+          if (k < ne) buf.push_back(ev[k]);
+          if (k < no) buf.push_back(od[k]);
+        }
+      }
+    }
+    std::copy(tmp.begin(), tmp.end(), ops);
+  }
+};
+
+}  // namespace
+
+int batch_order_ops(uint32_t n, uint64_t *ops, const uint32_t *offs, uint32_t depth) {
+  if (n < 1 || n > kBatchMaxN || !offs) return -1;
+  for (uint32_t l = 0; l < depth; ++l)
+    if (offs[l + 1] < offs[l]) return -1;
+  if (offs[depth] > offs[0] && !ops) return -1;
+  const uint32_t W = (2 * n + 63) / 64;
+  std::vector<uint64_t> tmp;
+  LayerOrder lo;
+  for (uint32_t l = 0; l < depth; ++l) lo.run(ops + offs[l], offs[l + 1] - offs[l], W, tmp);
+  return 0;
 }
 
 // Teams per compute unit for a launch's LDS size.

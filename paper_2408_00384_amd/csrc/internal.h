@@ -265,6 +265,9 @@ hipError_t launch_measure_persist(const TabDev &t, uint32_t kc, const uint32_t *
 // Batched circuits: team in {64, 128, 256, 512, 1024}, 1 <= maxn <= kBatchMaxN,
 // 1 <= max_shots <= 64 (hipErrorInvalidValue otherwise).
 constexpr uint32_t kBatchMaxN = 256;
+// Reorders the ops of every layer (host memory, in place) for the batch
+// kernel's LDS banks; -1 on n outside 1..kBatchMaxN, NULL or decreasing offsets.
+int batch_order_ops(uint32_t n, uint64_t *ops, const uint32_t *offs, uint32_t depth);
 hipError_t launch_batch(const void *descs, const uint64_t *ops, const uint32_t *offs, uint8_t *out,
                         const uint32_t *order, uint32_t count, uint64_t seed, uint32_t *work,
                         uint32_t team, uint32_t maxn, uint32_t max_shots, int num_cus, hipStream_t st);
