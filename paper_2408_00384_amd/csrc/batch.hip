@@ -16,7 +16,8 @@
 // qubits, MW = ceil(2 maxn / 64) row words, MWl the power of two >= MW, SS =
 // most shots): X[j][w] and Z[j][w] (column-major, column stride Wl = the power
 // of two >= the circuit's W, maxn * MWl words each), signs R[w][s] (MW * SS),
-// pending gate signs (MW), and the waves' counter slots (2 * waves * MWl).
+// pending gate signs (MW), the waves' counter slots (two sets of 2 * waves *
+// MWl) and the next measured column's x words (two sets of MW).
 // Occupancy follows from that size, so a launch of small circuits keeps more
 // teams per compute unit.
 //
@@ -46,7 +47,7 @@ struct BatchLds {
     mw = (2 * maxn + 63) / 64;
     mwl = mw <= 1 ? 1u : (1u << (32 - __builtin_clz(mw - 1)));
     ss = max_shots;
-    words = 2 * maxn * mwl + mw * ss + mw + 2 * nwave * mwl;
+    words = 2 * maxn * mwl + mw * ss + mw + 4 * nwave * mwl + 2 * mw;
   }
 };
 
@@ -66,9 +67,10 @@ __global__ void __launch_bounds__(TEAM) k_batch(const BatchDescDev *__restrict__
   uint64_t *const sZ = sX + maxn * lay.mwl;
   uint64_t *const sR = sZ + maxn * lay.mwl;      // signs, stride SS
   uint64_t *const sP = sR + lay.mw * SS;         // gate sign flips (same for every shot)
-  uint64_t *const sC0 = sP + lay.mw;             // counter slots
-  uint64_t *const sC1 = sC0 + NWAVE * lay.mwl;
-  __shared__ uint32_t s_circ, s_par, s_y;
+  uint64_t *const sC0 = sP + lay.mw;             // counter slots, two sets (measurement parity)
+  uint64_t *const sC1 = sC0 + 2 * NWAVE * lay.mwl;
+  uint64_t *const sN = sC1 + 2 * NWAVE * lay.mwl; // column of the next measurement, two sets
+  __shared__ uint32_t s_circ, s_par[2], s_y[2];
   const uint32_t tid = threadIdx.x, lane = tid & 63;
   const uint32_t wave = __builtin_amdgcn_readfirstlane(tid >> 6);
 
@@ -137,17 +139,21 @@ __global__ void __launch_bounds__(TEAM) k_batch(const BatchDescDev *__restrict__
         // Wl = 8.
         const uint32_t w0 = K == 2 ? t + 4 * (k0 & 1u) : t, w1 = t + 4 * ((k0 & 1u) ^ 1u);
         const bool hl = w0 < W, hh = K == 2 && w1 < W;
+        const uint32_t stride = K == 2 ? 8u : Wl;   // column stride (words); 8 whenever K = 2
+        // this thread's words of column 0 in X and Z; column c is c * stride
+        // words on
+        uint64_t *const xl = sX + w0, *const zl = sZ + w0, *const xh = sX + w1, *const zh = sZ + w1;
         T racc = zero;
-        auto load = [&](const uint64_t *col) -> T {
-          if constexpr (K == 2) return T{col[w0], col[w1]};
-          else return col[w0];
+        auto load = [&](uint64_t *lo, uint64_t *hi, uint32_t c) -> T {
+          if constexpr (K == 2) return T{lo[c * stride], hi[c * stride]};
+          else return lo[c * stride];
         };
-        auto store = [&](uint64_t *col, T v) {
+        auto store = [&](uint64_t *lo, uint64_t *hi, uint32_t c, T v) {
           if constexpr (K == 2) {
-            col[w0] = v.lo;
-            col[w1] = v.hi;
+            lo[c * stride] = v.lo;
+            hi[c * stride] = v.hi;
           } else {
-            col[w0] = v;
+            lo[c * stride] = v;
           }
         };
         // Two ops on this thread's row words (ops of a layer act on distinct
@@ -173,30 +179,39 @@ __global__ void __launch_bounds__(TEAM) k_batch(const BatchDescDev *__restrict__
           T xa[2], za[2], xb[2], zb[2];
 #pragma unroll
           for (int u = 0; u < 2; ++u) {
-            xa[u] = load(sX + a[u] * Wl);
-            za[u] = load(sZ + a[u] * Wl);
-            xb[u] = load(sX + b[u] * Wl);
-            zb[u] = load(sZ + b[u] * Wl);
+            xa[u] = load(xl, xh, a[u]);
+            za[u] = load(zl, zh, a[u]);
+            xb[u] = load(xl, xh, b[u]);
+            zb[u] = load(zl, zh, b[u]);
           }
           // code 0 is the identity, so the single-qubit updates run without a
-          // branch (nearly every op has one)
+          // branch (nearly every op has one).  When the wave's two-qubit ops
+          // are all CNOTs (a wave-uniform test), the CNOT runs under a lane
+          // mask instead of the per-kind branches.
+          const bool only_cnot = __ballot((pr[0] != PAIR_NONE && pr[0] != PAIR_CNOT) ||
+                                          (pr[1] != PAIR_NONE && pr[1] != PAIR_CNOT)) == 0;
 #pragma unroll
           for (int u = 0; u < 2; ++u) {
             sq_apply(ca[u], xa[u], za[u], racc);
-            if (pr[u] != PAIR_NONE) {
-              sq_apply(cb[u], xb[u], zb[u], racc);
+            sq_apply(cb[u], xb[u], zb[u], racc);   // cb = 0 without a second qubit
+            if (only_cnot) {
+              const T mc = mask_if<T>(pr[u] == PAIR_CNOT);
+              racc ^= bop3<LUT_AND3>(mc, xa[u], bop3<LUT_AND_ANDN>(zb[u], mc, xb[u] ^ za[u]));
+              xb[u] ^= xa[u] & mc;
+              za[u] ^= zb[u] & mc;
+            } else if (pr[u] != PAIR_NONE) {
               pair_apply(pr[u], xa[u], za[u], xb[u], zb[u], racc);
             }
           }
 #pragma unroll
           for (int u = 0; u < 2; ++u) {
             if (pr[u] != PAIR_NONE) {
-              store(sX + b[u] * Wl, xb[u]);
-              store(sZ + b[u] * Wl, zb[u]);
+              store(xl, xh, b[u], xb[u]);
+              store(zl, zh, b[u], zb[u]);
             }
             if (go[u]) {
-              store(sX + a[u] * Wl, xa[u]);
-              store(sZ + a[u] * Wl, za[u]);
+              store(xl, xh, a[u], xa[u]);
+              store(zl, zh, a[u], za[u]);
             }
           }
         };
@@ -244,11 +259,14 @@ __global__ void __launch_bounds__(TEAM) k_batch(const BatchDescDev *__restrict__
     uint8_t *cout = out + d.out_off;
     // Pivot of measurement a (smallest stabilizer row with x_a = 1) and, per
     // lane word, its update mask (random) or product-row mask T
-    // (deterministic); every wave computes them from column a.
+    // (deterministic); every wave computes them from the x words of column a
+    // as staged in sN[a & 1] (the column itself may already be changing under
+    // a wave that has gone on to sweep measurement a).
     auto select = [&](uint32_t a, uint32_t &p, uint64_t &m) {
+      const uint64_t *col = sN + (a & 1u) * lay.mw;
       uint32_t cand = kNone;
       if (lane < W && lane >= (n >> 6)) {
-        uint64_t v = sX[a * Wl + lane];
+        uint64_t v = col[lane];
         if (lane == (n >> 6)) v &= ~0ull << (n & 63);
         if (v) cand = lane * 64 + uint32_t(__builtin_ctzll(v));
       }
@@ -257,13 +275,13 @@ __global__ void __launch_bounds__(TEAM) k_batch(const BatchDescDev *__restrict__
       m = 0;
       if (wl < W) {
         if (p != kNone) {
-          m = sX[a * Wl + wl];
+          m = col[wl];
           if (wl == (p >> 6)) m &= ~(1ull << (p & 63));
         } else {
           const uint32_t q = n >> 6, sh = n & 63;
           auto src = [&](int32_t i) -> uint64_t {
             if (i < 0 || i >= int32_t((n + 63) / 64)) return 0ull;
-            uint64_t v = sX[a * Wl + i];
+            uint64_t v = col[i];
             if (uint32_t(i) == q && sh) v &= (1ull << sh) - 1;
             return v;
           };
@@ -273,24 +291,27 @@ __global__ void __launch_bounds__(TEAM) k_batch(const BatchDescDev *__restrict__
         }
       }
     };
-    // Two barriers per measurement: after the sweep (the columns are final,
-    // so every wave selects measurement a + 1 while wave 0 updates the signs
-    // of a) and after the signs.  The sweep needs none before it: the
-    // selection's reads of column a happened before the last barrier, the
-    // signs it reads are not written by the sweep, and a column's words are
-    // read and written by one wave in program order.
+    // One barrier per measurement a, after the sweep (or the deterministic
+    // sums): then every wave selects a + 1 from the staged column while wave
+    // 0 sums the counters and updates the signs of a, and each wave goes on
+    // to sweep a + 1 without waiting for wave 0.  That is safe because the
+    // signs, the outcome bytes and the anomaly count are wave 0's alone; the
+    // counter slots, the deterministic sums and the staged column are double
+    // buffered by measurement parity (a set is written again two measurements
+    // later, after a barrier that wave 0 reaches only once it has read it);
+    // a column's words are read and written by one lane in program order
+    // within the sweeps; and the deterministic branch, which reads every
+    // column, does so before the barrier that any later sweep comes after.
     uint32_t p;
     uint64_t m;
-    select(0, p, m);
-    if (tid == 0) { s_par = 0; s_y = 0; }
+    if (tid < W) sN[tid] = sX[tid];   // column 0 staged
+    if (tid < 2) { s_par[tid] = 0; s_y[tid] = 0; }
     lds_barrier();
+    select(0, p, m);
+    const uint32_t own = slot;        // lanes (sub, wl) of this slot own columns j = slot (mod slots)
     for (uint32_t a = 0; a < n; ++a) {
-      // pivot signs of every shot, final since the barrier that ended a - 1
-      uint64_t rpw = 0;   // bit s = r_p of shot s (wave-uniform)
-      if (p != kNone) {
-        const uint32_t b = lane < S ? uint32_t(sR[(p >> 6) * SS + lane] >> (p & 63)) & 1u : 0u;
-        rpw = __ballot(b);
-      }
+      const uint32_t ab = a & 1u;
+      uint64_t *const c0s = sC0 + ab * NWAVE * Wl, *const c1s = sC1 + ab * NWAVE * Wl;
       uint32_t p_next = kNone;
       uint64_t m_next = 0;
       if (p != kNone) {
@@ -351,18 +372,24 @@ __global__ void __launch_bounds__(TEAM) k_batch(const BatchDescDev *__restrict__
           c0 ^= b0;
         }
         if (lane < Wl) {
-          sC0[wave * Wl + lane] = c0;
-          sC1[wave * Wl + lane] = c1;
+          c0s[wave * Wl + lane] = c0;
+          c1s[wave * Wl + lane] = c1;
         }
+        // the owner lanes stage column a + 1 as measurement a left it
+        if (a + 1 < n && wl < W && (a + 1) % slots == own)
+          sN[(ab ^ 1u) * lay.mw + wl] = sX[(a + 1) * Wl + wl];
         lds_barrier();
         if (a + 1 < n) select(a + 1, p_next, m_next);
         // reduce counters per word (wave 0), then update the signs of all shots
         if (wave == 0) {
+          // pivot signs of every shot (bit s = r_p of shot s)
+          const uint32_t rb = lane < S ? uint32_t(sR[wp * SS + lane] >> (p & 63)) & 1u : 0u;
+          const uint64_t rpw = __ballot(rb);
           uint64_t t0 = 0, t1 = 0;
           if (lane < Wl && lane < W) {
 #pragma unroll
             for (int wv = 0; wv < NWAVE; ++wv) {
-              const uint64_t b0 = sC0[wv * Wl + lane], b1 = sC1[wv * Wl + lane];
+              const uint64_t b0 = c0s[wv * Wl + lane], b1 = c1s[wv * Wl + lane];
               t1 ^= b1 ^ (t0 & b0);
               t0 ^= b0;
             }
@@ -419,10 +446,13 @@ __global__ void __launch_bounds__(TEAM) k_batch(const BatchDescDev *__restrict__
             carry ^= uint32_t(__popcll(zt)) & 1u;
           }
         }
-        if (par & 1u) atomicXor(&s_par, 1u);
-        if (ycnt) atomicAdd(&s_y, ycnt);
+        if (par & 1u) atomicXor(&s_par[ab], 1u);
+        if (ycnt) atomicAdd(&s_y[ab], ycnt);
+        // measurement a changed nothing: column a + 1 staged as it stands
+        if (a + 1 < n && wl < W && (a + 1) % slots == own)
+          sN[(ab ^ 1u) * lay.mw + wl] = sX[(a + 1) * Wl + wl];
         lds_barrier();
-        if (a + 1 < n) select(a + 1, p_next, m_next);   // measurement a changed nothing
+        if (a + 1 < n) select(a + 1, p_next, m_next);
         if (wave == 0) {
           // shuffles with the whole wave active (lane w holds mask word w)
           uint32_t rt = 0;
@@ -430,12 +460,12 @@ __global__ void __launch_bounds__(TEAM) k_batch(const BatchDescDev *__restrict__
             const uint64_t Tw = __shfl(m, int(w));
             if (lane < S) rt ^= uint32_t(__popcll(Tw & sR[w * SS + lane])) & 1u;
           }
-          if (lane < S) cout[size_t(lane) * n + a] = uint8_t(rt ^ (s_par & 1u) ^ ((s_y >> 1) & 1u));
+          const uint32_t par_a = s_par[ab], y_a = s_y[ab];
+          if (lane < S) cout[size_t(lane) * n + a] = uint8_t(rt ^ (par_a & 1u) ^ ((y_a >> 1) & 1u));
+          if (lane == 0 && (y_a & 1u)) atomicAdd(errors + 1, 1u);
+          if (lane == 0) { s_par[ab] = 0; s_y[ab] = 0; }   // after wave 0's reads above
         }
-        if (wave == 0 && lane == 0 && (s_y & 1u)) atomicAdd(errors + 1, 1u);
       }
-      if (tid == 0) { s_par = 0; s_y = 0; }   // after this thread's (wave 0's) reads above
-      lds_barrier();
       p = p_next;
       m = m_next;
     }
