@@ -48,8 +48,8 @@ VALU_PEAK_TOPS = 157.3 / 2
 TRAFFIC = {
     "k_meas_xz": {
         "sources": ("paper_2408_00384_amd/csrc/measure_persist.hip", "paper_2408_00384_amd/csrc/internal.h"),
-        "sha256": "12b2e3a34d4a3d5cf753ee2261711d3ac66cf81453b6bb501f34d97c2fddb354",
-        "bytes_per_launch": 1.1217e+09,
+        "sha256": "c8a4532da9a63235bed89403dcae8bca45091d66bd19b9ce85e53809d499be39",
+        "bytes_per_launch": 1.1224e+09,
         "summary": "profiles/k_meas_xz_plain_n10000_measure_all.md",
     },
 }
