@@ -141,8 +141,7 @@ __global__ void __launch_bounds__(kThreads) k_meas_xz(TabDev t, PersistArgs a) {
   __shared__ unsigned long long s_s0[kPersistMaxWp], s_s1[kPersistMaxWp];   // workgroup counter sums
   __shared__ uint32_t s_q[kPersistMaxChunk];            // this chunk's measured qubits
   __shared__ uint32_t s_p[2];                           // pivot row of measurement m in s_p[m & 1]
-  __shared__ uint32_t s_xpm[2][kWaves], s_zpm[2][kWaves];   // per wave: bit k = slot k
-  __shared__ uint32_t s_abort, s_par, s_y, s_acc[2];
+  __shared__ uint32_t s_abort, s_par, s_y;
   const uint32_t tid = threadIdx.x, lane = tid & 63;
   const uint32_t wave = __builtin_amdgcn_readfirstlane(tid >> 6);
   const uint32_t g = blockIdx.x, G = a.G;
@@ -162,8 +161,6 @@ __global__ void __launch_bounds__(kThreads) k_meas_xz(TabDev t, PersistArgs a) {
   for (uint32_t i = tid; i < a.k; i += blockDim.x) s_q[i] = a.qubits[i];
   if (tid == 0) {
     s_abort = 0;
-    s_acc[0] = 0;
-    s_acc[1] = 0;
     s_p[0] = kNone;
     s_p[1] = kNone;
     s_par = 0;
@@ -208,7 +205,8 @@ __global__ void __launch_bounds__(kThreads) k_meas_xz(TabDev t, PersistArgs a) {
   }
   lds_barrier();
   if (s_abort) return;
-  unsigned long long sup_acc = 0;     // this workgroup's share of 2 s + s_x + s_z (thread 0)
+  // this wave's share of the pivot-row support 2 s + s_x + s_z (wave-uniform)
+  unsigned long long wave_sup = 0;
   uint32_t n_random = 0, n_det = 0;
 
 #pragma unroll 1
@@ -238,35 +236,30 @@ __global__ void __launch_bounds__(kThreads) k_meas_xz(TabDev t, PersistArgs a) {
     }
     const uint32_t gw = p != kNone ? wp : 0;
     const uint64_t g_lo = ld_relaxed64(nsrc + 2 * gw), g_hi = ld_relaxed64(nsrc + 2 * gw + 1);
-    if (p != kNone && ln == (wp & 63)) {
-      // the lane holding row p: its bits in the owned columns (every slot
-      // read, no branch, so the LDS reads overlap; slots past ns hold zeros)
+    // The pivot row's bits in this wave's columns (bit k = slot k): every lane
+    // takes bit p of its own word (p >> 6) of every slot (no branch, so the
+    // LDS reads overlap; slots past ns hold zeros), and the lane holding row
+    // p hands its pair to the whole wave through a lane read.  Only this wave
+    // reads them, so no barrier or LDS round trip is needed.
+    uint32_t xm = 0, zm = 0;
+    if (p != kNone) {
       const uint32_t ip = wp >> 6, sh = p & 63;
-      uint32_t xm = 0, zm = 0;
+      uint32_t xl = 0, zl = 0;
 #pragma unroll
       for (int i = 0; i < L; ++i) {
         if (uint32_t(i) != ip) continue;   // wave-uniform: one branch picks the word
 #pragma unroll
         for (int k = 0; k < CW; ++k) {
-          xm |= uint32_t((xr[k][i] >> sh) & 1u) << k;
-          zm |= uint32_t((zw[(k * L + i) * 64] >> sh) & 1u) << k;
+          xl |= uint32_t((xr[k][i] >> sh) & 1u) << k;
+          zl |= uint32_t((zw[(k * L + i) * 64] >> sh) & 1u) << k;
         }
       }
-      s_xpm[b][wave] = xm;
-      s_zpm[b][wave] = zm;
-      atomicAdd(&s_acc[b], uint32_t(2 * __popc(xm | zm) + __popc(xm) + __popc(zm)));
+      xm = uint32_t(__builtin_amdgcn_readlane(int(xl), int(wp & 63)));
+      zm = uint32_t(__builtin_amdgcn_readlane(int(zl), int(wp & 63)));
+      wave_sup += uint32_t(2 * __popc(xm | zm) + __popc(xm) + __popc(zm));
     }
-    // The pivot-row bits of this wave's columns are read by this wave only, so
-    // phase b needs no workgroup barrier: the values other waves meet on are
-    // reset by thread 0 once their last reader is past a barrier (s_p[b] and
-    // s_par / s_y in phase c, s_acc double-buffered).
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
-    __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
     // ---- phase b: sweep m, then publish a_{m+2}
     if (p != kNone) {
-      const uint32_t xm = __builtin_amdgcn_readfirstlane(s_xpm[b][wave]);
-      const uint32_t zm = __builtin_amdgcn_readfirstlane(s_zpm[b][wave]);
       uint64_t mw[L], c0[L], c1[L];
 #pragma unroll
       for (int i = 0; i < L; ++i) {
@@ -448,10 +441,7 @@ __global__ void __launch_bounds__(kThreads) k_meas_xz(TabDev t, PersistArgs a) {
         s_s1[w] = 0;
       }
       if (tid == 0) {
-        // pivot-row support over this workgroup's columns: 2 s + s_x + s_z
-        sup_acc += s_acc[b];
         ++n_random;
-        s_acc[b] = 0;
       }
     } else if (tid == 0) {
       if (s_par) atomicXor(t.detpar + m, 1u);
@@ -484,8 +474,8 @@ __global__ void __launch_bounds__(kThreads) k_meas_xz(TabDev t, PersistArgs a) {
       }
     }
   }
+  if (lane == 0 && wave_sup) atomicAdd(reinterpret_cast<unsigned long long *>(t.state + ST_SUPPORT), wave_sup);
   if (tid == 0) {
-    if (sup_acc) atomicAdd(reinterpret_cast<unsigned long long *>(t.state + ST_SUPPORT), sup_acc);
     if (g == 0) {
       atomicAdd(&t.state[ST_RANDOM_CNT], n_random);
       atomicAdd(&t.state[ST_DET_CNT], n_det);
