@@ -334,11 +334,16 @@ __global__ void __launch_bounds__(kThreads) k_meas_xz(TabDev t, PersistArgs a) {
       }
       __builtin_amdgcn_wave_barrier();
       if (ln < ns) {
-        uint64_t *zk = sZ + size_t(wave) * CW * L * 64 + size_t(ln) * L * 64;   // this lane's slot
-        uint64_t &za = zk[ipn * 64 + (wpn & 63)];
-        za = ((zm >> ln) & 1u) ? (za | bpn) : (za & ~bpn);
-        uint64_t &zb = zk[ip * 64 + (wp & 63)];
-        zb = (g + (wave + ln * kWaves) * G == am) ? (zb | bpb) : (zb & ~bpb);
+        // clear, then set, the two bits with LDS atomics that return nothing
+        // (a wave's LDS operations complete in order), so no read-modify-write
+        // round trip sits on the iteration's path
+        unsigned long long *zk = reinterpret_cast<unsigned long long *>(
+            sZ + size_t(wave) * CW * L * 64 + size_t(ln) * L * 64);   // this lane's slot
+        unsigned long long *za = zk + ipn * 64 + (wpn & 63), *zb = zk + ip * 64 + (wp & 63);
+        atomicAnd(za, ~bpn);
+        atomicAnd(zb, ~bpb);
+        atomicOr(za, ((zm >> ln) & 1u) ? bpn : 0ull);
+        atomicOr(zb, g + (wave + ln * kWaves) * G == am ? bpb : 0ull);
       }
     }
     if (m + 2 < a.k) {
