@@ -48,8 +48,8 @@ VALU_PEAK_TOPS = 157.3 / 2
 TRAFFIC = {
     "k_meas_xz": {
         "sources": ("paper_2408_00384_amd/csrc/measure_persist.hip", "paper_2408_00384_amd/csrc/internal.h"),
-        "sha256": "c8a4532da9a63235bed89403dcae8bca45091d66bd19b9ce85e53809d499be39",
-        "bytes_per_launch": 1.1224e+09,
+        "sha256": "09f7ac8514d610188a899c7140616b3bf5c1c5c6c1be21e5187d6928cdeecbf2",
+        "bytes_per_launch": 1.1221e+09,
         "summary": "profiles/k_meas_xz_plain_n10000_measure_all.md",
     },
 }
