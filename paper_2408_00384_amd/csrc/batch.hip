@@ -35,6 +35,12 @@
 
 namespace cliff {
 
+// Number of ops a gate-loop step applies per thread, as a type.
+template <int N>
+struct OpCount {
+  static constexpr int value = N;
+};
+
 struct BatchDescDev {
   uint32_t n, depth, shots, reserved;
   uint64_t ops_off, offs_off, out_off, circuit_id;
@@ -161,11 +167,12 @@ __global__ void __launch_bounds__(TEAM) k_batch(const BatchDescDev *__restrict__
         // the second op's reads do not wait behind the first op's writes.
         // Loads are unconditional (an absent or malformed op reads column 0, a
         // single-qubit op its own column twice); stores only for present ops.
-        auto apply2 = [&](uint64_t op0, bool has_op0, uint64_t op1, bool has_op1) {
+        auto apply = [&](auto count, uint64_t op0, bool has_op0, uint64_t op1, bool has_op1) {
+          constexpr int N = decltype(count)::value;   // 1 when no lane of the wave has a second op
           uint32_t a[2], b[2], pr[2], ca[2], cb[2];
           bool go[2];
 #pragma unroll
-          for (int u = 0; u < 2; ++u) {
+          for (int u = 0; u < N; ++u) {
             const uint64_t op = u ? op1 : op0;
             const bool has = u ? has_op1 : has_op0;
             go[u] = has && op_valid(op, n);
@@ -178,7 +185,7 @@ __global__ void __launch_bounds__(TEAM) k_batch(const BatchDescDev *__restrict__
           }
           T xa[2], za[2], xb[2], zb[2];
 #pragma unroll
-          for (int u = 0; u < 2; ++u) {
+          for (int u = 0; u < N; ++u) {
             xa[u] = load(xl, xh, a[u]);
             za[u] = load(zl, zh, a[u]);
             xb[u] = load(xl, xh, b[u]);
@@ -188,10 +195,12 @@ __global__ void __launch_bounds__(TEAM) k_batch(const BatchDescDev *__restrict__
           // branch (nearly every op has one).  When the wave's two-qubit ops
           // are all CNOTs (a wave-uniform test), the CNOT runs under a lane
           // mask instead of the per-kind branches.
-          const bool only_cnot = __ballot((pr[0] != PAIR_NONE && pr[0] != PAIR_CNOT) ||
-                                          (pr[1] != PAIR_NONE && pr[1] != PAIR_CNOT)) == 0;
+          bool other = false;
 #pragma unroll
-          for (int u = 0; u < 2; ++u) {
+          for (int u = 0; u < N; ++u) other |= pr[u] != PAIR_NONE && pr[u] != PAIR_CNOT;
+          const bool only_cnot = __ballot(other) == 0;
+#pragma unroll
+          for (int u = 0; u < N; ++u) {
             sq_apply(ca[u], xa[u], za[u], racc);
             sq_apply(cb[u], xb[u], zb[u], racc);   // cb = 0 without a second qubit
             if (only_cnot) {
@@ -204,7 +213,7 @@ __global__ void __launch_bounds__(TEAM) k_batch(const BatchDescDev *__restrict__
             }
           }
 #pragma unroll
-          for (int u = 0; u < 2; ++u) {
+          for (int u = 0; u < N; ++u) {
             if (pr[u] != PAIR_NONE) {
               store(xl, xh, b[u], xb[u]);
               store(zl, zh, b[u], zb[u]);
@@ -222,11 +231,17 @@ __global__ void __launch_bounds__(TEAM) k_batch(const BatchDescDev *__restrict__
           const uint64_t g0 = fetch(b0 + k0), g1 = fetch(b0 + k0 + kst);
           {
             // the two prefetched ops in straight-line code, so their wait does
-            // not cover the loads just issued for the next layer
-            if (a0 + k0 < a1) apply2(f0, true, f1, a0 + k0 + kst < a1);
+            // not cover the loads just issued for the next layer; a wave none
+            // of whose lanes has a second op applies one (wave-uniform test)
+            if (a0 + k0 < a1) {
+              const bool second = a0 + k0 + kst < a1;
+              if (__ballot(second)) apply(OpCount<2>{}, f0, true, f1, second);
+              else apply(OpCount<1>{}, f0, true, f1, false);
+            }
             for (uint32_t k = a0 + k0 + 2 * kst; k < a1; k += 2 * kst) {
               const bool two = k + kst < a1;
-              apply2(cops[k], true, cops[two ? k + kst : k], two);
+              if (__ballot(two)) apply(OpCount<2>{}, cops[k], true, cops[two ? k + kst : k], two);
+              else apply(OpCount<1>{}, cops[k], true, 0ull, false);
             }
           }
           lds_barrier();
