@@ -285,8 +285,9 @@ __global__ void __launch_bounds__(TEAM) k_batch(const BatchDescDev *__restrict__
         if (lane == (n >> 6)) v &= ~0ull << (n & 63);
         if (v) cand = lane * 64 + uint32_t(__builtin_ctzll(v));
       }
-      for (int off = 32; off > 0; off >>= 1) cand = min(cand, uint32_t(__shfl_xor(int(cand), off)));
-      p = __builtin_amdgcn_readfirstlane(cand);
+      // lane w holds word w, so the first lane with a candidate has the smallest row
+      const uint64_t bal = __ballot(cand != kNone);
+      p = bal ? uint32_t(__builtin_amdgcn_readlane(int(cand), int(__builtin_ctzll(bal)))) : kNone;
       m = 0;
       if (wl < W) {
         if (p != kNone) {
