@@ -333,6 +333,10 @@ __global__ void __launch_bounds__(TEAM) k_batch(const BatchDescDev *__restrict__
       if (p != kNone) {
         const uint32_t pn = p - n, wpn = pn >> 6, wp = p >> 6;
         const uint64_t bpn = 1ull << (pn & 63), bpb = 1ull << (p & 63);
+        // this lane's bits of rows p - n and p (zero where its word holds
+        // neither): overwritten in every column by the pivot row's bits, and
+        // by x = 0, z = [column is a], as masked selects
+        const uint64_t Bpn = wl == wpn ? bpn : 0ull, Bp = wl == wp ? bpb : 0ull, F = Bpn | Bp;
         uint64_t c0 = 0, c1 = 0;
         if (wl < W) {
           // two columns per pass, all loads first (distinct columns: the
@@ -366,14 +370,8 @@ __global__ void __launch_bounds__(TEAM) k_batch(const BatchDescDev *__restrict__
               c1 ^= bop3<LUT_AND_XNOR>(anti, c0, sel);
               c0 ^= anti;
               uint64_t nx = bop3<LUT_AND_XOR>(X1, m, x), nz = bop3<LUT_AND_XOR>(Z1, m, z);
-              if (wl == wpn) {
-                nx = xpj ? (nx | bpn) : (nx & ~bpn);
-                nz = zpj ? (nz | bpn) : (nz & ~bpn);
-              }
-              if (wl == wp) {
-                nx &= ~bpb;
-                nz = (j == a) ? (nz | bpb) : (nz & ~bpb);
-              }
+              nx = (nx & ~F) | (X1 & Bpn);
+              nz = (nz & ~F) | (Z1 & Bpn) | (mask_if<uint64_t>(j == a) & Bp);
               sX[j * Wl + wl] = nx;
               sZ[j * Wl + wl] = nz;
             }
