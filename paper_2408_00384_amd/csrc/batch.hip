@@ -17,7 +17,8 @@
 // most shots): X[j][w] and Z[j][w] (column-major, column stride Wl = the power
 // of two >= the circuit's W, maxn * MWl words each), signs R[w][s] (MW * SS),
 // pending gate signs (MW), the waves' counter slots (two sets of 2 * waves *
-// MWl) and the next measured column's x words (two sets of MW).
+// MWl), the next measured column's x words (two sets of MW) and the random
+// outcome bits (maxn * SS bits).
 // Occupancy follows from that size, so a launch of small circuits keeps more
 // teams per compute unit.
 //
@@ -53,7 +54,7 @@ struct BatchLds {
     mw = (2 * maxn + 63) / 64;
     mwl = mw <= 1 ? 1u : (1u << (32 - __builtin_clz(mw - 1)));
     ss = max_shots;
-    words = 2 * maxn * mwl + mw * ss + mw + 4 * nwave * mwl + 2 * mw;
+    words = 2 * maxn * mwl + mw * ss + mw + 4 * nwave * mwl + 2 * mw + (maxn * ss + 63) / 64;
   }
 };
 
@@ -76,6 +77,7 @@ __global__ void __launch_bounds__(TEAM) k_batch(const BatchDescDev *__restrict__
   uint64_t *const sC0 = sP + lay.mw;             // counter slots, two sets (measurement parity)
   uint64_t *const sC1 = sC0 + 2 * NWAVE * lay.mwl;
   uint64_t *const sN = sC1 + 2 * NWAVE * lay.mwl; // column of the next measurement, two sets
+  uint64_t *const sO = sN + 2 * lay.mw;           // random outcome bits, bit m * S + shot
   __shared__ uint32_t s_circ, s_par[2], s_y[2];
   const uint32_t tid = threadIdx.x, lane = tid & 63;
   const uint32_t wave = __builtin_amdgcn_readfirstlane(tid >> 6);
@@ -104,6 +106,15 @@ __global__ void __launch_bounds__(TEAM) k_batch(const BatchDescDev *__restrict__
       sZ[i] = (w == (zr >> 6)) ? (1ull << (zr & 63)) : 0ull;
     }
     for (uint32_t i = tid; i < W * SS; i += TEAM) sR[i] = 0;
+    // the Philox bit of every (measurement, shot), all waves at once, packed
+    // 64 to a word by a ballot: the measurement loop then reads its bits
+    // instead of running the generator on the sign-updating wave
+    for (uint32_t base = wave * 64; base < n * S; base += TEAM) {
+      const uint32_t i = base + lane;
+      const uint32_t bit = i < n * S ? outcome_bit(seed, d.circuit_id, i % S, i / S) : 0u;
+      const uint64_t word = __ballot(bit);
+      if (lane == 0) sO[base / 64] = word;
+    }
     if (tid < lay.mw) sP[tid] = 0;
     __syncthreads();
     // ---- gate layers: thread <-> (op, K row words).  From W = 5 on K = 2, the
@@ -421,7 +432,7 @@ __global__ void __launch_bounds__(TEAM) k_batch(const BatchDescDev *__restrict__
               rv ^= mw & (c1w ^ (rpb ? ~0ull : 0ull));
               if (w == wpn) rv = rpb ? (rv | bpn) : (rv & ~bpn);
               if (w == wp) {
-                const uint32_t o = outcome_bit(seed, d.circuit_id, sh, a);
+                const uint32_t o = uint32_t(sO[(a * S + sh) / 64] >> ((a * S + sh) & 63)) & 1u;
                 rv = o ? (rv | bpb) : (rv & ~bpb);
                 cout[size_t(sh) * n + a] = uint8_t(o);
               }
