@@ -107,18 +107,26 @@ int cliff_calibrate(cliff_ctx *ctx, int kind, double *out);
 #define CLIFF_GATES_FUSED 2
 int cliff_ctx_set_gate_mode(cliff_ctx *ctx, int mode);
 
-/* Measurement strategy.  AUTO: the register-resident path when the tableau
- * shape allows it (ceil(2n/64) <= 320, i.e. n <= 10240, and the columns fit
- * the registers and LDS of at most 256 compute units), else one kernel per
- * measurement.  STEP: always one kernel per measurement.
- * PERSISTENT: always the register-resident path (EINVAL if n does not fit).
- * Results are identical; only speed differs.  The register-resident path is
- * the faster one for random and for deterministic measurements alike: a GHZ
- * measure-all (n - 1 of n outcomes deterministic) takes 61 ms there at
- * n = 10,000 against 125 ms with STEP, and 9 against 26 ms at n = 4,096. */
+/* Measurement strategy.  PERSISTENT: the register-resident path (the tableau
+ * held in registers and LDS of up to 256 compute units for a chunk of
+ * measurements, one rowsum sweep per measurement); EINVAL when the tableau
+ * shape does not fit (ceil(2n/64) <= 320, i.e. n <= 10240).  BLOCKED: the
+ * register-resident path where each chunk's leading run of random
+ * measurements is applied in blocks of up to 32 as one low-rank update (the
+ * per-measurement kernels take the chunk's remaining measurements from its
+ * first deterministic one); where the blocked launch shape does not fit
+ * (n in (8 L * 255, 64 L] for L = ceil(2n/4096), e.g. n = 2041..2048,
+ * 8161..8192, 10201..10240) it is PERSISTENT.  STEP: one kernel per
+ * measurement.  AUTO: BLOCKED for n >= 2048, PERSISTENT below, STEP where
+ * neither fits.  Results are identical; only speed differs.  A measure-all of
+ * a dense state at n = 10,000 takes 22.5 ms with BLOCKED against 38.7 ms with
+ * PERSISTENT (7,000: 14.5 against 22.5 ms; 2,100: 4.3 against 4.6 ms); a GHZ
+ * measure-all (n - 1 of n outcomes deterministic) takes 61 ms with the
+ * register-resident path at n = 10,000 against 125 ms with STEP. */
 #define CLIFF_MEASURE_AUTO 0
 #define CLIFF_MEASURE_STEP 1
 #define CLIFF_MEASURE_PERSISTENT 2
+#define CLIFF_MEASURE_BLOCKED 3
 int cliff_ctx_set_measure_mode(cliff_ctx *ctx, int mode);
 
 /* Failure handling of the register-resident path.  Its workgroups wait for

@@ -159,7 +159,7 @@ def cliff_ctx_num_cus(ctx) -> int:
 
 
 GATES_AUTO, GATES_PER_LAYER, GATES_FUSED = 0, 1, 2
-MEASURE_AUTO, MEASURE_STEP, MEASURE_PERSISTENT = 0, 1, 2
+MEASURE_AUTO, MEASURE_STEP, MEASURE_PERSISTENT, MEASURE_BLOCKED = 0, 1, 2, 3
 
 
 CAL_LDS, CAL_VALU = 0, 1
@@ -500,4 +500,4 @@ __all__ = [n for n in list(globals()) if n.startswith("cliff_")] + [
     "CLIFF_EINTERNAL", "OP_H", "OP_S", "OP_CNOT", "OP_SDG", "OP_X", "OP_Y", "OP_Z", "OP_CZ",
     "OP_SWAP", "BASIS_Z", "BASIS_X", "BASIS_Y", "CliffError", "LIB_PATH", "exported_symbols",
     "PROF_KINDS", "BATCH_DESC_DTYPE", "BATCH_TEAMS", "BATCH_MAXN", "GATES_AUTO", "GATES_PER_LAYER",
-    "GATES_FUSED", "MEASURE_AUTO", "MEASURE_STEP", "MEASURE_PERSISTENT", "CAL_LDS", "CAL_VALU"]
+    "GATES_FUSED", "MEASURE_AUTO", "MEASURE_STEP", "MEASURE_PERSISTENT", "MEASURE_BLOCKED", "CAL_LDS", "CAL_VALU"]

@@ -293,7 +293,7 @@ int cliff_ctx_inject_abort(cliff_ctx *c, uint64_t at) {
 
 int cliff_ctx_set_measure_mode(cliff_ctx *c, int mode) {
   if (!c) return fail(CLIFF_EINVAL, "cliff_ctx_set_measure_mode: NULL context");
-  if (mode < CLIFF_MEASURE_AUTO || mode > CLIFF_MEASURE_PERSISTENT)
+  if (mode < CLIFF_MEASURE_AUTO || mode > CLIFF_MEASURE_BLOCKED)
     return fail(CLIFF_EINVAL, "cliff_ctx_set_measure_mode: bad mode %d", mode);
   c->measure_mode = mode;
   return CLIFF_OK;
@@ -818,10 +818,10 @@ extern "C" int cliff_apply_gates_many(cliff_tab *const *tabs, const uint8_t *con
 // else one step kernel per measurement.
 // `abort_at` (test aid): the pass's measurement at which its workgroups give
 // up as on a timed-out wait, or UINT64_MAX.
-// The context's chunk scratch for chunks of kc measurements of t's shape,
-// grown (after both streams drain) when a larger shape comes along.
-static int ctx_persist_scratch(cliff_ctx *c, const Dims &d, uint32_t kc, uint8_t **base) {
-  const size_t need = persist_scratch_layout(d, kc).total;
+// The context's chunk scratch (`need` bytes: the per-measurement kernels'
+// and, when used, the blocked pass's), grown (after both streams drain) when
+// a larger shape comes along.
+static int ctx_persist_scratch(cliff_ctx *c, size_t need, uint8_t **base) {
   if (c->pscratch_bytes < need) {
     HIP_TRY(hipStreamSynchronize(c->stream));
     HIP_TRY(hipStreamSynchronize(c->aux));
@@ -850,31 +850,48 @@ static int measure_pass(cliff_tab *t, const uint32_t *qubits, size_t cnt, uint64
   hipStream_t st = c->stream;
   uint32_t G, L, CW;
   const bool shape_ok = persist_layout(t->d.n) && persist_shape(t->d.n, uint32_t(c->num_cus), &G, &L, &CW);
-  if (c->measure_mode == CLIFF_MEASURE_PERSISTENT && !shape_ok)
+  uint32_t bG = 0, bL = 0;
+  const bool blk_ok = shape_ok && blk_shape(t->d.n, uint32_t(c->num_cus), &bG, &bL);
+  if ((c->measure_mode == CLIFF_MEASURE_PERSISTENT || c->measure_mode == CLIFF_MEASURE_BLOCKED) && !shape_ok)
     return fail(CLIFF_EINVAL, "register-resident measurement does not fit n = %u", t->d.n);
+  // the allocation-free entry keeps to the per-measurement kernels
+  const bool use_blk = !noalloc && blk_ok &&
+                       (c->measure_mode == CLIFF_MEASURE_BLOCKED ||
+                        (c->measure_mode == CLIFF_MEASURE_AUTO && t->d.n >= kBlkAutoMinN));
   if (c->measure_mode != CLIFF_MEASURE_STEP && shape_ok) {
     const uint32_t *dq = nullptr;
     uint8_t *base = nullptr;
     uint32_t kc = 0;
     int rc;
+    size_t blk_at = 0, blk_set = 0;
     if (noalloc) {
       rc = noalloc_persist_scratch(c, t->d, qubits, cnt, &kc, &base, &dq);
     } else {
       kc = persist_chunk(t->d.n);
+      size_t need = persist_scratch_layout(t->d, kc).total;
+      if (use_blk) {
+        blk_at = align256(need);
+        blk_set = align256(blk_scratch_layout(t->d, kc, bG).total);
+        need = blk_at + 2 * blk_set;
+      }
       rc = upload_stream(c, nullptr, 0, qubits, cnt, nullptr, &dq);
-      if (!rc) rc = ctx_persist_scratch(c, t->d, kc, &base);
+      if (!rc) rc = ctx_persist_scratch(c, need, &base);
     }
     if (rc) return rc;
     TabDev dv = t->dev;
     persist_scratch_bind(dv, t->d, kc, base);
+    BlkDev bsets[2];
+    if (use_blk)
+      for (int i = 0; i < 2; ++i) bsets[i] = blk_scratch_bind(t->d, kc, bG, base + blk_at + size_t(i) * blk_set);
     PersistStreams ps{st, c->aux, {c->persist_ev[0], c->persist_ev[1], c->persist_ev[2], c->persist_ev[3]}};
     uint32_t done = 0;
     hipError_t e = launch_measure_persist(dv, kc, dq, uint32_t(cnt), seed, circuit, shot0, m0,
-                                          c->num_cus, ps, &c->prof, &done, abort_at);
+                                          c->num_cus, ps, &c->prof, &done, abort_at,
+                                          use_blk ? bsets : nullptr, bG, bL);
     if (done) t->persist_used = true;
     if (e == hipSuccess) return CLIFF_OK;
     (void)hipGetLastError();
-    if (c->measure_mode == CLIFF_MEASURE_PERSISTENT || done)
+    if (c->measure_mode == CLIFF_MEASURE_PERSISTENT || c->measure_mode == CLIFF_MEASURE_BLOCKED || done)
       return fail(CLIFF_EDEVICE, "cooperative launch failed after %u measurements: %s", done,
                   hipGetErrorString(e));
     // nothing measured yet: fall through, the step kernels need no co-residency

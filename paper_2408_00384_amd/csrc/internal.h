@@ -220,6 +220,69 @@ inline void persist_scratch_bind(TabDev &t, const Dims &d, uint32_t kc, uint8_t 
 }
 
 
+// Blocked pass over a chunk's random measurements (measure_block.hip): blocks
+// of up to kBlkK measurements, each applied to the register-held tableau as
+// one low-rank update.  Per chunk: the block's measured columns handed to the
+// planner, U and the pivots of every block, per-workgroup sign partials, the
+// reduced sign flips, and four counters (columns published, blocks planned,
+// measurements done by the pass, spare).
+constexpr uint32_t kBlkK = 32;
+// Smallest n for which the automatic measurement mode takes the blocked pass.
+constexpr uint32_t kBlkAutoMinN = 2048;
+struct BlkDev {
+  uint64_t *cols;    // [kBlkK][Wp] measured columns of the block being planned
+  uint64_t *U;       // [NB][kBlkK][Wp] U columns (rows that absorbed pivot t)
+  uint64_t *part;    // [NB][G][3][Wp] per workgroup: (Y_old - Y_new) mod 4 (two planes), z.x parity
+  uint64_t *H;       // [NB][Wp] sign flips of the block's kept and replaced rows
+  uint32_t *piv;     // [NB][kBlkK] pivot rows
+  uint32_t *rowu;    // [NB][kBlkK] pivots absorbed by the pivot row at its step
+  uint32_t *ppart;   // [NB][G][2 + kBlkK] per workgroup: pivot Y counts (two planes), Gram rows
+  uint32_t *nb;      // [NB] measurements of each block (0: none)
+  uint32_t *sync;    // [4] counters
+  uint32_t NB;
+};
+struct BlkArgs {
+  const uint32_t *qubits;   // device, this chunk's k entries
+  uint32_t k, G;
+  uint32_t abort_at;        // as for the per-measurement kernels (kNone: never)
+};
+struct BlkScratchLayout {
+  size_t cols, U, part, H, piv, rowu, ppart, nb, sync, total;
+};
+inline BlkScratchLayout blk_scratch_layout(const Dims &d, uint32_t kc, uint32_t G) {
+  BlkScratchLayout o;
+  size_t cur = 0;
+  auto take = [&](size_t bytes) { size_t at = cur; cur = align256(cur + bytes); return at; };
+  const size_t NB = (size_t(kc) + kBlkK - 1) / kBlkK;
+  o.cols = take(size_t(kBlkK) * d.Wp * 8);
+  o.U = take(NB * kBlkK * d.Wp * 8);
+  o.part = take(NB * G * 3 * d.Wp * 8);
+  o.H = take(NB * d.Wp * 8);
+  o.piv = take(NB * kBlkK * 4);
+  o.rowu = take(NB * kBlkK * 4);
+  o.ppart = take(NB * G * (2 + kBlkK) * 4);
+  o.nb = take(NB * 4);
+  o.sync = take(16);
+  o.total = cur;
+  return o;
+}
+inline BlkDev blk_scratch_bind(const Dims &d, uint32_t kc, uint32_t G, uint8_t *base) {
+  const BlkScratchLayout o = blk_scratch_layout(d, kc, G);
+  BlkDev s;
+  s.cols = reinterpret_cast<uint64_t *>(base + o.cols);
+  s.U = reinterpret_cast<uint64_t *>(base + o.U);
+  s.part = reinterpret_cast<uint64_t *>(base + o.part);
+  s.H = reinterpret_cast<uint64_t *>(base + o.H);
+  s.piv = reinterpret_cast<uint32_t *>(base + o.piv);
+  s.rowu = reinterpret_cast<uint32_t *>(base + o.rowu);
+  s.ppart = reinterpret_cast<uint32_t *>(base + o.ppart);
+  s.nb = reinterpret_cast<uint32_t *>(base + o.nb);
+  s.sync = reinterpret_cast<uint32_t *>(base + o.sync);
+  s.NB = uint32_t((size_t(kc) + kBlkK - 1) / kBlkK);
+  return s;
+}
+
+
 // ---- launchers (each defined in the .hip file holding its kernels) ----------
 hipError_t launch_init_zero(const TabDev &t, hipStream_t st);
 hipError_t launch_fold_pending(const TabDev &t, hipStream_t st);
@@ -249,6 +312,16 @@ hipError_t launch_measure_list(const TabDev &t, const uint32_t *qubits, uint32_t
                                Profiler *prof);
 hipError_t launch_clear_state(const TabDev &t, hipStream_t st);
 bool persist_shape(uint32_t n, uint32_t num_cus, uint32_t *G, uint32_t *L, uint32_t *CW);
+// Blocked pass: G sweeper workgroups (plus one planner) and L row words per
+// lane for n qubits (false = not usable on num_cus compute units).
+bool blk_shape(uint32_t n, uint32_t num_cus, uint32_t *G, uint32_t *L);
+// One chunk of cnt measurements: the blocked pass (it stops at the first
+// deterministic measurement and leaves the count done in s.sync[2]), then
+// its sign finalize (on the stream that finalizes the chunk).
+hipError_t launch_blk_chunk(const TabDev &t, const BlkDev &s, const uint32_t *dev_qubits, uint32_t cnt,
+                            uint32_t G, uint32_t L, uint32_t abort_at, hipStream_t st);
+hipError_t launch_blk_finalize(const TabDev &t, const BlkDev &s, uint32_t cnt, uint32_t base, uint64_t seed,
+                               uint64_t circuit, uint64_t shot0, uint64_t m0, uint32_t G, hipStream_t st);
 // Streams and events of the register-resident path: chunk c's x/z kernel
 // runs on `main` while chunk c - 1's reduction and sign walk run on `aux`;
 // ev[0..1] mark x/z done and ev[2..3] finalize done per scratch buffer.
@@ -258,10 +331,14 @@ struct PersistStreams {
 };
 // *done = measurements whose launches were all enqueued (chunks before a failure).
 // t carries the chunk scratch for chunks of kc measurements (persist_scratch_bind).
+// blk: null, or two scratch sets of the blocked pass (blk_scratch_bind for kc
+// and blk_G) that then takes each chunk's leading random measurements with
+// the launch shape (blk_G, blk_L) of blk_shape.
 hipError_t launch_measure_persist(const TabDev &t, uint32_t kc, const uint32_t *dev_qubits, uint32_t k,
                                   uint64_t seed, uint64_t circuit, uint64_t shot0, uint64_t m0,
                                   int num_cus, const PersistStreams &ps, Profiler *prof, uint32_t *done,
-                                  uint64_t abort_at);
+                                  uint64_t abort_at, const BlkDev *blk = nullptr, uint32_t blk_G = 0,
+                                  uint32_t blk_L = 0);
 // Batched circuits: team in {64, 128, 256, 512, 1024}, 1 <= maxn <= kBatchMaxN,
 // 1 <= max_shots <= 64 (hipErrorInvalidValue otherwise).
 constexpr uint32_t kBatchMaxN = 256;

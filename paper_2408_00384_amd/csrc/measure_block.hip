@@ -1,0 +1,836 @@
+// Blocked measurement: a run of random Z-measurements applied to a tableau
+// held in registers as one low-rank update per block of up to 32
+// measurements, instead of one rowsum sweep (and one hand-off between
+// workgroups) per measurement.
+//
+// Method: paper Sec. 2 (Aaronson & Gottesman 2004 tableau rules); outcomes,
+// tableau bits and signs are those of the step-by-step rule.
+//
+//  * A random measurement of qubit a with pivot p (smallest stabilizer row
+//    with x = 1 on column a) multiplies every other row with x = 1 on column
+//    a by row p, copies row p into row p - n and sets row p to Z_a with the
+//    outcome as sign.  On the bits of each column this is linear in the rows,
+//    the same map for every column.  Composed over a block of measurements
+//    with pivots p_0 .. p_{k-1}, every row i that is not a pivot row ends as
+//        new_i = [i not replaced] old_i  XOR  sum_t U[i][t] old_{p_t},
+//    old = the rows at the block's start, the replaced rows being p_t - n
+//    (their old contents are dropped), and each pivot row p_t ends as Z_{a_t}.
+//    The planner builds U (2n x k bits, bit-sliced: U column t over all row
+//    words) from the block's measured columns alone, one measurement after
+//    the other; then every column takes a single update (the sweep):
+//        x ^= sum over t with x[p_t] = 1 of U_t,  same for z.
+//  * Signs.  Every product formed is of commuting Pauli rows, so a final row
+//    is the product of its factors (old_i if kept, and the pivot rows in
+//    U[i]) in any order, and its sign is
+//        sum of the factors' signs + (sum of the factors' Y counts
+//        - Y count of the result) / 2 + sum over factor pairs a < b of
+//        z(a).x(b)   (mod 2),
+//    Y count = number of columns with x = z = 1 (i^(x.z) X^x Z^z is the
+//    Hermitian Pauli of (x, z)).  With old_i taken first, the pair sum is
+//    z(old_i).(x_new_i ^ x_old_i) plus the pivot rows' Gram matrix
+//    G[a][b] = z(old_{p_a}).x(old_{p_b}) over the pairs in U[i].  The sweep
+//    sums per row (Y_old - Y_new) mod 4 and the z.x parity, and per pivot
+//    its Y count and its Gram row; the finalize kernels add them up and
+//    apply the signs, a GF(2) product per shot like the x/z update.
+//  * A deterministic measurement ends the blocked pass of its chunk: the
+//    count done here is left in device memory, and the per-measurement
+//    kernels of measure_persist.hip take the chunk's other measurements from
+//    there without a host round trip.
+//
+// Launch: G sweeper workgroups own the columns as in measure_persist.hip
+// (workgroup g the columns g (mod G), 8 waves, L whole columns of L row
+// words per lane per wave, x and z in registers) plus one planner workgroup
+// (one row word per thread, the block's columns and U in registers).  Per
+// block the owners publish the block's measured columns (plain stores, a
+// release fence, a counter), the planner publishes U and the pivots the same
+// way, and each sweeper workgroup stages U in LDS and applies it.  Every wait
+// is bounded and watches the tableau's abort flag.
+#include <utility>
+
+#include "internal.h"
+#include "philox.h"
+
+namespace cliff {
+
+namespace {
+
+constexpr uint32_t kBlkSpinLimit = 1u << 20;
+constexpr uint32_t kBlkWaves = 8;
+constexpr uint32_t kBlkThreads = kBlkWaves * 64;
+constexpr uint32_t kBlkSignThreads = 256;
+
+__device__ __forceinline__ uint64_t bbit(uint32_t b) { return 1ull << (b & 63); }
+
+// Loads of data another workgroup published (coherent across the chip's L2
+// slices without invalidating them): each is issued after the counter that
+// announced the data was seen.
+__device__ __forceinline__ uint32_t blk_ld(const uint32_t *p) {
+  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ uint64_t blk_ld64(const uint64_t *p) {
+  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Wait until *ctr >= target; false when the wait gave up (the abort flag is
+// then raised) or the flag was already raised.
+__device__ __forceinline__ bool blk_wait(const uint32_t *ctr, uint32_t target, uint32_t *abort_flag) {
+  uint32_t spins = 0;
+  while (blk_ld(ctr) < target) {
+    if (blk_ld(abort_flag)) return false;
+    if (++spins > kBlkSpinLimit) {
+      atomicOr(abort_flag, 1u);
+      return false;
+    }
+    __builtin_amdgcn_s_sleep(1);
+  }
+  return !blk_ld(abort_flag);
+}
+
+__device__ __forceinline__ void fence_release() { __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent"); }
+
+// Smallest stabilizer row with x = 1 in word w (value v) of a column, or kNone.
+__device__ __forceinline__ uint32_t blk_candidate(uint64_t v, uint32_t w, uint32_t n, uint32_t W) {
+  if (w >= W || w < (n >> 6)) return kNone;
+  if (w == (n >> 6)) v &= ~0ull << (n & 63);
+  return v ? w * 64 + uint32_t(__builtin_ctzll(v)) : kNone;
+}
+
+struct BlkShared {
+  uint64_t K[kPersistMaxWp];                     // rows p_t and p_t - n of the block
+  unsigned long long E0[kPersistMaxWp], E1[kPersistMaxWp], ZX[kPersistMaxWp];
+  uint32_t own[kPersistMaxChunk];                // owner of each measured column: g << 8 | wave << 4 | slot
+  uint32_t P[kBlkK], RU[kBlkK], gam[kBlkK], ycnt[kBlkK];
+  uint32_t cp[2][kBlkWaves], crb[2][kBlkWaves];  // planner: each wave's candidate pivot and its bits
+  uint32_t abort;
+};
+
+// ---------------------------------------------------------------- planner --
+// Thread w holds row word w of the block's columns and of U in one array,
+// split in 32-bit halves (lo: rows 64 w .. 64 w + 31): element i is column
+// a_i while measurement i is to come and U column i once it is done (the
+// column becomes its own U column: M = the rows with x = 1 on it, less p and
+// p - n, plus row p - n).  Measurement t with pivot p:
+//   rows in M absorb row p: element i ^= M for every i whose bit p is set
+//   (U columns: the pivots row p had absorbed; columns: x[p] there);
+//   row p - n takes row p's bits, row p is cleared.
+// One workgroup barrier per measurement: each wave offers its smallest
+// candidate row together with that row's bits of every element, and every
+// thread takes the smallest offer.  The 32 steps are instantiated one by one
+// (a template per step) so that every element index is a constant.
+// Rows p - n are fixed once per block: no pivot search reads destabilizer
+// rows, and no other row's update reads them, so during the block their bits
+// are left as the updates make them while lane t of wave 0 tracks replaced
+// row p_t - n's bits over the elements (rq) by the rule every row follows:
+// at step t' its bit of element i flips when its bit of element t' is set
+// and row p_t' has bit i set.
+struct PlanCtx {
+  uint32_t kbmax, kb, m0b, b;
+  uint32_t rq, qrow;   // wave 0, lane t: replaced row p_t - n and its bits
+  bool aborted;
+};
+
+template <uint32_t TT>
+__device__ __forceinline__ bool plan_step(uint32_t (&lo)[kBlkK], uint32_t (&hi)[kBlkK], PlanCtx &pc,
+                                          const TabDev &t, const BlkDev &s, const BlkArgs &a, BlkShared &sh) {
+  if (TT >= pc.kbmax) return false;
+  const uint32_t tid = threadIdx.x, lane = tid & 63;
+  const uint32_t wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+  const uint32_t n = t.n, W = t.W, w = tid;
+  if (pc.m0b + TT == a.abort_at) {   // injected: stop as after a timed-out wait
+    if (tid == 0) atomicOr(t.abort_flag, 1u);
+    pc.aborted = true;
+    return false;
+  }
+  constexpr uint32_t slot = TT & 1u;
+  const uint32_t cl = lo[TT], ch = hi[TT];
+  {
+    const uint32_t cand = blk_candidate((uint64_t(ch) << 32) | cl, w, n, W);
+    const uint64_t bal = __ballot(cand != kNone);
+    uint32_t pv = kNone, rbv = 0;
+    if (bal) {
+      const uint32_t l = uint32_t(__builtin_ctzll(bal));
+      pv = uint32_t(__builtin_amdgcn_readlane(int(cand), int(l)));
+      const uint32_t sft = pv & 31;
+      uint32_t v = 0;
+      if (pv & 32) {
+#pragma unroll
+        for (uint32_t i = 0; i < kBlkK; ++i) v |= ((hi[i] >> sft) & 1u) << i;
+      } else {
+#pragma unroll
+        for (uint32_t i = 0; i < kBlkK; ++i) v |= ((lo[i] >> sft) & 1u) << i;
+      }
+      rbv = uint32_t(__builtin_amdgcn_readlane(int(v), int(l)));
+    }
+    if (lane == 0) {
+      sh.cp[slot][wave] = pv;
+      sh.crb[slot][wave] = rbv;
+    }
+  }
+  lds_barrier();
+  uint32_t p = kNone, rb = 0;
+#pragma unroll
+  for (uint32_t v = 0; v < kBlkWaves; ++v) {
+    const uint32_t pv = sh.cp[slot][v], rv = sh.crb[slot][v];
+    rb = pv < p ? rv : rb;
+    p = pv < p ? pv : p;
+  }
+  if (p == kNone) {   // deterministic: the block ends before it
+    pc.kb = TT;
+    return false;
+  }
+  const uint32_t wp = p >> 6, pn = p - n;
+  if (tid == 0) {
+    s.piv[size_t(pc.b) * kBlkK + TT] = p;
+    s.rowu[size_t(pc.b) * kBlkK + TT] = rb & ((1u << TT) - 1u);
+  }
+  // rows of M absorb row p; with row p in the mask, its own bit (set exactly
+  // where rb is) clears in the same XOR.  Element TT becomes U column TT: M
+  // (plus row p - n, set at the block's end).
+  const uint32_t bpl = w == wp && !(p & 32) ? 1u << (p & 31) : 0u;
+  const uint32_t bph = w == wp && (p & 32) ? 1u << (p & 31) : 0u;
+#pragma unroll
+  for (uint32_t i = 0; i < kBlkK; ++i) {
+    if (i == TT) {
+      lo[i] ^= bpl;
+      hi[i] ^= bph;
+    } else {
+      const uint32_t msk = 0u - ((rb >> i) & 1u);
+      lo[i] ^= cl & msk;
+      hi[i] ^= ch & msk;
+    }
+  }
+  if (wave == 0) {
+    const uint32_t x = rb & ~(1u << TT);
+    if (lane < TT) pc.rq ^= ((pc.rq >> TT) & 1u) ? x : 0u;
+    if (lane == TT) {
+      pc.rq = rb | (1u << TT);
+      pc.qrow = pn;
+    }
+  }
+  // each step starts from the elements as registers (keeps the compiler from
+  // carrying XOR expressions of several steps)
+#pragma unroll
+  for (uint32_t i = 0; i < kBlkK; ++i) asm volatile("" : "+v"(lo[i]), "+v"(hi[i]));
+  return true;
+}
+
+template <uint32_t... TT>
+__device__ __forceinline__ void plan_block(uint32_t (&lo)[kBlkK], uint32_t (&hi)[kBlkK], PlanCtx &pc,
+                                           const TabDev &t, const BlkDev &s, const BlkArgs &a, BlkShared &sh,
+                                           std::integer_sequence<uint32_t, TT...>) {
+  bool go = true;
+  ((go = go && plan_step<TT>(lo, hi, pc, t, s, a, sh)), ...);
+}
+
+__device__ __forceinline__ void blk_planner(const TabDev &t, const BlkDev &s, const BlkArgs &a, BlkShared &sh) {
+  const uint32_t tid = threadIdx.x, lane = tid & 63;
+  const uint32_t wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+  const uint32_t W = t.W, Wp = t.Wp, k = a.k, w = tid;
+  PlanCtx pc;
+  pc.aborted = false;
+  uint32_t lo[kBlkK], hi[kBlkK];
+  for (uint32_t b = 0;; ++b) {
+    const uint32_t m0b = b * kBlkK;
+    if (m0b >= k) break;
+    const uint32_t kbmax = k - m0b < kBlkK ? k - m0b : kBlkK;
+    if (tid == 0) sh.abort = blk_wait(&s.sync[0], m0b + kbmax, t.abort_flag) ? 0u : 1u;
+    __syncthreads();
+    if (sh.abort) return;
+#pragma unroll
+    for (uint32_t i = 0; i < kBlkK; ++i) {
+      const uint64_t v = (i < kbmax && w < W) ? blk_ld64(s.cols + size_t(i) * Wp + w) : 0ull;
+      lo[i] = uint32_t(v);
+      hi[i] = uint32_t(v >> 32);
+    }
+    pc.kbmax = kbmax;
+    pc.kb = kbmax;
+    pc.m0b = m0b;
+    pc.b = b;
+    pc.rq = 0;
+    pc.qrow = 0;
+    plan_block(lo, hi, pc, t, s, a, sh, std::make_integer_sequence<uint32_t, kBlkK>{});
+    if (pc.aborted) return;
+    const uint32_t kb = pc.kb;
+    if (w < W) {
+#pragma unroll
+      for (uint32_t i = 0; i < kBlkK; ++i)
+        if (i < kb) s.U[(size_t(b) * kBlkK + i) * Wp + w] = (uint64_t(hi[i]) << 32) | lo[i];
+    }
+    fence_release();
+    __syncthreads();
+    // the replaced rows' bits, tracked by wave 0, written over the stored U
+    if (wave == 0 && lane < kb) {
+      unsigned long long *col = reinterpret_cast<unsigned long long *>(s.U + size_t(b) * kBlkK * Wp + (pc.qrow >> 6));
+      const unsigned long long m = bbit(pc.qrow);
+      for (uint32_t i = 0; i < kb; ++i) {
+        if ((pc.rq >> i) & 1u)
+          atomicOr(col + size_t(i) * Wp, m);
+        else
+          atomicAnd(col + size_t(i) * Wp, ~m);
+      }
+    }
+    fence_release();
+    __syncthreads();
+    if (tid == 0) {
+      s.nb[b] = kb;
+      if (kb < kbmax) s.sync[2] = m0b + kb;
+      fence_release();
+      __hip_atomic_store(&s.sync[1], b + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+    if (kb < kbmax) return;
+  }
+  if (tid == 0) s.sync[2] = k;
+}
+
+// ---------------------------------------------------------------- sweeper --
+template <int L>
+__device__ __forceinline__ void blk_sweeper(const TabDev &t, const BlkDev &s, const BlkArgs &a, BlkShared &sh, uint64_t *sU) {
+  constexpr int CW = L;
+  constexpr uint32_t US = 64 * L;   // row stride of U in LDS (words)
+  const uint32_t tid = threadIdx.x, lane = tid & 63;
+  const uint32_t wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+  const uint32_t g = blockIdx.x, G = a.G, n = t.n, W = t.W, Wp = t.Wp, k = a.k;
+  const uint32_t C = g < n ? (n - g + G - 1) / G : 0;
+  const uint32_t ns = C > wave ? (C - wave + kBlkWaves - 1) / kBlkWaves : 0;
+  const uint32_t me = (g << 8) | (wave << 4);
+
+  uint64_t xr[CW][L], zr[CW][L];
+#pragma unroll
+  for (int c = 0; c < CW; ++c) {
+    const uint32_t col = g + (wave + uint32_t(c) * kBlkWaves) * G;
+#pragma unroll
+    for (int i = 0; i < L; ++i) {
+      const uint32_t w = uint32_t(i) * 64 + lane;
+      const bool have = uint32_t(c) < ns && w < W;
+      const size_t at = have ? size_t(col) * Wp + w : 0;
+      const uint64_t xv = t.X[at], zv = t.Z[at];
+      xr[c][i] = have ? xv : 0ull;
+      zr[c][i] = have ? zv : 0ull;
+    }
+  }
+  unsigned long long sup = 0;
+  uint32_t done = 0;
+  // this wave's columns measured in [m0, m0 + cnt), as they stand now, for
+  // the planner
+  auto publish_cols = [&](uint32_t m0, uint32_t cnt) {
+    for (uint32_t tt = 0; tt < cnt; ++tt) {
+      const uint32_t o = sh.own[m0 + tt];
+      if ((o & ~15u) != me) continue;   // wave-uniform
+      const uint32_t cs = o & 15u;
+#pragma unroll
+      for (int c = 0; c < CW; ++c) {
+        if (uint32_t(c) != cs) continue;
+#pragma unroll
+        for (int i = 0; i < L; ++i) {
+          const uint32_t w = uint32_t(i) * 64 + lane;
+          if (w < W) s.cols[size_t(tt) * Wp + w] = xr[c][i];
+        }
+      }
+      fence_release();
+      if (lane == 0) atomicAdd(&s.sync[0], 1u);
+    }
+  };
+  for (uint32_t b = 0;; ++b) {
+    const uint32_t m0b = b * kBlkK;
+    if (m0b >= k) break;
+    const uint32_t kbmax = k - m0b < kBlkK ? k - m0b : kBlkK;
+    // ---- the first block's columns (later blocks' come out of the previous
+    // block's sweep, see below)
+    if (b == 0) publish_cols(m0b, kbmax);
+    // ---- the plan of block b
+    if (tid == 0) sh.abort = blk_wait(&s.sync[1], b + 1, t.abort_flag) ? 0u : 1u;
+    __syncthreads();
+    if (sh.abort) return;
+    // every load of the block's plan is issued before the first is used
+    // (entries past the block's count are stale and never read)
+    const uint32_t kb = blk_ld(s.nb + b);
+    {
+      uint32_t pv = 0, rv = 0;
+      if (tid < kBlkK) {
+        pv = blk_ld(s.piv + size_t(b) * kBlkK + tid);
+        rv = blk_ld(s.rowu + size_t(b) * kBlkK + tid);
+      }
+      // U in passes of kPass loads per thread, all in flight together
+      constexpr uint32_t kStage = (kBlkK * US + kBlkThreads - 1) / kBlkThreads, kPass = 5;
+#pragma unroll
+      for (uint32_t j0 = 0; j0 < kStage; j0 += kPass) {
+        uint64_t tmp[kPass];
+#pragma unroll
+        for (uint32_t j = 0; j < kPass; ++j) {
+          const uint32_t idx = tid + (j0 + j) * kBlkThreads, i = idx / US, w = idx % US;
+          tmp[j] = (j0 + j < kStage && i < kBlkK && w < W) ? blk_ld64(s.U + (size_t(b) * kBlkK + i) * Wp + w) : 0ull;
+        }
+#pragma unroll
+        for (uint32_t j = 0; j < kPass; ++j) {
+          const uint32_t idx = tid + (j0 + j) * kBlkThreads;
+          if (j0 + j < kStage && idx < kBlkK * US) sU[idx] = tmp[j];
+        }
+        __builtin_amdgcn_sched_barrier(0);
+      }
+      if (tid < kBlkK) {
+        sh.P[tid] = pv;
+        sh.RU[tid] = rv;
+        sh.gam[tid] = 0;
+        sh.ycnt[tid] = 0;
+      }
+    }
+    if (kb == 0) break;
+    for (uint32_t w = tid; w < W; w += kBlkThreads) {
+      sh.K[w] = 0;
+      sh.E0[w] = 0;
+      sh.E1[w] = 0;
+      sh.ZX[w] = 0;
+    }
+    __syncthreads();
+    for (uint32_t i = tid; i < kb; i += kBlkThreads) {
+      const uint32_t p = sh.P[i], pn = p - n;
+      atomicOr(reinterpret_cast<unsigned long long *>(&sh.K[p >> 6]), (unsigned long long)bbit(p));
+      atomicOr(reinterpret_cast<unsigned long long *>(&sh.K[pn >> 6]), (unsigned long long)bbit(pn));
+    }
+    __syncthreads();
+    // ---- x and z of this wave's columns at the pivot rows (bit i = pivot i):
+    // lane i fetches row p_i's word from the lane holding it (a cross-lane
+    // permute per slot with stabilizer rows), and ballots collect the bits
+    uint32_t bx[CW], bz[CW];
+    {
+      const uint32_t pi = sh.P[lane < kb ? lane : 0u];
+      const uint32_t wpi = pi >> 6, src = (wpi & 63u) << 2, ipi = wpi >> 6, sft = pi & 63u;
+      uint32_t xb[CW], zb[CW];
+#pragma unroll
+      for (int c = 0; c < CW; ++c) {
+        xb[c] = 0;
+        zb[c] = 0;
+      }
+#pragma unroll
+      for (int ii = 0; ii < L; ++ii) {
+        if (uint32_t(ii) < ((n >> 6) >> 6)) continue;   // destabilizer words only
+#pragma unroll
+        for (int c = 0; c < CW; ++c) {
+          const uint32_t xl = uint32_t(__builtin_amdgcn_ds_bpermute(int(src), int(uint32_t(xr[c][ii]))));
+          const uint32_t xh = uint32_t(__builtin_amdgcn_ds_bpermute(int(src), int(uint32_t(xr[c][ii] >> 32))));
+          const uint32_t zl = uint32_t(__builtin_amdgcn_ds_bpermute(int(src), int(uint32_t(zr[c][ii]))));
+          const uint32_t zh = uint32_t(__builtin_amdgcn_ds_bpermute(int(src), int(uint32_t(zr[c][ii] >> 32))));
+          const uint32_t xw = sft & 32 ? xh : xl, zw = sft & 32 ? zh : zl;
+          if (ipi == uint32_t(ii)) {
+            xb[c] = (xw >> (sft & 31)) & 1u;
+            zb[c] = (zw >> (sft & 31)) & 1u;
+          }
+          // one column's permutes at a time (bounds the registers they hold)
+          __builtin_amdgcn_sched_barrier(0);
+        }
+      }
+      const bool mine = lane < kb;
+#pragma unroll
+      for (int c = 0; c < CW; ++c) {
+        bx[c] = uint32_t(__ballot(mine && xb[c]));
+        bz[c] = uint32_t(__ballot(mine && zb[c]));
+      }
+    }
+    // ---- Y counts of the kept rows before the update (added to the
+    // workgroup's mod-4 sums in LDS: the XOR's old value gives the carry);
+    // drop rows p_t, p_t - n
+    uint64_t zx[L];
+#pragma unroll
+    for (int i = 0; i < L; ++i) {
+      const uint32_t w = uint32_t(i) * 64 + lane;
+      const uint64_t kw = w < W ? sh.K[w] : 0ull;
+      uint64_t e0 = 0, e1 = 0;
+      zx[i] = 0;
+#pragma unroll
+      for (int c = 0; c < CW; ++c) {
+        const uint64_t y = xr[c][i] & zr[c][i] & ~kw;
+        e1 ^= e0 & y;
+        e0 ^= y;
+        xr[c][i] &= ~kw;
+        zr[c][i] &= ~kw;
+      }
+      if (w < W) {
+        const unsigned long long old = atomicXor(&sh.E0[w], (unsigned long long)e0);
+        atomicXor(&sh.E1[w], (unsigned long long)(e1 ^ (old & e0)));
+      }
+    }
+    // ---- this wave's columns measured in the next block: x first, and
+    // handed to the planner at once, so that it plans the next block while
+    // this sweep goes on
+    uint32_t early = 0;
+    {
+      const uint32_t m0n = m0b + kBlkK;
+      const uint32_t kbn = (kb == kbmax && m0n < k) ? (k - m0n < kBlkK ? k - m0n : kBlkK) : 0u;
+      for (uint32_t tt = 0; tt < kbn; ++tt) {
+        const uint32_t o = sh.own[m0n + tt];
+        if ((o & ~15u) == me) early |= 1u << (o & 15u);
+      }
+      if (early) {   // wave-uniform
+        for (uint32_t i = 0; i < kb; ++i) {
+          uint64_t u[L];
+#pragma unroll
+          for (int ii = 0; ii < L; ++ii) u[ii] = sU[i * US + uint32_t(ii) * 64 + lane];
+#pragma unroll
+          for (int c = 0; c < CW; ++c) {
+            if (((early >> c) & 1u) && ((bx[c] >> i) & 1u)) {
+#pragma unroll
+              for (int ii = 0; ii < L; ++ii) xr[c][ii] ^= u[ii];
+            }
+          }
+        }
+        publish_cols(m0n, kbn);
+      }
+    }
+    // ---- x ^= U (x at the pivots), with the z.x parity of the kept rows
+    for (uint32_t i = 0; i < kb; ++i) {
+      uint64_t u[L];
+#pragma unroll
+      for (int ii = 0; ii < L; ++ii) u[ii] = sU[i * US + uint32_t(ii) * 64 + lane];
+#pragma unroll
+      for (int c = 0; c < CW; ++c) {
+        if ((bx[c] >> i) & 1u) {
+          const bool upd = !((early >> c) & 1u);
+#pragma unroll
+          for (int ii = 0; ii < L; ++ii) {
+            if (upd) xr[c][ii] ^= u[ii];
+            zx[ii] ^= zr[c][ii] & u[ii];
+          }
+        }
+      }
+    }
+    // ---- z ^= U (z at the pivots)
+    for (uint32_t i = 0; i < kb; ++i) {
+      uint64_t u[L];
+#pragma unroll
+      for (int ii = 0; ii < L; ++ii) u[ii] = sU[i * US + uint32_t(ii) * 64 + lane];
+#pragma unroll
+      for (int c = 0; c < CW; ++c) {
+        if ((bz[c] >> i) & 1u) {
+#pragma unroll
+          for (int ii = 0; ii < L; ++ii) zr[c][ii] ^= u[ii];
+        }
+      }
+    }
+    // ---- pivot rows of this wave's measured columns: z = 1 on the column
+    for (uint32_t i = 0; i < kb; ++i) {
+      const uint32_t o = sh.own[m0b + i];
+      if ((o & ~15u) != me) continue;
+      const uint32_t cs = o & 15u, p = sh.P[i], wp = p >> 6, ip = wp >> 6;
+      const uint64_t bit = lane == (wp & 63) ? bbit(p) : 0ull;
+#pragma unroll
+      for (int c = 0; c < CW; ++c) {
+        if (uint32_t(c) != cs) continue;
+#pragma unroll
+        for (int ii = 0; ii < L; ++ii)
+          if (uint32_t(ii) == ip) zr[c][ii] |= bit;
+      }
+    }
+    // ---- minus the Y counts after the update: count them (mod 4) and add
+    // three times the count
+#pragma unroll
+    for (int i = 0; i < L; ++i) {
+      const uint32_t w = uint32_t(i) * 64 + lane;
+      uint64_t e0 = 0, e1 = 0;
+#pragma unroll
+      for (int c = 0; c < CW; ++c) {
+        const uint64_t y = xr[c][i] & zr[c][i];
+        e1 ^= e0 & y;
+        e0 ^= y;
+      }
+      // -(e0 + 2 e1) = e0 + 2 (e1 ^ e0)  (mod 4)
+      e1 ^= e0;
+      if (w < W) {
+        const unsigned long long old = atomicXor(&sh.E0[w], (unsigned long long)e0);
+        atomicXor(&sh.E1[w], (unsigned long long)(e1 ^ (old & e0)));
+        atomicXor(&sh.ZX[w], (unsigned long long)zx[i]);
+      }
+    }
+    // ---- per pivot: Y count (mod 4), Gram row, and the support of the pivot
+    // row at its step (for the device counters)
+    // (lane i: pivot i)
+    {
+      const uint32_t la = lane & 31u;
+      const uint32_t ru = lane < kb ? sh.RU[la] : 0u;
+      uint32_t ycnt = 0, gacc = 0, sups = 0;
+#pragma unroll
+      for (int c = 0; c < CW; ++c) {
+        const uint32_t bxc = bx[c], bzc = bz[c];
+        ycnt += ((bxc & bzc) >> la) & 1u;
+        gacc ^= ((bzc >> la) & 1u) ? bxc : 0u;
+        // the pivot row at its step: row p_i plus the pivots it had absorbed
+        const uint32_t xs = ((bxc >> la) ^ uint32_t(__popc(bxc & ru))) & 1u;
+        const uint32_t zs = ((bzc >> la) ^ uint32_t(__popc(bzc & ru))) & 1u;
+        sups += 2 * (xs | zs) + xs + zs;
+      }
+      if (lane < kb) {
+        if (ycnt) atomicAdd(&sh.ycnt[la], ycnt);
+        if (gacc) atomicXor(&sh.gam[la], gacc);
+        sup += sups;
+      }
+    }
+    // ---- store this workgroup's partials
+    __syncthreads();
+    uint64_t *part = s.part + (size_t(b) * G + g) * 3 * Wp;
+    for (uint32_t w = tid; w < W; w += kBlkThreads) {
+      part[w] = sh.E0[w];
+      part[Wp + w] = sh.E1[w];
+      part[2 * Wp + w] = sh.ZX[w];
+    }
+    uint32_t *pp = s.ppart + (size_t(b) * G + g) * (2 + kBlkK);
+    if (wave == 0) {
+      // pivot Y counts mod 4 as two bit planes
+      const uint32_t yc = lane < kb ? sh.ycnt[lane] & 3u : 0u;
+      const uint32_t y0 = uint32_t(__ballot(yc & 1u)), y1 = uint32_t(__ballot(yc & 2u));
+      if (lane == 0) {
+        pp[0] = y0;
+        pp[1] = y1;
+      }
+      if (lane < kb) pp[2 + lane] = sh.gam[lane];
+    }
+    done += kb;
+    if (kb < kbmax) break;
+  }
+  // ---- the tableau back to HBM
+#pragma unroll
+  for (int c = 0; c < CW; ++c) {
+    if (uint32_t(c) >= ns) continue;
+    const uint32_t col = g + (wave + uint32_t(c) * kBlkWaves) * G;
+#pragma unroll
+    for (int i = 0; i < L; ++i) {
+      const uint32_t w = uint32_t(i) * 64 + lane;
+      if (w < W) {
+        t.X[size_t(col) * Wp + w] = xr[c][i];
+        t.Z[size_t(col) * Wp + w] = zr[c][i];
+      }
+    }
+  }
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) sup += __shfl_xor(sup, off);
+  if (lane == 0 && sup) atomicAdd(reinterpret_cast<unsigned long long *>(t.state + ST_SUPPORT), sup);
+  if (g == 0 && tid == 0 && done) atomicAdd(&t.state[ST_RANDOM_CNT], done);
+}
+
+template <int L>
+__global__ void __launch_bounds__(kBlkThreads) k_blk(TabDev t, BlkDev s, BlkArgs a) {
+  extern __shared__ uint64_t s_dynU[];
+  __shared__ BlkShared sh;
+  // an earlier chunk of this pass gave up: leave everything as it is
+  if (__builtin_amdgcn_readfirstlane(blk_ld(t.abort_flag))) return;
+  for (uint32_t m = threadIdx.x; m < a.k; m += kBlkThreads) {
+    const uint32_t j = a.qubits[m], q = j / a.G;
+    sh.own[m] = ((j % a.G) << 8) | ((q & 7u) << 4) | (q >> 3);
+  }
+  __syncthreads();
+  if (blockIdx.x == a.G)
+    blk_planner(t, s, a, sh);
+  else
+    blk_sweeper<L>(t, s, a, sh, s_dynU);
+}
+
+// Clear the pass counters and block counts of a chunk (kernel stores only:
+// capture-safe).
+__global__ void k_blk_begin(BlkDev s) {
+  const uint32_t i = threadIdx.x;
+  if (i < 4) s.sync[i] = 0;
+  for (uint32_t b = i; b < s.NB; b += blockDim.x) s.nb[b] = 0;
+}
+
+// ---------------------------------------------------------------- reduce ---
+// Per block and row word: the sign flips H = (Y_old - Y_new + sum of the
+// absorbed pivots' Y counts) / 2 + z.x parity + the Gram pairs of the absorbed
+// pivots (mod 2), summed over the sweeper workgroups; the low bit of the
+// phase must vanish on every row but the pivot rows (counted as anomalies).
+__global__ void __launch_bounds__(256) k_blk_reduce(TabDev t, BlkDev s, uint32_t G) {
+  __shared__ uint32_t s_yp0, s_yp1, s_gam[kBlkK], s_P[kBlkK];
+  const uint32_t b = blockIdx.x, tid = threadIdx.x;
+  if (b >= s.NB) return;
+  const uint32_t kb = s.nb[b];
+  if (kb == 0 || blk_ld(t.abort_flag)) return;
+  const uint32_t n = t.n, W = t.W, Wp = t.Wp;
+  if (tid < kBlkK) s_gam[tid] = 0;
+  if (tid == 0) {
+    s_yp0 = 0;
+    s_yp1 = 0;
+  }
+  if (tid < kb) s_P[tid] = s.piv[size_t(b) * kBlkK + tid];
+  __syncthreads();
+  for (uint32_t q = tid; q < G; q += blockDim.x) {
+    const uint32_t *pp = s.ppart + (size_t(b) * G + q) * (2 + kBlkK);
+    const uint32_t v0 = pp[0], v1 = pp[1];
+    const uint32_t old = atomicXor(&s_yp0, v0);
+    atomicXor(&s_yp1, v1 ^ (old & v0));
+    for (uint32_t i = 0; i < kb; ++i) {
+      const uint32_t gv = pp[2 + i];
+      if (gv) atomicXor(&s_gam[i], gv);
+    }
+  }
+  __syncthreads();
+  const uint32_t w = blockIdx.y * blockDim.x + tid;
+  if (w >= W) return;
+  uint64_t c0 = 0, c1 = 0, zx = 0;
+  for (uint32_t q = 0; q < G; ++q) {
+    const uint64_t *part = s.part + (size_t(b) * G + q) * 3 * Wp;
+    const uint64_t v0 = part[w], v1 = part[Wp + w], v2 = part[2 * Wp + w];
+    c1 ^= v1 ^ (c0 & v0);
+    c0 ^= v0;
+    zx ^= v2;
+  }
+  uint64_t repl = 0, cons = 0;
+  for (uint32_t i = 0; i < kb; ++i) {
+    const uint32_t p = s_P[i], pn = p - n;
+    if ((p >> 6) == w) cons |= bbit(p);
+    if ((pn >> 6) == w) repl |= bbit(pn);
+  }
+  const uint64_t *U = s.U + size_t(b) * kBlkK * Wp + w;
+  uint64_t u[kBlkK];
+#pragma unroll
+  for (uint32_t i = 0; i < kBlkK; ++i) u[i] = i < kb ? U[size_t(i) * Wp] : 0ull;
+  const uint32_t yp0 = s_yp0, yp1 = s_yp1;
+#pragma unroll
+  for (uint32_t i = 0; i < kBlkK; ++i) {
+    if ((yp0 >> i) & 1u) {
+      c1 ^= c0 & u[i];
+      c0 ^= u[i];
+    }
+    if ((yp1 >> i) & 1u) c1 ^= u[i];
+  }
+  c1 ^= zx & ~repl;
+#pragma unroll
+  for (uint32_t ia = 0; ia + 1 < kBlkK; ++ia) {
+    const uint32_t gm = ia + 1 < kb ? s_gam[ia] & ~((2u << ia) - 1u) : 0u;   // pairs (ia, ib > ia)
+    uint64_t acc = 0;
+#pragma unroll
+    for (uint32_t ib = ia + 1; ib < kBlkK; ++ib)
+      if ((gm >> ib) & 1u) acc ^= u[ib];
+    c1 ^= u[ia] & acc;
+  }
+  const uint64_t odd = c0 & ~cons;
+  if (odd) atomicAdd(&t.state[ST_ANOMALY], uint32_t(__popcll(odd)));
+  s.H[size_t(b) * Wp + w] = c1 & ~cons;
+}
+
+// ---------------------------------------------------------------- signs ---
+// One workgroup per shot walks the chunk's blocks in order with the shot's
+// sign column in registers (two row words per thread):
+//   r = [kept] r ^ H ^ sum over pivots t with r[p_t] = 1 of U_t,
+// then the pivot rows take the outcomes (Philox bits).  Measurement i of
+// block b has index base + 32 b + i in the call.
+__global__ void __launch_bounds__(kBlkSignThreads) k_blk_signs(TabDev t, BlkDev s, uint32_t k, uint32_t base,
+                                                               uint64_t seed, uint64_t circuit, uint64_t shot0,
+                                                               uint64_t m0) {
+  __shared__ uint64_t s_r[kPersistMaxWp];
+  __shared__ uint32_t s_P[kBlkK], s_o, s_rp;
+  const uint32_t sh = blockIdx.x, tid = threadIdx.x, lane = tid & 63, n = t.n, W = t.W, Wp = t.Wp, S = t.S;
+  if (blk_ld(t.abort_flag)) return;
+  uint64_t r[2];
+#pragma unroll
+  for (uint32_t j = 0; j < 2; ++j) {
+    const uint32_t w = tid + j * kBlkSignThreads;
+    r[j] = w < W ? t.R[size_t(w) * S + sh] : 0ull;
+  }
+  uint32_t done = 0;
+  for (uint32_t b = 0; b < s.NB && b * kBlkK < k; ++b) {
+    const uint32_t kb = s.nb[b];
+    if (kb == 0) break;
+#pragma unroll
+    for (uint32_t j = 0; j < 2; ++j) {
+      const uint32_t w = tid + j * kBlkSignThreads;
+      if (w < W) s_r[w] = r[j];
+    }
+    if (tid < kb) s_P[tid] = s.piv[size_t(b) * kBlkK + tid];
+    __syncthreads();
+    if (tid < 64) {
+      // signs of the pivot rows at the block's start; outcome bits
+      const uint32_t p = tid < kb ? s_P[tid] : 0u;
+      const uint64_t rp = __ballot(tid < kb && ((s_r[p >> 6] >> (p & 63)) & 1u));
+      const uint32_t slot = base + b * kBlkK + tid;
+      uint32_t o = 0;
+      if (tid < kb) {
+        o = outcome_bit(seed, circuit, shot0 + sh, m0 + slot);
+        t.out[size_t(slot) * S + sh] = uint8_t(o);
+        if (sh == 0) t.kind[slot] = 1;
+      }
+      const uint64_t ob = __ballot(o != 0);
+      if (lane == 0) {
+        s_rp = uint32_t(rp);
+        s_o = uint32_t(ob);
+      }
+    }
+    __syncthreads();
+    const uint32_t rp = s_rp, ob = s_o;
+#pragma unroll
+    for (uint32_t j = 0; j < 2; ++j) {
+      const uint32_t w = tid + j * kBlkSignThreads;
+      if (w >= W) continue;
+      uint64_t kill = 0, set = 0;
+      for (uint32_t i = 0; i < kb; ++i) {
+        const uint32_t p = s_P[i], pn = p - n;
+        if ((p >> 6) == w) {
+          kill |= bbit(p);
+          if ((ob >> i) & 1u) set |= bbit(p);
+        }
+        if ((pn >> 6) == w) kill |= bbit(pn);
+      }
+      uint64_t v = (r[j] & ~kill) ^ s.H[size_t(b) * Wp + w];
+      const uint64_t *U = s.U + size_t(b) * kBlkK * Wp + w;
+      for (uint32_t i = 0; i < kb; ++i)
+        if ((rp >> i) & 1u) v ^= U[size_t(i) * Wp];
+      r[j] = v | set;
+    }
+    done += kb;
+    __syncthreads();
+  }
+  (void)done;
+#pragma unroll
+  for (uint32_t j = 0; j < 2; ++j) {
+    const uint32_t w = tid + j * kBlkSignThreads;
+    if (w < W) t.R[size_t(w) * S + sh] = r[j];
+  }
+}
+
+}  // namespace
+
+// Launch shape of the blocked pass for n qubits: G sweeper workgroups (plus
+// one planner) with L row words per lane and L columns per wave.
+bool blk_shape(uint32_t n, uint32_t num_cus, uint32_t *G, uint32_t *L) {
+  if (!persist_layout(n)) return false;
+  const uint32_t W = (2 * n + 63) / 64;
+  const uint32_t l = (W + 63) / 64;
+  const uint32_t per = kBlkWaves * l;
+  const uint32_t g = (n + per - 1) / per;
+  if (g + 1 > num_cus || g + 1 > kPersistMaxGroups) return false;
+  *G = g;
+  *L = l;
+  return true;
+}
+
+size_t blk_lds_bytes(uint32_t L) { return size_t(kBlkK) * 64 * L * 8; }
+
+hipError_t launch_blk_chunk(const TabDev &t, const BlkDev &s, const uint32_t *dev_qubits, uint32_t cnt,
+                            uint32_t G, uint32_t L, uint32_t abort_at, hipStream_t st) {
+  if (cnt == 0 || cnt > kPersistMaxChunk || (cnt + kBlkK - 1) / kBlkK > s.NB || L < 1 || L > 5)
+    return hipErrorInvalidValue;
+  const void *fns[5] = {reinterpret_cast<const void *>(k_blk<1>), reinterpret_cast<const void *>(k_blk<2>),
+                        reinterpret_cast<const void *>(k_blk<3>), reinterpret_cast<const void *>(k_blk<4>),
+                        reinterpret_cast<const void *>(k_blk<5>)};
+  static bool attr_set[5] = {false, false, false, false, false};
+  if (!attr_set[L - 1]) {
+    hipError_t e = hipFuncSetAttribute(fns[L - 1], hipFuncAttributeMaxDynamicSharedMemorySize,
+                                       int(blk_lds_bytes(L)));
+    if (e != hipSuccess) return e;
+    attr_set[L - 1] = true;
+  }
+  k_blk_begin<<<1, 256, 0, st>>>(s);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  BlkArgs a{dev_qubits, cnt, G, abort_at};
+  TabDev targ = t;
+  BlkDev sarg = s;
+  void *args[] = {&targ, &sarg, &a};
+  return hipLaunchCooperativeKernel(fns[L - 1], dim3(G + 1), dim3(kBlkThreads), args, blk_lds_bytes(L), st);
+}
+
+hipError_t launch_blk_finalize(const TabDev &t, const BlkDev &s, uint32_t cnt, uint32_t base, uint64_t seed,
+                               uint64_t circuit, uint64_t shot0, uint64_t m0, uint32_t G, hipStream_t st) {
+  const uint32_t nb = (cnt + kBlkK - 1) / kBlkK;
+  k_blk_reduce<<<dim3(nb, (t.W + 255) / 256), 256, 0, st>>>(t, s, G);
+  k_blk_signs<<<t.S, kBlkSignThreads, 0, st>>>(t, s, cnt, base, seed, circuit, shot0, m0);
+  return hipGetLastError();
+}
+
+}  // namespace cliff

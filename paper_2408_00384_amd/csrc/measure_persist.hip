@@ -56,7 +56,13 @@ struct PersistArgs {
   uint32_t k, G;
   uint32_t abort_at;        // measurement of this chunk at which every workgroup stops as if
                             // a wait had timed out (kNone: never; a test aid for the error path)
+  const uint32_t *skip;     // device: leading measurements of the chunk already done by the
+                            // blocked pass (null: none)
 };
+
+// The chunk's measurements left after the blocked pass (its count of done
+// measurements in device memory, written by the kernel before this one).
+__device__ __forceinline__ uint32_t chunk_skip(const uint32_t *skip) { return skip ? *skip : 0u; }
 
 __device__ __forceinline__ uint64_t pbit(uint32_t b) { return 1ull << (b & 63); }
 
@@ -158,6 +164,13 @@ __global__ void __launch_bounds__(kThreads) k_meas_xz(TabDev t, PersistArgs a) {
   // waits only for the waves that have not ended, and every later wait is
   // bounded and sees the raised flag.
   if (__builtin_amdgcn_readfirstlane(ld_relaxed(t.abort_flag))) return;
+  {
+    const uint32_t sk = __builtin_amdgcn_readfirstlane(chunk_skip(a.skip));
+    a.qubits += sk;
+    a.k -= sk;
+    if (a.abort_at != kNone) a.abort_at = a.abort_at >= sk ? a.abort_at - sk : kNone;
+    if (a.k == 0) return;
+  }
   for (uint32_t i = tid; i < a.k; i += blockDim.x) s_q[i] = a.qubits[i];
   if (tid == 0) {
     s_abort = 0;
@@ -491,7 +504,8 @@ __global__ void __launch_bounds__(kThreads) k_meas_xz(TabDev t, PersistArgs a) {
 // --------------------------------------------------------------- reduce ---
 // c1[m][w] from the partials of all workgroups (mod-4 sum), with the check
 // that the low counter plane vanishes on every updated row but p-n.
-__global__ void __launch_bounds__(256) k_meas_reduce(TabDev t, uint32_t k, uint32_t G) {
+__global__ void __launch_bounds__(256) k_meas_reduce(TabDev t, uint32_t k, uint32_t G, const uint32_t *skip) {
+  k -= chunk_skip(skip);
   const uint32_t m = blockIdx.x, w = blockIdx.y * blockDim.x + threadIdx.x;
   if (m >= k || w >= t.W) return;
   const uint32_t p = t.pivall[m];
@@ -527,7 +541,13 @@ constexpr uint32_t kSignThreads = 256;
 constexpr uint32_t kSignWords = 2;   // words per thread
 
 __global__ void __launch_bounds__(kSignThreads) k_meas_signs(TabDev t, uint32_t k, uint32_t base, uint64_t seed,
-                                                             uint64_t circuit, uint64_t shot0, uint64_t m0) {
+                                                             uint64_t circuit, uint64_t shot0, uint64_t m0,
+                                                             const uint32_t *skip) {
+  {
+    const uint32_t sk = chunk_skip(skip);
+    k -= sk;
+    base += sk;
+  }
   // pivots, and per deterministic measurement bit 0 = the x/z parity term,
   // bits 1-2 = the Y count mod 4 (small enough to sit beside the x/z kernel)
   __shared__ uint32_t s_piv[kPersistMaxChunk];
@@ -645,8 +665,15 @@ __global__ void __launch_bounds__(kSignThreads) k_meas_signs(TabDev t, uint32_t 
 // memset: capture-safe).  Blocks 0 and 1 publish; every block clears a share
 // of the slots.  The abort flag is left alone: it stays raised until the
 // host has reported it, so later chunks of an aborted pass do nothing.
-__global__ void __launch_bounds__(1024) k_meas_begin(TabDev t, const uint32_t *qubits, uint32_t k) {
+__global__ void __launch_bounds__(1024) k_meas_begin(TabDev t, const uint32_t *qubits, uint32_t k,
+                                                     const uint32_t *skip) {
   __shared__ uint32_t s_p;
+  {
+    const uint32_t sk = chunk_skip(skip);
+    qubits += sk;
+    k -= sk;
+    if (k == 0) return;
+  }
   const uint32_t tid = threadIdx.x;
   const size_t per = 2 * size_t(t.Wp);
   for (size_t i = size_t(blockIdx.x) * blockDim.x + tid + 2 * per; i < size_t(k) * per;
@@ -704,7 +731,7 @@ bool persist_shape(uint32_t n, uint32_t num_cus, uint32_t *G, uint32_t *L, uint3
 hipError_t launch_measure_persist(const TabDev &t, uint32_t kc, const uint32_t *dev_qubits, uint32_t k,
                                   uint64_t seed, uint64_t circuit, uint64_t shot0, uint64_t m0,
                                   int num_cus, const PersistStreams &ps, Profiler *prof, uint32_t *done,
-                                  uint64_t abort_at) {
+                                  uint64_t abort_at, const BlkDev *blk, uint32_t blk_G, uint32_t blk_L) {
   *done = 0;
   uint32_t G, L, CW;
   if (!persist_shape(t.n, uint32_t(num_cus), &G, &L, &CW)) return hipErrorInvalidValue;
@@ -736,6 +763,17 @@ hipError_t launch_measure_persist(const TabDev &t, uint32_t kc, const uint32_t *
     // set b is free once chunk c - 2's finalize is done
     hipError_t e = hipStreamWaitEvent(st, ps.ev[2 + b], 0);
     if (e != hipSuccess) return e;
+    const uint32_t ab = (abort_at >= base && abort_at < uint64_t(base) + cnt) ? uint32_t(abort_at - base) : kNone;
+    // the blocked pass takes the chunk's leading random measurements; the
+    // kernels below do the rest (from the count it leaves in device memory)
+    const uint32_t *skip = nullptr;
+    if (blk) {
+      if (prof) prof->begin(PK_SWEEP, st);
+      e = launch_blk_chunk(tv, blk[b], dev_qubits + base, cnt, blk_G, blk_L, ab, st);
+      if (prof) prof->end(PK_SWEEP, st);
+      if (e != hipSuccess) return e;
+      skip = blk[b].sync + 2;
+    }
     // A plain launch goes to another hardware queue than the cooperative x/z
     // kernel, and each hand-off between the two is a cross-queue dependency
     // (10-20 us).  Launched cooperatively it shares the x/z kernel's queue:
@@ -747,16 +785,16 @@ hipError_t launch_measure_persist(const TabDev &t, uint32_t kc, const uint32_t *
       TabDev barg = tv;
       const uint32_t *qarg = dev_qubits + base;
       uint32_t carg = cnt;
-      void *bargs[] = {&barg, &qarg, &carg};
+      const uint32_t *sarg = skip;
+      void *bargs[] = {&barg, &qarg, &carg, &sarg};
       e = hipLaunchCooperativeKernel(reinterpret_cast<const void *>(k_meas_begin), dim3(64), dim3(1024), bargs, 0, st);
     } else {
-      k_meas_begin<<<64, 1024, 0, st>>>(tv, dev_qubits + base, cnt);
+      k_meas_begin<<<64, 1024, 0, st>>>(tv, dev_qubits + base, cnt, skip);
       e = hipGetLastError();
     }
     if (prof) prof->end(PK_SELECT, st);
     if (e != hipSuccess) return e;
-    const uint32_t ab = (abort_at >= base && abort_at < uint64_t(base) + cnt) ? uint32_t(abort_at - base) : kNone;
-    PersistArgs a{dev_qubits + base, cnt, G, ab};
+    PersistArgs a{dev_qubits + base, cnt, G, ab, skip};
     TabDev targ = tv;
     void *args[] = {&targ, &a};
     if (prof) prof->begin(PK_SWEEP, st);
@@ -769,8 +807,12 @@ hipError_t launch_measure_persist(const TabDev &t, uint32_t kc, const uint32_t *
     e = hipStreamWaitEvent(aux, ps.ev[b], 0);
     if (e != hipSuccess) return e;
     if (prof) prof->begin(PK_FINAL, aux);
-    k_meas_reduce<<<dim3(cnt, (t.W + 255) / 256), 256, 0, aux>>>(tv, cnt, G);
-    k_meas_signs<<<t.S, kSignThreads, 0, aux>>>(tv, cnt, base, seed, circuit, shot0, m0);
+    if (blk) {
+      e = launch_blk_finalize(tv, blk[b], cnt, base, seed, circuit, shot0, m0, blk_G, aux);
+      if (e != hipSuccess) return e;
+    }
+    k_meas_reduce<<<dim3(cnt, (t.W + 255) / 256), 256, 0, aux>>>(tv, cnt, G, skip);
+    k_meas_signs<<<t.S, kSignThreads, 0, aux>>>(tv, cnt, base, seed, circuit, shot0, m0, skip);
     if (prof) prof->end(PK_FINAL, aux);
     e = hipGetLastError();
     if (e != hipSuccess) return e;

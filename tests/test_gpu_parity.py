@@ -26,11 +26,12 @@ def ctx():
     c.close()
 
 
-@pytest.fixture(params=["step", "persistent"])
+@pytest.fixture(params=["step", "persistent", "blocked"])
 def measure_mode(request, ctx):
-    from paper_2408_00384_amd import (MEASURE_AUTO, MEASURE_PERSISTENT, MEASURE_STEP,
+    from paper_2408_00384_amd import (MEASURE_AUTO, MEASURE_BLOCKED, MEASURE_PERSISTENT, MEASURE_STEP,
                                       cliff_ctx_set_measure_mode)
-    cliff_ctx_set_measure_mode(ctx.handle, MEASURE_STEP if request.param == "step" else MEASURE_PERSISTENT)
+    mode = {"step": MEASURE_STEP, "persistent": MEASURE_PERSISTENT, "blocked": MEASURE_BLOCKED}[request.param]
+    cliff_ctx_set_measure_mode(ctx.handle, mode)
     yield request.param
     cliff_ctx_set_measure_mode(ctx.handle, MEASURE_AUTO)
 
@@ -411,27 +412,30 @@ def test_large_n_partial_measure_vs_oracle(ctx, measure_mode, n):
 @pytest.mark.parametrize("n,shots", [(1, 1), (33, 65), (700, 3), (1024, 128), (1500, 2), (2048, 2),
                                      (2100, 130), (4096, 2), (6000, 2), (8192, 2), (8200, 1), (10000, 2)])
 def test_persistent_equals_step_measure_all(ctx, n, shots):
-    """Register-resident and per-measurement-kernel paths agree bit for bit
-    on a full measure-all (tableau and every shot's outcomes); n covers each
-    row-word count per lane (1..5, with 8200 leaving the fifth nearly empty),
-    a single row word (n = 1, 33) and 65 or 130 shots two or three sign words
-    per row."""
-    from paper_2408_00384_amd import (MEASURE_AUTO, MEASURE_PERSISTENT, MEASURE_STEP,
+    """Register-resident (per-measurement and blocked) and per-measurement-
+    kernel paths agree bit for bit on a full measure-all (tableau and every
+    shot's outcomes); n covers each row-word count per lane (1..5, with 8200
+    leaving the fifth nearly empty), a single row word (n = 1, 33) and 65 or
+    130 shots two or three sign words per row."""
+    from paper_2408_00384_amd import (MEASURE_AUTO, MEASURE_BLOCKED, MEASURE_PERSISTENT, MEASURE_STEP,
                                       cliff_ctx_set_measure_mode)
     c = layered_circuit(n, 20 if n > 4096 else 12, shots, gen_seed=[41, n], circuit_id=6)
     res = {}
-    for mode in (MEASURE_STEP, MEASURE_PERSISTENT):
+    for mode in (MEASURE_STEP, MEASURE_PERSISTENT, MEASURE_BLOCKED):
         cliff_ctx_set_measure_mode(ctx.handle, mode)
         t = _tab(ctx, n, shots).apply_circuit_gates(c)
         out, rnd = t.measure(c.qubits, seed=c.seed, circuit=6)
         res[mode] = (out, rnd, t.export(), t.anomalies())
         t.close()
     cliff_ctx_set_measure_mode(ctx.handle, MEASURE_AUTO)
-    a, b = res[MEASURE_STEP], res[MEASURE_PERSISTENT]
-    assert np.array_equal(a[0], b[0]) and np.array_equal(a[1], b[1])
-    for A, B in zip(a[2], b[2]):
-        assert np.array_equal(A, B)
-    assert a[3] == 0 and b[3] == 0
+    a = res[MEASURE_STEP]
+    for mode in (MEASURE_PERSISTENT, MEASURE_BLOCKED):
+        b = res[mode]
+        assert np.array_equal(a[0], b[0]) and np.array_equal(a[1], b[1])
+        for A, B in zip(a[2], b[2]):
+            assert np.array_equal(A, B)
+        assert b[3] == 0
+    assert a[3] == 0
 
 
 def _check_symplectic_sample(t, n, seed, k=128, include=()):
@@ -544,27 +548,28 @@ def test_persistent_ghz_mostly_deterministic(ctx):
     4095 deterministic (all equal to the first).  Register-resident path
     against the per-measurement path over all of them, and against the oracle
     on the first 40."""
-    from paper_2408_00384_amd import (MEASURE_AUTO, MEASURE_PERSISTENT, MEASURE_STEP,
+    from paper_2408_00384_amd import (MEASURE_AUTO, MEASURE_BLOCKED, MEASURE_PERSISTENT, MEASURE_STEP,
                                       cliff_ctx_set_measure_mode)
     n, shots = 4096, 4
     ops = [0] + [2] * (n - 1)
     a = [0] + list(range(n - 1))
     b = [0] + list(range(1, n))
     res = {}
-    for mode in (MEASURE_STEP, MEASURE_PERSISTENT):
+    for mode in (MEASURE_STEP, MEASURE_PERSISTENT, MEASURE_BLOCKED):
         cliff_ctx_set_measure_mode(ctx.handle, mode)
         t = _tab(ctx, n, shots).apply_gates(ops, a, b)
         out, rnd = t.measure(np.arange(n), seed=17, circuit=2)
         res[mode] = (out, rnd, t.export(), t.anomalies())
         t.close()
     cliff_ctx_set_measure_mode(ctx.handle, MEASURE_AUTO)
-    out, rnd, tab, anom = res[MEASURE_PERSISTENT]
-    assert rnd[0] == 1 and rnd[1:].sum() == 0 and anom == 0
-    assert all(len(set(row.tolist())) == 1 for row in out)
     so, sr, stab, _ = res[MEASURE_STEP]
-    assert np.array_equal(out, so) and np.array_equal(rnd, sr)
-    for A, B in zip(tab, stab):
-        assert np.array_equal(A, B)
+    for mode in (MEASURE_PERSISTENT, MEASURE_BLOCKED):
+        out, rnd, tab, anom = res[mode]
+        assert rnd[0] == 1 and rnd[1:].sum() == 0 and anom == 0
+        assert all(len(set(row.tolist())) == 1 for row in out)
+        assert np.array_equal(out, so) and np.array_equal(rnd, sr)
+        for A, B in zip(tab, stab):
+            assert np.array_equal(A, B)
     ref = oracle.Tableau(n)
     ref.apply_gates(np.array(ops, np.uint8), np.array(a, np.uint32), np.array(b, np.uint32))
     for s_ in range(shots):
