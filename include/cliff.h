@@ -115,7 +115,7 @@ int cliff_ctx_set_gate_mode(cliff_ctx *ctx, int mode);
  * measurements is applied in blocks of up to 32 as one low-rank update (the
  * per-measurement kernels take the chunk's remaining measurements from its
  * first deterministic one); where the blocked launch shape does not fit
- * (n in (8 L * 255, 64 L] for L = ceil(2n/4096), e.g. n = 2041..2048,
+ * (n in (2040 L, 2048 L] for L = ceil(2n/4096), e.g. n = 2041..2048,
  * 8161..8192, 10201..10240) it is PERSISTENT.  STEP: one kernel per
  * measurement.  AUTO: BLOCKED for n >= 2048, PERSISTENT below, STEP where
  * neither fits.  Results are identical; only speed differs.  A measure-all of
