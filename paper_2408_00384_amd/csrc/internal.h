@@ -236,6 +236,8 @@ struct BlkDev {
   uint64_t *H;       // [NB][Wp] sign flips of the block's kept and replaced rows
   uint32_t *piv;     // [NB][kBlkK] pivot rows
   uint32_t *rowu;    // [NB][kBlkK] pivots absorbed by the pivot row at its step
+  uint32_t *qrow;    // [NB][kBlkK] replaced rows p_t - n
+  uint32_t *rq;      // [NB][kBlkK] their bits of U (bit i: U column i)
   uint32_t *ppart;   // [NB][G][2 + kBlkK] per workgroup: pivot Y counts (two planes), Gram rows
   uint32_t *nb;      // [NB] measurements of each block (0: none)
   uint32_t *sync;    // [4] counters
@@ -247,7 +249,7 @@ struct BlkArgs {
   uint32_t abort_at;        // as for the per-measurement kernels (kNone: never)
 };
 struct BlkScratchLayout {
-  size_t cols, U, part, H, piv, rowu, ppart, nb, sync, total;
+  size_t cols, U, part, H, piv, rowu, qrow, rq, ppart, nb, sync, total;
 };
 inline BlkScratchLayout blk_scratch_layout(const Dims &d, uint32_t kc, uint32_t G) {
   BlkScratchLayout o;
@@ -260,6 +262,8 @@ inline BlkScratchLayout blk_scratch_layout(const Dims &d, uint32_t kc, uint32_t 
   o.H = take(NB * d.Wp * 8);
   o.piv = take(NB * kBlkK * 4);
   o.rowu = take(NB * kBlkK * 4);
+  o.qrow = take(NB * kBlkK * 4);
+  o.rq = take(NB * kBlkK * 4);
   o.ppart = take(NB * G * (2 + kBlkK) * 4);
   o.nb = take(NB * 4);
   o.sync = take(16);
@@ -275,6 +279,8 @@ inline BlkDev blk_scratch_bind(const Dims &d, uint32_t kc, uint32_t G, uint8_t *
   s.H = reinterpret_cast<uint64_t *>(base + o.H);
   s.piv = reinterpret_cast<uint32_t *>(base + o.piv);
   s.rowu = reinterpret_cast<uint32_t *>(base + o.rowu);
+  s.qrow = reinterpret_cast<uint32_t *>(base + o.qrow);
+  s.rq = reinterpret_cast<uint32_t *>(base + o.rq);
   s.ppart = reinterpret_cast<uint32_t *>(base + o.ppart);
   s.nb = reinterpret_cast<uint32_t *>(base + o.nb);
   s.sync = reinterpret_cast<uint32_t *>(base + o.sync);

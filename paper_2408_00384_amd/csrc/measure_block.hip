@@ -100,7 +100,7 @@ struct BlkShared {
   unsigned long long E0[kPersistMaxWp], E1[kPersistMaxWp], ZX[kPersistMaxWp];
   uint32_t own[kPersistMaxChunk];                // owner of each measured column: g << 8 | wave << 4 | slot
   uint32_t P[kBlkK], RU[kBlkK], gam[kBlkK], ycnt[kBlkK];
-  uint32_t cp[2][kBlkWaves], crb[2][kBlkWaves];  // planner: each wave's candidate pivot and its bits
+  unsigned long long best[3];   // planner: smallest offer (pivot << 32 | its bits), by step mod 3
   uint32_t abort;
 };
 
@@ -115,8 +115,12 @@ struct BlkShared {
 //   row p - n takes row p's bits, row p is cleared.
 // One workgroup barrier per measurement: each wave offers its smallest
 // candidate row together with that row's bits of every element, and every
-// thread takes the smallest offer.  The 32 steps are instantiated one by one
-// (a template per step) so that every element index is a constant.
+// thread takes the smallest offer (one LDS atomic-min on pivot << 32 | its
+// bits).  The 32 steps are instantiated one by one (a template per step) so
+// that element indices are constants, and a step past the block's end or
+// after a deterministic measurement runs with an all-zero update rather than
+// leaving early (exits with the 64 element registers live made the compiler
+// keep copies of them in scratch).
 // Rows p - n are fixed once per block: no pivot search reads destabilizer
 // rows, and no other row's update reads them, so during the block their bits
 // are left as the updates make them while lane t of wave 0 tracks replaced
@@ -126,25 +130,28 @@ struct BlkShared {
 struct PlanCtx {
   uint32_t kbmax, kb, m0b, b;
   uint32_t rq, qrow;   // wave 0, lane t: replaced row p_t - n and its bits
-  bool aborted;
+  bool aborted, stopped;
 };
 
-template <uint32_t TT>
-__device__ __forceinline__ bool plan_step(uint32_t (&lo)[kBlkK], uint32_t (&hi)[kBlkK], PlanCtx &pc,
+template <uint32_t D>
+__device__ __forceinline__ void plan_step(uint32_t (&lo)[kBlkK], uint32_t (&hi)[kBlkK], PlanCtx &pc,
                                           const TabDev &t, const BlkDev &s, const BlkArgs &a, BlkShared &sh) {
-  if (TT >= pc.kbmax) return false;
+  constexpr uint32_t tt = D;   // the block's measurement index of this step
+  if (tt >= pc.kbmax) pc.stopped = true;
   const uint32_t tid = threadIdx.x, lane = tid & 63;
   const uint32_t wave = __builtin_amdgcn_readfirstlane(tid >> 6);
   const uint32_t n = t.n, W = t.W, w = tid;
-  if (pc.m0b + TT == a.abort_at) {   // injected: stop as after a timed-out wait
+  if (!pc.stopped && pc.m0b + tt == a.abort_at) {   // injected: stop as after a timed-out wait
     if (tid == 0) atomicOr(t.abort_flag, 1u);
     pc.aborted = true;
-    return false;
+    pc.stopped = true;
   }
-  constexpr uint32_t slot = TT & 1u;
-  const uint32_t cl = lo[TT], ch = hi[TT];
+  const bool live = !pc.stopped;
+  const uint32_t slot = tt % 3u;
+  const uint32_t cl = lo[D], ch = hi[D];
   {
-    const uint32_t cand = blk_candidate((uint64_t(ch) << 32) | cl, w, n, W);
+    // this wave's smallest candidate and that row's bits of the elements
+    const uint32_t cand = live ? blk_candidate((uint64_t(ch) << 32) | cl, w, n, W) : kNone;
     const uint64_t bal = __ballot(cand != kNone);
     uint32_t pv = kNone, rbv = 0;
     if (bal) {
@@ -161,36 +168,33 @@ __device__ __forceinline__ bool plan_step(uint32_t (&lo)[kBlkK], uint32_t (&hi)[
       }
       rbv = uint32_t(__builtin_amdgcn_readlane(int(v), int(l)));
     }
-    if (lane == 0) {
-      sh.cp[slot][wave] = pv;
-      sh.crb[slot][wave] = rbv;
-    }
+    if (bal && lane == 0) atomicMin(&sh.best[slot], (static_cast<unsigned long long>(pv) << 32) | rbv);
   }
+  // the slot of step tt + 1 was last read before this step began
+  if (tid == 0) sh.best[slot == 2 ? 0 : slot + 1] = ~0ull;
   lds_barrier();
-  uint32_t p = kNone, rb = 0;
-#pragma unroll
-  for (uint32_t v = 0; v < kBlkWaves; ++v) {
-    const uint32_t pv = sh.cp[slot][v], rv = sh.crb[slot][v];
-    rb = pv < p ? rv : rb;
-    p = pv < p ? pv : p;
+  const unsigned long long bk = sh.best[slot];
+  const uint32_t p = uint32_t(bk >> 32);
+  uint32_t rb = uint32_t(bk);   // row p's bits of the elements
+  if (live && p == kNone) {   // deterministic: the block ends before it
+    pc.kb = tt;
+    pc.stopped = true;
   }
-  if (p == kNone) {   // deterministic: the block ends before it
-    pc.kb = TT;
-    return false;
-  }
+  const bool go = !pc.stopped;
+  if (!go) rb = 0;
   const uint32_t wp = p >> 6, pn = p - n;
-  if (tid == 0) {
-    s.piv[size_t(pc.b) * kBlkK + TT] = p;
-    s.rowu[size_t(pc.b) * kBlkK + TT] = rb & ((1u << TT) - 1u);
+  if (go && tid == 0) {
+    s.piv[size_t(pc.b) * kBlkK + tt] = p;
+    s.rowu[size_t(pc.b) * kBlkK + tt] = rb & ((1u << tt) - 1u);
   }
   // rows of M absorb row p; with row p in the mask, its own bit (set exactly
-  // where rb is) clears in the same XOR.  Element TT becomes U column TT: M
+  // where rb is) clears in the same XOR.  Element tt becomes U column tt: M
   // (plus row p - n, set at the block's end).
-  const uint32_t bpl = w == wp && !(p & 32) ? 1u << (p & 31) : 0u;
-  const uint32_t bph = w == wp && (p & 32) ? 1u << (p & 31) : 0u;
+  const uint32_t bpl = go && w == wp && !(p & 32) ? 1u << (p & 31) : 0u;
+  const uint32_t bph = go && w == wp && (p & 32) ? 1u << (p & 31) : 0u;
 #pragma unroll
   for (uint32_t i = 0; i < kBlkK; ++i) {
-    if (i == TT) {
+    if (i == D) {
       lo[i] ^= bpl;
       hi[i] ^= bph;
     } else {
@@ -199,11 +203,11 @@ __device__ __forceinline__ bool plan_step(uint32_t (&lo)[kBlkK], uint32_t (&hi)[
       hi[i] ^= ch & msk;
     }
   }
-  if (wave == 0) {
-    const uint32_t x = rb & ~(1u << TT);
-    if (lane < TT) pc.rq ^= ((pc.rq >> TT) & 1u) ? x : 0u;
-    if (lane == TT) {
-      pc.rq = rb | (1u << TT);
+  if (go && wave == 0) {
+    const uint32_t x = rb & ~(1u << tt);
+    if (lane < tt) pc.rq ^= ((pc.rq >> tt) & 1u) ? x : 0u;
+    if (lane == tt) {
+      pc.rq = rb | (1u << tt);
       pc.qrow = pn;
     }
   }
@@ -211,15 +215,13 @@ __device__ __forceinline__ bool plan_step(uint32_t (&lo)[kBlkK], uint32_t (&hi)[
   // carrying XOR expressions of several steps)
 #pragma unroll
   for (uint32_t i = 0; i < kBlkK; ++i) asm volatile("" : "+v"(lo[i]), "+v"(hi[i]));
-  return true;
 }
 
-template <uint32_t... TT>
+template <uint32_t... D>
 __device__ __forceinline__ void plan_block(uint32_t (&lo)[kBlkK], uint32_t (&hi)[kBlkK], PlanCtx &pc,
                                            const TabDev &t, const BlkDev &s, const BlkArgs &a, BlkShared &sh,
-                                           std::integer_sequence<uint32_t, TT...>) {
-  bool go = true;
-  ((go = go && plan_step<TT>(lo, hi, pc, t, s, a, sh)), ...);
+                                           std::integer_sequence<uint32_t, D...>) {
+  (plan_step<D>(lo, hi, pc, t, s, a, sh), ...);
 }
 
 __device__ __forceinline__ void blk_planner(const TabDev &t, const BlkDev &s, const BlkArgs &a, BlkShared &sh) {
@@ -233,7 +235,12 @@ __device__ __forceinline__ void blk_planner(const TabDev &t, const BlkDev &s, co
     const uint32_t m0b = b * kBlkK;
     if (m0b >= k) break;
     const uint32_t kbmax = k - m0b < kBlkK ? k - m0b : kBlkK;
-    if (tid == 0) sh.abort = blk_wait(&s.sync[0], m0b + kbmax, t.abort_flag) ? 0u : 1u;
+    if (tid == 0) {
+      sh.best[0] = ~0ull;
+      sh.best[1] = ~0ull;
+      sh.best[2] = ~0ull;
+      sh.abort = blk_wait(&s.sync[0], m0b + kbmax, t.abort_flag) ? 0u : 1u;
+    }
     __syncthreads();
     if (sh.abort) return;
 #pragma unroll
@@ -248,6 +255,7 @@ __device__ __forceinline__ void blk_planner(const TabDev &t, const BlkDev &s, co
     pc.b = b;
     pc.rq = 0;
     pc.qrow = 0;
+    pc.stopped = false;
     plan_block(lo, hi, pc, t, s, a, sh, std::make_integer_sequence<uint32_t, kBlkK>{});
     if (pc.aborted) return;
     const uint32_t kb = pc.kb;
@@ -256,18 +264,11 @@ __device__ __forceinline__ void blk_planner(const TabDev &t, const BlkDev &s, co
       for (uint32_t i = 0; i < kBlkK; ++i)
         if (i < kb) s.U[(size_t(b) * kBlkK + i) * Wp + w] = (uint64_t(hi[i]) << 32) | lo[i];
     }
-    fence_release();
-    __syncthreads();
-    // the replaced rows' bits, tracked by wave 0, written over the stored U
+    // the replaced rows and their bits of U (the stored U has stale bits
+    // there; its readers write these over them)
     if (wave == 0 && lane < kb) {
-      unsigned long long *col = reinterpret_cast<unsigned long long *>(s.U + size_t(b) * kBlkK * Wp + (pc.qrow >> 6));
-      const unsigned long long m = bbit(pc.qrow);
-      for (uint32_t i = 0; i < kb; ++i) {
-        if ((pc.rq >> i) & 1u)
-          atomicOr(col + size_t(i) * Wp, m);
-        else
-          atomicAnd(col + size_t(i) * Wp, ~m);
-      }
+      s.qrow[size_t(b) * kBlkK + lane] = pc.qrow;
+      s.rq[size_t(b) * kBlkK + lane] = pc.rq;
     }
     fence_release();
     __syncthreads();
@@ -386,6 +387,16 @@ __device__ __forceinline__ void blk_sweeper(const TabDev &t, const BlkDev &s, co
       const uint32_t p = sh.P[i], pn = p - n;
       atomicOr(reinterpret_cast<unsigned long long *>(&sh.K[p >> 6]), (unsigned long long)bbit(p));
       atomicOr(reinterpret_cast<unsigned long long *>(&sh.K[pn >> 6]), (unsigned long long)bbit(pn));
+      // replaced row i: its bits of the staged U
+      const uint32_t row = blk_ld(s.qrow + size_t(b) * kBlkK + i), bits = blk_ld(s.rq + size_t(b) * kBlkK + i);
+      unsigned long long *col = reinterpret_cast<unsigned long long *>(sU + (row >> 6));
+      const unsigned long long m = bbit(row);
+      for (uint32_t j = 0; j < kb; ++j) {
+        if ((bits >> j) & 1u)
+          atomicOr(col + j * US, m);
+        else
+          atomicAnd(col + j * US, ~m);
+      }
     }
     __syncthreads();
     // ---- x and z of this wave's columns at the pivot rows (bit i = pivot i):
@@ -622,6 +633,24 @@ __global__ void __launch_bounds__(kBlkThreads) k_blk(TabDev t, BlkDev s, BlkArgs
     blk_sweeper<L>(t, s, a, sh, s_dynU);
 }
 
+// The replaced rows' bits written over the stored U of every block (one
+// thread per replaced row), for the finalize kernels.
+__global__ void __launch_bounds__(kBlkK) k_blk_patch(TabDev t, BlkDev s) {
+  const uint32_t b = blockIdx.x, q = threadIdx.x;
+  if (b >= s.NB || blk_ld(t.abort_flag)) return;
+  const uint32_t kb = s.nb[b];
+  if (q >= kb) return;
+  const uint32_t row = s.qrow[size_t(b) * kBlkK + q], bits = s.rq[size_t(b) * kBlkK + q];
+  unsigned long long *col = reinterpret_cast<unsigned long long *>(s.U + size_t(b) * kBlkK * t.Wp + (row >> 6));
+  const unsigned long long m = bbit(row);
+  for (uint32_t j = 0; j < kb; ++j) {
+    if ((bits >> j) & 1u)
+      atomicOr(col + size_t(j) * t.Wp, m);
+    else
+      atomicAnd(col + size_t(j) * t.Wp, ~m);
+  }
+}
+
 // Clear the pass counters and block counts of a chunk (kernel stores only:
 // capture-safe).
 __global__ void k_blk_begin(BlkDev s) {
@@ -828,6 +857,7 @@ hipError_t launch_blk_chunk(const TabDev &t, const BlkDev &s, const uint32_t *de
 hipError_t launch_blk_finalize(const TabDev &t, const BlkDev &s, uint32_t cnt, uint32_t base, uint64_t seed,
                                uint64_t circuit, uint64_t shot0, uint64_t m0, uint32_t G, hipStream_t st) {
   const uint32_t nb = (cnt + kBlkK - 1) / kBlkK;
+  k_blk_patch<<<nb, kBlkK, 0, st>>>(t, s);
   k_blk_reduce<<<dim3(nb, (t.W + 255) / 256), 256, 0, st>>>(t, s, G);
   k_blk_signs<<<t.S, kBlkSignThreads, 0, st>>>(t, s, cnt, base, seed, circuit, shot0, m0);
   return hipGetLastError();
