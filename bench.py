@@ -10,14 +10,17 @@ Default workload: n = 10,000 qubits, 20 layers of random H/S/CNOT-matching,
 measure all, 1 shot (the rowsum-dominated single-tableau case).
 
 One JSON line is printed with circuits/s, the roofline of the dominant kernel
-and the CPU oracle timed on a bounded sample of the same workload.  The
-dominant kernel is the register-resident rowsum kernel k_meas_xz, which keeps
-the tableau in registers and LDS, so its bound is the ALU: its algorithmic
-32-bit lane operations (from the device-side support counters) over its time
-(HIP events recorded on its stream around every launch of the timed steps),
-against the MI355X's vector rate.  The HBM-equivalent rate of the same sweep
-is kept as effective_alg_gbs.  On the per-measurement path (n > 10,240) the
-sweep streams the tableau through HBM and is reported against HBM.
+and the CPU oracle timed on a bounded sample of the same workload.  At the
+default size the dominant kernel is k_blk, the blocked measurement pass
+(random measurements applied 32 at a time as one low-rank update to the
+tableau held in registers); where it does not run, the register-resident
+rowsum kernel k_meas_xz.  Both keep the tableau on chip, so their bound is
+the ALU: the method's algorithmic 32-bit lane operations (from the
+device-side support counters) over the kernel's time (HIP events recorded on
+its stream around every launch of the timed steps), against the MI355X's
+vector rate.  The HBM-equivalent rate of the same work is kept as
+effective_alg_gbs.  On the per-measurement path (n > 10,240) the sweep
+streams the tableau through HBM and is reported against HBM.
 
 Further legs on the same line: the n = 64 and n = 1,024 workloads, the
 batched 4,096-circuit workload (batched vs one circuit per launch, wall and
@@ -46,6 +49,12 @@ VALU_PEAK_TOPS = 157.3 / 2
 # (FETCH_SIZE and WRITE_SIZE, each scaled by what it reads for a copy of known
 # size), valid only for the kernel sources they were taken on.
 TRAFFIC = {
+    "k_blk": {
+        "sources": ("paper_2408_00384_amd/csrc/measure_block.hip", "paper_2408_00384_amd/csrc/internal.h"),
+        "sha256": "",
+        "bytes_per_launch": 0.0,
+        "summary": "profiles/k_blk_plain_n10000_measure_all.md",
+    },
     "k_meas_xz": {
         "sources": ("paper_2408_00384_amd/csrc/measure_persist.hip", "paper_2408_00384_amd/csrc/internal.h"),
         "sha256": "09f7ac8514d610188a899c7140616b3bf5c1c5c6c1be21e5187d6928cdeecbf2",
@@ -72,8 +81,9 @@ WORKLOADS = {
 }
 
 
-def alu_roofline(counters, n, steps, sweep_ms, launches, traffic):
-    """Roofline of the register-resident rowsum kernel (k_meas_xz).
+def alu_roofline(counters, n, steps, sweep_ms, launches, traffic, blocked=False):
+    """Roofline of the register-resident kernel that measured (k_blk, the
+    blocked pass, or k_meas_xz, one rowsum sweep per measurement).
 
     Per random measurement with pivot-row support s (columns where the pivot
     row is not I), s_x (with an X part) and s_z (with a Z part), the sweep
@@ -83,7 +93,10 @@ def alu_roofline(counters, n, steps, sweep_ms, launches, traffic):
     operations, i.e. 8 s + 4 (s_x + s_z) = 4 (2 s + s_x + s_z) 32-bit lane
     operations per row word.  The device counters give sum(2 s + s_x + s_z)
     through the algorithmic bytes (8 W (2 s + s_x + s_z + 3) + 80 n per random
-    measurement, 8 n W per deterministic one)."""
+    measurement, 8 n W per deterministic one).  The blocked pass does the
+    same measurements with fewer operations (the phase terms are summed once
+    per block of 32); the count stays the method's, so that the two kernels
+    are measured on one scale."""
     W = (2 * n + 63) // 64
     nr, nd = counters["random"], counters["deterministic"]
     sup = (counters["alg_bytes"] - nr * (24 * W + 80 * n) - nd * 8 * n * W) // (8 * W)
@@ -93,7 +106,9 @@ def alu_roofline(counters, n, steps, sweep_ms, launches, traffic):
     achieved = ops_launch / avg_s / 1e12 if avg_s > 0 else 0.0
     sweep_bytes = counters["alg_bytes"] - (8 * W * 3 + 80 * n) * nr
     return {
-        "kernel": "k_meas_xz (register-resident rowsum sweep, one launch per chunk of measurements)",
+        "kernel": ("k_blk (blocked measurement pass: 32 random measurements per low-rank update, one launch "
+                   "per chunk of measurements)" if blocked else
+                   "k_meas_xz (register-resident rowsum sweep, one launch per chunk of measurements)"),
         "bound": "alu", "achieved": achieved, "peak": VALU_PEAK_TOPS, "unit": "TOP/s",
         "frac": achieved / VALU_PEAK_TOPS,
         "traffic": traffic,
@@ -780,9 +795,13 @@ def main():
     # counter planes and row rewrites belong to the finalize kernels
     sweep_step = alg_step - (8 * W * 3 + 80 * n) * nr
     sweep_ms, sweep_launches = prof["sweep"]
+    blk_ms, blk_launches = prof["blocked"]
     persistent = sweep_launches < steps * len(qubits)
-    meas_ms = sum(prof[k][0] for k in ("select", "sweep", "final"))
-    if persistent:
+    meas_ms = sum(prof[k][0] for k in ("select", "sweep", "final", "blocked"))
+    if blk_launches and blk_ms > sweep_ms:
+        roofline = alu_roofline(counters, n, steps, blk_ms, blk_launches,
+                                traffic_for("k_blk") if args.workload == "large" else None, blocked=True)
+    elif persistent:
         roofline = alu_roofline(counters, n, steps, sweep_ms, sweep_launches,
                                 traffic_for("k_meas_xz") if args.workload == "large" else None)
     else:

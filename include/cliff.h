@@ -347,7 +347,7 @@ int cliff_tab_reset_counters(cliff_tab *tab);
 /* Kernel timing (tracing aid): when enabled, every kernel launch made through
  * the context is bracketed by HIP events on its stream.  Kinds: 0 gate sweep,
  * 1 pivot select, 2 rowsum sweep, 3 finalize, 4 other (init/fold/copy),
- * 5 batched circuits.  Enabling (or disabling) resets the totals; reading
+ * 5 batched circuits, 6 blocked measurement pass (its x/z kernel).  Enabling (or disabling) resets the totals; reading
  * synchronizes and returns total milliseconds and launch count of a kind. */
 int cliff_ctx_profile(cliff_ctx *ctx, int enable);
 int cliff_ctx_profile_read(cliff_ctx *ctx, int kind, double *ms, uint64_t *launches);

@@ -425,7 +425,7 @@ def cliff_tab_reset_counters(tab):
     _check(_lib.cliff_tab_reset_counters(tab), "cliff_tab_reset_counters")
 
 
-PROF_KINDS = ("gate", "select", "sweep", "final", "other", "batch")
+PROF_KINDS = ("gate", "select", "sweep", "final", "other", "batch", "blocked")
 
 
 def cliff_ctx_profile(ctx, enable: bool):

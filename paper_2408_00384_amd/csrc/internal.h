@@ -50,7 +50,7 @@ enum : uint32_t {
 };
 
 // Kernel classes timed by the profiler.
-enum ProfKind : int { PK_GATE = 0, PK_SELECT, PK_SWEEP, PK_FINAL, PK_OTHER, PK_BATCH, kProfKinds };
+enum ProfKind : int { PK_GATE = 0, PK_SELECT, PK_SWEEP, PK_FINAL, PK_OTHER, PK_BATCH, PK_BLOCKED, kProfKinds };
 
 // Optional hipEvent timing of kernel launches, per kernel class: events are
 // recorded on the launch stream right before and after each launch and

@@ -768,9 +768,9 @@ hipError_t launch_measure_persist(const TabDev &t, uint32_t kc, const uint32_t *
     // kernels below do the rest (from the count it leaves in device memory)
     const uint32_t *skip = nullptr;
     if (blk) {
-      if (prof) prof->begin(PK_SWEEP, st);
+      if (prof) prof->begin(PK_BLOCKED, st);
       e = launch_blk_chunk(tv, blk[b], dev_qubits + base, cnt, blk_G, blk_L, ab, st);
-      if (prof) prof->end(PK_SWEEP, st);
+      if (prof) prof->end(PK_BLOCKED, st);
       if (e != hipSuccess) return e;
       skip = blk[b].sync + 2;
     }
