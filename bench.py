@@ -51,8 +51,8 @@ VALU_PEAK_TOPS = 157.3 / 2
 TRAFFIC = {
     "k_blk": {
         "sources": ("paper_2408_00384_amd/csrc/measure_block.hip", "paper_2408_00384_amd/csrc/internal.h"),
-        "sha256": "",
-        "bytes_per_launch": 0.0,
+        "sha256": "abcc6fde6e656f3e33444613c0baa8d55e5a24fb1d53721c949ab3423f5fdc39",
+        "bytes_per_launch": 1.717e+08,
         "summary": "profiles/k_blk_plain_n10000_measure_all.md",
     },
     "k_meas_xz": {
