@@ -149,7 +149,10 @@ __device__ __forceinline__ void plan_step(uint32_t (&lo)[kBlkK], uint32_t (&hi)[
   const bool live = !pc.stopped;
   const uint32_t slot = tt % 3u;
   const uint32_t cl = lo[D], ch = hi[D];
-  {
+  // waves past the last row word hold nothing: they only keep the barriers
+  // (and leave the issue slots of their SIMD to the wave sharing it)
+  const bool holds = wave * 64 < W;
+  if (holds) {
     // this wave's smallest candidate and that row's bits of the elements
     const uint32_t cand = live ? blk_candidate((uint64_t(ch) << 32) | cl, w, n, W) : kNone;
     const uint64_t bal = __ballot(cand != kNone);
@@ -190,17 +193,19 @@ __device__ __forceinline__ void plan_step(uint32_t (&lo)[kBlkK], uint32_t (&hi)[
   // rows of M absorb row p; with row p in the mask, its own bit (set exactly
   // where rb is) clears in the same XOR.  Element tt becomes U column tt: M
   // (plus row p - n, set at the block's end).
-  const uint32_t bpl = go && w == wp && !(p & 32) ? 1u << (p & 31) : 0u;
-  const uint32_t bph = go && w == wp && (p & 32) ? 1u << (p & 31) : 0u;
+  if (holds) {
+    const uint32_t bpl = go && w == wp && !(p & 32) ? 1u << (p & 31) : 0u;
+    const uint32_t bph = go && w == wp && (p & 32) ? 1u << (p & 31) : 0u;
 #pragma unroll
-  for (uint32_t i = 0; i < kBlkK; ++i) {
-    if (i == D) {
-      lo[i] ^= bpl;
-      hi[i] ^= bph;
-    } else {
-      const uint32_t msk = 0u - ((rb >> i) & 1u);
-      lo[i] ^= cl & msk;
-      hi[i] ^= ch & msk;
+    for (uint32_t i = 0; i < kBlkK; ++i) {
+      if (i == D) {
+        lo[i] ^= bpl;
+        hi[i] ^= bph;
+      } else {
+        const uint32_t msk = 0u - ((rb >> i) & 1u);
+        lo[i] ^= cl & msk;
+        hi[i] ^= ch & msk;
+      }
     }
   }
   if (go && wave == 0) {
