@@ -51,7 +51,7 @@ VALU_PEAK_TOPS = 157.3 / 2
 TRAFFIC = {
     "k_blk": {
         "sources": ("paper_2408_00384_amd/csrc/measure_block.hip", "paper_2408_00384_amd/csrc/internal.h"),
-        "sha256": "abcc6fde6e656f3e33444613c0baa8d55e5a24fb1d53721c949ab3423f5fdc39",
+        "sha256": "ca035eaad62ac7a8b80d14ccbd548be5cb8fd139e858359db34401d303c9ee72",
         "bytes_per_launch": 1.717e+08,
         "summary": "profiles/k_blk_plain_n10000_measure_all.md",
     },
