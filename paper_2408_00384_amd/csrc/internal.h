@@ -225,12 +225,13 @@ inline void persist_scratch_bind(TabDev &t, const Dims &d, uint32_t kc, uint8_t 
 // one low-rank update.  Per chunk: the block's measured columns handed to the
 // planner, U and the pivots of every block, per-workgroup sign partials, the
 // reduced sign flips, and four counters (columns published, blocks planned,
-// measurements done by the pass, spare).
+// measurements done by the pass, columns handed over through the second
+// buffer).
 constexpr uint32_t kBlkK = 32;
 // Smallest n for which the automatic measurement mode takes the blocked pass.
 constexpr uint32_t kBlkAutoMinN = 2048;
 struct BlkDev {
-  uint64_t *cols;    // [kBlkK][Wp] measured columns of the block being planned
+  uint64_t *cols;    // [2][kBlkK][Wp] measured columns of blocks to plan (block c in buffer c mod 2)
   uint64_t *U;       // [NB][kBlkK][Wp] U columns (rows that absorbed pivot t)
   uint64_t *part;    // [NB][G][3][Wp] per workgroup: (Y_old - Y_new) mod 4 (two planes), z.x parity
   uint64_t *H;       // [NB][Wp] sign flips of the block's kept and replaced rows
@@ -256,7 +257,7 @@ inline BlkScratchLayout blk_scratch_layout(const Dims &d, uint32_t kc, uint32_t 
   size_t cur = 0;
   auto take = [&](size_t bytes) { size_t at = cur; cur = align256(cur + bytes); return at; };
   const size_t NB = (size_t(kc) + kBlkK - 1) / kBlkK;
-  o.cols = take(size_t(kBlkK) * d.Wp * 8);
+  o.cols = take(2 * size_t(kBlkK) * d.Wp * 8);
   o.U = take(NB * kBlkK * d.Wp * 8);
   o.part = take(NB * G * 3 * d.Wp * 8);
   o.H = take(NB * d.Wp * 8);

@@ -40,11 +40,14 @@
 // Launch: G sweeper workgroups own the columns as in measure_persist.hip
 // (workgroup g the columns g (mod G), 8 waves, L whole columns of L row
 // words per lane per wave, x and z in registers) plus one planner workgroup
-// (one row word per thread, the block's columns and U in registers).  Per
-// block the owners publish the block's measured columns (plain stores, a
-// release fence, a counter), the planner publishes U and the pivots the same
-// way, and each sweeper workgroup stages U in LDS and applies it.  Every wait
-// is bounded and watches the tableau's abort flag.
+// (one row word per thread, the block's columns and U in registers).  The
+// owners of block c's measured columns hand them over during the sweep of
+// block c - 2 (plain stores, a release fence, a counter; two buffers
+// alternate), updated to before block c - 1; the planner, having published
+// U of block c - 1 the same way, applies that U to them itself and plans
+// block c at once, while each sweeper workgroup stages the published U in
+// LDS and applies it to its columns.  Every wait is bounded and watches the
+// tableau's abort flag.
 #include <utility>
 
 #include "internal.h"
@@ -100,6 +103,7 @@ struct BlkShared {
   unsigned long long E0[kPersistMaxWp], E1[kPersistMaxWp], ZX[kPersistMaxWp];
   uint32_t own[kPersistMaxChunk];                // owner of each measured column: g << 8 | wave << 4 | slot
   uint32_t P[kBlkK], RU[kBlkK], gam[kBlkK], ycnt[kBlkK];
+  alignas(16) uint32_t V[kBlkK];   // planner: the next block's columns' bits at this block's pivot rows
   unsigned long long best[3];   // planner: smallest offer (pivot << 32 | its bits), by step mod 3
   uint32_t abort;
 };
@@ -229,31 +233,43 @@ __device__ __forceinline__ void plan_block(uint32_t (&lo)[kBlkK], uint32_t (&hi)
   (plan_step<D>(lo, hi, pc, t, s, a, sh), ...);
 }
 
-__device__ __forceinline__ void blk_planner(const TabDev &t, const BlkDev &s, const BlkArgs &a, BlkShared &sh) {
+// After publishing block b the planner brings block b + 1's measured columns
+// (as they stood before block b, handed over by their owners during the
+// sweep of block b - 1) up to date itself: x ^= sum over pivots t with
+// x[p_t] = 1 of U_t, rows p_t and p_t - n set apart, a 32 x 32 GF(2) product
+// per row word.  It then plans block b + 1 at once instead of waiting for the
+// sweepers to update and hand over those columns.
+__device__ __forceinline__ void blk_planner(const TabDev &t, const BlkDev &s, const BlkArgs &a, BlkShared &sh,
+                                            uint64_t *sN, uint32_t US) {
   const uint32_t tid = threadIdx.x, lane = tid & 63;
   const uint32_t wave = __builtin_amdgcn_readfirstlane(tid >> 6);
-  const uint32_t W = t.W, Wp = t.Wp, k = a.k, w = tid;
+  const uint32_t n = t.n, W = t.W, Wp = t.Wp, k = a.k, w = tid;
   PlanCtx pc;
   pc.aborted = false;
   uint32_t lo[kBlkK], hi[kBlkK];
+  uint32_t cum[2] = {0u, 0u};   // columns handed over so far through each of the two buffers
+  {
+    const uint32_t kb0 = k < kBlkK ? k : kBlkK;
+    cum[0] = kb0;
+    if (tid == 0) sh.abort = blk_wait(&s.sync[0], kb0, t.abort_flag) ? 0u : 1u;
+    __syncthreads();
+    if (sh.abort) return;
+#pragma unroll
+    for (uint32_t i = 0; i < kBlkK; ++i) {
+      const uint64_t v = (i < kb0 && w < W) ? blk_ld64(s.cols + size_t(i) * Wp + w) : 0ull;
+      lo[i] = uint32_t(v);
+      hi[i] = uint32_t(v >> 32);
+    }
+  }
   for (uint32_t b = 0;; ++b) {
     const uint32_t m0b = b * kBlkK;
-    if (m0b >= k) break;
     const uint32_t kbmax = k - m0b < kBlkK ? k - m0b : kBlkK;
     if (tid == 0) {
       sh.best[0] = ~0ull;
       sh.best[1] = ~0ull;
       sh.best[2] = ~0ull;
-      sh.abort = blk_wait(&s.sync[0], m0b + kbmax, t.abort_flag) ? 0u : 1u;
     }
     __syncthreads();
-    if (sh.abort) return;
-#pragma unroll
-    for (uint32_t i = 0; i < kBlkK; ++i) {
-      const uint64_t v = (i < kbmax && w < W) ? blk_ld64(s.cols + size_t(i) * Wp + w) : 0ull;
-      lo[i] = uint32_t(v);
-      hi[i] = uint32_t(v >> 32);
-    }
     pc.kbmax = kbmax;
     pc.kb = kbmax;
     pc.m0b = m0b;
@@ -275,6 +291,26 @@ __device__ __forceinline__ void blk_planner(const TabDev &t, const BlkDev &s, co
       s.qrow[size_t(b) * kBlkK + lane] = pc.qrow;
       s.rq[size_t(b) * kBlkK + lane] = pc.rq;
     }
+    const uint32_t m0n = m0b + kBlkK;
+    const bool last = kb < kbmax || m0n >= k;
+    const uint32_t kbn = last ? 0u : (k - m0n < kBlkK ? k - m0n : kBlkK);
+    const uint32_t nbuf = (b + 1) & 1u;
+    // ---- block b + 1's columns, as they stood before block b (waited for
+    // and loaded while the stores of U drain; all 32 loads in flight before
+    // the first is used)
+    if (!last) {
+      cum[nbuf] += kbn;
+      if (tid == 0) sh.abort = blk_wait(&s.sync[nbuf ? 3 : 0], cum[nbuf], t.abort_flag) ? 0u : 1u;
+      __syncthreads();
+      if (sh.abort) return;
+    }
+    uint32_t nl[kBlkK], nh[kBlkK];
+#pragma unroll
+    for (uint32_t j = 0; j < kBlkK; ++j) {
+      const uint64_t v = (j < kbn && w < W) ? blk_ld64(s.cols + (size_t(nbuf) * kBlkK + j) * Wp + w) : 0ull;
+      nl[j] = uint32_t(v);
+      nh[j] = uint32_t(v >> 32);
+    }
     fence_release();
     __syncthreads();
     if (tid == 0) {
@@ -283,9 +319,90 @@ __device__ __forceinline__ void blk_planner(const TabDev &t, const BlkDev &s, co
       fence_release();
       __hip_atomic_store(&s.sync[1], b + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     }
-    if (kb < kbmax) return;
+    if (last) {
+      if (kb == kbmax && tid == 0) s.sync[2] = k;
+      return;
+    }
+#pragma unroll
+    for (uint32_t j = 0; j < kBlkK; ++j)
+      if (w < US) sN[j * US + w] = (uint64_t(nh[j]) << 32) | nl[j];
+    if (w < W) {
+      sh.K[w] = 0;
+      sh.ZX[w] = 0;
+    }
+    __syncthreads();
+    // wave 0, lane t < kb: V_t = the columns' bits at pivot row p_t (bit j:
+    // column j), and replaced row p_t - n: its bit of column j is the parity
+    // of column j's bits at the pivots its U row holds, written over the
+    // staged column; rows p_t marked in sh.K, rows p_t - n in sh.ZX
+    if (wave == 0) {
+      const bool mine = lane < kb;
+      const uint32_t q = pc.qrow, p = q + n;
+      uint32_t v = 0, oq = 0;
+      if (mine) {
+        for (uint32_t j = 0; j < kbn; ++j) {
+          v |= uint32_t((sN[j * US + (p >> 6)] >> (p & 63)) & 1u) << j;
+          oq |= uint32_t((sN[j * US + (q >> 6)] >> (q & 63)) & 1u) << j;
+        }
+        atomicOr(reinterpret_cast<unsigned long long *>(&sh.K[p >> 6]), (unsigned long long)bbit(p));
+        atomicOr(&sh.ZX[q >> 6], (unsigned long long)bbit(q));
+      }
+      if (lane < kBlkK) sh.V[lane] = v;   // 0 for t >= kb
+      uint32_t f = 0;
+#pragma unroll
+      for (uint32_t tt = 0; tt < kBlkK; ++tt) {
+        const uint32_t vt = uint32_t(__builtin_amdgcn_readlane(int(v), int(tt)));
+        f ^= ((pc.rq >> tt) & 1u) ? vt : 0u;
+      }
+      if (mine) {
+        const uint32_t d = f ^ oq;
+        unsigned long long *col = reinterpret_cast<unsigned long long *>(sN + (q >> 6));
+        const unsigned long long m = bbit(q);
+        for (uint32_t j = 0; j < kbn; ++j)
+          if ((d >> j) & 1u) atomicXor(col + size_t(j) * US, m);
+      }
+    }
+    __syncthreads();
+    // the next block's columns brought up to date: pivot rows cleared,
+    // x ^= sum over t with V_t set of U_t (U's stale replaced rows left
+    // out), replaced rows taken from sN; waves past the last row word
+    // hold nothing
+    if (wave * 64 < W) {
+      const uint64_t kq = w < W ? sh.K[w] : 0ull, qq = w < W ? uint64_t(sh.ZX[w]) : 0ull;
+      const uint32_t kl = ~uint32_t(kq | qq), kh = ~uint32_t((kq | qq) >> 32), ql = ~uint32_t(qq), qh = ~uint32_t(qq >> 32);
+#pragma unroll
+      for (uint32_t j = 0; j < kBlkK; ++j) {
+        nl[j] &= kl;
+        nh[j] &= kh;
+      }
+      // (V_t = 0 past the block's count: those elements, not U columns,
+      // drop out; V read four pivots at a time)
+#pragma unroll
+      for (uint32_t t4 = 0; t4 < kBlkK / 4; ++t4) {
+        const uint4 v4 = reinterpret_cast<const uint4 *>(sh.V)[t4];
+        const uint32_t vq[4] = {v4.x, v4.y, v4.z, v4.w};
+#pragma unroll
+        for (uint32_t r = 0; r < 4; ++r) {
+          const uint32_t tt = 4 * t4 + r;
+          const uint32_t vt = __builtin_amdgcn_readfirstlane(vq[r]);
+          const uint32_t ul = lo[tt] & ql, uh = hi[tt] & qh;
+#pragma unroll
+          for (uint32_t j = 0; j < kBlkK; ++j) {
+            const uint32_t msk = 0u - ((vt >> j) & 1u);
+            nl[j] ^= ul & msk;
+            nh[j] ^= uh & msk;
+          }
+        }
+        __builtin_amdgcn_sched_barrier(0);
+      }
+#pragma unroll
+      for (uint32_t j = 0; j < kBlkK; ++j) {
+        const uint64_t f = qq ? sN[j * US + w] & qq : 0ull;
+        lo[j] = nl[j] | uint32_t(f);
+        hi[j] = nh[j] | uint32_t(f >> 32);
+      }
+    }
   }
-  if (tid == 0) s.sync[2] = k;
 }
 
 // ---------------------------------------------------------------- sweeper --
@@ -318,7 +435,7 @@ __device__ __forceinline__ void blk_sweeper(const TabDev &t, const BlkDev &s, co
   uint32_t done = 0;
   // this wave's columns measured in [m0, m0 + cnt), as they stand now, for
   // the planner
-  auto publish_cols = [&](uint32_t m0, uint32_t cnt) {
+  auto publish_cols = [&](uint32_t m0, uint32_t cnt, uint32_t buf) {
     for (uint32_t tt = 0; tt < cnt; ++tt) {
       const uint32_t o = sh.own[m0 + tt];
       if ((o & ~15u) != me) continue;   // wave-uniform
@@ -329,20 +446,23 @@ __device__ __forceinline__ void blk_sweeper(const TabDev &t, const BlkDev &s, co
 #pragma unroll
         for (int i = 0; i < L; ++i) {
           const uint32_t w = uint32_t(i) * 64 + lane;
-          if (w < W) s.cols[size_t(tt) * Wp + w] = xr[c][i];
+          if (w < W) s.cols[(size_t(buf) * kBlkK + tt) * Wp + w] = xr[c][i];
         }
       }
       fence_release();
-      if (lane == 0) atomicAdd(&s.sync[0], 1u);
+      if (lane == 0) atomicAdd(&s.sync[buf ? 3 : 0], 1u);
     }
   };
   for (uint32_t b = 0;; ++b) {
     const uint32_t m0b = b * kBlkK;
     if (m0b >= k) break;
     const uint32_t kbmax = k - m0b < kBlkK ? k - m0b : kBlkK;
-    // ---- the first block's columns (later blocks' come out of the previous
-    // block's sweep, see below)
-    if (b == 0) publish_cols(m0b, kbmax);
+    // ---- the first two blocks' columns (later blocks' come out of the sweep
+    // two blocks before, see below); block c goes through buffer c mod 2
+    if (b == 0) {
+      publish_cols(0, kbmax, 0);
+      if (kBlkK < k) publish_cols(kBlkK, k - kBlkK < kBlkK ? k - kBlkK : kBlkK, 1);
+    }
     // ---- the plan of block b
     if (tid == 0) sh.abort = blk_wait(&s.sync[1], b + 1, t.abort_flag) ? 0u : 1u;
     __syncthreads();
@@ -465,12 +585,12 @@ __device__ __forceinline__ void blk_sweeper(const TabDev &t, const BlkDev &s, co
         atomicXor(&sh.E1[w], (unsigned long long)(e1 ^ (old & e0)));
       }
     }
-    // ---- this wave's columns measured in the next block: x first, and
-    // handed to the planner at once, so that it plans the next block while
-    // this sweep goes on
+    // ---- this wave's columns measured two blocks on: x first, and handed
+    // to the planner at once (it brings them up to date with the next
+    // block's update itself)
     uint32_t early = 0;
     {
-      const uint32_t m0n = m0b + kBlkK;
+      const uint32_t m0n = m0b + 2 * kBlkK;
       const uint32_t kbn = (kb == kbmax && m0n < k) ? (k - m0n < kBlkK ? k - m0n : kBlkK) : 0u;
       for (uint32_t tt = 0; tt < kbn; ++tt) {
         const uint32_t o = sh.own[m0n + tt];
@@ -489,7 +609,7 @@ __device__ __forceinline__ void blk_sweeper(const TabDev &t, const BlkDev &s, co
             }
           }
         }
-        publish_cols(m0n, kbn);
+        publish_cols(m0n, kbn, b & 1u);
       }
     }
     // ---- x ^= U (x at the pivots), with the z.x parity of the kept rows
@@ -633,7 +753,7 @@ __global__ void __launch_bounds__(kBlkThreads) k_blk(TabDev t, BlkDev s, BlkArgs
   }
   __syncthreads();
   if (blockIdx.x == a.G)
-    blk_planner(t, s, a, sh);
+    blk_planner(t, s, a, sh, s_dynU, 64u * L);
   else
     blk_sweeper<L>(t, s, a, sh, s_dynU);
 }
@@ -683,20 +803,33 @@ __global__ void __launch_bounds__(256) k_blk_reduce(TabDev t, BlkDev s, uint32_t
   }
   if (tid < kb) s_P[tid] = s.piv[size_t(b) * kBlkK + tid];
   __syncthreads();
-  for (uint32_t q = tid; q < G; q += blockDim.x) {
-    const uint32_t *pp = s.ppart + (size_t(b) * G + q) * (2 + kBlkK);
-    const uint32_t v0 = pp[0], v1 = pp[1];
-    const uint32_t old = atomicXor(&s_yp0, v0);
-    atomicXor(&s_yp1, v1 ^ (old & v0));
-    for (uint32_t i = 0; i < kb; ++i) {
-      const uint32_t gv = pp[2 + i];
-      if (gv) atomicXor(&s_gam[i], gv);
+  // pivot partials: thread (i, q0) = (tid mod 32, tid / 32) sums Gram row i
+  // (and, for i = 0, the Y-count planes) over workgroups q0, q0 + 8, ...
+  {
+    const uint32_t i = tid & 31u, q0 = tid >> 5, nq = blockDim.x >> 5;
+    uint32_t gv = 0, y0 = 0, y1 = 0;
+#pragma unroll 4
+    for (uint32_t q = q0; q < G; q += nq) {
+      const uint32_t *pp = s.ppart + (size_t(b) * G + q) * (2 + kBlkK);
+      if (i < kb) gv ^= pp[2 + i];
+      if (i == 0) {
+        const uint32_t v0 = pp[0], v1 = pp[1];
+        y1 ^= v1 ^ (y0 & v0);
+        y0 ^= v0;
+      }
+    }
+    if (i < kb && gv) atomicXor(&s_gam[i], gv);
+    if (i == 0) {
+      const uint32_t old = atomicXor(&s_yp0, y0);
+      atomicXor(&s_yp1, y1 ^ (old & y0));
     }
   }
   __syncthreads();
   const uint32_t w = blockIdx.y * blockDim.x + tid;
   if (w >= W) return;
   uint64_t c0 = 0, c1 = 0, zx = 0;
+  // (unrolled: the workgroups' loads in flight together)
+#pragma unroll 8
   for (uint32_t q = 0; q < G; ++q) {
     const uint64_t *part = s.part + (size_t(b) * G + q) * 3 * Wp;
     const uint64_t v0 = part[w], v1 = part[Wp + w], v2 = part[2 * Wp + w];
@@ -761,6 +894,17 @@ __global__ void __launch_bounds__(kBlkSignThreads) k_blk_signs(TabDev t, BlkDev 
   for (uint32_t b = 0; b < s.NB && b * kBlkK < k; ++b) {
     const uint32_t kb = s.nb[b];
     if (kb == 0) break;
+    // this block's H and U words of the thread's two row words, all loads in
+    // flight together (none depends on the signs)
+    uint64_t h[2], u[2][kBlkK];
+#pragma unroll
+    for (uint32_t j = 0; j < 2; ++j) {
+      const uint32_t w = tid + j * kBlkSignThreads;
+      h[j] = w < W ? s.H[size_t(b) * Wp + w] : 0ull;
+      const uint64_t *U = s.U + size_t(b) * kBlkK * Wp + w;
+#pragma unroll
+      for (uint32_t i = 0; i < kBlkK; ++i) u[j][i] = (i < kb && w < W) ? U[size_t(i) * Wp] : 0ull;
+    }
 #pragma unroll
     for (uint32_t j = 0; j < 2; ++j) {
       const uint32_t w = tid + j * kBlkSignThreads;
@@ -800,10 +944,9 @@ __global__ void __launch_bounds__(kBlkSignThreads) k_blk_signs(TabDev t, BlkDev 
         }
         if ((pn >> 6) == w) kill |= bbit(pn);
       }
-      uint64_t v = (r[j] & ~kill) ^ s.H[size_t(b) * Wp + w];
-      const uint64_t *U = s.U + size_t(b) * kBlkK * Wp + w;
-      for (uint32_t i = 0; i < kb; ++i)
-        if ((rp >> i) & 1u) v ^= U[size_t(i) * Wp];
+      uint64_t v = (r[j] & ~kill) ^ h[j];
+#pragma unroll
+      for (uint32_t i = 0; i < kBlkK; ++i) v ^= ((rp >> i) & 1u) ? u[j][i] : 0ull;
       r[j] = v | set;
     }
     done += kb;
