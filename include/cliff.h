@@ -289,8 +289,9 @@ int cliff_apply_cond_paulis(cliff_tab *tab, const uint32_t *qubits, const uint8_
  * nothing and stages nothing through the context: the qubit list and the
  * register-resident pass's chunk scratch live in a static device array of
  * CLIFF_NOALLOC_SCRATCH_BYTES that the library keeps on each GPU it runs on
- * until the process ends (its chunks are as large as fits there: 48
- * measurements instead of 819 at n = 10,000, so large n run slower than with
+ * until the process ends (its chunks are as large as fits there, 48
+ * measurements at n = 10,000, and it does not take the blocked pass, where
+ * cliff_measure_record takes chunks of 2048, so large n run slower than with
  * cliff_measure_record).  Every call on a GPU uses that GPU's one array:
  * calls that overlap on one GPU (several host threads, or contexts on
  * different streams) race and must be serialized by the caller.

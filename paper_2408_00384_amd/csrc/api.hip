@@ -867,7 +867,7 @@ static int measure_pass(cliff_tab *t, const uint32_t *qubits, size_t cnt, uint64
     if (noalloc) {
       rc = noalloc_persist_scratch(c, t->d, qubits, cnt, &kc, &base, &dq);
     } else {
-      kc = persist_chunk(t->d.n);
+      kc = persist_chunk(t->d.n, use_blk);
       size_t need = persist_scratch_layout(t->d, kc).total;
       if (use_blk) {
         blk_at = align256(need);

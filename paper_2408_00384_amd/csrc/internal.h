@@ -109,7 +109,7 @@ struct TabDev {
 };
 
 constexpr uint32_t kPersistMaxGroups = 256;
-constexpr uint32_t kPersistMaxChunk = 1024;   // measurements per chunk (qubit list held in LDS)
+constexpr uint32_t kPersistMaxChunk = 2048;   // measurements per chunk (qubit list held in LDS)
 constexpr uint32_t kPersistMaxWp = 320;       // row words: at most 5 per lane of a wave
 inline bool persist_layout(uint32_t n) {
   return n >= 1 && (2 * n + 63) / 64 <= kPersistMaxWp;
@@ -120,10 +120,13 @@ inline bool persist_layout(uint32_t n) {
 // per measurement) is not hidden behind a later chunk, so below n = 8192 the
 // size follows sqrt(42 n) (the largest power of two up to sqrt(48 n)).  It is
 // bounded by the HBM kept for per-workgroup counter partials: 1 GB for
-// n >= 8192 (where the chunk is as large as that allows), else 256 MB.
-inline uint32_t persist_chunk(uint32_t n) {
+// n >= 8192 (where the chunk is as large as that allows), else 256 MB.  With
+// the blocked pass (whose chunks cost about 150 us each at n = 10,000 and
+// whose finalize is about 0.25 us per measurement) n >= 8192 takes 2.5 GiB:
+// 2048 measurements per chunk up to the largest n.
+inline uint32_t persist_chunk(uint32_t n, bool blocked = false) {
   const uint32_t Wp = (((2 * n + 63) / 64) + 7) & ~7u;
-  const size_t budget = n >= 8192 ? (size_t(1) << 30) : (size_t(256) << 20);
+  const size_t budget = n >= 8192 ? (blocked ? (size_t(5) << 29) : (size_t(1) << 30)) : (size_t(256) << 20);
   size_t kc = budget / (size_t(kPersistMaxGroups) * Wp * 16);
   if (n < 8192) {
     size_t target = 16;
@@ -135,8 +138,6 @@ inline uint32_t persist_chunk(uint32_t n) {
   if (kc > n) kc = n;
   return uint32_t(kc);
 }
-
-
 
 // Largest supported qubit count (pivot bits of a workgroup's columns in LDS).
 constexpr uint32_t kMaxQubits = 1u << 20;

@@ -754,9 +754,16 @@ hipError_t launch_measure_persist(const TabDev &t, uint32_t kc, const uint32_t *
                  : L == 4 ? reinterpret_cast<const void *>(k_meas_xz<4, 4>)
                           : reinterpret_cast<const void *>(k_meas_xz<5, 5>);
   (void)CW;   // = L, fixed by the instance
+  // Large chunks end the pass with a short one: the last chunk's finalize is
+  // the one no later chunk hides.  (Set 1's entries at offset kc still end by
+  // n: only when kc + kTail <= n.)
+  constexpr uint32_t kTail = 256;
+  const bool split_tail = kc >= 4 * kTail && kc + kTail <= t.n;
   uint32_t last = 0;
-  for (uint32_t base = 0, c = 0; base < k; base += kc, ++c) {
-    const uint32_t cnt = k - base < kc ? k - base : kc;
+  for (uint32_t base = 0, c = 0, cnt = 0; base < k; base += cnt, ++c) {
+    const uint32_t rem = k - base;
+    cnt = rem < kc ? rem : kc;
+    if (split_tail && rem > 2 * kTail && rem <= kc + kTail) cnt = rem - kTail;
     const uint32_t b = c & 1u;
     last = b;
     const TabDev &tv = tb[b];
@@ -777,9 +784,10 @@ hipError_t launch_measure_persist(const TabDev &t, uint32_t kc, const uint32_t *
     // A plain launch goes to another hardware queue than the cooperative x/z
     // kernel, and each hand-off between the two is a cross-queue dependency
     // (10-20 us).  Launched cooperatively it shares the x/z kernel's queue:
-    // 1.5-2.4 % faster at n = 10,000 (chunks of 819), 1-5 % slower from
-    // n = 256 to 8,000 (chunks of at most 341), where the cooperative path's
-    // own cost per launch outweighs it; so only for the 1 GB chunks.
+    // 1.5-2.4 % faster at n = 10,000 (measured with chunks of 819), 1-5 %
+    // slower from n = 256 to 8,000 (chunks of at most 341), where the
+    // cooperative path's own cost per launch outweighs it; so only for the
+    // large chunks of n >= 8192.
     if (prof) prof->begin(PK_SELECT, st);
     if (t.n >= 8192) {
       TabDev barg = tv;
