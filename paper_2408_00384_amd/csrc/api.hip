@@ -127,7 +127,7 @@ struct cliff_ctx {
   // register-resident measurement: second stream and its events, and the
   // chunk scratch (grown on demand to the largest shape measured)
   hipStream_t aux = nullptr;
-  hipEvent_t persist_ev[4] = {nullptr, nullptr, nullptr, nullptr};
+  hipEvent_t persist_ev[6] = {nullptr, nullptr, nullptr, nullptr, nullptr, nullptr};
   uint8_t *pscratch = nullptr;
   size_t pscratch_bytes = 0;
   int gate_mode = CLIFF_GATES_AUTO;
@@ -883,7 +883,8 @@ static int measure_pass(cliff_tab *t, const uint32_t *qubits, size_t cnt, uint64
     BlkDev bsets[2];
     if (use_blk)
       for (int i = 0; i < 2; ++i) bsets[i] = blk_scratch_bind(t->d, kc, bG, base + blk_at + size_t(i) * blk_set);
-    PersistStreams ps{st, c->aux, {c->persist_ev[0], c->persist_ev[1], c->persist_ev[2], c->persist_ev[3]}};
+    PersistStreams ps{st, c->aux, {c->persist_ev[0], c->persist_ev[1], c->persist_ev[2], c->persist_ev[3],
+                                   c->persist_ev[4], c->persist_ev[5]}};
     uint32_t done = 0;
     hipError_t e = launch_measure_persist(dv, kc, dq, uint32_t(cnt), seed, circuit, shot0, m0,
                                           c->num_cus, ps, &c->prof, &done, abort_at,

@@ -333,9 +333,11 @@ hipError_t launch_blk_finalize(const TabDev &t, const BlkDev &s, uint32_t cnt, u
 // Streams and events of the register-resident path: chunk c's x/z kernel
 // runs on `main` while chunk c - 1's reduction and sign walk run on `aux`;
 // ev[0..1] mark x/z done and ev[2..3] finalize done per scratch buffer.
+// ev[b]: chunk of scratch set b enqueued on main; ev[2 + b]: its finalize
+// done on aux; ev[4 + b]: its blocked pass done on main.
 struct PersistStreams {
   hipStream_t main, aux;
-  hipEvent_t ev[4];
+  hipEvent_t ev[6];
 };
 // *done = measurements whose launches were all enqueued (chunks before a failure).
 // t carries the chunk scratch for chunks of kc measurements (persist_scratch_bind).

@@ -780,6 +780,16 @@ hipError_t launch_measure_persist(const TabDev &t, uint32_t kc, const uint32_t *
       if (prof) prof->end(PK_BLOCKED, st);
       if (e != hipSuccess) return e;
       skip = blk[b].sync + 2;
+      // its finalize needs only the blocked pass's own results: on the second
+      // stream from here, during the launches below (a finalize dispatched
+      // after the next chunk's blocked pass has taken the CUs waits for it)
+      e = hipEventRecord(ps.ev[4 + b], st);
+      if (e == hipSuccess) e = hipStreamWaitEvent(aux, ps.ev[4 + b], 0);
+      if (e != hipSuccess) return e;
+      if (prof) prof->begin(PK_FINAL, aux);
+      e = launch_blk_finalize(tv, blk[b], cnt, base, seed, circuit, shot0, m0, blk_G, aux);
+      if (prof) prof->end(PK_FINAL, aux);
+      if (e != hipSuccess) return e;
     }
     // A plain launch goes to another hardware queue than the cooperative x/z
     // kernel, and each hand-off between the two is a cross-queue dependency
@@ -815,10 +825,6 @@ hipError_t launch_measure_persist(const TabDev &t, uint32_t kc, const uint32_t *
     e = hipStreamWaitEvent(aux, ps.ev[b], 0);
     if (e != hipSuccess) return e;
     if (prof) prof->begin(PK_FINAL, aux);
-    if (blk) {
-      e = launch_blk_finalize(tv, blk[b], cnt, base, seed, circuit, shot0, m0, blk_G, aux);
-      if (e != hipSuccess) return e;
-    }
     k_meas_reduce<<<dim3(cnt, (t.W + 255) / 256), 256, 0, aux>>>(tv, cnt, G, skip);
     k_meas_signs<<<t.S, kSignThreads, 0, aux>>>(tv, cnt, base, seed, circuit, shot0, m0, skip);
     if (prof) prof->end(PK_FINAL, aux);
