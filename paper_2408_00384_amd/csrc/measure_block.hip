@@ -109,8 +109,9 @@ struct BlkShared {
 };
 
 // ---------------------------------------------------------------- planner --
-// Thread w holds row word w of the block's columns and of U in one array,
-// split in 32-bit halves (lo: rows 64 w .. 64 w + 31): element i is column
+// Each thread holds one row word w (plan_group below) of the block's columns
+// and of U in one array, split in 32-bit halves (lo: rows 64 w .. 64 w + 31),
+// threads past the last word nothing: element i is column
 // a_i while measurement i is to come and U column i once it is done (the
 // column becomes its own U column: M = the rows with x = 1 on it, less p and
 // p - n, plus row p - n).  Measurement t with pivot p:
@@ -137,6 +138,15 @@ struct PlanCtx {
   bool aborted, stopped;
 };
 
+// Row-word group of planner wave `wave` (thread: word 64 group + lane).  With
+// five groups (W > 256, so n > 8192) waves 0 and 4 share a SIMD: they take
+// groups 0 and 1, destabilizer rows only, which never search for a pivot,
+// and waves 1-3 the groups that do.
+__device__ __forceinline__ uint32_t plan_group(uint32_t wave, uint32_t W) {
+  if (W <= 256) return wave;
+  return wave == 4 ? 1u : (wave >= 1 && wave <= 3) ? wave + 1 : wave;
+}
+
 template <uint32_t D>
 __device__ __forceinline__ void plan_step(uint32_t (&lo)[kBlkK], uint32_t (&hi)[kBlkK], PlanCtx &pc,
                                           const TabDev &t, const BlkDev &s, const BlkArgs &a, BlkShared &sh) {
@@ -144,7 +154,7 @@ __device__ __forceinline__ void plan_step(uint32_t (&lo)[kBlkK], uint32_t (&hi)[
   if (tt >= pc.kbmax) pc.stopped = true;
   const uint32_t tid = threadIdx.x, lane = tid & 63;
   const uint32_t wave = __builtin_amdgcn_readfirstlane(tid >> 6);
-  const uint32_t n = t.n, W = t.W, w = tid;
+  const uint32_t n = t.n, W = t.W, grp = plan_group(wave, W), w = grp * 64 + lane;
   if (!pc.stopped && pc.m0b + tt == a.abort_at) {   // injected: stop as after a timed-out wait
     if (tid == 0) atomicOr(t.abort_flag, 1u);
     pc.aborted = true;
@@ -155,7 +165,7 @@ __device__ __forceinline__ void plan_step(uint32_t (&lo)[kBlkK], uint32_t (&hi)[
   const uint32_t cl = lo[D], ch = hi[D];
   // waves past the last row word hold nothing: they only keep the barriers
   // (and leave the issue slots of their SIMD to the wave sharing it)
-  const bool holds = wave * 64 < W;
+  const bool holds = grp * 64 < W;
   if (holds) {
     // this wave's smallest candidate and that row's bits of the elements
     const uint32_t cand = live ? blk_candidate((uint64_t(ch) << 32) | cl, w, n, W) : kNone;
@@ -243,7 +253,7 @@ __device__ __forceinline__ void blk_planner(const TabDev &t, const BlkDev &s, co
                                             uint64_t *sN, uint32_t US) {
   const uint32_t tid = threadIdx.x, lane = tid & 63;
   const uint32_t wave = __builtin_amdgcn_readfirstlane(tid >> 6);
-  const uint32_t n = t.n, W = t.W, Wp = t.Wp, k = a.k, w = tid;
+  const uint32_t n = t.n, W = t.W, Wp = t.Wp, k = a.k, grp = plan_group(wave, W), w = grp * 64 + lane;
   PlanCtx pc;
   pc.aborted = false;
   uint32_t lo[kBlkK], hi[kBlkK];
@@ -367,7 +377,7 @@ __device__ __forceinline__ void blk_planner(const TabDev &t, const BlkDev &s, co
     // x ^= sum over t with V_t set of U_t (U's stale replaced rows left
     // out), replaced rows taken from sN; waves past the last row word
     // hold nothing
-    if (wave * 64 < W) {
+    if (grp * 64 < W) {
       const uint64_t kq = w < W ? sh.K[w] : 0ull, qq = w < W ? uint64_t(sh.ZX[w]) : 0ull;
       const uint32_t kl = ~uint32_t(kq | qq), kh = ~uint32_t((kq | qq) >> 32), ql = ~uint32_t(qq), qh = ~uint32_t(qq >> 32);
 #pragma unroll
