@@ -51,8 +51,8 @@ VALU_PEAK_TOPS = 157.3 / 2
 TRAFFIC = {
     "k_blk": {
         "sources": ("paper_2408_00384_amd/csrc/measure_block.hip", "paper_2408_00384_amd/csrc/internal.h"),
-        "sha256": "ca035eaad62ac7a8b80d14ccbd548be5cb8fd139e858359db34401d303c9ee72",
-        "bytes_per_launch": 1.717e+08,
+        "sha256": "764ee49cbb0c5dc716fb5d018fef67565b5f70bdef0e2c5c707ff47321be96a4",
+        "bytes_per_launch": 2.504e+08,
         "summary": "profiles/k_blk_plain_n10000_measure_all.md",
     },
     "k_meas_xz": {
