@@ -174,3 +174,32 @@ def test_abort_in_blocked_pass(ctx, at):
     finally:
         cliff_ctx_inject_abort(ctx.handle, NONE)
         _mode(ctx, MEASURE_AUTO)
+
+
+@pytest.mark.parametrize("n,depth", [(8500, 1), (10000, 2)])
+def test_large_mixed_equals_step(ctx, n, depth):
+    """Above n = 8192 (five planner word groups; chunks of 2048, the pass
+    ending with a short one) on a shallow circuit that mixes random and
+    deterministic outcomes: each chunk's blocked pass stops at its first
+    deterministic measurement and the per-measurement kernels finish the
+    chunk from the count it left.  Tableau, outcomes and both shots' signs
+    equal the step path's (itself checked against the oracle elsewhere)."""
+    from paper_2408_00384_amd import MEASURE_BLOCKED, MEASURE_STEP, DeviceTableau
+    c = layered_circuit(n, depth, 2, gen_seed=[66, n, depth], circuit_id=17)
+    res = {}
+    try:
+        for mode in (MEASURE_STEP, MEASURE_BLOCKED):
+            _mode(ctx, mode)
+            t = DeviceTableau(ctx, n, 2).apply_circuit_gates(c)
+            out, rnd = t.measure(c.qubits, seed=c.seed, circuit=17)
+            res[mode] = (out, rnd, t.export(), t.anomalies())
+            t.close()
+    finally:
+        from paper_2408_00384_amd import MEASURE_AUTO
+        _mode(ctx, MEASURE_AUTO)
+    a, b = res[MEASURE_STEP], res[MEASURE_BLOCKED]
+    assert 0.05 < b[1].mean() < 0.95
+    assert np.array_equal(a[0], b[0]) and np.array_equal(a[1], b[1])
+    for A, B in zip(a[2], b[2]):
+        assert np.array_equal(A, B)
+    assert a[3] == 0 and b[3] == 0
