@@ -350,9 +350,15 @@ __device__ __forceinline__ void blk_planner(const TabDev &t, const BlkDev &s, co
       const uint32_t q = pc.qrow, p = q + n;
       uint32_t v = 0, oq = 0;
       if (mine) {
-        for (uint32_t j = 0; j < kbn; ++j) {
-          v |= uint32_t((sN[j * US + (p >> 6)] >> (p & 63)) & 1u) << j;
-          oq |= uint32_t((sN[j * US + (q >> 6)] >> (q & 63)) & 1u) << j;
+        // (columns past kbn are staged as zeros; the 32-bit halves holding
+        // rows p and q, eight reads of each in flight at a time)
+        const uint32_t *s32 = reinterpret_cast<const uint32_t *>(sN);
+        const uint32_t ap = (p >> 5), aq = (q >> 5), sp = p & 31, sq = q & 31;
+#pragma unroll
+        for (uint32_t j = 0; j < kBlkK; ++j) {
+          v |= ((s32[j * 2 * US + ap] >> sp) & 1u) << j;
+          oq |= ((s32[j * 2 * US + aq] >> sq) & 1u) << j;
+          if ((j & 7u) == 7u) __builtin_amdgcn_sched_barrier(0);
         }
         atomicOr(reinterpret_cast<unsigned long long *>(&sh.K[p >> 6]), (unsigned long long)bbit(p));
         atomicOr(&sh.ZX[q >> 6], (unsigned long long)bbit(q));
@@ -368,7 +374,8 @@ __device__ __forceinline__ void blk_planner(const TabDev &t, const BlkDev &s, co
         const uint32_t d = f ^ oq;
         unsigned long long *col = reinterpret_cast<unsigned long long *>(sN + (q >> 6));
         const unsigned long long m = bbit(q);
-        for (uint32_t j = 0; j < kbn; ++j)
+#pragma unroll
+        for (uint32_t j = 0; j < kBlkK; ++j)
           if ((d >> j) & 1u) atomicXor(col + size_t(j) * US, m);
       }
     }
