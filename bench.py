@@ -51,7 +51,7 @@ VALU_PEAK_TOPS = 157.3 / 2
 TRAFFIC = {
     "k_blk": {
         "sources": ("paper_2408_00384_amd/csrc/measure_block.hip", "paper_2408_00384_amd/csrc/internal.h"),
-        "sha256": "764ee49cbb0c5dc716fb5d018fef67565b5f70bdef0e2c5c707ff47321be96a4",
+        "sha256": "d0591700c4fd548384f4b071c29ba6eda2e19432f124b57408adbbc1331c61a8",
         "bytes_per_launch": 2.504e+08,
         "summary": "profiles/k_blk_plain_n10000_measure_all.md",
     },
