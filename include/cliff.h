@@ -119,8 +119,8 @@ int cliff_ctx_set_gate_mode(cliff_ctx *ctx, int mode);
  * 8161..8192, 10201..10240) it is PERSISTENT.  STEP: one kernel per
  * measurement.  AUTO: BLOCKED for n >= 2048, PERSISTENT below, STEP where
  * neither fits.  Results are identical; only speed differs.  A measure-all of
- * a dense state at n = 10,000 takes 18.3 ms with BLOCKED against 38.5 ms with
- * PERSISTENT (6,000: 11.2 against 16.3 ms; 2,100: 3.9 against 4.6 ms); a GHZ
+ * a dense state at n = 10,000 takes 16.1 ms with BLOCKED against 38.7 ms with
+ * PERSISTENT (6,000: 9.5 against 16.5 ms; 2,100: 4.0 against 4.6 ms); a GHZ
  * measure-all (n - 1 of n outcomes deterministic) takes 61 ms with the
  * register-resident path at n = 10,000 against 125 ms with STEP. */
 #define CLIFF_MEASURE_AUTO 0

@@ -122,13 +122,17 @@ inline bool persist_layout(uint32_t n) {
 // bounded by the HBM kept for per-workgroup counter partials: 1 GB for
 // n >= 8192 (where the chunk is as large as that allows), else 256 MB.  With
 // the blocked pass (whose chunks cost about 150 us each at n = 10,000 and
-// whose finalize is about 0.25 us per measurement) n >= 8192 takes 2.5 GiB:
-// 2048 measurements per chunk up to the largest n.
+// whose finalize is about 0.25 us per measurement) n >= 3000 takes 2.5 GiB:
+// 2048 measurements per chunk up to the largest n, faster from n = 3,000 on
+// dense and shallow circuits alike; at n = 2,100 shallow circuits, whose
+// chunks mostly run per measurement, were slower with them.
+constexpr uint32_t kBlkBigChunkMinN = 3000;
 inline uint32_t persist_chunk(uint32_t n, bool blocked = false) {
   const uint32_t Wp = (((2 * n + 63) / 64) + 7) & ~7u;
-  const size_t budget = n >= 8192 ? (blocked ? (size_t(5) << 29) : (size_t(1) << 30)) : (size_t(256) << 20);
+  const bool big = blocked && n >= kBlkBigChunkMinN;
+  const size_t budget = big ? (size_t(5) << 29) : n >= 8192 ? (size_t(1) << 30) : (size_t(256) << 20);
   size_t kc = budget / (size_t(kPersistMaxGroups) * Wp * 16);
-  if (n < 8192) {
+  if (n < 8192 && !big) {
     size_t target = 16;
     while (4 * target * target <= size_t(48) * n) target *= 2;
     if (kc > target) kc = target;
