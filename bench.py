@@ -51,7 +51,7 @@ VALU_PEAK_TOPS = 157.3 / 2
 TRAFFIC = {
     "k_blk": {
         "sources": ("paper_2408_00384_amd/csrc/measure_block.hip", "paper_2408_00384_amd/csrc/internal.h"),
-        "sha256": "d0591700c4fd548384f4b071c29ba6eda2e19432f124b57408adbbc1331c61a8",
+        "sha256": "c6b91930278990bdaec921c5e613334314a5fd1f9e98758708a7a49e753da28e",
         "bytes_per_launch": 2.504e+08,
         "summary": "profiles/k_blk_plain_n10000_measure_all.md",
     },
