@@ -867,15 +867,27 @@ static int measure_pass(cliff_tab *t, const uint32_t *qubits, size_t cnt, uint64
     if (noalloc) {
       rc = noalloc_persist_scratch(c, t->d, qubits, cnt, &kc, &base, &dq);
     } else {
+      auto need_for = [&](uint32_t kc_) {
+        size_t need = persist_scratch_layout(t->d, kc_).total;
+        if (use_blk) {
+          blk_at = align256(need);
+          blk_set = align256(blk_scratch_layout(t->d, kc_, bG).total);
+          need = blk_at + 2 * blk_set;
+        }
+        return need;
+      };
       kc = persist_chunk(t->d.n, use_blk);
-      size_t need = persist_scratch_layout(t->d, kc).total;
-      if (use_blk) {
-        blk_at = align256(need);
-        blk_set = align256(blk_scratch_layout(t->d, kc, bG).total);
-        need = blk_at + 2 * blk_set;
-      }
       rc = upload_stream(c, nullptr, 0, qubits, cnt, nullptr, &dq);
-      if (!rc) rc = ctx_persist_scratch(c, need, &base);
+      if (!rc) {
+        rc = ctx_persist_scratch(c, need_for(kc), &base);
+        // the blocked pass's large chunks did not fit in device memory: the
+        // per-measurement path's chunk size (same results, more chunks)
+        const uint32_t kc_small = persist_chunk(t->d.n, false);
+        if (rc == CLIFF_ENOMEM && kc_small < kc) {
+          kc = kc_small;
+          rc = ctx_persist_scratch(c, need_for(kc), &base);
+        }
+      }
     }
     if (rc) return rc;
     TabDev dv = t->dev;

@@ -203,3 +203,46 @@ def test_large_mixed_equals_step(ctx, n, depth):
     for A, B in zip(a[2], b[2]):
         assert np.array_equal(A, B)
     assert a[3] == 0 and b[3] == 0
+
+
+def test_large_chunks_fall_back_when_memory_is_short():
+    """With the device nearly full (all but 4 GiB held by a torch
+    allocation), the blocked pass's chunk scratch at n = 10,000 (about 5.6 GB
+    for chunks of 2048) cannot be allocated; the call then takes the
+    per-measurement chunk size (about 2.3 GB) and gives the oracle's results;
+    cliff_last_error reports the refused allocation."""
+    import torch
+    from paper_2408_00384_amd import (MEASURE_BLOCKED, CliffError, Context, DeviceTableau, cliff_ctx_set_measure_mode,
+                                      cliff_last_error)
+    n, shots = 10000, 1
+    c = layered_circuit(n, 14, shots, gen_seed=[67, n], circuit_id=18)
+    q = np.arange(70, dtype=np.uint32)
+    cx = Context(0)
+    try:
+        cliff_ctx_set_measure_mode(cx.handle, MEASURE_BLOCKED)
+        t = DeviceTableau(cx, n, shots).apply_circuit_gates(c)
+        torch.cuda.synchronize()
+        free, _ = torch.cuda.mem_get_info()
+        keep = 4 << 30
+        if free <= keep + (1 << 30):
+            pytest.skip("less than 5 GiB of device memory free")
+        # a known failure first, so that the message checked below is this call's
+        with pytest.raises(CliffError):
+            cliff_ctx_set_measure_mode(cx.handle, 99)
+        assert "measurement scratch" not in cliff_last_error()
+        hold = torch.empty(free - keep, dtype=torch.uint8, device="cuda")
+        try:
+            out, rnd = t.measure(q, seed=c.seed, circuit=18)
+        finally:
+            del hold
+            torch.cuda.empty_cache()
+        # the large-chunk allocation was refused and the call recovered
+        assert "measurement scratch" in cliff_last_error()
+        want_out, want_kinds, tabs = _oracle_run(c, q, shots)
+        assert np.array_equal(rnd, want_kinds) and np.array_equal(out, want_out)
+        gx, gz, gr = t.export()
+        x, z, r = tabs[0]
+        assert np.array_equal(gx, x) and np.array_equal(gz, z) and np.array_equal(gr[0], r)
+        t.close()
+    finally:
+        cx.close()
