@@ -189,8 +189,12 @@ __device__ __forceinline__ void fused_body(uint64_t *X, uint64_t *Z, uint64_t *P
 }
 
 // One tableau, 32-row groups (twice as many workgroups as 64-row ones: a
-// single tableau is latency-bound, not throughput-bound).
-__global__ void __launch_bounds__(256) k_gates_fused(TabDev t, const uint64_t *__restrict__ ops,
+// single tableau is latency-bound, not throughput-bound).  Launched with up
+// to 1024 threads: 16 waves share a group's layer work, so that more LDS
+// round trips are in flight per SIMD (n = 10,000, 20 layers: 30 % less time
+// than with 256 threads).
+constexpr uint32_t kFusedMaxThreads = 1024;
+__global__ void __launch_bounds__(kFusedMaxThreads) k_gates_fused(TabDev t, const uint64_t *__restrict__ ops,
                                                      const uint32_t *__restrict__ offs, uint32_t depth) {
   extern __shared__ uint64_t lds_u64[];
   __shared__ uint32_t s_r;
@@ -344,7 +348,9 @@ hipError_t launch_gates_fused(const TabDev &t, const uint64_t *ops, const uint32
     attr_set = true;
   }
   const uint32_t halves = (2 * t.n + 31) / 32;
-  k_gates_fused<<<halves, 256, lds, st>>>(t, ops, dev_offs, depth);
+  // (below n = 512 a layer has too few ops for 16 waves)
+  const uint32_t threads = t.n >= 512 ? kFusedMaxThreads : 256;
+  k_gates_fused<<<halves, threads, lds, st>>>(t, ops, dev_offs, depth);
   return hipGetLastError();
 }
 
